@@ -1,0 +1,122 @@
+"""Objective values, KKT residuals and the D-seminorm (oracle, FP64).
+
+* ``tv``: anisotropic |Dx|_1 (Section 4.1) or isotropic sum_p |(Dx)_p|_2.
+* ``objective``: CT 1/2 |Ex - b|^2 + lambda TV(x) (Section 4.1); PET the
+  Poisson negative log-likelihood sum_i [y_i - b_i log y_i + log Gamma(b_i+1)]
+  with y = Ex + r, plus lambda TV(x) (Section 4.2; the log Gamma constant makes
+  it the exact negative log-likelihood and does not move the minimiser).
+  Outside the domain of l (y_i <= 0 with b_i > 0, or y_i < 0 with b_i = 0) the
+  value is +inf.
+* ``kkt``: for the pair (eq. RCP, eq. dual) at a primal-dual point (x, y):
+  dual feasibility |A^T y| and the fixed-point residual
+  |y - prox_{alpha g*}(y + alpha(A x - b~))| (zero exactly at a saddle point).
+* ``d_seminorm_sq``: D^2(x, y) = |y - alpha A x|^2 + x^T(alpha M - alpha^2 A^T A) x
+  of Section 3.2, with M = F^-1 diag(mu) F.
+
+Parity: pinned through the tests of the solvers (KKT -> 0 at the common
+limit of NCS, PDHG and ADMM) and the Lemma (monotone) invariant.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import gammaln
+
+from . import prox
+from .problems import Params, Problem
+
+
+def tv(prob: Problem, x: np.ndarray) -> float:
+    g = prob.D @ x
+    n = prob.n
+    if prob.tv == "aniso":
+        return float(np.abs(g).sum())
+    return float(np.sqrt(g[:n] ** 2 + g[n:] ** 2).sum())
+
+
+def data_term(prob: Problem, proj: np.ndarray) -> float:
+    """g_data(E x) given proj = E x."""
+    if prob.kind == "ct":
+        r = proj - prob.b
+        return 0.5 * float(r @ r)
+    y = proj + prob.bg
+    b = prob.b
+    pos = b > 0
+    if np.any(y[pos] <= 0) or np.any(y[~pos] < 0):
+        return float("inf")
+    val = np.where(pos, y - b * np.log(np.where(pos, y, 1.0)), y) + gammaln(b + 1.0)
+    return float(val.sum())
+
+
+def objective(prob: Problem, x: np.ndarray) -> float:
+    return data_term(prob, prob.E @ x) + prob.lam * tv(prob, x)
+
+
+def stacked_A(prob: Problem, par: Params):
+    """Callables for A = [E; (beta/alpha) D] and A^T, and the offset b~ = [b; 0] (CT)
+    or [-r; 0] (PET, where the data block is l(. + r) with zero offset)."""
+    ratio = par.beta / par.alpha
+    m = prob.m
+
+    def A(x):
+        return np.concatenate([prob.E @ x, ratio * (prob.D @ x)])
+
+    def At(y):
+        return prob.Et @ y[:m] + ratio * (prob.Dt @ y[m:])
+
+    if prob.kind == "ct":
+        btil = np.concatenate([prob.b, np.zeros(2 * prob.n)])
+    else:
+        btil = np.concatenate([-prob.bg, np.zeros(2 * prob.n)])
+    return A, At, btil
+
+
+def prox_conj(prob: Problem, par: Params):
+    """prox_{alpha g*} for the stacked g, derived by the Moreau identity
+    (Section 2, eq. Moreau) from the primal proximal maps of g."""
+    a = par.alpha
+    m, n = prob.m, prob.n
+    s_tv = prob.lam * par.alpha / par.beta   # weight of |z| in g after scaling D by beta/alpha
+
+    def data_prox(z, t):
+        if prob.kind == "ct":
+            return prox.prox_quadratic(z, t)
+        return prox.prox_poisson(z, prob.b, t)
+
+    def tv_prox(z, t):
+        if prob.tv == "aniso":
+            return prox.soft_threshold(z, t * s_tv)
+        zh, zv = z[:n], z[n:]
+        nrm = np.sqrt(zh * zh + zv * zv)
+        shrink = np.maximum(nrm - t * s_tv, 0.0) / np.where(nrm > 0, nrm, 1.0)
+        return np.concatenate([zh * shrink, zv * shrink])
+
+    def pc(w):
+        return np.concatenate([prox.moreau_conj(data_prox, w[:m], a),
+                               prox.moreau_conj(tv_prox, w[m:], a)])
+
+    return pc
+
+
+def kkt(prob: Problem, par: Params, x: np.ndarray, y: np.ndarray) -> tuple[float, float]:
+    A, At, btil = stacked_A(prob, par)
+    pc = prox_conj(prob, par)
+    r_dual = float(np.linalg.norm(At(y)))
+    r_fix = float(np.linalg.norm(y - pc(y + par.alpha * (A(x) - btil))))
+    return r_dual, r_fix
+
+
+def quad_M(mu: np.ndarray, x: np.ndarray) -> float:
+    """x^T M x with M = F^-1 diag(mu) F."""
+    n_side = mu.shape[0]
+    img = x.reshape(n_side, n_side)
+    mx = np.real(np.fft.ifft2(mu * np.fft.fft2(img)))
+    return float((img * mx).sum())
+
+
+def d_seminorm_sq(prob: Problem, par: Params, mu: np.ndarray, dx: np.ndarray,
+                  dy: np.ndarray) -> float:
+    A, _, _ = stacked_A(prob, par)
+    a = par.alpha
+    adx = A(dx)
+    r = dy - a * adx
+    return float(r @ r) + a * quad_M(mu, dx) - a * a * float(adx @ adx)

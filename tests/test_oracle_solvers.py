@@ -1,0 +1,182 @@
+"""Pins of the oracle's iterations: special cases, the appendix change of
+variables, the common limit of NCS / PDHG / ADMM (Theorem 1) with KKT
+residuals, and the monotone / summable lemmas of Section 3.2 under A3.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import objective, operators, problems, solvers
+
+N, NA, NS = 16, 24, 24
+
+
+def _ct(tv="aniso", lam=0.05, seed=3):
+    return problems.ct_problem(N, NA, NS, seed, lam, tv=tv)
+
+
+def _pet(tv="iso", lam=0.5, seed=4):
+    return problems.pet_problem(N, NA, NS, seed, lam, total_counts=2e4, tv=tv)
+
+
+def _dense_circulant(mu):
+    n = mu.shape[0]
+    eye = np.eye(n * n).reshape(n * n, n, n)
+    cols = np.real(np.fft.ifft2(mu[None] * np.fft.fft2(eye), axes=(1, 2)))
+    return cols.reshape(n * n, n * n).T
+
+
+def _gamma_a3(prob, par):
+    """Smallest gamma with gamma I + M0 >= alpha A^T A (assumption A3)."""
+    base = problems.Params(par.alpha, par.beta, 0.0, par.c_r,
+                           problems.resolved_mu_dc(prob, problems.Params(par.alpha, par.beta, 0.0)))
+    m0 = _dense_circulant(problems.eigenvalues(prob, base))
+    ata = solvers.normal_matrix(prob, par)
+    return float(np.linalg.eigvalsh(par.alpha * ata - m0)[-1])
+
+
+def _a3_params(prob, alpha=0.05, beta=0.1):
+    par = problems.Params(alpha, beta, 0.0)
+    g = _gamma_a3(prob, par) * 1.01 + 1e-9
+    return problems.Params(alpha, beta, g)
+
+
+@pytest.mark.parametrize("kind", ["ct_aniso", "ct_iso", "pet_iso"])
+def test_constant_multiplier_ncs_is_pdhg(kind):
+    prob = {"ct_aniso": lambda: _ct("aniso"), "ct_iso": lambda: _ct("iso"), "pet_iso": _pet}[kind]()
+    par = problems.Params(0.02, 0.05, 0.0)
+    gp = 1.05 * par.alpha * np.linalg.eigvalsh(solvers.normal_matrix(prob, par))[-1]
+    h = np.full((N, N), 1.0 / gp)
+    tr = solvers.ncs(prob, par, 60, h=h)
+    x, y, _ = solvers.pdhg(prob, par, gp, 60)
+    np.testing.assert_allclose(tr.x, x, rtol=0, atol=1e-10 * np.abs(x).max())
+    np.testing.assert_allclose(tr.u, y[: prob.m], rtol=0, atol=1e-10 * np.abs(y[: prob.m]).max())
+    np.testing.assert_allclose(tr.v, y[prob.m:], rtol=0, atol=1e-10 * max(1.0, np.abs(y[prob.m:]).max()))
+
+
+@pytest.mark.parametrize("kind", ["ct_aniso", "pet_iso"])
+def test_application_form_is_general_ncs(kind):
+    # The CT/PET forms of Section 4 with the mask equal eq. (NCS) with
+    # M^+ = F^-1 diag(h) F on A = [E; (beta/alpha) D].
+    prob = _ct() if kind == "ct_aniso" else _pet()
+    par = problems.Params(0.03, 0.09, 20.0)
+    h = problems.multiplier(prob, par)
+    tr = solvers.ncs(prob, par, 40)
+    x, y, _ = solvers.ncs_generic(prob, par, lambda z: operators.apply_circulant(h, z.reshape(N, N)).ravel(), 40)
+    np.testing.assert_allclose(tr.x, x, rtol=0, atol=1e-10 * np.abs(x).max())
+    np.testing.assert_allclose(tr.u, y[: prob.m], rtol=0, atol=1e-10 * np.abs(y[: prob.m]).max())
+
+
+@pytest.mark.parametrize("kind", ["ct_aniso", "ct_iso", "pet_iso"])
+def test_classic_admm_is_reduced_admm(kind):
+    # Section 7.1: ADMM in the (z, x, multiplier) form equals eq. (ADMM) after the
+    # change of variables y^{k+1} = prox_{alpha g*}(alpha(A x^k - b~ - l^k)).
+    prob = {"ct_aniso": lambda: _ct("aniso"), "ct_iso": lambda: _ct("iso"), "pet_iso": _pet}[kind]()
+    par = problems.Params(0.5, 0.2, 0.0)
+    ata = solvers.normal_matrix(prob, par)
+    cho = sla.cho_factor(ata)
+    K = 25
+    xs, y1 = solvers.admm_classic(prob, par, K, np.zeros(prob.n),
+                                  np.zeros(prob.m + 2 * prob.n), lambda z: sla.cho_solve(cho, z))
+    x, _, _ = solvers.admm(prob, par, K, x0=np.zeros(prob.n), y0=y1, record=False)
+    np.testing.assert_allclose(x, xs[-1], rtol=0, atol=1e-8 * np.abs(xs[-1]).max())
+
+
+def test_common_limit_and_kkt():
+    # Theorem 1: NCS (A3 holds), PDHG and ADMM reach the same primal solution and
+    # data dual (x* unique: E is injective here); KKT residuals vanish.
+    prob = _ct("aniso")
+    par = _a3_params(prob)
+    assert np.linalg.svd(prob.E.toarray(), compute_uv=False)[-1] > 1e-6
+    tr = solvers.ncs(prob, par, 6000, record=False)
+    gp = 1.01 * par.alpha * np.linalg.eigvalsh(solvers.normal_matrix(prob, par))[-1]
+    xp, yp, _ = solvers.pdhg(prob, par, gp, 20000, record=False)
+    xa, ya, _ = solvers.admm(prob, par, 3000, record=False)
+    scale = np.abs(xa).max()
+    np.testing.assert_allclose(tr.x, xa, atol=1e-6 * scale)
+    np.testing.assert_allclose(xp, xa, atol=1e-6 * scale)
+    np.testing.assert_allclose(tr.u, ya[: prob.m], atol=1e-6 * np.abs(ya[: prob.m]).max())
+    y = np.concatenate([tr.u, tr.v])
+    r_dual, r_fix = objective.kkt(prob, par, tr.x, y)
+    assert r_dual < 1e-6 * np.linalg.norm(prob.Et @ tr.u)
+    assert r_fix < 1e-6 * (1 + np.linalg.norm(y))
+    # the limit is a minimiser: small perturbations do not lower f
+    f0 = objective.objective(prob, xa)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        assert objective.objective(prob, xa + 1e-3 * rng.standard_normal(prob.n)) >= f0 - 1e-9 * abs(f0)
+
+
+def test_monotone_and_summable_lemmas_under_a3():
+    # Section 3.2, Lemma (monotone) and Lemma (summable), in the D-seminorm.
+    prob = _ct("aniso")
+    par = _a3_params(prob)
+    mu = problems.eigenvalues(prob, par)
+    K = 150
+    xs, ys = [np.zeros(prob.n)], [np.zeros(prob.m + 2 * prob.n)]
+    x, u, v = xs[0], np.zeros(prob.m), np.zeros(2 * prob.n)
+    for _ in range(K):
+        tr = solvers.ncs(prob, par, 1, x0=x, u0=u, v0=v, record=False)
+        x, u, v = tr.x, tr.u, tr.v
+        xs.append(x)
+        ys.append(np.concatenate([u, v]))
+    star = solvers.ncs(prob, par, 8000, record=False)
+    ystar = np.concatenate([star.u, star.v])
+    d_step = [objective.d_seminorm_sq(prob, par, mu, xs[k + 1] - xs[k], ys[k + 1] - ys[k]) for k in range(K)]
+    d_star = [objective.d_seminorm_sq(prob, par, mu, xs[k] - star.x, ys[k] - ystar) for k in range(K)]
+    assert min(d_step) >= -1e-9 * max(d_step)           # A3 makes D a seminorm
+    for k in range(K - 1):
+        assert d_step[k + 1] <= d_step[k] * (1 + 1e-9) + 1e-12
+        assert d_star[k + 1] <= d_star[k] * (1 + 1e-9) + 1e-12
+    for k in range(K):
+        assert d_step[k] <= d_star[0] / (k + 1) * (1 + 1e-6) + 1e-12
+
+
+def test_paper_ordering_of_iteration_counts():
+    # Section 1.2 / Section 3.1: with M close to alpha A^T A, NCS needs far fewer
+    # iterations than PDHG, and ADMM (exact M) fewer still.
+    prob = problems.ct_problem(32, 45, 48, 5, 0.01)
+    par = problems.Params(0.01, 0.03, 0.3 * 0.01 * operators.default_c_r(32, 45))
+    xa, ya, obj_a = solvers.admm(prob, par, 400)
+    fstar = np.nanmin(obj_a)
+    gp = 1.01 * par.alpha * np.linalg.eigvalsh(solvers.normal_matrix(prob, par))[-1]
+    _, _, obj_p = solvers.pdhg(prob, par, gp, 1500)
+    obj_n = solvers.ncs(prob, par, 1500).obj
+    fstar = min(fstar, np.nanmin(obj_p), np.nanmin(obj_n))
+
+    def first(obj):
+        g = (obj - fstar) / abs(fstar)
+        idx = np.nonzero(g <= 1e-3)[0]
+        return idx[0] + 1 if idx.size else 10 ** 9
+
+    ka, kn, kp = first(obj_a), first(obj_n), first(obj_p)
+    assert ka <= kn < kp, (ka, kn, kp)
+    assert kp >= 1.5 * kn, (kn, kp)
+
+
+def test_pet_objective_domain_and_constant():
+    prob = _pet()
+    x = prob.x_true.copy()
+    f = objective.objective(prob, x)
+    assert np.isfinite(f)
+    # all-negative image leaves the domain of l wherever E x + r < 0
+    assert objective.objective(prob, -10 * np.ones(prob.n) - x) == np.inf
+    # constant: NLL of the exact mean is close to the Poisson entropy, not the raw l
+    y = prob.E @ x + prob.bg
+    raw = float(np.sum(y - prob.b * np.log(y)))
+    assert objective.data_term(prob, prob.E @ x) > raw
+
+
+def test_tv_of_step_image():
+    prob = _ct("aniso", lam=1.0)
+    img = np.zeros((N, N))
+    img[:, N // 2:] = 2.0                     # one vertical edge of height 2 over N rows
+    assert objective.tv(prob, img.ravel()) == pytest.approx(2.0 * N)
+    img2 = np.zeros((N, N))
+    img2[N // 2:, N // 2:] = 1.0              # corner: N/2 horizontal + N/2 vertical unit jumps
+    assert objective.tv(prob, img2.ravel()) == pytest.approx(N)
+    prob_iso = _ct("iso", lam=1.0)
+    dot = np.zeros((N, N))
+    dot[5, 5] = 1.0                           # pixel (5,5) pairs (1, 1); (5,4) and (4,5) one unit each
+    assert objective.tv(prob, dot.ravel()) == pytest.approx(4.0)
+    assert objective.tv(prob_iso, dot.ravel()) == pytest.approx(2.0 + np.sqrt(2.0))
