@@ -5,8 +5,11 @@
   Poisson negative log-likelihood sum_i [y_i - b_i log y_i + log Gamma(b_i+1)]
   with y = Ex + r, plus lambda TV(x) (Section 4.2; the log Gamma constant makes
   it the exact negative log-likelihood and does not move the minimiser).
-  Outside the domain of l (y_i <= 0 with b_i > 0, or y_i < 0 with b_i = 0) the
-  value is +inf.
+  A ray with b_i > 0 and y_i <= 0 makes the value +inf.  A ray with b_i = 0
+  contributes y_i for every sign of y_i: its l is y + indicator(y >= 0), and
+  NCS iterates reach y_i < 0 only on such rays, approaching y_i = 0 in the
+  limit, so the indicator is dropped when the objective is reported (the value
+  is the paper's on the domain).
 * ``kkt``: for the pair (eq. RCP, eq. dual) at a primal-dual point (x, y):
   dual feasibility |A^T y| and the fixed-point residual
   |y - prox_{alpha g*}(y + alpha(A x - b~))| (zero exactly at a saddle point).
@@ -41,8 +44,9 @@ def data_term(prob: Problem, proj: np.ndarray) -> float:
     y = proj + prob.bg
     b = prob.b
     pos = b > 0
-    if np.any(y[pos] <= 0) or np.any(y[~pos] < 0):
+    if np.any(y[pos] <= 0):
         return float("inf")
+    # b_i = 0: l = y_i on its domain y_i >= 0, evaluated as y_i for every y_i
     val = np.where(pos, y - b * np.log(np.where(pos, y, 1.0)), y) + gammaln(b + 1.0)
     return float(val.sum())
 

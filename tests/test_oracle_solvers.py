@@ -159,7 +159,7 @@ def test_pet_objective_domain_and_constant():
     x = prob.x_true.copy()
     f = objective.objective(prob, x)
     assert np.isfinite(f)
-    # all-negative image leaves the domain of l wherever E x + r < 0
+    # an all-negative image leaves the domain of l on rays with b > 0
     assert objective.objective(prob, -10 * np.ones(prob.n) - x) == np.inf
     # constant: NLL of the exact mean is close to the Poisson entropy, not the raw l
     y = prob.E @ x + prob.bg
