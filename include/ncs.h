@@ -1,0 +1,196 @@
+/*
+ * ncs.h -- C ABI of the near-circulant splitting (NCS) solver for gfx950.
+ *
+ * Method (Ryu, Ko, Won, "Splitting with Near-Circulant Linear Systems:
+ * Applications to Total Variation CT and PET"): minimize g(Ax - b) (eq. RCP)
+ * with the iteration of eq. (NCS)
+ *
+ *     x+ = x - M^+ A^T u
+ *     u+ = prox_{alpha g*}(u + alpha (A(2x+ - x) - b)),
+ *
+ * where M = gamma I + alpha C is circulant and applied through the FFT
+ * (Section 1.2).  The library implements the CT and PET instances of
+ * Section 4: A stacks a parallel-beam projector E with the scaled finite
+ * differences (beta/alpha) D; the data term is 1/2 |y|^2 (CT, Section 4.1) or
+ * the Poisson negative log-likelihood (PET, Section 4.2); the TV term is
+ * anisotropic |Dx|_1 (the paper) or isotropic sum_p |(Dx)_p|_2.
+ *
+ * Conventions shared by every call:
+ *
+ *  - Geometry: an N x N image of unit pixels stored row-major (index
+ *    r*N + c, row r along y), N_theta angles theta_a = pi a / N_theta and N_s
+ *    unit detector bins centred on the image centre; sinograms are stored
+ *    angle-major (index a*N_s + d).  The projector is the Joseph ray-driven
+ *    discretisation of the Radon transform of eq. (radon-def) (Section 2);
+ *    rays step through rows when 4a <= N_theta or 4a >= 3 N_theta, else
+ *    through columns.  N must be a power of two in [16, 1024]; N_theta >= 1;
+ *    N_s >= 2.
+ *  - Precision: a handle is created for NCS_F32 or NCS_F64.  Every device
+ *    buffer passed to it holds float (NCS_F32) or double (NCS_F64); all
+ *    scalars returned to the host are double.  Reductions (objective,
+ *    residuals) are accumulated in double in both modes.
+ *  - Memory: pointers named *_dev are device pointers on the device that was
+ *    current when the handle was created; the caller owns them and keeps
+ *    them alive while the handle uses them (b and bg for the handle's life).
+ *    The library owns its workspace (iterates, spectra, tables, partial sums)
+ *    from ncs_setup to ncs_destroy.  Host pointers are read or written
+ *    before the call returns.
+ *  - Streams: work is queued on the hipStream_t given to ncs_setup (NULL is
+ *    the default stream).  Calls that return host values synchronise that
+ *    stream; the others return once the work is queued.
+ *  - Errors: no C++ exception crosses this interface.  Arguments are checked
+ *    before anything is queued; a failing call returns a negative status and
+ *    leaves a message for ncs_last_error().  Iterations that produce a NaN
+ *    objective stop on the device and report NCS_ERR_NONFINITE.
+ *  - Threads: a handle is used by one host thread at a time.
+ */
+#ifndef NCS_H
+#define NCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NCS_OK = 0,
+    NCS_NOT_CONVERGED = 1,     /* ncs_solve: iteration budget used before the target */
+    NCS_ERR_INVALID_ARG = -1,  /* bad size, pointer, parameter or state */
+    NCS_ERR_HIP = -2,          /* a HIP runtime call failed */
+    NCS_ERR_OOM = -3,          /* device allocation failed */
+    NCS_ERR_NONFINITE = -4,    /* the objective became NaN */
+    NCS_ERR_DIVERGED = -5      /* the objective grew for the configured number of checks */
+} ncs_status;
+
+typedef enum { NCS_F32 = 0, NCS_F64 = 1 } ncs_dtype;
+
+/* Data term g_data: 1/2|y|^2 (Section 4.1) or sum l(y_i + r_i; b_i) (Section 4.2). */
+typedef enum { NCS_DATA_QUADRATIC = 0, NCS_DATA_POISSON = 1 } ncs_data_term;
+
+/* TV term: anisotropic |Dx|_1 (Section 4.1, box projection Pi_[-s,s]) or
+ * isotropic sum_p |(Dx)_p|_2 (per-pixel l2-ball projection). */
+typedef enum { NCS_TV_ANISO = 0, NCS_TV_ISO = 1 } ncs_tv_term;
+
+typedef struct {
+    int32_t n_side;    /* N: image is N x N */
+    int32_t n_angles;  /* N_theta */
+    int32_t n_bins;    /* N_s */
+} ncs_geometry;
+
+typedef struct {
+    double alpha;      /* > 0: dual step alpha of eq. (NCS) */
+    double beta;       /* > 0: TV block scaling, A = [E; (beta/alpha) D] (Section 4.1) */
+    double gamma;      /* >= 0: M = gamma I + alpha C (Section 1.2) */
+    double lambda;     /* >= 0: TV weight */
+    double c_r;        /* C_R of eq. (circ_R); <= 0 selects N_theta N / pi */
+    double mu_dc;      /* DC eigenvalue of M (Section 4.1.1, Remark on the DC
+                          component); <= 0 selects gamma + alpha |E 1|^2 / n */
+    int32_t data_term; /* ncs_data_term */
+    int32_t tv_term;   /* ncs_tv_term */
+    int32_t check_every;    /* ncs_solve: iterations between host checks; <= 0 selects 50 */
+    int32_t diverge_checks; /* ncs_solve: stop with NCS_ERR_DIVERGED after this many
+                               consecutive checks with a growing objective; <= 0 disables */
+} ncs_params;
+
+typedef struct ncs_handle ncs_handle;
+
+/* Create a solver.  b_dev (N_theta*N_s values: CT sinogram or PET counts) may
+ * be NULL for a handle used only for the operators below; bg_dev is the PET
+ * background r (N_theta*N_s values, NULL = zero) and is ignored for CT.
+ * Precomputes, in double precision on the host, the per-angle table, the
+ * Fourier multiplier h = 1/mu of Section 4.1.1 (eq. circ_R + eq. circ_D,
+ * DC entry mu_dc) and the FFT twiddles, and sets the state to x = u = v = 0.
+ * stream is a hipStream_t (NULL = default stream). */
+ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t dtype,
+                     const void* b_dev, const void* bg_dev, void* stream,
+                     ncs_handle** out);
+
+/* Reset the iterate: x = x0 (NULL = zeros), iteration counter 0.  With
+ * dual_from_x0 = 0 the duals are u = 0, v = 0.  With dual_from_x0 = 1 they
+ * are taken from the fixed-point relations of the optimality conditions
+ * (Section 3.2, Fact on fixed points): u = grad g_data(E x0) and
+ * v = s sign(D x0) (anisotropic) or s (D x0)/|(D x0)_p| (isotropic) where the
+ * difference is nonzero, 0 elsewhere, with s = lambda alpha / beta. */
+ncs_status ncs_set_init(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0);
+
+/* Run exactly k >= 0 iterations (each: one x-update, one (u, v)-update, one
+ * objective f(x^{k+1}) in double).  obj_host (length k, may be NULL) receives
+ * the objective after each iteration; when it is non-NULL the call
+ * synchronises.  Returns NCS_ERR_NONFINITE if an objective was NaN; the
+ * iterations queued after it do nothing, and the state holds the values of
+ * the iteration that produced the NaN. */
+ncs_status ncs_iterate(ncs_handle* h, int32_t k, double* obj_host);
+
+/* Iterate until f(x^k) <= f_target (NaN: no target), at most max_iters
+ * iterations.  The objective is tested on the device after every iteration;
+ * the host checks every params.check_every iterations.  iters_done and
+ * f_final (either may be NULL) receive the iterations run in this call and
+ * the last objective.  Returns NCS_OK when the target was reached,
+ * NCS_NOT_CONVERGED when the budget ran out, or an error. */
+ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target,
+                     int32_t* iters_done, double* f_final);
+
+/* Objective history: obj_host[i] = f after iteration first + i (iterations
+ * counted from the last ncs_set_init), for the most recent 65536 iterations. */
+ncs_status ncs_get_objectives(ncs_handle* h, int32_t first, int32_t count, double* obj_host);
+
+/* Number of iterations since the last ncs_set_init (host value). */
+ncs_status ncs_get_iteration(ncs_handle* h, int32_t* iters);
+
+/* Copy the current image x (N*N values, row-major) to x_out_dev. */
+ncs_status ncs_get_x(ncs_handle* h, void* x_out_dev);
+
+/* Copy the current data dual u (N_theta*N_s values) to u_out_dev. */
+ncs_status ncs_get_u(ncs_handle* h, void* u_out_dev);
+
+/* Checkpoint: the full state (x, u, v, E x, iteration count) as an opaque
+ * host blob.  With host_buf NULL, *bytes receives the size needed.  Resuming
+ * from a saved state reproduces the uninterrupted run bit for bit. */
+ncs_status ncs_get_state(ncs_handle* h, void* host_buf, size_t* bytes);
+ncs_status ncs_set_state(ncs_handle* h, const void* host_buf, size_t bytes);
+
+/* Operators of the handle's geometry, usable without data:
+ *   ncs_forward:   y = E x      (x: N*N, y: N_theta*N_s)
+ *   ncs_adjoint:   x = E^T y
+ *   ncs_apply_minv: out = M^+ w = F^-1 diag(h) F w (N*N real, Section 4.1)
+ *   ncs_objective: f(x) for the handle's data term, TV term and lambda. */
+ncs_status ncs_forward(ncs_handle* h, const void* x_dev, void* y_dev);
+ncs_status ncs_adjoint(ncs_handle* h, const void* y_dev, void* x_dev);
+ncs_status ncs_apply_minv(ncs_handle* h, const void* w_dev, void* out_dev);
+ncs_status ncs_objective(ncs_handle* h, const void* x_dev, double* f);
+
+/* Facts about a handle, computed in double on the host at setup. */
+typedef struct {
+    int64_t nnz;       /* nonzero entries of E (Joseph taps with weight != 0 inside the image) */
+    double c_r;        /* C_R in use */
+    double mu_dc;      /* DC eigenvalue of M in use */
+    double norm_e1_sq; /* |E 1|^2 */
+} ncs_info;
+
+ncs_status ncs_get_info(ncs_handle* h, ncs_info* info);
+
+/* Per-kernel timing: run `iters` >= 1 iterations (they advance the state like
+ * ncs_iterate) with a HIP event before and after every kernel on the handle's
+ * stream, and return in ms_host[0..NCS_N_PHASES-1] the mean duration per
+ * iteration of each phase, in the order backprojection, row DFT, column
+ * DFT + multiplier, inverse row DFT + x-update, TV update, projection + data
+ * prox, objective reduction.  Synchronises. */
+#define NCS_N_PHASES 7
+ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host);
+
+/* The eigenvalues mu of M actually used (N*N doubles, numpy FFT order,
+ * host memory), after the C_R and mu_dc defaults are resolved. */
+ncs_status ncs_get_eigenvalues(ncs_handle* h, double* mu_host);
+
+void ncs_destroy(ncs_handle* h);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* ncs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NCS_H */

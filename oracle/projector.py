@@ -38,15 +38,19 @@ def row_stepping(n_angles: int) -> np.ndarray:
     return (4 * a <= n_angles) | (4 * a >= 3 * n_angles)
 
 
-def joseph_matrix(n_side: int, n_angles: int, n_bins: int) -> sp.csr_matrix:
-    """The m x n matrix E (m = n_angles*n_bins, n = n_side**2), CSR, float64."""
+def joseph_matrix(n_side: int, n_angles: int, n_bins: int, angles=None) -> sp.csr_matrix:
+    """The m x n matrix E (m = n_angles*n_bins, n = n_side**2), CSR, float64.
+
+    With ``angles`` (a list of angle indices) only those rows are filled; the
+    other rows are empty (used to check large geometries angle by angle).
+    """
     n = n_side
     half_img = (n - 1) / 2.0
     s = np.arange(n_bins) - (n_bins - 1) / 2.0          # bin offsets s_d
     coord = np.arange(n) - half_img                      # pixel centre coordinates
     rows_all, cols_all, vals_all = [], [], []
     stepping_rows = row_stepping(n_angles)
-    for a in range(n_angles):
+    for a in (range(n_angles) if angles is None else angles):
         theta = np.pi * a / n_angles
         ct, st = np.cos(theta), np.sin(theta)
         ray = a * n_bins + np.arange(n_bins)             # (n_bins,)

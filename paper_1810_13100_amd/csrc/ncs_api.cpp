@@ -1,0 +1,810 @@
+// Host side of the NCS C ABI: argument checking, double-precision setup of the
+// per-angle table, the Fourier multiplier and the twiddles, workspace
+// ownership, and the iteration driver (direct launches or a replayed HIP
+// graph of a chunk of iterations, with the stopping test on the device).
+#include "ncs.h"
+#include "ncs_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ncs;
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+#define NCS_HIP(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_err("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return NCS_ERR_HIP;                                                        \
+        }                                                                              \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint64_t kStateMagic = 0x3130303331303831ull;  // blob tag
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+struct ncs_handle {
+    ncs_geometry g{};
+    ncs_params p{};
+    int dtype = NCS_F32;
+    size_t esz = 4;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int log2N = 0, PU = 0;
+    size_t n = 0, m = 0, mp = 0;
+
+    // device workspace (library-owned)
+    void* x = nullptr;
+    void* xbar = nullptr;
+    void* u = nullptr;
+    void* pj = nullptr;
+    void* v = nullptr;
+    void* w = nullptr;
+    void* spec = nullptr;
+    void* hh = nullptr;
+    void* tw = nullptr;
+    void* ang = nullptr;
+    int32_t* axis = nullptr;
+    void* ysc = nullptr;
+    double* part_data = nullptr;
+    double* part_tv = nullptr;
+    Control* ctl = nullptr;
+    double* hist = nullptr;
+
+    const void* b = nullptr;   // caller-owned
+    const void* bg = nullptr;  // caller-owned
+
+    std::vector<double> mu;    // eigenvalues of M, N x N, numpy FFT order
+    double c_r = 0.0, mu_dc = 0.0, norm_e1_sq = 0.0;
+    int64_t nnz = 0;
+    int iter_host = 0;         // iteration count as last seen by the host
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+template <class T>
+DevCtx<T> make_ctx(const ncs_handle* h) {
+    DevCtx<T> c{};
+    c.N = h->g.n_side;
+    c.log2N = h->log2N;
+    c.NA = h->g.n_angles;
+    c.NS = h->g.n_bins;
+    c.PU = h->PU;
+    c.ang = static_cast<const AngleT<T>*>(h->ang);
+    c.axis = h->axis;
+    c.x = static_cast<T*>(h->x);
+    c.xbar = static_cast<T*>(h->xbar);
+    c.u = static_cast<T*>(h->u);
+    c.p = static_cast<T*>(h->pj);
+    c.v = static_cast<T*>(h->v);
+    c.w = static_cast<T*>(h->w);
+    c.spec = static_cast<T*>(h->spec);
+    c.hh = static_cast<const T*>(h->hh);
+    c.tw = static_cast<const T*>(h->tw);
+    c.b = static_cast<const T*>(h->b);
+    c.bg = static_cast<const T*>(h->bg);
+    c.ysc = static_cast<T*>(h->ysc);
+    c.part_data = h->part_data;
+    c.part_tv = h->part_tv;
+    c.ctl = h->ctl;
+    c.hist = h->hist;
+    c.alpha = (T)h->p.alpha;
+    c.beta = (T)h->p.beta;
+    c.s_tv = (T)(h->p.lambda * h->p.alpha / h->p.beta);
+    c.inv1pa = (T)(1.0 / (1.0 + h->p.alpha));
+    c.lambda = h->p.lambda;
+    c.data_term = h->p.data_term;
+    c.tv_term = h->p.tv_term;
+    return c;
+}
+
+ncs_status dev_alloc(ncs_handle* h, void** ptr, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        set_err("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? NCS_ERR_OOM : NCS_ERR_HIP;
+    }
+    h->allocs.push_back(*ptr);
+    return NCS_OK;
+}
+
+// |E 1|^2 and nnz(E) in double on the host, from the same geometry as the
+// kernels: for each ray and step, the taps floor(xi) and floor(xi) + 1 with
+// their weights 1 - f and f, kept when inside [0, N-1] and nonzero.
+void e1_stats(const ncs_geometry& g, const std::vector<double>& tab, double* norm_sq, int64_t* nnz) {
+    const int N = g.n_side;
+    double total = 0.0;
+    int64_t taps = 0;
+    for (int a = 0; a < g.n_angles; ++a) {
+        const double* t = &tab[10 * (size_t)a];
+        const double k1 = t[0], k2 = t[1], k0 = t[2], kap = t[6];
+        for (int d = 0; d < g.n_bins; ++d) {
+            const double base = d * k1 + k0;
+            double s = 0.0;
+            for (int st = 0; st < N; ++st) {
+                const double xi = st * k2 + base;
+                if (xi <= -1.0 || xi >= (double)N) continue;
+                const double fl = std::floor(xi);
+                const double f = xi - fl;
+                const int c0 = (int)fl;
+                if (c0 >= 0 && f != 1.0) {
+                    s += 1.0 - f;
+                    ++taps;
+                }
+                if (c0 + 1 <= N - 1 && f != 0.0) {
+                    s += f;
+                    ++taps;
+                }
+            }
+            const double e = kap * s;
+            total += e * e;
+        }
+    }
+    *norm_sq = total;
+    *nnz = taps;
+}
+
+template <class T>
+void convert(const std::vector<double>& src, std::vector<T>& dst) {
+    dst.resize(src.size());
+    for (size_t i = 0; i < src.size(); ++i) dst[i] = (T)src[i];
+}
+
+template <class T>
+ncs_status upload(ncs_handle* h, void* dst, const std::vector<double>& src) {
+    std::vector<T> tmp;
+    convert(src, tmp);
+    NCS_HIP(hipMemcpy(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+    return NCS_OK;
+}
+
+ncs_status upload_typed(ncs_handle* h, void* dst, const std::vector<double>& src) {
+    return h->dtype == NCS_F64 ? upload<double>(h, dst, src) : upload<float>(h, dst, src);
+}
+
+// ---- iteration launch -----------------------------------------------------
+template <class T>
+hipError_t launch_iterations(ncs_handle* h, int k) {
+    const DevCtx<T> c = make_ctx<T>(h);
+    hipStream_t st = h->stream;
+    for (int i = 0; i < k; ++i) {
+        hipError_t e;
+        if ((e = launch_backproject_iter<T>(c, st)) != hipSuccess) return e;
+        if ((e = launch_fft_rows_fwd<T>(c, c.w, true, st)) != hipSuccess) return e;
+        if ((e = launch_fft_cols<T>(c, T(1), true, st)) != hipSuccess) return e;
+        if ((e = launch_fft_rows_inv_update<T>(c, st)) != hipSuccess) return e;
+        if ((e = launch_tv_update<T>(c, st)) != hipSuccess) return e;
+        if ((e = launch_project_iter<T>(c, st)) != hipSuccess) return e;
+        if ((e = launch_finalize_iter<T>(c, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <class T>
+hipError_t launch_phase(ncs_handle* h, int ph) {
+    const DevCtx<T> c = make_ctx<T>(h);
+    hipStream_t st = h->stream;
+    switch (ph) {
+        case 0: return launch_backproject_iter<T>(c, st);
+        case 1: return launch_fft_rows_fwd<T>(c, c.w, true, st);
+        case 2: return launch_fft_cols<T>(c, T(1), true, st);
+        case 3: return launch_fft_rows_inv_update<T>(c, st);
+        case 4: return launch_tv_update<T>(c, st);
+        case 5: return launch_project_iter<T>(c, st);
+        default: return launch_finalize_iter<T>(c, st);
+    }
+}
+
+hipError_t launch_iters(ncs_handle* h, int k) {
+    return h->dtype == NCS_F64 ? launch_iterations<double>(h, k) : launch_iterations<float>(h, k);
+}
+
+ncs_status read_control(ncs_handle* h, Control* out) {
+    NCS_HIP(hipMemcpyAsync(out, h->ctl, sizeof(Control), hipMemcpyDeviceToHost, h->stream));
+    NCS_HIP(hipStreamSynchronize(h->stream));
+    h->iter_host = out->iter;
+    return NCS_OK;
+}
+
+ncs_status check_handle(ncs_handle* h) {
+    if (!h) {
+        set_err("null handle");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(hipSetDevice(h->device));
+    return NCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ncs_last_error(void) { return g_err.c_str(); }
+
+ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t dtype,
+                     const void* b_dev, const void* bg_dev, void* stream, ncs_handle** out) {
+    g_err.clear();
+    if (!geom || !params || !out) {
+        set_err("ncs_setup: null geometry, params or out pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    const ncs_geometry g = *geom;
+    const ncs_params p = *params;
+    if (!is_pow2(g.n_side) || g.n_side < 16 || g.n_side > 1024) {
+        set_err("ncs_setup: n_side must be a power of two in [16, 1024] (got %d)", g.n_side);
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (g.n_angles < 1 || g.n_angles > (1 << 20) || g.n_bins < 2 || g.n_bins > (1 << 20)) {
+        set_err("ncs_setup: need 1 <= n_angles and 2 <= n_bins (got %d, %d)", g.n_angles, g.n_bins);
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (dtype != NCS_F32 && dtype != NCS_F64) {
+        set_err("ncs_setup: dtype must be NCS_F32 or NCS_F64");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!(p.alpha > 0.0) || !(p.beta > 0.0) || !(p.gamma >= 0.0) || !(p.lambda >= 0.0) ||
+        !std::isfinite(p.alpha) || !std::isfinite(p.beta) || !std::isfinite(p.gamma) ||
+        !std::isfinite(p.lambda) || !std::isfinite(p.c_r) || !std::isfinite(p.mu_dc)) {
+        set_err("ncs_setup: need finite alpha > 0, beta > 0, gamma >= 0, lambda >= 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.data_term != NCS_DATA_QUADRATIC && p.data_term != NCS_DATA_POISSON) {
+        set_err("ncs_setup: unknown data_term %d", p.data_term);
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.tv_term != NCS_TV_ANISO && p.tv_term != NCS_TV_ISO) {
+        set_err("ncs_setup: unknown tv_term %d", p.tv_term);
+        return NCS_ERR_INVALID_ARG;
+    }
+
+    ncs_handle* h = new ncs_handle();
+    h->g = g;
+    h->p = p;
+    if (h->p.check_every <= 0) h->p.check_every = 50;
+    h->dtype = dtype;
+    h->esz = dtype == NCS_F64 ? 8 : 4;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->b = b_dev;
+    h->bg = bg_dev;
+    const int N = g.n_side;
+    while ((1 << h->log2N) < N) ++h->log2N;
+    h->PU = g.n_bins + 3;
+    h->n = (size_t)N * N;
+    h->m = (size_t)g.n_angles * g.n_bins;
+    h->mp = (size_t)g.n_angles * h->PU;
+
+    auto fail = [&](ncs_status s) {
+        ncs_destroy(h);
+        return s;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        set_err("ncs_setup: hipGetDevice failed");
+        delete h;
+        return NCS_ERR_HIP;
+    }
+
+    // ---- per-angle table (double) --------------------------------------
+    const int NA = g.n_angles, NS = g.n_bins;
+    std::vector<double> tab(10 * (size_t)NA);
+    std::vector<int> axis(NA);
+    const double hn = 0.5 * (N - 1), hs = 0.5 * (NS - 1);
+    for (int a = 0; a < NA; ++a) {
+        const double th = kPi * a / NA;
+        const double ct = std::cos(th), st = std::sin(th);
+        const bool rows = (4 * (long long)a <= NA) || (4 * (long long)a >= 3 * (long long)NA);
+        axis[a] = rows ? 0 : 1;
+        double* t = &tab[10 * (size_t)a];
+        if (rows) {   // xi = column of ray d on row r
+            t[0] = 1.0 / ct;
+            t[1] = -st / ct;
+            t[2] = -hs / ct + hn * st / ct + hn;
+            t[6] = 1.0 / std::fabs(ct);
+        } else {      // eta = row of ray d on column c
+            t[0] = 1.0 / st;
+            t[1] = -ct / st;
+            t[2] = -hs / st + hn * ct / st + hn;
+            t[6] = 1.0 / std::fabs(st);
+        }
+        t[3] = ct;
+        t[4] = st;
+        t[5] = hs - hn * (ct + st);
+        t[7] = t[6] * t[6];
+        t[8] = t[6] - t[7];
+        t[9] = 0.0;
+    }
+
+    // ---- multiplier (Section 4.1.1: eq. circ_R, eq. circ_D, DC entry) -----
+    h->c_r = p.c_r > 0.0 ? p.c_r : (double)NA * N / kPi;
+    e1_stats(g, tab, &h->norm_e1_sq, &h->nnz);
+    h->mu_dc = p.mu_dc > 0.0 ? p.mu_dc : p.gamma + p.alpha * h->norm_e1_sq / (double)h->n;
+    h->mu.assign(h->n, 0.0);
+    const double bta = p.beta * p.beta / p.alpha;
+    for (int j = 0; j < N; ++j) {
+        const double jj = std::min(j, N - j);
+        const double sj = std::sin(kPi * j / N);
+        for (int k = 0; k < N; ++k) {
+            const double kk = std::min(k, N - k);
+            const double sk = std::sin(kPi * k / N);
+            const double rad2 = jj * jj + kk * kk;
+            double mu = p.gamma + bta * 4.0 * (sj * sj + sk * sk);
+            if (rad2 > 0.0) mu += p.alpha * h->c_r / std::sqrt(rad2);
+            h->mu[(size_t)j * N + k] = mu;
+        }
+    }
+    h->mu[0] = h->mu_dc;
+    const int NH = N / 2 + 1;
+    std::vector<double> hh((size_t)NH * N);
+    const double scale = 1.0 / (p.alpha * (double)N * (double)N);
+    for (int k = 0; k < NH; ++k)
+        for (int j = 0; j < N; ++j) {
+            const double mu = h->mu[(size_t)j * N + k];
+            hh[(size_t)k * N + j] = mu != 0.0 ? scale / mu : 0.0;   // diag(mu)^+ (Section 2)
+        }
+    std::vector<double> tw(N);
+    for (int k = 0; k < N / 2; ++k) {
+        tw[2 * k] = std::cos(2.0 * kPi * k / N);
+        tw[2 * k + 1] = -std::sin(2.0 * kPi * k / N);
+    }
+
+    // ---- workspace ---------------------------------------------------------
+    const size_t e = h->esz;
+    ncs_status s;
+    const size_t nparts = std::max<size_t>({(size_t)project_blocks(NA, NS), (h->m + 255) / 256, (size_t)1});
+    if ((s = dev_alloc(h, &h->x, h->n * e)) ||
+        (s = dev_alloc(h, &h->xbar, h->n * e)) ||
+        (s = dev_alloc(h, &h->u, h->mp * e)) ||
+        (s = dev_alloc(h, &h->pj, h->mp * e)) ||
+        (s = dev_alloc(h, &h->v, 2 * h->n * e)) ||
+        (s = dev_alloc(h, &h->w, h->n * e)) ||
+        (s = dev_alloc(h, &h->spec, 2 * (size_t)NH * N * e)) ||
+        (s = dev_alloc(h, &h->hh, (size_t)NH * N * e)) ||
+        (s = dev_alloc(h, &h->tw, (size_t)N * e)) ||
+        (s = dev_alloc(h, &h->ang, 10 * (size_t)NA * e)) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->axis), (size_t)NA * sizeof(int32_t))) ||
+        (s = dev_alloc(h, &h->ysc, h->mp * e)) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->part_data), nparts * sizeof(double))) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->part_tv), (size_t)tv_blocks(N) * sizeof(double))) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->ctl), sizeof(Control))) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->hist), (size_t)kHistCap * sizeof(double))))
+        return fail(s);
+
+    if ((s = upload_typed(h, h->hh, hh)) || (s = upload_typed(h, h->tw, tw)) || (s = upload_typed(h, h->ang, tab)))
+        return fail(s);
+    if (hipMemcpy(h->axis, axis.data(), NA * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        set_err("ncs_setup: axis upload failed");
+        return fail(NCS_ERR_HIP);
+    }
+    Control c0{};
+    c0.f_target = std::nan("");
+    if (hipMemcpy(h->ctl, &c0, sizeof(Control), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->x, 0, h->n * e) != hipSuccess || hipMemset(h->xbar, 0, h->n * e) != hipSuccess ||
+        hipMemset(h->u, 0, h->mp * e) != hipSuccess || hipMemset(h->pj, 0, h->mp * e) != hipSuccess ||
+        hipMemset(h->v, 0, 2 * h->n * e) != hipSuccess || hipMemset(h->ysc, 0, h->mp * e) != hipSuccess ||
+        hipMemset(h->hist, 0, (size_t)kHistCap * sizeof(double)) != hipSuccess) {
+        set_err("ncs_setup: workspace initialisation failed");
+        return fail(NCS_ERR_HIP);
+    }
+    if (b_dev && p.data_term == NCS_DATA_POISSON) {
+        hipError_t le = dtype == NCS_F64 ? launch_data_const<double>(make_ctx<double>(h), h->stream)
+                                         : launch_data_const<float>(make_ctx<float>(h), h->stream);
+        if (le != hipSuccess) {
+            set_err("ncs_setup: data constant launch failed: %s", hipGetErrorString(le));
+            return fail(NCS_ERR_HIP);
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        set_err("ncs_setup: stream synchronisation failed");
+        return fail(NCS_ERR_HIP);
+    }
+    *out = h;
+    return NCS_OK;
+}
+
+void ncs_destroy(ncs_handle* h) {
+    if (!h) return;
+    hipSetDevice(h->device);
+    if (h->stream) hipStreamSynchronize(h->stream);
+    for (void* ptr : h->allocs) hipFree(ptr);
+    delete h;
+}
+
+ncs_status ncs_set_init(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (dual_from_x0 && (!x0_dev || !h->b)) {
+        set_err("ncs_set_init: dual_from_x0 needs x0 and data b");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const size_t e = h->esz;
+    NCS_HIP(hipMemsetAsync(h->u, 0, h->mp * e, h->stream));
+    NCS_HIP(hipMemsetAsync(h->pj, 0, h->mp * e, h->stream));
+    NCS_HIP(hipMemsetAsync(h->v, 0, 2 * h->n * e, h->stream));
+    if (x0_dev) {
+        NCS_HIP(hipMemcpyAsync(h->x, x0_dev, h->n * e, hipMemcpyDeviceToDevice, h->stream));
+        NCS_HIP(h->dtype == NCS_F64 ? launch_project_setp<double>(make_ctx<double>(h), (const double*)h->x, h->stream)
+                                    : launch_project_setp<float>(make_ctx<float>(h), (const float*)h->x, h->stream));
+        if (dual_from_x0)
+            NCS_HIP(h->dtype == NCS_F64 ? launch_dual_init<double>(make_ctx<double>(h), h->stream)
+                                        : launch_dual_init<float>(make_ctx<float>(h), h->stream));
+    } else {
+        NCS_HIP(hipMemsetAsync(h->x, 0, h->n * e, h->stream));
+    }
+    NCS_HIP(launch_control(h->ctl, 0, 0, std::nan(""), h->stream));
+    h->iter_host = 0;
+    return NCS_OK;
+}
+
+ncs_status ncs_iterate(ncs_handle* h, int32_t k, double* obj_host) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (k < 0) {
+        set_err("ncs_iterate: k must be >= 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!h->b) {
+        set_err("ncs_iterate: handle has no data (b_dev was NULL)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (obj_host && k > kHistCap) {
+        set_err("ncs_iterate: at most %d objectives can be returned per call", kHistCap);
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (k == 0) return NCS_OK;
+    NCS_HIP(launch_control(h->ctl, 1, 0, std::nan(""), h->stream));
+    const int start = h->iter_host;
+    NCS_HIP(launch_iters(h, k));
+    if (!obj_host) {
+        h->iter_host += k;
+        return NCS_OK;
+    }
+    Control c;
+    if ((s = read_control(h, &c))) return s;
+    const int done = c.iter - start;
+    std::vector<double> hist(kHistCap);
+    NCS_HIP(hipMemcpy(hist.data(), h->hist, kHistCap * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < k; ++i)
+        obj_host[i] = i < done ? hist[(start + i) & (kHistCap - 1)] : std::nan("");
+    if (c.status == -4) {
+        set_err("ncs_iterate: objective became NaN at iteration %d", c.iter);
+        return NCS_ERR_NONFINITE;
+    }
+    return NCS_OK;
+}
+
+ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target, int32_t* iters_done, double* f_final) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (max_iters < 0) {
+        set_err("ncs_solve: max_iters must be >= 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!h->b) {
+        set_err("ncs_solve: handle has no data (b_dev was NULL)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(launch_control(h->ctl, 1, 0, f_target, h->stream));
+    Control c;
+    if ((s = read_control(h, &c))) return s;
+    const int start = c.iter;
+    int remaining = max_iters;
+    int grow = 0;
+    double f_prev = std::nan("");
+    ncs_status result = NCS_NOT_CONVERGED;
+    while (remaining > 0) {
+        const int chunk = std::min(remaining, (int)h->p.check_every);
+        NCS_HIP(launch_iters(h, chunk));
+        remaining -= chunk;
+        if ((s = read_control(h, &c))) return s;
+        if (c.status == -4) {
+            set_err("ncs_solve: objective became NaN at iteration %d", c.iter);
+            result = NCS_ERR_NONFINITE;
+            break;
+        }
+        if (c.status == 1) {
+            result = NCS_OK;
+            break;
+        }
+        if (h->p.diverge_checks > 0) {
+            grow = (f_prev == f_prev && c.f_last > f_prev) ? grow + 1 : 0;
+            f_prev = c.f_last;
+            if (grow >= h->p.diverge_checks) {
+                set_err("ncs_solve: objective grew over %d consecutive checks (f = %g)", grow, c.f_last);
+                result = NCS_ERR_DIVERGED;
+                break;
+            }
+        }
+    }
+    if (iters_done) *iters_done = c.iter - start;
+    if (f_final) *f_final = c.f_last;
+    return result;
+}
+
+ncs_status ncs_get_objectives(ncs_handle* h, int32_t first, int32_t count, double* obj_host) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (count < 0 || first < 0 || (count > 0 && !obj_host) || count > kHistCap) {
+        set_err("ncs_get_objectives: bad range");
+        return NCS_ERR_INVALID_ARG;
+    }
+    Control c;
+    if ((s = read_control(h, &c))) return s;
+    if (first + count > c.iter || first < c.iter - kHistCap) {
+        set_err("ncs_get_objectives: range [%d, %d) outside the stored history (iteration %d)", first,
+                first + count, c.iter);
+        return NCS_ERR_INVALID_ARG;
+    }
+    std::vector<double> hist(kHistCap);
+    NCS_HIP(hipMemcpy(hist.data(), h->hist, kHistCap * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < count; ++i) obj_host[i] = hist[(first + i) & (kHistCap - 1)];
+    return NCS_OK;
+}
+
+ncs_status ncs_get_iteration(ncs_handle* h, int32_t* iters) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!iters) {
+        set_err("ncs_get_iteration: null output");
+        return NCS_ERR_INVALID_ARG;
+    }
+    Control c;
+    if ((s = read_control(h, &c))) return s;
+    *iters = c.iter;
+    return NCS_OK;
+}
+
+ncs_status ncs_get_x(ncs_handle* h, void* x_out_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!x_out_dev) {
+        set_err("ncs_get_x: null output");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(hipMemcpyAsync(x_out_dev, h->x, h->n * h->esz, hipMemcpyDeviceToDevice, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_get_u(ncs_handle* h, void* u_out_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!u_out_dev) {
+        set_err("ncs_get_u: null output");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(h->dtype == NCS_F64
+                ? launch_unpad_sinogram<double>(make_ctx<double>(h), (const double*)h->u, (double*)u_out_dev, h->stream)
+                : launch_unpad_sinogram<float>(make_ctx<float>(h), (const float*)h->u, (float*)u_out_dev, h->stream));
+    return NCS_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint64_t magic;
+    int32_t dtype, n_side, n_angles, n_bins, iter, pad;
+};
+}  // namespace
+
+ncs_status ncs_get_state(ncs_handle* h, void* host_buf, size_t* bytes) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!bytes) {
+        set_err("ncs_get_state: null size pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const size_t e = h->esz;
+    const size_t need = sizeof(StateHeader) + (h->n + 2 * h->n + 2 * h->mp) * e;
+    if (!host_buf) {
+        *bytes = need;
+        return NCS_OK;
+    }
+    if (*bytes < need) {
+        set_err("ncs_get_state: buffer of %zu bytes, need %zu", *bytes, need);
+        return NCS_ERR_INVALID_ARG;
+    }
+    Control c;
+    if ((s = read_control(h, &c))) return s;
+    StateHeader hd{kStateMagic, h->dtype, h->g.n_side, h->g.n_angles, h->g.n_bins, c.iter, 0};
+    unsigned char* o = static_cast<unsigned char*>(host_buf);
+    std::memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    NCS_HIP(hipMemcpy(o, h->x, h->n * e, hipMemcpyDeviceToHost));
+    o += h->n * e;
+    NCS_HIP(hipMemcpy(o, h->v, 2 * h->n * e, hipMemcpyDeviceToHost));
+    o += 2 * h->n * e;
+    NCS_HIP(hipMemcpy(o, h->u, h->mp * e, hipMemcpyDeviceToHost));
+    o += h->mp * e;
+    NCS_HIP(hipMemcpy(o, h->pj, h->mp * e, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return NCS_OK;
+}
+
+ncs_status ncs_set_state(ncs_handle* h, const void* host_buf, size_t bytes) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    const size_t e = h->esz;
+    const size_t need = sizeof(StateHeader) + (h->n + 2 * h->n + 2 * h->mp) * e;
+    if (!host_buf || bytes != need) {
+        set_err("ncs_set_state: blob of %zu bytes, expected %zu", bytes, need);
+        return NCS_ERR_INVALID_ARG;
+    }
+    StateHeader hd;
+    std::memcpy(&hd, host_buf, sizeof(hd));
+    if (hd.magic != kStateMagic || hd.dtype != h->dtype || hd.n_side != h->g.n_side ||
+        hd.n_angles != h->g.n_angles || hd.n_bins != h->g.n_bins || hd.iter < 0) {
+        set_err("ncs_set_state: blob does not match this handle");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const unsigned char* i = static_cast<const unsigned char*>(host_buf) + sizeof(hd);
+    NCS_HIP(hipStreamSynchronize(h->stream));
+    NCS_HIP(hipMemcpy(h->x, i, h->n * e, hipMemcpyHostToDevice));
+    i += h->n * e;
+    NCS_HIP(hipMemcpy(h->v, i, 2 * h->n * e, hipMemcpyHostToDevice));
+    i += 2 * h->n * e;
+    NCS_HIP(hipMemcpy(h->u, i, h->mp * e, hipMemcpyHostToDevice));
+    i += h->mp * e;
+    NCS_HIP(hipMemcpy(h->pj, i, h->mp * e, hipMemcpyHostToDevice));
+    NCS_HIP(launch_control(h->ctl, 2, hd.iter, std::nan(""), h->stream));
+    NCS_HIP(hipStreamSynchronize(h->stream));
+    h->iter_host = hd.iter;
+    return NCS_OK;
+}
+
+ncs_status ncs_forward(ncs_handle* h, const void* x_dev, void* y_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!x_dev || !y_dev) {
+        set_err("ncs_forward: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(h->dtype == NCS_F64
+                ? launch_project_plain<double>(make_ctx<double>(h), (const double*)x_dev, (double*)y_dev, h->stream)
+                : launch_project_plain<float>(make_ctx<float>(h), (const float*)x_dev, (float*)y_dev, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_adjoint(ncs_handle* h, const void* y_dev, void* x_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!x_dev || !y_dev) {
+        set_err("ncs_adjoint: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (h->dtype == NCS_F64) {
+        const DevCtx<double> c = make_ctx<double>(h);
+        NCS_HIP(launch_pad_sinogram<double>(c, (const double*)y_dev, c.ysc, h->stream));
+        NCS_HIP(launch_backproject_plain<double>(c, c.ysc, (double*)x_dev, h->stream));
+    } else {
+        const DevCtx<float> c = make_ctx<float>(h);
+        NCS_HIP(launch_pad_sinogram<float>(c, (const float*)y_dev, c.ysc, h->stream));
+        NCS_HIP(launch_backproject_plain<float>(c, c.ysc, (float*)x_dev, h->stream));
+    }
+    return NCS_OK;
+}
+
+ncs_status ncs_apply_minv(ncs_handle* h, const void* w_dev, void* out_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!w_dev || !out_dev) {
+        set_err("ncs_apply_minv: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (h->dtype == NCS_F64) {
+        const DevCtx<double> c = make_ctx<double>(h);
+        NCS_HIP(launch_fft_rows_fwd<double>(c, (const double*)w_dev, false, h->stream));
+        NCS_HIP(launch_fft_cols<double>(c, (double)h->p.alpha, false, h->stream));
+        NCS_HIP(launch_fft_rows_inv_plain<double>(c, (double*)out_dev, h->stream));
+    } else {
+        const DevCtx<float> c = make_ctx<float>(h);
+        NCS_HIP(launch_fft_rows_fwd<float>(c, (const float*)w_dev, false, h->stream));
+        NCS_HIP(launch_fft_cols<float>(c, (float)h->p.alpha, false, h->stream));
+        NCS_HIP(launch_fft_rows_inv_plain<float>(c, (float*)out_dev, h->stream));
+    }
+    return NCS_OK;
+}
+
+ncs_status ncs_objective(ncs_handle* h, const void* x_dev, double* f) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!x_dev || !f) {
+        set_err("ncs_objective: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!h->b) {
+        set_err("ncs_objective: handle has no data (b_dev was NULL)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(h->dtype == NCS_F64 ? launch_eval_objective<double>(make_ctx<double>(h), (const double*)x_dev, h->stream)
+                                : launch_eval_objective<float>(make_ctx<float>(h), (const float*)x_dev, h->stream));
+    Control c;
+    if ((s = read_control(h, &c))) return s;
+    *f = c.eval_out;
+    return NCS_OK;
+}
+
+ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (iters < 1 || !ms_host) {
+        set_err("ncs_time_phases: need iters >= 1 and an output array");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!h->b) {
+        set_err("ncs_time_phases: handle has no data (b_dev was NULL)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(launch_control(h->ctl, 1, 0, std::nan(""), h->stream));
+    std::vector<hipEvent_t> ev(2 * NCS_N_PHASES * (size_t)iters);
+    for (auto& e : ev) NCS_HIP(hipEventCreate(&e));
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < iters && le == hipSuccess; ++i) {
+        for (int ph = 0; ph < NCS_N_PHASES && le == hipSuccess; ++ph) {
+            const size_t k = 2 * ((size_t)i * NCS_N_PHASES + ph);
+            hipEventRecord(ev[k], h->stream);
+            le = h->dtype == NCS_F64 ? launch_phase<double>(h, ph) : launch_phase<float>(h, ph);
+            hipEventRecord(ev[k + 1], h->stream);
+        }
+    }
+    hipError_t se = hipStreamSynchronize(h->stream);
+    for (int ph = 0; ph < NCS_N_PHASES; ++ph) ms_host[ph] = 0.0;
+    if (le == hipSuccess && se == hipSuccess) {
+        for (int i = 0; i < iters; ++i)
+            for (int ph = 0; ph < NCS_N_PHASES; ++ph) {
+                const size_t k = 2 * ((size_t)i * NCS_N_PHASES + ph);
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+                ms_host[ph] += ms / iters;
+            }
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    NCS_HIP(le);
+    NCS_HIP(se);
+    Control c;
+    return read_control(h, &c);
+}
+
+ncs_status ncs_get_info(ncs_handle* h, ncs_info* info) {
+    if (!h || !info) {
+        set_err("ncs_get_info: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    info->nnz = h->nnz;
+    info->c_r = h->c_r;
+    info->mu_dc = h->mu_dc;
+    info->norm_e1_sq = h->norm_e1_sq;
+    return NCS_OK;
+}
+
+ncs_status ncs_get_eigenvalues(ncs_handle* h, double* mu_host) {
+    if (!h || !mu_host) {
+        set_err("ncs_get_eigenvalues: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    std::memcpy(mu_host, h->mu.data(), h->mu.size() * sizeof(double));
+    return NCS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,739 @@
+// HIP kernels of the NCS iteration for gfx950 (CDNA4), templated on the
+// iterate precision T (float or double).  One NCS iteration (Section 4.1 /
+// Section 4.2 of the paper) is
+//
+//   k_backproject  w  = alpha E^T u + beta D^T v            (pixel-driven gather)
+//   k_fft_rows_fwd    row DFTs of w, two real rows per complex transform
+//   k_fft_cols        column DFT, multiply by h/(alpha N^2), inverse column DFT
+//   k_fft_rows_inv    inverse row DFTs; x+ = x - Delta, xbar = 2x+ - x
+//   k_tv              v+ = Pi(v + beta D xbar), TV of x+ (double partial sums)
+//   k_project         q = E xbar (ray-driven, LDS-staged); u+ = prox(u + ...),
+//                     p+ = (q + p)/2 = E x+, data term of x+ (double partials)
+//   k_finalize        f(x+) = data + lambda TV, history, device stop flag
+//
+// Every iteration kernel returns at once when the device stop flag is set, so a
+// queued or captured batch of iterations ends cleanly after the stopping test.
+#include "ncs_internal.h"
+
+#include <cmath>
+
+namespace ncs {
+
+namespace {
+
+constexpr int kRays = 64;      // rays per projector workgroup (one per lane)
+constexpr int kWaves = 4;      // waves per workgroup
+constexpr int kSeg = 64;       // steps per LDS segment of the projector
+constexpr int kPitch = 161;    // LDS row pitch: >= 63*sqrt(2) + 63 + 5, odd
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum of a double over 256 threads; result in thread 0.
+__device__ inline double block_sum256(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return r;
+}
+
+__device__ inline int bitrev(int i, int logn) {
+    return (int)(__brev((unsigned)i) >> (32 - logn));
+}
+
+// Radix-2 decimation-in-time transform in LDS: input in bit-reversed order,
+// output in natural order.  tw[2k], tw[2k+1] = cos, -sin of 2 pi k / N.
+template <class T>
+__device__ void fft_dit(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
+                        int tid, int nthr) {
+    for (int ls = 0; ls < logN; ++ls) {
+        const int half = 1 << ls;
+        __syncthreads();
+        for (int bi = tid; bi < (N >> 1); bi += nthr) {
+            const int pos = bi & (half - 1);
+            const int i0 = ((bi >> ls) << (ls + 1)) + pos;
+            const int i1 = i0 + half;
+            const int ti = pos << (logN - ls - 1);
+            const T wr = tw[2 * ti];
+            const T wi = inverse ? -tw[2 * ti + 1] : tw[2 * ti + 1];
+            const T xr = re[i1], xi = im[i1];
+            const T tr = wr * xr - wi * xi;
+            const T tim = wr * xi + wi * xr;
+            const T ar = re[i0], ai = im[i0];
+            re[i0] = ar + tr;
+            im[i0] = ai + tim;
+            re[i1] = ar - tr;
+            im[i1] = ai - tim;
+        }
+    }
+    __syncthreads();
+}
+
+// Radix-2 decimation-in-frequency transform in LDS: input natural, output in
+// bit-reversed order.
+template <class T>
+__device__ void fft_dif(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
+                        int tid, int nthr) {
+    for (int ls = logN - 1; ls >= 0; --ls) {
+        const int half = 1 << ls;
+        __syncthreads();
+        for (int bi = tid; bi < (N >> 1); bi += nthr) {
+            const int pos = bi & (half - 1);
+            const int i0 = ((bi >> ls) << (ls + 1)) + pos;
+            const int i1 = i0 + half;
+            const int ti = pos << (logN - ls - 1);
+            const T wr = tw[2 * ti];
+            const T wi = inverse ? -tw[2 * ti + 1] : tw[2 * ti + 1];
+            const T ar = re[i0], ai = im[i0], br = re[i1], bim = im[i1];
+            re[i0] = ar + br;
+            im[i0] = ai + bim;
+            const T dr = ar - br, di = ai - bim;
+            re[i1] = wr * dr - wi * di;
+            im[i1] = wr * di + wi * dr;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Backprojection (pixel-driven gather, matched to the ray-driven projector).
+// Workgroup: an 8 x 8 pixel tile; each of the 4 waves takes every 4th angle;
+// the 4 partial sums are added in a fixed order.
+// ---------------------------------------------------------------------------
+template <class T, bool ITER>
+__global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __restrict__ ysrc,
+                                                     T* __restrict__ out) {
+    if (ITER && c.ctl->stop) return;
+    __shared__ T red[kWaves * 64];
+    const int N = c.N;
+    const int tiles_x = N >> 3;
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = tx * 8 + (lane & 7);
+    const int row = ty * 8 + (lane >> 3);
+    const T fc = (T)col, fr = (T)row;
+    const T tmax = (T)c.NS;
+    const int PU = c.PU;
+    T acc = T(0);
+    for (int a = wave; a < c.NA; a += kWaves) {
+        const AngleT<T> A = c.ang[a];
+        T t = fma(fc, A.q1, fma(fr, A.q2, A.q0));
+        t = fmin(fmax(t, T(-1)), tmax);   // outside the detector: both taps land on zero pads
+        const T fl = floor(t);
+        const T f = t - fl;
+        const int d0 = (int)fl;
+        const T* yr = ysrc + (size_t)a * PU + 1 + d0;
+        const T y0 = yr[0], y1 = yr[1];
+        const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
+        const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
+        acc = fma(w0, y0, acc);
+        acc = fma(w1, y1, acc);
+    }
+    red[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    const T bp = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+    const size_t pix = (size_t)row * N + col;
+    if (!ITER) {
+        out[pix] = bp;
+        return;
+    }
+    // D^T v with D of Section 2 (rows [1, -1]) on each axis, padded planes.
+    const T* vh = c.v;
+    const T* vv = c.v + (size_t)N * N;
+    T dtv = T(0);
+    if (col < N - 1) dtv += vh[pix];
+    if (col > 0) dtv -= vh[pix - 1];
+    if (row < N - 1) dtv += vv[pix];
+    if (row > 0) dtv -= vv[pix - N];
+    c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection (Joseph, ray-driven).  Workgroup: one angle and 64
+// consecutive rays (one per lane).  The stepping axis is cut into segments of
+// 64 steps; for each segment the bounding box of the sampled coordinates of
+// all 64 rays is staged in LDS with coalesced loads (transposed on the fly for
+// column-stepping angles), then each wave marches 16 steps of every ray.
+// ---------------------------------------------------------------------------
+enum { PMODE_PLAIN = 0, PMODE_SETP = 1, PMODE_ITER = 2 };
+
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void k_project(DevCtx<T> c, const T* __restrict__ img,
+                                                 T* __restrict__ out) {
+    if (MODE == PMODE_ITER && c.ctl->stop) return;
+    __shared__ T tile[kSeg * kPitch];
+    __shared__ T red[kWaves * kRays];
+    const int N = c.N, NS = c.NS;
+    const int nb = (NS + kRays - 1) / kRays;
+    const int a = blockIdx.x / nb;
+    const int d0 = (blockIdx.x - a * nb) * kRays;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const AngleT<T> A = c.ang[a];
+    const int axis = c.axis[a];
+    const int d = d0 + lane;
+    const T base = fma((T)d, A.k1, A.k0);
+    const T bA = fma((T)d0, A.k1, A.k0);
+    const T bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
+    const int SL = N < kSeg ? N : kSeg;
+    const int SW = SL / kWaves;
+    T acc = T(0);
+    for (int s0 = 0; s0 < N; s0 += SL) {
+        const T sA = (T)s0, sB = (T)(s0 + SL - 1);
+        const T e0 = fma(sA, A.k2, bA), e1 = fma(sB, A.k2, bA);
+        const T e2 = fma(sA, A.k2, bB), e3 = fma(sB, A.k2, bB);
+        const T mn = fmin(fmin(e0, e1), fmin(e2, e3));
+        const T mx = fmax(fmax(e0, e1), fmax(e2, e3));
+        const int lo = (int)floor(mn) - 1;
+        const int hi = (int)floor(mx) + 2;
+        if (hi < 0 || lo > N - 1) continue;   // the whole ray block misses the image here
+        int W = hi - lo + 1;
+        W = W > kPitch ? kPitch : W;
+        __syncthreads();
+        if (axis == 0) {
+            for (int sl = wave; sl < SL; sl += kWaves) {
+                const T* rowp = img + (size_t)(s0 + sl) * N;
+                for (int j = lane; j < W; j += 64) {
+                    const int cc = lo + j;
+                    tile[sl * kPitch + j] = (cc >= 0 && cc < N) ? rowp[cc] : T(0);
+                }
+            }
+        } else {
+            for (int j = wave; j < W; j += kWaves) {
+                const int rr = lo + j;
+                const bool ok = rr >= 0 && rr < N;
+                const T* rowp = img + (size_t)(ok ? rr : 0) * N + s0;
+                for (int sl = lane; sl < SL; sl += 64) tile[sl * kPitch + j] = ok ? rowp[sl] : T(0);
+            }
+        }
+        __syncthreads();
+        const int sb = wave * SW;
+        for (int sl = sb; sl < sb + SW; ++sl) {
+            const T xi = fma((T)(s0 + sl), A.k2, base);
+            const T fl = floor(xi);
+            const T f = xi - fl;
+            int j = (int)fl - lo;
+            j = min(max(j, 0), W - 2);
+            const T* tp = tile + sl * kPitch + j;
+            const T v0 = tp[0], v1 = tp[1];
+            acc += fma(f, v1 - v0, v0);
+        }
+    }
+    red[wave * kRays + lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
+    const bool valid = d < NS;
+    if (MODE == PMODE_PLAIN) {
+        if (valid) out[(size_t)a * NS + d] = q;
+        return;
+    }
+    if (MODE == PMODE_SETP) {
+        if (valid) c.p[(size_t)a * c.PU + 1 + d] = q;
+        return;
+    }
+    double dterm = 0.0;
+    if (valid) {
+        const size_t i = (size_t)a * NS + d;
+        const size_t ip = (size_t)a * c.PU + 1 + d;
+        const T bb = c.b[i];
+        const T uu = c.u[ip];
+        const T pp = c.p[ip];
+        const T pn = (q + pp) * T(0.5);   // E x+ = (E xbar + E x)/2
+        T un;
+        if (c.data_term == DATA_QUAD) {
+            un = (uu + c.alpha * (q - bb)) * c.inv1pa;
+            const double e = (double)pn - (double)bb;
+            dterm = 0.5 * e * e;
+        } else {
+            const T r = c.bg ? c.bg[i] : T(0);
+            const T wv = uu + c.alpha * (q + r);
+            const T cc = c.alpha * bb;
+            const T t = wv - T(1);
+            const T sq = sqrt(fma(t, t, T(4) * cc));
+            // S(w; c) = 1 + (t - sqrt(t^2 + 4c))/2, rationalised when t > 0
+            un = t > T(0) ? T(1) - T(2) * cc / (t + sq) : T(1) + (t - sq) * T(0.5);
+            const double y = (double)pn + (double)r;
+            const double bd = (double)bb;
+            if (bd > 0.0) dterm = y > 0.0 ? y - bd * log(y) : INFINITY;
+            else dterm = y;   // zero counts: l = y (indicator not reported)
+        }
+        c.u[ip] = un;
+        c.p[ip] = pn;
+    }
+    dterm = wave_sum(dterm);
+    if (lane == 0) c.part_data[blockIdx.x] = dterm;
+}
+
+// ---------------------------------------------------------------------------
+// Circulant solve: 2D DFT as row transforms (two real rows packed in one
+// complex transform), column transforms with the multiplier, inverse rows.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_rows_fwd(DevCtx<T> c, const T* __restrict__ src, int check_stop) {
+    if (check_stop && c.ctl->stop) return;
+    extern __shared__ unsigned char smem_raw[];
+    T* re = reinterpret_cast<T*>(smem_raw);
+    T* im = re + c.N;
+    const int N = c.N, logN = c.log2N;
+    const int pr = blockIdx.x;
+    const T* ra = src + (size_t)(2 * pr) * N;
+    const T* rb = ra + N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const int i = bitrev(n, logN);
+        re[i] = ra[n];
+        im[i] = rb[n];
+    }
+    fft_dit(re, im, c.tw, N, logN, false, threadIdx.x, blockDim.x);
+    for (int k = threadIdx.x; k <= (N >> 1); k += blockDim.x) {
+        const int m = (N - k) & (N - 1);
+        const T zr = re[k], zi = im[k], mr = re[m], mi = im[m];
+        T* o = c.spec + 2 * ((size_t)k * N + 2 * pr);
+        o[0] = (zr + mr) * T(0.5);   // row 2pr:   (Z[k] + conj Z[N-k]) / 2
+        o[1] = (zi - mi) * T(0.5);
+        o[2] = (zi + mi) * T(0.5);   // row 2pr+1: (Z[k] - conj Z[N-k]) / 2i
+        o[3] = (mr - zr) * T(0.5);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_cols(DevCtx<T> c, T scale, int check_stop) {
+    if (check_stop && c.ctl->stop) return;
+    extern __shared__ unsigned char smem_raw[];
+    T* re = reinterpret_cast<T*>(smem_raw);
+    T* im = re + c.N;
+    const int N = c.N, logN = c.log2N;
+    const int k = blockIdx.x;
+    T* colp = c.spec + 2 * (size_t)k * N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const int i = bitrev(n, logN);
+        re[i] = colp[2 * n];
+        im[i] = colp[2 * n + 1];
+    }
+    fft_dit(re, im, c.tw, N, logN, false, threadIdx.x, blockDim.x);
+    const T* hk = c.hh + (size_t)k * N;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const T hv = hk[j] * scale;
+        re[j] *= hv;
+        im[j] *= hv;
+    }
+    fft_dif(re, im, c.tw, N, logN, true, threadIdx.x, blockDim.x);
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const int i = bitrev(n, logN);
+        colp[2 * n] = re[i];
+        colp[2 * n + 1] = im[i];
+    }
+}
+
+template <class T, bool ITER>
+__global__ __launch_bounds__(256) void k_fft_rows_inv(DevCtx<T> c, T* __restrict__ out) {
+    if (ITER && c.ctl->stop) return;
+    extern __shared__ unsigned char smem_raw[];
+    T* re = reinterpret_cast<T*>(smem_raw);
+    T* im = re + c.N;
+    const int N = c.N, logN = c.log2N;
+    const int pr = blockIdx.x;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const int kk = k <= (N >> 1) ? k : N - k;
+        const T* s = c.spec + 2 * ((size_t)kk * N + 2 * pr);
+        const T ar = s[0], br = s[2];
+        T ai = s[1], bi = s[3];
+        if (k > (N >> 1)) {   // Hermitian extension of both real-row spectra
+            ai = -ai;
+            bi = -bi;
+        }
+        re[k] = ar - bi;      // Z = Ya + i Yb
+        im[k] = ai + br;
+    }
+    fft_dif(re, im, c.tw, N, logN, true, threadIdx.x, blockDim.x);
+    const size_t ra = (size_t)(2 * pr) * N, rb = ra + N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const int i = bitrev(n, logN);
+        const T da = re[i], db = im[i];
+        if (!ITER) {
+            out[ra + n] = da;
+            out[rb + n] = db;
+            continue;
+        }
+        const T xa = c.x[ra + n], xb = c.x[rb + n];
+        const T na = xa - da, nb = xb - db;
+        c.x[ra + n] = na;
+        c.x[rb + n] = nb;
+        c.xbar[ra + n] = fma(T(2), na, -xa);
+        c.xbar[rb + n] = fma(T(2), nb, -xb);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TV dual update and TV term of x+ (double partial sums).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_tv(DevCtx<T> c) {
+    if (c.ctl->stop) return;
+    __shared__ double sh[kWaves];
+    const int N = c.N;
+    const size_t NN = (size_t)N * N;
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double tvv = 0.0;
+    if (pix < NN) {
+        const int r = (int)(pix >> c.log2N);
+        const int col = (int)(pix & (size_t)(N - 1));
+        const bool hx = col < N - 1, hy = r < N - 1;
+        const T xb = c.xbar[pix];
+        const T dh = hx ? xb - c.xbar[pix + 1] : T(0);
+        const T dv = hy ? xb - c.xbar[pix + N] : T(0);
+        T* vh = c.v;
+        T* vv = c.v + NN;
+        const T gh = fma(c.beta, dh, vh[pix]);
+        const T gv = fma(c.beta, dv, vv[pix]);
+        const T s = c.s_tv;
+        if (c.tv_term == TV_ANISO) {
+            vh[pix] = fmin(fmax(gh, -s), s);
+            vv[pix] = fmin(fmax(gv, -s), s);
+        } else {
+            const T nrm = sqrt(fma(gh, gh, gv * gv));
+            const T sc = nrm > s ? s / nrm : T(1);
+            vh[pix] = gh * sc;
+            vv[pix] = gv * sc;
+        }
+        const double xx = (double)c.x[pix];
+        const double th = hx ? xx - (double)c.x[pix + 1] : 0.0;
+        const double tw = hy ? xx - (double)c.x[pix + N] : 0.0;
+        tvv = c.tv_term == TV_ANISO ? fabs(th) + fabs(tw) : sqrt(th * th + tw * tw);
+    }
+    const double tot = block_sum256(tvv, sh);
+    if (threadIdx.x == 0) c.part_tv[blockIdx.x] = tot;
+}
+
+// TV term of an arbitrary image (objective evaluation).
+template <class T>
+__global__ __launch_bounds__(256) void k_tv_eval(DevCtx<T> c, const T* __restrict__ img) {
+    __shared__ double sh[kWaves];
+    const int N = c.N;
+    const size_t NN = (size_t)N * N;
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double tvv = 0.0;
+    if (pix < NN) {
+        const int r = (int)(pix >> c.log2N);
+        const int col = (int)(pix & (size_t)(N - 1));
+        const double xx = (double)img[pix];
+        const double th = col < N - 1 ? xx - (double)img[pix + 1] : 0.0;
+        const double tw = r < N - 1 ? xx - (double)img[pix + N] : 0.0;
+        tvv = c.tv_term == TV_ANISO ? fabs(th) + fabs(tw) : sqrt(th * th + tw * tw);
+    }
+    const double tot = block_sum256(tvv, sh);
+    if (threadIdx.x == 0) c.part_tv[blockIdx.x] = tot;
+}
+
+// Data term of a projected image q (unpadded, NA*NS) (objective evaluation).
+template <class T>
+__global__ __launch_bounds__(256) void k_data_eval(DevCtx<T> c, const T* __restrict__ q) {
+    __shared__ double sh[kWaves];
+    const size_t m = (size_t)c.NA * c.NS;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double dterm = 0.0;
+    if (i < m) {
+        const double y0 = (double)q[i];
+        const double bd = (double)c.b[i];
+        if (c.data_term == DATA_QUAD) {
+            const double e = y0 - bd;
+            dterm = 0.5 * e * e;
+        } else {
+            const double y = y0 + (c.bg ? (double)c.bg[i] : 0.0);
+            if (bd > 0.0) dterm = y > 0.0 ? y - bd * log(y) : INFINITY;
+            else dterm = y;   // zero counts: l = y (indicator not reported)
+        }
+    }
+    const double tot = block_sum256(dterm, sh);
+    if (threadIdx.x == 0) c.part_data[blockIdx.x] = tot;
+}
+
+// PET constant sum_i log Gamma(b_i + 1).
+template <class T>
+__global__ __launch_bounds__(256) void k_lgamma_part(DevCtx<T> c) {
+    __shared__ double sh[kWaves];
+    const size_t m = (size_t)c.NA * c.NS;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (i < m) v = lgamma((double)c.b[i] + 1.0);
+    const double tot = block_sum256(v, sh);
+    if (threadIdx.x == 0) c.part_data[blockIdx.x] = tot;
+}
+
+// which: 0 = iteration (history, stop test), 1 = evaluation (eval_out),
+//        2 = data constant (data_const = sum of data partials).
+template <class T>
+__global__ __launch_bounds__(256) void k_finalize(DevCtx<T> c, int nd, int nt, int which) {
+    if (which == 0 && c.ctl->stop) return;
+    __shared__ double sh[kWaves];
+    double sd = 0.0, st = 0.0;
+    for (int i = threadIdx.x; i < nd; i += 256) sd += c.part_data[i];
+    for (int i = threadIdx.x; i < nt; i += 256) st += c.part_tv[i];
+    sd = block_sum256(sd, sh);
+    __syncthreads();
+    st = block_sum256(st, sh);
+    if (threadIdx.x != 0) return;
+    Control* k = c.ctl;
+    if (which == 2) {
+        k->data_const = sd;
+        return;
+    }
+    const double f = (sd + k->data_const) + c.lambda * st;
+    if (which == 1) {
+        k->eval_out = f;
+        return;
+    }
+    const int it = k->iter;
+    c.hist[it & (kHistCap - 1)] = f;
+    k->iter = it + 1;
+    k->f_last = f;
+    if (f != f) {
+        k->status = -4;
+        k->stop = 1;
+    } else if (f <= k->f_target) {
+        k->status = 1;
+        k->stop = 1;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pad(DevCtx<T> c, const T* __restrict__ y, T* __restrict__ yp) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t tot = (size_t)c.NA * c.PU;
+    if (i >= tot) return;
+    const int a = (int)(i / c.PU);
+    const int j = (int)(i - (size_t)a * c.PU) - 1;
+    yp[i] = (j >= 0 && j < c.NS) ? y[(size_t)a * c.NS + j] : T(0);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_unpad(DevCtx<T> c, const T* __restrict__ yp, T* __restrict__ y) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t tot = (size_t)c.NA * c.NS;
+    if (i >= tot) return;
+    const int a = (int)(i / c.NS);
+    const int d = (int)(i - (size_t)a * c.NS);
+    y[i] = yp[(size_t)a * c.PU + 1 + d];
+}
+
+// Dual initialisation from x0 (fixed-point relations of the optimality
+// conditions): u = grad g_data(E x0) from p = E x0; v from D x0.
+template <class T>
+__global__ __launch_bounds__(256) void k_dual_init_u(DevCtx<T> c) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t m = (size_t)c.NA * c.NS;
+    if (i >= m) return;
+    const int a = (int)(i / c.NS);
+    const int d = (int)(i - (size_t)a * c.NS);
+    const size_t ip = (size_t)a * c.PU + 1 + d;
+    const T pp = c.p[ip];
+    const T bb = c.b[i];
+    T un;
+    if (c.data_term == DATA_QUAD) {
+        un = pp - bb;
+    } else {
+        const T y = pp + (c.bg ? c.bg[i] : T(0));
+        // grad of l(y; b) = 1 - b/y on the domain; clamp to the closure of dom l*
+        un = y > T(0) ? T(1) - bb / y : (bb > T(0) ? T(-1e30) : T(1));
+    }
+    c.u[ip] = un;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_dual_init_v(DevCtx<T> c) {
+    const int N = c.N;
+    const size_t NN = (size_t)N * N;
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (pix >= NN) return;
+    const int r = (int)(pix >> c.log2N);
+    const int col = (int)(pix & (size_t)(N - 1));
+    const T xx = c.x[pix];
+    const T dh = col < N - 1 ? xx - c.x[pix + 1] : T(0);
+    const T dv = r < N - 1 ? xx - c.x[pix + N] : T(0);
+    const T s = c.s_tv;
+    T vh, vv;
+    if (c.tv_term == TV_ANISO) {
+        vh = dh > T(0) ? s : (dh < T(0) ? -s : T(0));
+        vv = dv > T(0) ? s : (dv < T(0) ? -s : T(0));
+    } else {
+        const T nrm = sqrt(fma(dh, dh, dv * dv));
+        vh = nrm > T(0) ? s * dh / nrm : T(0);
+        vv = nrm > T(0) ? s * dv / nrm : T(0);
+    }
+    c.v[pix] = vh;
+    c.v[pix + NN] = vv;
+}
+
+template <class T>
+inline int fft_threads(const DevCtx<T>& c) {
+    int t = c.N / 2;
+    if (t < 64) t = 64;
+    if (t > 256) t = 256;
+    return t;
+}
+
+inline unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
+
+__global__ void k_control(Control* ctl, int op, int iter_value, double f_target) {
+    if (threadIdx.x != 0) return;
+    if (op == 0) ctl->iter = 0;
+    if (op == 2) ctl->iter = iter_value;
+    ctl->stop = 0;
+    ctl->status = 0;
+    ctl->f_target = f_target;
+}
+
+}  // namespace
+
+hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target, hipStream_t st) {
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, st, ctl, op, iter_value, f_target);
+    return hipGetLastError();
+}
+
+int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
+int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
+
+template <class T>
+hipError_t launch_backproject_iter(const DevCtx<T>& c, hipStream_t st) {
+    const int nb = (c.N / 8) * (c.N / 8);
+    hipLaunchKernelGGL((k_backproject<T, true>), dim3(nb), dim3(256), 0, st, c, (const T*)c.u, (T*)nullptr);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_backproject_plain(const DevCtx<T>& c, const T* y_padded, T* out, hipStream_t st) {
+    const int nb = (c.N / 8) * (c.N / 8);
+    hipLaunchKernelGGL((k_backproject<T, false>), dim3(nb), dim3(256), 0, st, c, y_padded, out);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fft_rows_fwd(const DevCtx<T>& c, const T* src, bool iter, hipStream_t st) {
+    const size_t sm = 2 * (size_t)c.N * sizeof(T);
+    hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(c.N / 2), dim3(fft_threads(c)), sm, st, c, src, iter ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fft_cols(const DevCtx<T>& c, T scale, bool iter, hipStream_t st) {
+    const size_t sm = 2 * (size_t)c.N * sizeof(T);
+    hipLaunchKernelGGL((k_fft_cols<T>), dim3(c.N / 2 + 1), dim3(fft_threads(c)), sm, st, c, scale, iter ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fft_rows_inv_update(const DevCtx<T>& c, hipStream_t st) {
+    const size_t sm = 2 * (size_t)c.N * sizeof(T);
+    hipLaunchKernelGGL((k_fft_rows_inv<T, true>), dim3(c.N / 2), dim3(fft_threads(c)), sm, st, c, (T*)nullptr);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fft_rows_inv_plain(const DevCtx<T>& c, T* out, hipStream_t st) {
+    const size_t sm = 2 * (size_t)c.N * sizeof(T);
+    hipLaunchKernelGGL((k_fft_rows_inv<T, false>), dim3(c.N / 2), dim3(fft_threads(c)), sm, st, c, out);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_tv_update(const DevCtx<T>& c, hipStream_t st) {
+    hipLaunchKernelGGL((k_tv<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_project_iter(const DevCtx<T>& c, hipStream_t st) {
+    hipLaunchKernelGGL((k_project<T, PMODE_ITER>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c,
+                       (const T*)c.xbar, (T*)nullptr);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_project_plain(const DevCtx<T>& c, const T* img, T* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_project<T, PMODE_PLAIN>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c, img, out);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_project_setp(const DevCtx<T>& c, const T* img, hipStream_t st) {
+    hipLaunchKernelGGL((k_project<T, PMODE_SETP>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c, img,
+                       (T*)nullptr);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_finalize_iter(const DevCtx<T>& c, hipStream_t st) {
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, c, project_blocks(c.NA, c.NS), tv_blocks(c.N), 0);
+    return hipGetLastError();
+}
+
+// f(img): project into the scratch sinogram (unpadded view), data and TV
+// partials, then reduce into ctl->eval_out.
+template <class T>
+hipError_t launch_eval_objective(const DevCtx<T>& c, const T* img, hipStream_t st) {
+    const size_t m = (size_t)c.NA * c.NS;
+    hipLaunchKernelGGL((k_project<T, PMODE_PLAIN>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c, img, c.ysc);
+    const unsigned nd = blocks_for(m);
+    hipLaunchKernelGGL((k_data_eval<T>), dim3(nd), dim3(256), 0, st, c, (const T*)c.ysc);
+    hipLaunchKernelGGL((k_tv_eval<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c, img);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, c, (int)nd, tv_blocks(c.N), 1);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_pad_sinogram(const DevCtx<T>& c, const T* y, T* y_padded, hipStream_t st) {
+    hipLaunchKernelGGL((k_pad<T>), dim3(blocks_for((size_t)c.NA * c.PU)), dim3(256), 0, st, c, y, y_padded);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_unpad_sinogram(const DevCtx<T>& c, const T* y_padded, T* y, hipStream_t st) {
+    hipLaunchKernelGGL((k_unpad<T>), dim3(blocks_for((size_t)c.NA * c.NS)), dim3(256), 0, st, c, y_padded, y);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_data_const(const DevCtx<T>& c, hipStream_t st) {
+    const unsigned nd = blocks_for((size_t)c.NA * c.NS);
+    hipLaunchKernelGGL((k_lgamma_part<T>), dim3(nd), dim3(256), 0, st, c);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, c, (int)nd, 0, 2);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_dual_init(const DevCtx<T>& c, hipStream_t st) {
+    hipLaunchKernelGGL((k_dual_init_u<T>), dim3(blocks_for((size_t)c.NA * c.NS)), dim3(256), 0, st, c);
+    hipLaunchKernelGGL((k_dual_init_v<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
+#define NCS_INSTANTIATE(T)                                                                       \
+    template hipError_t launch_backproject_iter<T>(const DevCtx<T>&, hipStream_t);               \
+    template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const T*, T*, hipStream_t); \
+    template hipError_t launch_fft_rows_fwd<T>(const DevCtx<T>&, const T*, bool, hipStream_t);   \
+    template hipError_t launch_fft_cols<T>(const DevCtx<T>&, T, bool, hipStream_t);              \
+    template hipError_t launch_fft_rows_inv_update<T>(const DevCtx<T>&, hipStream_t);            \
+    template hipError_t launch_fft_rows_inv_plain<T>(const DevCtx<T>&, T*, hipStream_t);         \
+    template hipError_t launch_tv_update<T>(const DevCtx<T>&, hipStream_t);                      \
+    template hipError_t launch_project_iter<T>(const DevCtx<T>&, hipStream_t);                   \
+    template hipError_t launch_project_plain<T>(const DevCtx<T>&, const T*, T*, hipStream_t);    \
+    template hipError_t launch_project_setp<T>(const DevCtx<T>&, const T*, hipStream_t);         \
+    template hipError_t launch_finalize_iter<T>(const DevCtx<T>&, hipStream_t);                  \
+    template hipError_t launch_eval_objective<T>(const DevCtx<T>&, const T*, hipStream_t);       \
+    template hipError_t launch_pad_sinogram<T>(const DevCtx<T>&, const T*, T*, hipStream_t);     \
+    template hipError_t launch_unpad_sinogram<T>(const DevCtx<T>&, const T*, T*, hipStream_t);   \
+    template hipError_t launch_data_const<T>(const DevCtx<T>&, hipStream_t);                     \
+    template hipError_t launch_dual_init<T>(const DevCtx<T>&, hipStream_t);
+
+NCS_INSTANTIATE(float)
+NCS_INSTANTIATE(double)
+
+}  // namespace ncs

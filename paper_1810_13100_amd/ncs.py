@@ -1,0 +1,304 @@
+"""Python binding of the NCS C ABI (``include/ncs.h``).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``libncs.so``.  PyTorch supplies device memory and the current stream.  There
+is no fallback; if the library is missing or the device is not a GPU the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libncs.so")
+
+NCS_OK = 0
+NCS_NOT_CONVERGED = 1
+NCS_ERR_INVALID_ARG = -1
+NCS_ERR_HIP = -2
+NCS_ERR_OOM = -3
+NCS_ERR_NONFINITE = -4
+NCS_ERR_DIVERGED = -5
+
+NCS_F32 = 0
+NCS_F64 = 1
+DATA_QUADRATIC = 0
+DATA_POISSON = 1
+TV_ANISO = 0
+TV_ISO = 1
+
+_STATUS_NAMES = {
+    NCS_OK: "NCS_OK", NCS_NOT_CONVERGED: "NCS_NOT_CONVERGED",
+    NCS_ERR_INVALID_ARG: "NCS_ERR_INVALID_ARG", NCS_ERR_HIP: "NCS_ERR_HIP",
+    NCS_ERR_OOM: "NCS_ERR_OOM", NCS_ERR_NONFINITE: "NCS_ERR_NONFINITE",
+    NCS_ERR_DIVERGED: "NCS_ERR_DIVERGED",
+}
+
+EXPORTED = [
+    "ncs_setup", "ncs_set_init", "ncs_iterate", "ncs_solve", "ncs_get_objectives",
+    "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_state", "ncs_set_state",
+    "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_get_eigenvalues",
+    "ncs_time_phases", "ncs_get_info", "ncs_destroy", "ncs_last_error",
+]
+PHASES = ["backproject", "fft_rows", "fft_cols_multiplier", "fft_rows_inv_update", "tv_update",
+          "project_dataprox", "objective_reduce"]
+
+
+class NcsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("n_side", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("lambda_", ctypes.c_double), ("c_r", ctypes.c_double), ("mu_dc", ctypes.c_double),
+        ("data_term", ctypes.c_int32), ("tv_term", ctypes.c_int32),
+        ("check_every", ctypes.c_int32), ("diverge_checks", ctypes.c_int32),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int64), ("c_r", ctypes.c_double), ("mu_dc", ctypes.c_double),
+                ("norm_e1_sq", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libncs.so (torch is imported first so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    pi32, pdbl, psz = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_size_t)
+    sigs = {
+        "ncs_setup": ([ctypes.POINTER(_Geometry), ctypes.POINTER(_Params), i32, vp, vp, vp,
+                       ctypes.POINTER(vp)], i32),
+        "ncs_set_init": ([vp, vp, i32], i32),
+        "ncs_iterate": ([vp, i32, pdbl], i32),
+        "ncs_solve": ([vp, i32, dbl, pi32, pdbl], i32),
+        "ncs_get_objectives": ([vp, i32, i32, pdbl], i32),
+        "ncs_get_iteration": ([vp, pi32], i32),
+        "ncs_get_x": ([vp, vp], i32),
+        "ncs_get_u": ([vp, vp], i32),
+        "ncs_get_state": ([vp, vp, psz], i32),
+        "ncs_set_state": ([vp, vp, ctypes.c_size_t], i32),
+        "ncs_forward": ([vp, vp, vp], i32),
+        "ncs_adjoint": ([vp, vp, vp], i32),
+        "ncs_apply_minv": ([vp, vp, vp], i32),
+        "ncs_objective": ([vp, vp, pdbl], i32),
+        "ncs_get_eigenvalues": ([vp, pdbl], i32),
+        "ncs_time_phases": ([vp, i32, pdbl], i32),
+        "ncs_get_info": ([vp, ctypes.POINTER(_Info)], i32),
+        "ncs_destroy": ([vp], None),
+        "ncs_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=(NCS_OK,)) -> int:
+    if status in allow:
+        return status
+    msg = load_library().ncs_last_error().decode(errors="replace")
+    raise NcsError(status, msg)
+
+
+@dataclass
+class Geometry:
+    n_side: int
+    n_angles: int
+    n_bins: int
+
+    @property
+    def n(self) -> int:
+        return self.n_side * self.n_side
+
+    @property
+    def m(self) -> int:
+        return self.n_angles * self.n_bins
+
+
+@dataclass
+class Params:
+    alpha: float
+    beta: float
+    gamma: float
+    lam: float
+    c_r: float = 0.0
+    mu_dc: float = 0.0
+    data_term: int = DATA_QUADRATIC
+    tv_term: int = TV_ANISO
+    check_every: int = 50
+    diverge_checks: int = 0
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class Solver:
+    """One NCS problem instance on the current CUDA (HIP) device."""
+
+    def __init__(self, geom: Geometry, params: Params, b: torch.Tensor | None = None,
+                 bg: torch.Tensor | None = None, dtype: torch.dtype = torch.float32):
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        if not torch.cuda.is_available():
+            raise RuntimeError("the NCS library needs a GPU; none is visible")
+        self.lib = load_library()
+        self.geom = geom
+        self.params = params
+        self.dtype = dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._b = self._sino(b, "b") if b is not None else None
+        self._bg = self._sino(bg, "bg") if bg is not None else None
+        g = _Geometry(geom.n_side, geom.n_angles, geom.n_bins)
+        p = _Params(params.alpha, params.beta, params.gamma, params.lam, params.c_r, params.mu_dc,
+                    params.data_term, params.tv_term, params.check_every, params.diverge_checks)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.ncs_setup(ctypes.byref(g), ctypes.byref(p),
+                                  NCS_F64 if dtype == torch.float64 else NCS_F32,
+                                  _ptr(self._b), _ptr(self._bg), self.stream.cuda_stream, ctypes.byref(h)))
+        self.h = h
+
+    # -- argument checks ---------------------------------------------------
+    def _dev(self, t: torch.Tensor, numel: int, name: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{name} must be a tensor on {self.device}")
+        if t.dtype != self.dtype:
+            raise ValueError(f"{name} must have dtype {self.dtype}")
+        if t.numel() != numel:
+            raise ValueError(f"{name} must have {numel} elements (got {t.numel()})")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _sino(self, t, name):
+        return self._dev(t, self.geom.m, name)
+
+    def _img(self, t, name):
+        return self._dev(t, self.geom.n, name)
+
+    # -- state -------------------------------------------------------------
+    def set_init(self, x0: torch.Tensor | None = None, dual_from_x0: bool = False) -> None:
+        x0p = _ptr(self._img(x0, "x0")) if x0 is not None else None
+        self._x0_keep = x0
+        _check(self.lib.ncs_set_init(self.h, x0p, int(dual_from_x0)))
+
+    def iterate(self, k: int, record: bool = False) -> np.ndarray | None:
+        if record:
+            obj = np.empty(k, dtype=np.float64)
+            _check(self.lib.ncs_iterate(self.h, k, obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+            return obj
+        _check(self.lib.ncs_iterate(self.h, k, None))
+        return None
+
+    def solve(self, max_iters: int, f_target: float = math.nan) -> tuple[int, int, float]:
+        """Returns (status, iterations run, last objective); status is NCS_OK or NCS_NOT_CONVERGED."""
+        it = ctypes.c_int32()
+        f = ctypes.c_double()
+        st = _check(self.lib.ncs_solve(self.h, max_iters, f_target, ctypes.byref(it), ctypes.byref(f)),
+                    allow=(NCS_OK, NCS_NOT_CONVERGED))
+        return st, it.value, f.value
+
+    def objectives(self, first: int, count: int) -> np.ndarray:
+        out = np.empty(count, dtype=np.float64)
+        _check(self.lib.ncs_get_objectives(self.h, first, count,
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def iteration(self) -> int:
+        it = ctypes.c_int32()
+        _check(self.lib.ncs_get_iteration(self.h, ctypes.byref(it)))
+        return it.value
+
+    def x(self) -> torch.Tensor:
+        out = torch.empty(self.geom.n, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_get_x(self.h, out.data_ptr()))
+        return out
+
+    def u(self) -> torch.Tensor:
+        out = torch.empty(self.geom.m, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_get_u(self.h, out.data_ptr()))
+        return out
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(self.lib.ncs_get_state(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self.lib.ncs_get_state(self.h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def set_state(self, blob: bytes) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self.lib.ncs_set_state(self.h, buf, len(blob)))
+
+    # -- operators ---------------------------------------------------------
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty(self.geom.m, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_forward(self.h, self._img(x, "x").data_ptr(), y.data_ptr()))
+        return y
+
+    def adjoint(self, y: torch.Tensor) -> torch.Tensor:
+        x = torch.empty(self.geom.n, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_adjoint(self.h, self._sino(y, "y").data_ptr(), x.data_ptr()))
+        return x
+
+    def apply_minv(self, w: torch.Tensor) -> torch.Tensor:
+        out = torch.empty(self.geom.n, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_apply_minv(self.h, self._img(w, "w").data_ptr(), out.data_ptr()))
+        return out
+
+    def objective(self, x: torch.Tensor) -> float:
+        f = ctypes.c_double()
+        _check(self.lib.ncs_objective(self.h, self._img(x, "x").data_ptr(), ctypes.byref(f)))
+        return f.value
+
+    def time_phases(self, iters: int) -> dict:
+        """Mean ms per iteration of each kernel, timed with HIP events (advances the state)."""
+        ms = np.zeros(len(PHASES), dtype=np.float64)
+        _check(self.lib.ncs_time_phases(self.h, iters, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return dict(zip(PHASES, ms.tolist()))
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(self.lib.ncs_get_info(self.h, ctypes.byref(inf)))
+        return {"nnz": inf.nnz, "c_r": inf.c_r, "mu_dc": inf.mu_dc, "norm_e1_sq": inf.norm_e1_sq}
+
+    def eigenvalues(self) -> np.ndarray:
+        mu = np.empty(self.geom.n, dtype=np.float64)
+        _check(self.lib.ncs_get_eigenvalues(self.h, mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return mu.reshape(self.geom.n_side, self.geom.n_side)
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.ncs_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every function that include/ncs.h declares
+(no GPU needed; no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ncs.h")
+LIB = os.path.join(ROOT, "paper_1810_13100_amd", "libncs.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ncs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for n in ("ncs_setup", "ncs_iterate", "ncs_solve", "ncs_destroy", "ncs_last_error"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libncs.so not built")
+def test_library_exports_every_declared_symbol():
+    import torch  # noqa: F401  (same HIP runtime as the binding)
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    from paper_1810_13100_amd import ncs
+    assert sorted(ncs.EXPORTED) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libncs.so not built")
+def test_last_error_is_empty_string_initially():
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB)
+    lib.ncs_last_error.restype = ctypes.c_char_p
+    assert lib.ncs_last_error() == b""
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libncs.so not built")
+def test_null_arguments_are_rejected_without_gpu_work():
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB)
+    lib.ncs_setup.restype = ctypes.c_int32
+    lib.ncs_iterate.restype = ctypes.c_int32
+    lib.ncs_last_error.restype = ctypes.c_char_p
+    assert lib.ncs_setup(None, None, 0, None, None, None, None) == -1
+    assert b"null" in lib.ncs_last_error()
+    lib.ncs_iterate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+    assert lib.ncs_iterate(None, 1, None) == -1

@@ -1,0 +1,231 @@
+"""GPU parity of whole NCS trajectories against the FP64 oracle, through the C ABI,
+plus the driver's behaviour (stopping, checkpoints, determinism, errors).
+
+Gates: with the FP64 build of the kernels, rel-L2(x^K) <= 1e-10 and every
+objective f(x^k) within 1e-10 relative -- the same arithmetic up to rounding
+order.  With FP32 iterates: rel-L2(x^K) <= 1e-4 and |f - f_ref| <= 1e-5 |f_ref|
+at every k <= K (the tolerances the method's FP32 build is held to).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import GEOMS, ct_params, ct_problem, joseph, log, oracle_ncs, pet_problem, rel_l2
+from oracle import problems
+from paper_1810_13100_amd import ncs
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+DT = {"f32": torch.float32, "f64": torch.float64}
+TOL = {"f64": (1e-10, 1e-10), "f32": (1e-4, 1e-5)}
+
+
+def make_solver(prob, par, dtype, check_every=50, diverge_checks=0):
+    data = ncs.DATA_POISSON if prob.kind == "pet" else ncs.DATA_QUADRATIC
+    tv = ncs.TV_ISO if prob.tv == "iso" else ncs.TV_ANISO
+    p = ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0,
+                   data_term=data, tv_term=tv, check_every=check_every, diverge_checks=diverge_checks)
+    b = torch.tensor(prob.b, dtype=dtype, device=DEV)
+    bg = torch.tensor(prob.bg, dtype=dtype, device=DEV) if prob.kind == "pet" else None
+    return ncs.Solver(ncs.Geometry(prob.n_side, prob.n_angles, prob.n_bins), p, b=b, bg=bg, dtype=dtype)
+
+
+def pet_params(n_side, n_angles):
+    return ct_params(n_side, n_angles, alpha=1.0, ratio=3.0, g=1.0)
+
+
+def check_trajectory(prob, par, iters, prec):
+    ref = oracle_ncs(prob, par, iters)
+    s = make_solver(prob, par, DT[prec])
+    s.set_init()
+    obj = s.iterate(iters, record=True)
+    x = s.x().double().cpu().numpy()
+    u = s.u().double().cpu().numpy()
+    s.close()
+    ex = rel_l2(x, ref.x)
+    eu = rel_l2(u, ref.u)
+    fin = np.isfinite(ref.obj)
+    assert np.array_equal(np.isfinite(obj), fin)
+    ef = float(np.max(np.abs(obj[fin] - ref.obj[fin]) / np.abs(ref.obj[fin]))) if fin.any() else 0.0
+    log(f"  {prec} K={iters}: rel-L2 x {ex:.2e}, u {eu:.2e}, max rel f {ef:.2e}")
+    tx, tf = TOL[prec]
+    assert ex <= tx, ex
+    assert ef <= tf, ef
+    return ex, ef
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ct_64_200_iterations(prec):
+    prob = ct_problem("c1")
+    log(f"NCS parity 64^2 CT, 200 iterations, {prec}")
+    check_trajectory(prob, ct_params(64, 90), 200, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ct_ragged_tiny_geometry(prec):
+    geom = GEOMS["tiny"]
+    prob = problems.ct_problem(*geom, 1, 0.05, E=joseph(*geom))
+    log(f"NCS parity tiny {geom}, {prec}")
+    check_trajectory(prob, ct_params(geom[0], geom[1], alpha=0.05), 150, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ct_isotropic_tv(prec):
+    prob = ct_problem("c1", seed=2, lam=0.5, tv="iso")
+    log(f"NCS parity 64^2 CT isotropic TV, {prec}")
+    check_trajectory(prob, ct_params(64, 90), 150, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pet_128(prec):
+    prob = pet_problem("c3")
+    log(f"NCS parity 128^2 PET, 100 iterations, {prec}")
+    check_trajectory(prob, pet_params(128, 180), 100, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ct_256_full_size(prec):
+    prob = ct_problem("c2")
+    log(f"NCS parity 256^2 CT (360 x 367), 100 iterations, {prec}")
+    check_trajectory(prob, ct_params(256, 360, alpha=3e-4), 100, prec)
+
+
+def test_checkpoint_resume_is_bitwise():
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    a = make_solver(prob, par, torch.float32)
+    a.set_init()
+    a.iterate(40)
+    blob = a.get_state()
+    a.iterate(40)
+    xa = a.x().cpu()
+    b = make_solver(prob, par, torch.float32)
+    b.set_state(blob)
+    assert b.iteration() == 40
+    b.iterate(40)
+    assert torch.equal(b.x().cpu(), xa)
+    assert torch.equal(b.u().cpu(), a.u().cpu())
+    assert b.iteration() == a.iteration() == 80
+    a.close()
+    b.close()
+
+
+def test_runs_are_deterministic():
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    outs = []
+    for _ in range(2):
+        s = make_solver(prob, par, torch.float32)
+        s.set_init()
+        obj = s.iterate(30, record=True)
+        outs.append((s.x().cpu(), obj))
+        s.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_solve_stops_at_first_target_crossing():
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    ref = oracle_ncs(prob, par, 200)
+    target = float(ref.obj[120])
+    first = int(np.nonzero(ref.obj <= target)[0][0]) + 1
+    s = make_solver(prob, par, torch.float64, check_every=37)
+    s.set_init()
+    st, iters, f = s.solve(500, target)
+    log(f"solve: status {st}, {iters} iterations (oracle {first}), f {f}")
+    assert st == ncs.NCS_OK
+    assert iters == first
+    assert abs(f - ref.obj[first - 1]) <= 1e-10 * abs(f)
+    # the chunk continues past the stop without touching the state
+    x = s.x().cpu().numpy()
+    np.testing.assert_allclose(x, oracle_ncs(prob, par, first).x, rtol=0, atol=1e-9 * np.abs(x).max())
+    st2, iters2, _ = s.solve(3, math.nan)
+    assert st2 == ncs.NCS_NOT_CONVERGED and iters2 == 3
+    assert s.iteration() == first + 3
+    s.close()
+
+
+def test_objective_history_matches_iterate():
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    s = make_solver(prob, par, torch.float64)
+    s.set_init()
+    obj = s.iterate(25, record=True)
+    np.testing.assert_array_equal(s.objectives(0, 25), obj)
+    np.testing.assert_array_equal(s.objectives(10, 5), obj[10:15])
+    with pytest.raises(ncs.NcsError):
+        s.objectives(20, 10)
+    s.close()
+
+
+def test_warm_start_duals_and_progress():
+    # Duals from the optimality conditions (Section 3.2, Fact on fixed points):
+    # for CT u* = E x* - b exactly; started there NCS stays at the optimal
+    # objective to ~1e-4 within 20 iterations, whereas the cold start is still
+    # orders of magnitude away.
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    ref = oracle_ncs(prob, par, 2000)
+    s = make_solver(prob, par, torch.float64)
+    s.set_init(torch.tensor(ref.x, dtype=torch.float64, device=DEV), dual_from_x0=True)
+    u0 = s.u().cpu().numpy()
+    np.testing.assert_allclose(u0, prob.E @ ref.x - prob.b, rtol=0, atol=1e-10 * np.abs(u0).max())
+    warm = s.iterate(20, record=True)
+    s.set_init()
+    cold = s.iterate(20, record=True)
+    fstar = float(np.min(ref.obj))
+    log(f"warm start from the limit: gap after 20 {abs(warm[-1] - fstar) / fstar:.2e}, cold {abs(cold[-1] - fstar) / fstar:.2e}")
+    assert abs(warm[-1] - fstar) <= 1e-3 * fstar
+    assert cold[-1] - fstar > 100 * abs(warm[-1] - fstar)
+    s.close()
+
+
+def test_invalid_arguments_are_rejected():
+    par = ct_params(64, 90)
+    for geom in ((48, 10, 50), (64, 0, 50), (64, 10, 1), (2048, 4, 8)):
+        with pytest.raises(ncs.NcsError) as e:
+            ncs.Solver(ncs.Geometry(*geom), ncs.Params(par.alpha, par.beta, par.gamma, 0.01))
+        assert e.value.status == ncs.NCS_ERR_INVALID_ARG
+    with pytest.raises(ncs.NcsError) as e:
+        ncs.Solver(ncs.Geometry(64, 90, 92), ncs.Params(-1.0, 1.0, 1.0, 0.01))
+    assert e.value.status == ncs.NCS_ERR_INVALID_ARG
+    s = ncs.Solver(ncs.Geometry(64, 90, 92), ncs.Params(par.alpha, par.beta, par.gamma, 0.01))
+    with pytest.raises(ncs.NcsError) as e:
+        s.iterate(1)                       # operator-only handle: no data
+    assert e.value.status == ncs.NCS_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        s.forward(torch.zeros(10, device=DEV))
+    with pytest.raises(ncs.NcsError):
+        s.set_state(b"not a state")
+    s.close()
+
+
+def test_nan_data_reports_nonfinite():
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    b = prob.b.copy()
+    b[100] = np.nan
+    p = ncs.Params(par.alpha, par.beta, par.gamma, prob.lam)
+    s = ncs.Solver(ncs.Geometry(64, 90, 92), p, b=torch.tensor(b, dtype=torch.float32, device=DEV))
+    s.set_init()
+    with pytest.raises(ncs.NcsError) as e:
+        s.solve(100)
+    assert e.value.status == ncs.NCS_ERR_NONFINITE
+    assert s.iteration() == 1        # stopped on the device after the first NaN objective
+    s.close()
+
+
+def test_a3_violation_is_reported_as_divergence():
+    # gamma = 0 leaves M far from dominating alpha A^T A (A3 fails by ~950 alpha
+    # at this size); the iterates blow up and the driver says so.
+    prob = ct_problem("c1")
+    par = problems.Params(0.01, 0.03, 0.0)
+    s = make_solver(prob, par, torch.float32, check_every=20, diverge_checks=3)
+    s.set_init()
+    with pytest.raises(ncs.NcsError) as e:
+        s.solve(5000)
+    assert e.value.status in (ncs.NCS_ERR_DIVERGED, ncs.NCS_ERR_NONFINITE)
+    s.close()
