@@ -92,6 +92,10 @@ typedef struct {
     int32_t check_every;    /* ncs_solve: iterations between host checks; <= 0 selects 50 */
     int32_t diverge_checks; /* ncs_solve: stop with NCS_ERR_DIVERGED after this many
                                consecutive checks with a growing objective; <= 0 disables */
+    int32_t projector; /* forward-projector kernel: 0 = time both at setup and keep the
+                          faster, 1 = LDS-staged image tiles, 2 = direct coalesced loads */
+    int32_t graph_chunk; /* iterations per replayed HIP graph; 0 selects 25, < 0 disables
+                            graphs (every kernel launched directly) */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;
@@ -167,6 +171,9 @@ typedef struct {
     double c_r;        /* C_R in use */
     double mu_dc;      /* DC eigenvalue of M in use */
     double norm_e1_sq; /* |E 1|^2 */
+    int32_t projector; /* forward-projector kernel in use (1 or 2) */
+    int32_t pad;
+    double projector_ms[2]; /* setup timing of the two variants (0 when not timed) */
 } ncs_info;
 
 ncs_status ncs_get_info(ncs_handle* h, ncs_info* info);

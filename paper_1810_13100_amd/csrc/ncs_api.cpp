@@ -57,6 +57,9 @@ struct ncs_handle {
     // device workspace (library-owned)
     void* x = nullptr;
     void* xbar = nullptr;
+    void* xbarT = nullptr;
+    void* xsc = nullptr;
+    void* xscT = nullptr;
     void* u = nullptr;
     void* pj = nullptr;
     void* v = nullptr;
@@ -78,6 +81,11 @@ struct ncs_handle {
     std::vector<double> mu;    // eigenvalues of M, N x N, numpy FFT order
     double c_r = 0.0, mu_dc = 0.0, norm_e1_sq = 0.0;
     int64_t nnz = 0;
+    int projector = 2;
+    double projector_ms[2] = {0.0, 0.0};
+    int graph_chunk = 25;                 // <= 0: no graphs
+    hipStream_t cap_stream = nullptr;     // private stream used only for graph capture
+    hipGraphExec_t graph_exec = nullptr;  // graph_chunk iterations
     int iter_host = 0;         // iteration count as last seen by the host
     std::vector<void*> allocs;
 };
@@ -92,10 +100,15 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
     c.NA = h->g.n_angles;
     c.NS = h->g.n_bins;
     c.PU = h->PU;
+    c.P = h->g.n_side + 4;
+    c.projector = h->projector;
     c.ang = static_cast<const AngleT<T>*>(h->ang);
     c.axis = h->axis;
     c.x = static_cast<T*>(h->x);
     c.xbar = static_cast<T*>(h->xbar);
+    c.xbarT = static_cast<T*>(h->xbarT);
+    c.xsc = static_cast<T*>(h->xsc);
+    c.xscT = static_cast<T*>(h->xscT);
     c.u = static_cast<T*>(h->u);
     c.p = static_cast<T*>(h->pj);
     c.v = static_cast<T*>(h->v);
@@ -188,9 +201,8 @@ ncs_status upload_typed(ncs_handle* h, void* dst, const std::vector<double>& src
 
 // ---- iteration launch -----------------------------------------------------
 template <class T>
-hipError_t launch_iterations(ncs_handle* h, int k) {
+hipError_t launch_iterations(ncs_handle* h, int k, hipStream_t st) {
     const DevCtx<T> c = make_ctx<T>(h);
-    hipStream_t st = h->stream;
     for (int i = 0; i < k; ++i) {
         hipError_t e;
         if ((e = launch_backproject_iter<T>(c, st)) != hipSuccess) return e;
@@ -219,8 +231,80 @@ hipError_t launch_phase(ncs_handle* h, int ph) {
     }
 }
 
+hipError_t launch_eager(ncs_handle* h, int k, hipStream_t st) {
+    return h->dtype == NCS_F64 ? launch_iterations<double>(h, k, st) : launch_iterations<float>(h, k, st);
+}
+
+// Capture graph_chunk iterations once (on a private stream) and keep the
+// executable graph; replays then cost one launch per chunk.  Any capture
+// failure switches the handle to direct launches.
+hipError_t ensure_graph(ncs_handle* h) {
+    if (h->graph_exec || h->graph_chunk <= 0) return hipSuccess;
+    hipError_t e;
+    if (!h->cap_stream && (e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        h->graph_chunk = 0;
+        return hipSuccess;
+    }
+    if ((e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        h->graph_chunk = 0;
+        return hipSuccess;
+    }
+    hipError_t le = launch_eager(h, h->graph_chunk, h->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(h->cap_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess || !graph) {
+        if (graph) hipGraphDestroy(graph);
+        hipGetLastError();
+        h->graph_chunk = 0;
+        return hipSuccess;
+    }
+    e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->graph_exec = nullptr;
+        hipGetLastError();
+        h->graph_chunk = 0;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_iters(ncs_handle* h, int k) {
-    return h->dtype == NCS_F64 ? launch_iterations<double>(h, k) : launch_iterations<float>(h, k);
+    if (h->graph_chunk > 0 && k >= h->graph_chunk) {
+        hipError_t e = ensure_graph(h);
+        if (e != hipSuccess) return e;
+        while (h->graph_exec && k >= h->graph_chunk) {
+            if ((e = hipGraphLaunch(h->graph_exec, h->stream)) != hipSuccess) return e;
+            k -= h->graph_chunk;
+        }
+    }
+    return k > 0 ? launch_eager(h, k, h->stream) : hipSuccess;
+}
+
+// Forward-projector selection: time both variants on this geometry (plain
+// projections of the zero scratch image) and keep the faster.
+template <class T>
+ncs_status autotune_projector(ncs_handle* h) {
+    hipEvent_t e0, e1;
+    NCS_HIP(hipEventCreate(&e0));
+    NCS_HIP(hipEventCreate(&e1));
+    T* out = static_cast<T*>(h->ysc);
+    const int reps = 5;
+    for (int variant = 1; variant <= 2; ++variant) {
+        h->projector = variant;
+        const DevCtx<T> c = make_ctx<T>(h);
+        NCS_HIP(launch_project_plain<T>(c, out, h->stream));   // warm-up
+        NCS_HIP(hipEventRecord(e0, h->stream));
+        for (int r = 0; r < reps; ++r) NCS_HIP(launch_project_plain<T>(c, out, h->stream));
+        NCS_HIP(hipEventRecord(e1, h->stream));
+        NCS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        NCS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        h->projector_ms[variant - 1] = ms / reps;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    h->projector = h->projector_ms[0] < h->projector_ms[1] ? 1 : 2;
+    return NCS_OK;
 }
 
 ncs_status read_control(ncs_handle* h, Control* out) {
@@ -286,6 +370,13 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
     h->g = g;
     h->p = p;
     if (h->p.check_every <= 0) h->p.check_every = 50;
+    if (p.projector < 0 || p.projector > 2) {
+        set_err("ncs_setup: projector must be 0 (auto), 1 (LDS) or 2 (direct)");
+        delete h;
+        return NCS_ERR_INVALID_ARG;
+    }
+    h->graph_chunk = p.graph_chunk == 0 ? 25 : (p.graph_chunk < 0 ? 0 : p.graph_chunk);
+    h->projector = p.projector == 0 ? 2 : p.projector;
     h->dtype = dtype;
     h->esz = dtype == NCS_F64 ? 8 : 4;
     h->stream = static_cast<hipStream_t>(stream);
@@ -376,7 +467,10 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
     ncs_status s;
     const size_t nparts = std::max<size_t>({(size_t)project_blocks(NA, NS), (h->m + 255) / 256, (size_t)1});
     if ((s = dev_alloc(h, &h->x, h->n * e)) ||
-        (s = dev_alloc(h, &h->xbar, h->n * e)) ||
+        (s = dev_alloc(h, &h->xbar, (size_t)N * (N + 4) * e)) ||
+        (s = dev_alloc(h, &h->xbarT, (size_t)N * (N + 4) * e)) ||
+        (s = dev_alloc(h, &h->xsc, (size_t)N * (N + 4) * e)) ||
+        (s = dev_alloc(h, &h->xscT, (size_t)N * (N + 4) * e)) ||
         (s = dev_alloc(h, &h->u, h->mp * e)) ||
         (s = dev_alloc(h, &h->pj, h->mp * e)) ||
         (s = dev_alloc(h, &h->v, 2 * h->n * e)) ||
@@ -402,7 +496,11 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
     Control c0{};
     c0.f_target = std::nan("");
     if (hipMemcpy(h->ctl, &c0, sizeof(Control), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(h->x, 0, h->n * e) != hipSuccess || hipMemset(h->xbar, 0, h->n * e) != hipSuccess ||
+        hipMemset(h->x, 0, h->n * e) != hipSuccess ||
+        hipMemset(h->xbar, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
+        hipMemset(h->xbarT, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
+        hipMemset(h->xsc, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
+        hipMemset(h->xscT, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
         hipMemset(h->u, 0, h->mp * e) != hipSuccess || hipMemset(h->pj, 0, h->mp * e) != hipSuccess ||
         hipMemset(h->v, 0, 2 * h->n * e) != hipSuccess || hipMemset(h->ysc, 0, h->mp * e) != hipSuccess ||
         hipMemset(h->hist, 0, (size_t)kHistCap * sizeof(double)) != hipSuccess) {
@@ -421,6 +519,10 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
         set_err("ncs_setup: stream synchronisation failed");
         return fail(NCS_ERR_HIP);
     }
+    if (p.projector == 0) {
+        s = dtype == NCS_F64 ? autotune_projector<double>(h) : autotune_projector<float>(h);
+        if (s) return fail(s);
+    }
     *out = h;
     return NCS_OK;
 }
@@ -429,6 +531,8 @@ void ncs_destroy(ncs_handle* h) {
     if (!h) return;
     hipSetDevice(h->device);
     if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     for (void* ptr : h->allocs) hipFree(ptr);
     delete h;
 }
@@ -446,8 +550,15 @@ ncs_status ncs_set_init(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0)
     NCS_HIP(hipMemsetAsync(h->v, 0, 2 * h->n * e, h->stream));
     if (x0_dev) {
         NCS_HIP(hipMemcpyAsync(h->x, x0_dev, h->n * e, hipMemcpyDeviceToDevice, h->stream));
-        NCS_HIP(h->dtype == NCS_F64 ? launch_project_setp<double>(make_ctx<double>(h), (const double*)h->x, h->stream)
-                                    : launch_project_setp<float>(make_ctx<float>(h), (const float*)h->x, h->stream));
+        if (h->dtype == NCS_F64) {
+            const DevCtx<double> c = make_ctx<double>(h);
+            NCS_HIP(launch_pad_image<double>(c, c.x, h->stream));
+            NCS_HIP(launch_project_setp<double>(c, h->stream));
+        } else {
+            const DevCtx<float> c = make_ctx<float>(h);
+            NCS_HIP(launch_pad_image<float>(c, c.x, h->stream));
+            NCS_HIP(launch_project_setp<float>(c, h->stream));
+        }
         if (dual_from_x0)
             NCS_HIP(h->dtype == NCS_F64 ? launch_dual_init<double>(make_ctx<double>(h), h->stream)
                                         : launch_dual_init<float>(make_ctx<float>(h), h->stream));
@@ -680,9 +791,15 @@ ncs_status ncs_forward(ncs_handle* h, const void* x_dev, void* y_dev) {
         set_err("ncs_forward: null pointer");
         return NCS_ERR_INVALID_ARG;
     }
-    NCS_HIP(h->dtype == NCS_F64
-                ? launch_project_plain<double>(make_ctx<double>(h), (const double*)x_dev, (double*)y_dev, h->stream)
-                : launch_project_plain<float>(make_ctx<float>(h), (const float*)x_dev, (float*)y_dev, h->stream));
+    if (h->dtype == NCS_F64) {
+        const DevCtx<double> c = make_ctx<double>(h);
+        NCS_HIP(launch_pad_image<double>(c, (const double*)x_dev, h->stream));
+        NCS_HIP(launch_project_plain<double>(c, (double*)y_dev, h->stream));
+    } else {
+        const DevCtx<float> c = make_ctx<float>(h);
+        NCS_HIP(launch_pad_image<float>(c, (const float*)x_dev, h->stream));
+        NCS_HIP(launch_project_plain<float>(c, (float*)y_dev, h->stream));
+    }
     return NCS_OK;
 }
 
@@ -795,6 +912,10 @@ ncs_status ncs_get_info(ncs_handle* h, ncs_info* info) {
     info->c_r = h->c_r;
     info->mu_dc = h->mu_dc;
     info->norm_e1_sq = h->norm_e1_sq;
+    info->projector = h->projector;
+    info->pad = 0;
+    info->projector_ms[0] = h->projector_ms[0];
+    info->projector_ms[1] = h->projector_ms[1];
     return NCS_OK;
 }
 

@@ -45,10 +45,15 @@ enum { TV_ANISO = 0, TV_ISO = 1 };
 template <class T>
 struct DevCtx {
     int N, log2N, NA, NS, PU;        // PU: padded sinogram pitch = NS + 3 (entry d at a*PU + 1 + d)
+    int P;                           // padded image pitch = N + 4 (pixel c of a row at offset c + 2)
+    int projector;                   // 1: LDS-staged tiles, 2: direct coalesced loads
     const AngleT<T>* ang;
     const int32_t* axis;
     T* x;        // N*N current image
-    T* xbar;     // N*N extrapolated image 2x+ - x
+    T* xbar;     // N*P padded extrapolated image 2x+ - x (two zero columns each side)
+    T* xbarT;    // N*P padded transpose of xbar (row c holds column c)
+    T* xsc;      // N*P padded scratch image (plain projections)
+    T* xscT;     // N*P padded scratch transpose
     T* u;        // NA*PU padded data dual
     T* p;        // NA*PU padded projection E x (kept by recurrence)
     T* v;        // 2*N*N TV dual (horizontal plane, vertical plane)
@@ -78,10 +83,13 @@ template <class T> hipError_t launch_fft_rows_inv_update(const DevCtx<T>& c, hip
 template <class T> hipError_t launch_fft_rows_inv_plain(const DevCtx<T>& c, T* out, hipStream_t st);
 template <class T> hipError_t launch_tv_update(const DevCtx<T>& c, hipStream_t st);
 template <class T> hipError_t launch_project_iter(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_project_plain(const DevCtx<T>& c, const T* img, T* out, hipStream_t st);
-template <class T> hipError_t launch_project_setp(const DevCtx<T>& c, const T* img, hipStream_t st);
+template <class T> hipError_t launch_pad_image(const DevCtx<T>& c, const T* img, hipStream_t st);
+// Plain projections read the padded scratch pair (xsc, xscT): call
+// launch_pad_image first.
+template <class T> hipError_t launch_project_plain(const DevCtx<T>& c, T* out, hipStream_t st);
+template <class T> hipError_t launch_project_setp(const DevCtx<T>& c, hipStream_t st);
 template <class T> hipError_t launch_finalize_iter(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_eval_objective(const DevCtx<T>& c, const T* img, hipStream_t st);
+template <class T> hipError_t launch_eval_objective(const DevCtx<T>& c, const T* img, hipStream_t st);   // pads img itself
 template <class T> hipError_t launch_pad_sinogram(const DevCtx<T>& c, const T* y, T* y_padded, hipStream_t st);
 template <class T> hipError_t launch_unpad_sinogram(const DevCtx<T>& c, const T* y_padded, T* y, hipStream_t st);
 template <class T> hipError_t launch_data_const(const DevCtx<T>& c, hipStream_t st);

@@ -5,10 +5,13 @@
 //   k_backproject  w  = alpha E^T u + beta D^T v            (pixel-driven gather)
 //   k_fft_rows_fwd    row DFTs of w, two real rows per complex transform
 //   k_fft_cols        column DFT, multiply by h/(alpha N^2), inverse column DFT
-//   k_fft_rows_inv    inverse row DFTs; x+ = x - Delta, xbar = 2x+ - x
+//   k_fft_rows_inv    inverse row DFTs; x+ = x - Delta, xbar = 2x+ - x (padded
+//                     row-major copy and padded transposed copy)
 //   k_tv              v+ = Pi(v + beta D xbar), TV of x+ (double partial sums)
-//   k_project         q = E xbar (ray-driven, LDS-staged); u+ = prox(u + ...),
-//                     p+ = (q + p)/2 = E x+, data term of x+ (double partials)
+//   k_project_direct  q = E xbar (ray-driven, coalesced loads from the copy
+//   / k_project_lds   whose rows run along the sampled axis, or LDS-staged
+//                     tiles); u+ = prox(u + ...), p+ = (q + p)/2 = E x+, data
+//                     term of x+ (double partials)
 //   k_finalize        f(x+) = data + lambda TV, history, device stop flag
 //
 // Every iteration kernel returns at once when the device stop flag is set, so a
@@ -45,6 +48,23 @@ __device__ inline double block_sum256(double v, double* sh) {
 
 __device__ inline int bitrev(int i, int logn) {
     return (int)(__brev((unsigned)i) >> (32 - logn));
+}
+
+// Two consecutive elements read with one load (element alignment only).
+template <class T>
+struct alignas(sizeof(T)) Pair {
+    T a, b;
+};
+
+template <class T>
+__device__ inline Pair<T> load_pair(const T* p) {
+    return *reinterpret_cast<const Pair<T>*>(p);
+}
+
+// float -> int with saturation (finite bounds for the loop-range arithmetic)
+template <class T>
+__device__ inline int sat_int(T v) {
+    return (int)fmin(fmax(v, T(-1.0e9)), T(1.0e9));
 }
 
 // Radix-2 decimation-in-time transform in LDS: input in bit-reversed order,
@@ -122,6 +142,7 @@ __global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __res
     const T tmax = (T)c.NS;
     const int PU = c.PU;
     T acc = T(0);
+#pragma unroll 4
     for (int a = wave; a < c.NA; a += kWaves) {
         const AngleT<T> A = c.ang[a];
         T t = fma(fc, A.q1, fma(fr, A.q2, A.q0));
@@ -129,12 +150,11 @@ __global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __res
         const T fl = floor(t);
         const T f = t - fl;
         const int d0 = (int)fl;
-        const T* yr = ysrc + (size_t)a * PU + 1 + d0;
-        const T y0 = yr[0], y1 = yr[1];
+        const Pair<T> y = load_pair(ysrc + (size_t)a * PU + 1 + d0);
         const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
         const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
-        acc = fma(w0, y0, acc);
-        acc = fma(w1, y1, acc);
+        acc = fma(w0, y.a, acc);
+        acc = fma(w1, y.b, acc);
     }
     red[wave * 64 + lane] = acc;
     __syncthreads();
@@ -165,72 +185,10 @@ __global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __res
 // ---------------------------------------------------------------------------
 enum { PMODE_PLAIN = 0, PMODE_SETP = 1, PMODE_ITER = 2 };
 
+// Epilogue shared by both projector variants: q is the ray sum of lane's ray.
 template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_project(DevCtx<T> c, const T* __restrict__ img,
-                                                 T* __restrict__ out) {
-    if (MODE == PMODE_ITER && c.ctl->stop) return;
-    __shared__ T tile[kSeg * kPitch];
-    __shared__ T red[kWaves * kRays];
-    const int N = c.N, NS = c.NS;
-    const int nb = (NS + kRays - 1) / kRays;
-    const int a = blockIdx.x / nb;
-    const int d0 = (blockIdx.x - a * nb) * kRays;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const AngleT<T> A = c.ang[a];
-    const int axis = c.axis[a];
-    const int d = d0 + lane;
-    const T base = fma((T)d, A.k1, A.k0);
-    const T bA = fma((T)d0, A.k1, A.k0);
-    const T bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
-    const int SL = N < kSeg ? N : kSeg;
-    const int SW = SL / kWaves;
-    T acc = T(0);
-    for (int s0 = 0; s0 < N; s0 += SL) {
-        const T sA = (T)s0, sB = (T)(s0 + SL - 1);
-        const T e0 = fma(sA, A.k2, bA), e1 = fma(sB, A.k2, bA);
-        const T e2 = fma(sA, A.k2, bB), e3 = fma(sB, A.k2, bB);
-        const T mn = fmin(fmin(e0, e1), fmin(e2, e3));
-        const T mx = fmax(fmax(e0, e1), fmax(e2, e3));
-        const int lo = (int)floor(mn) - 1;
-        const int hi = (int)floor(mx) + 2;
-        if (hi < 0 || lo > N - 1) continue;   // the whole ray block misses the image here
-        int W = hi - lo + 1;
-        W = W > kPitch ? kPitch : W;
-        __syncthreads();
-        if (axis == 0) {
-            for (int sl = wave; sl < SL; sl += kWaves) {
-                const T* rowp = img + (size_t)(s0 + sl) * N;
-                for (int j = lane; j < W; j += 64) {
-                    const int cc = lo + j;
-                    tile[sl * kPitch + j] = (cc >= 0 && cc < N) ? rowp[cc] : T(0);
-                }
-            }
-        } else {
-            for (int j = wave; j < W; j += kWaves) {
-                const int rr = lo + j;
-                const bool ok = rr >= 0 && rr < N;
-                const T* rowp = img + (size_t)(ok ? rr : 0) * N + s0;
-                for (int sl = lane; sl < SL; sl += 64) tile[sl * kPitch + j] = ok ? rowp[sl] : T(0);
-            }
-        }
-        __syncthreads();
-        const int sb = wave * SW;
-        for (int sl = sb; sl < sb + SW; ++sl) {
-            const T xi = fma((T)(s0 + sl), A.k2, base);
-            const T fl = floor(xi);
-            const T f = xi - fl;
-            int j = (int)fl - lo;
-            j = min(max(j, 0), W - 2);
-            const T* tp = tile + sl * kPitch + j;
-            const T v0 = tp[0], v1 = tp[1];
-            acc += fma(f, v1 - v0, v0);
-        }
-    }
-    red[wave * kRays + lane] = acc;
-    __syncthreads();
-    if (wave != 0) return;
-    const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
+__device__ inline void project_epilogue(const DevCtx<T>& c, int a, int d, int lane, T q, T* __restrict__ out) {
+    const int NS = c.NS;
     const bool valid = d < NS;
     if (MODE == PMODE_PLAIN) {
         if (valid) out[(size_t)a * NS + d] = q;
@@ -271,6 +229,129 @@ __global__ __launch_bounds__(256) void k_project(DevCtx<T> c, const T* __restric
     }
     dterm = wave_sum(dterm);
     if (lane == 0) c.part_data[blockIdx.x] = dterm;
+}
+
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void k_project_lds(DevCtx<T> c, const T* __restrict__ img,
+                                                     const T* __restrict__ imgT, T* __restrict__ out) {
+    (void)imgT;
+    if (MODE == PMODE_ITER && c.ctl->stop) return;
+    __shared__ T tile[kSeg * kPitch];
+    __shared__ T red[kWaves * kRays];
+    const int N = c.N, NS = c.NS;
+    const int nb = (NS + kRays - 1) / kRays;
+    const int a = blockIdx.x / nb;
+    const int d0 = (blockIdx.x - a * nb) * kRays;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const AngleT<T> A = c.ang[a];
+    const int axis = c.axis[a];
+    const int d = d0 + lane;
+    const T base = fma((T)d, A.k1, A.k0);
+    const T bA = fma((T)d0, A.k1, A.k0);
+    const T bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
+    const int SL = N < kSeg ? N : kSeg;
+    const int SW = SL / kWaves;
+    T acc = T(0);
+    for (int s0 = 0; s0 < N; s0 += SL) {
+        const T sA = (T)s0, sB = (T)(s0 + SL - 1);
+        const T e0 = fma(sA, A.k2, bA), e1 = fma(sB, A.k2, bA);
+        const T e2 = fma(sA, A.k2, bB), e3 = fma(sB, A.k2, bB);
+        const T mn = fmin(fmin(e0, e1), fmin(e2, e3));
+        const T mx = fmax(fmax(e0, e1), fmax(e2, e3));
+        const int lo = (int)floor(mn) - 1;
+        const int hi = (int)floor(mx) + 2;
+        if (hi < 0 || lo > N - 1) continue;   // the whole ray block misses the image here
+        int W = hi - lo + 1;
+        W = W > kPitch ? kPitch : W;
+        __syncthreads();
+        if (axis == 0) {
+            for (int sl = wave; sl < SL; sl += kWaves) {
+                const T* rowp = img + (size_t)(s0 + sl) * c.P + 2;
+                for (int j = lane; j < W; j += 64) {
+                    const int cc = lo + j;
+                    tile[sl * kPitch + j] = (cc >= 0 && cc < N) ? rowp[cc] : T(0);
+                }
+            }
+        } else {
+            for (int j = wave; j < W; j += kWaves) {
+                const int rr = lo + j;
+                const bool ok = rr >= 0 && rr < N;
+                const T* rowp = img + (size_t)(ok ? rr : 0) * c.P + 2 + s0;
+                for (int sl = lane; sl < SL; sl += 64) tile[sl * kPitch + j] = ok ? rowp[sl] : T(0);
+            }
+        }
+        __syncthreads();
+        const int sb = wave * SW;
+        for (int sl = sb; sl < sb + SW; ++sl) {
+            const T xi = fma((T)(s0 + sl), A.k2, base);
+            const T fl = floor(xi);
+            const T f = xi - fl;
+            int j = (int)fl - lo;
+            j = min(max(j, 0), W - 2);
+            const T* tp = tile + sl * kPitch + j;
+            const T v0 = tp[0], v1 = tp[1];
+            acc += fma(f, v1 - v0, v0);
+        }
+    }
+    red[wave * kRays + lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
+    project_epilogue<T, MODE>(c, a, d, lane, q, out);
+}
+
+// Direct variant: one lane per ray, the 4 waves split the steps.  Column-
+// stepping angles read the transposed copy so that every angle walks along
+// contiguous rows; two zero columns on each side of a row absorb taps that
+// fall off the image, so the clamped tap index needs no per-step test.
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void k_project_direct(DevCtx<T> c, const T* __restrict__ img,
+                                                        const T* __restrict__ imgT, T* __restrict__ out) {
+    if (MODE == PMODE_ITER && c.ctl->stop) return;
+    __shared__ T red[kWaves * kRays];
+    const int N = c.N, NS = c.NS, P = c.P;
+    const int nb = (NS + kRays - 1) / kRays;
+    const int a = blockIdx.x / nb;
+    const int d0 = (blockIdx.x - a * nb) * kRays;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const AngleT<T> A = c.ang[a];
+    const T* src = c.axis[a] == 0 ? img : imgT;
+    const int d = d0 + lane;
+    const T base = fma((T)d, A.k1, A.k0);
+    // Steps where some ray of the block has xi in [-2, N+1] (all rays of an
+    // angle share the slope k2 in s, so the block's xi at step s spans
+    // [blo, bhi] + s k2); the margin keeps the range conservative.
+    const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
+    const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
+    const T lo_x = T(-2), hi_x = T(N + 1);
+    const int SW = N / kWaves;
+    int s_begin = wave * SW, s_end = s_begin + SW;
+    if (A.k2 > T(0)) {
+        s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
+    } else if (A.k2 < T(0)) {
+        s_begin = max(s_begin, sat_int(floor((hi_x - blo) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
+    } else if (bhi < lo_x || blo > hi_x) {
+        s_end = s_begin;
+    }
+    T acc = T(0);
+#pragma unroll 4
+    for (int s = s_begin; s < s_end; ++s) {
+        const T xi = fma((T)s, A.k2, base);
+        const T fl = floor(xi);
+        const T f = xi - fl;
+        const int cc = min(max((int)fl, -2), N);
+        const Pair<T> v = load_pair(src + (size_t)s * P + cc + 2);
+        acc += fma(f, v.b - v.a, v.a);
+    }
+    red[wave * kRays + lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
+    project_epilogue<T, MODE>(c, a, d, lane, q, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,8 +448,10 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(DevCtx<T> c, T* __restrict
         const T na = xa - da, nb = xb - db;
         c.x[ra + n] = na;
         c.x[rb + n] = nb;
-        c.xbar[ra + n] = fma(T(2), na, -xa);
-        c.xbar[rb + n] = fma(T(2), nb, -xb);
+        const T ba = fma(T(2), na, -xa), bb = fma(T(2), nb, -xb);
+        c.xbar[(size_t)(2 * pr) * c.P + n + 2] = ba;
+        c.xbar[(size_t)(2 * pr + 1) * c.P + n + 2] = bb;
+        *reinterpret_cast<Pair<T>*>(c.xbarT + (size_t)n * c.P + 2 * pr + 2) = Pair<T>{ba, bb};
     }
 }
 
@@ -387,9 +470,10 @@ __global__ __launch_bounds__(256) void k_tv(DevCtx<T> c) {
         const int r = (int)(pix >> c.log2N);
         const int col = (int)(pix & (size_t)(N - 1));
         const bool hx = col < N - 1, hy = r < N - 1;
-        const T xb = c.xbar[pix];
-        const T dh = hx ? xb - c.xbar[pix + 1] : T(0);
-        const T dv = hy ? xb - c.xbar[pix + N] : T(0);
+        const T* xbp = c.xbar + (size_t)r * c.P + col + 2;
+        const T xb = xbp[0];
+        const T dh = hx ? xb - xbp[1] : T(0);
+        const T dv = hy ? xb - xbp[c.P] : T(0);
         T* vh = c.v;
         T* vv = c.v + NN;
         const T gh = fma(c.beta, dh, vh[pix]);
@@ -524,6 +608,19 @@ __global__ __launch_bounds__(256) void k_unpad(DevCtx<T> c, const T* __restrict_
     y[i] = yp[(size_t)a * c.PU + 1 + d];
 }
 
+// Write an image into the padded scratch pair (row-major and transposed).
+template <class T>
+__global__ __launch_bounds__(256) void k_pad_image(DevCtx<T> c, const T* __restrict__ img) {
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t NN = (size_t)c.N * c.N;
+    if (pix >= NN) return;
+    const int r = (int)(pix >> c.log2N);
+    const int col = (int)(pix & (size_t)(c.N - 1));
+    const T v = img[pix];
+    c.xsc[(size_t)r * c.P + col + 2] = v;
+    c.xscT[(size_t)col * c.P + r + 2] = v;
+}
+
 // Dual initialisation from x0 (fixed-point relations of the optimality
 // conditions): u = grad g_data(E x0) from p = E x0; v from D x0.
 template <class T>
@@ -649,24 +746,35 @@ hipError_t launch_tv_update(const DevCtx<T>& c, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <class T, int MODE>
+hipError_t launch_project(const DevCtx<T>& c, const T* img, const T* imgT, T* out, hipStream_t st) {
+    const dim3 grid(project_blocks(c.NA, c.NS)), block(256);
+    if (c.projector == 1)
+        hipLaunchKernelGGL((k_project_lds<T, MODE>), grid, block, 0, st, c, img, imgT, out);
+    else
+        hipLaunchKernelGGL((k_project_direct<T, MODE>), grid, block, 0, st, c, img, imgT, out);
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_project_iter(const DevCtx<T>& c, hipStream_t st) {
-    hipLaunchKernelGGL((k_project<T, PMODE_ITER>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c,
-                       (const T*)c.xbar, (T*)nullptr);
+    return launch_project<T, PMODE_ITER>(c, c.xbar, c.xbarT, (T*)nullptr, st);
+}
+
+template <class T>
+hipError_t launch_pad_image(const DevCtx<T>& c, const T* img, hipStream_t st) {
+    hipLaunchKernelGGL((k_pad_image<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c, img);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_project_plain(const DevCtx<T>& c, const T* img, T* out, hipStream_t st) {
-    hipLaunchKernelGGL((k_project<T, PMODE_PLAIN>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c, img, out);
-    return hipGetLastError();
+hipError_t launch_project_plain(const DevCtx<T>& c, T* out, hipStream_t st) {
+    return launch_project<T, PMODE_PLAIN>(c, c.xsc, c.xscT, out, st);
 }
 
 template <class T>
-hipError_t launch_project_setp(const DevCtx<T>& c, const T* img, hipStream_t st) {
-    hipLaunchKernelGGL((k_project<T, PMODE_SETP>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c, img,
-                       (T*)nullptr);
-    return hipGetLastError();
+hipError_t launch_project_setp(const DevCtx<T>& c, hipStream_t st) {
+    return launch_project<T, PMODE_SETP>(c, c.xsc, c.xscT, (T*)nullptr, st);
 }
 
 template <class T>
@@ -680,7 +788,9 @@ hipError_t launch_finalize_iter(const DevCtx<T>& c, hipStream_t st) {
 template <class T>
 hipError_t launch_eval_objective(const DevCtx<T>& c, const T* img, hipStream_t st) {
     const size_t m = (size_t)c.NA * c.NS;
-    hipLaunchKernelGGL((k_project<T, PMODE_PLAIN>), dim3(project_blocks(c.NA, c.NS)), dim3(256), 0, st, c, img, c.ysc);
+    hipError_t e;
+    if ((e = launch_pad_image<T>(c, img, st)) != hipSuccess) return e;
+    if ((e = launch_project<T, PMODE_PLAIN>(c, c.xsc, c.xscT, c.ysc, st)) != hipSuccess) return e;
     const unsigned nd = blocks_for(m);
     hipLaunchKernelGGL((k_data_eval<T>), dim3(nd), dim3(256), 0, st, c, (const T*)c.ysc);
     hipLaunchKernelGGL((k_tv_eval<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c, img);
@@ -724,8 +834,9 @@ hipError_t launch_dual_init(const DevCtx<T>& c, hipStream_t st) {
     template hipError_t launch_fft_rows_inv_plain<T>(const DevCtx<T>&, T*, hipStream_t);         \
     template hipError_t launch_tv_update<T>(const DevCtx<T>&, hipStream_t);                      \
     template hipError_t launch_project_iter<T>(const DevCtx<T>&, hipStream_t);                   \
-    template hipError_t launch_project_plain<T>(const DevCtx<T>&, const T*, T*, hipStream_t);    \
-    template hipError_t launch_project_setp<T>(const DevCtx<T>&, const T*, hipStream_t);         \
+    template hipError_t launch_project_plain<T>(const DevCtx<T>&, T*, hipStream_t);              \
+    template hipError_t launch_project_setp<T>(const DevCtx<T>&, hipStream_t);                   \
+    template hipError_t launch_pad_image<T>(const DevCtx<T>&, const T*, hipStream_t);            \
     template hipError_t launch_finalize_iter<T>(const DevCtx<T>&, hipStream_t);                  \
     template hipError_t launch_eval_objective<T>(const DevCtx<T>&, const T*, hipStream_t);       \
     template hipError_t launch_pad_sinogram<T>(const DevCtx<T>&, const T*, T*, hipStream_t);     \

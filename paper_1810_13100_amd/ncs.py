@@ -66,12 +66,14 @@ class _Params(ctypes.Structure):
         ("lambda_", ctypes.c_double), ("c_r", ctypes.c_double), ("mu_dc", ctypes.c_double),
         ("data_term", ctypes.c_int32), ("tv_term", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("diverge_checks", ctypes.c_int32),
+        ("projector", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
     ]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("nnz", ctypes.c_int64), ("c_r", ctypes.c_double), ("mu_dc", ctypes.c_double),
-                ("norm_e1_sq", ctypes.c_double)]
+                ("norm_e1_sq", ctypes.c_double), ("projector", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("projector_ms", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -151,6 +153,8 @@ class Params:
     tv_term: int = TV_ANISO
     check_every: int = 50
     diverge_checks: int = 0
+    projector: int = 0        # 0: autotune at setup, 1: LDS-staged, 2: direct
+    graph_chunk: int = 0      # 0: 25 iterations per HIP graph, < 0: no graphs
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -175,7 +179,8 @@ class Solver:
         self._bg = self._sino(bg, "bg") if bg is not None else None
         g = _Geometry(geom.n_side, geom.n_angles, geom.n_bins)
         p = _Params(params.alpha, params.beta, params.gamma, params.lam, params.c_r, params.mu_dc,
-                    params.data_term, params.tv_term, params.check_every, params.diverge_checks)
+                    params.data_term, params.tv_term, params.check_every, params.diverge_checks,
+                    params.projector, params.graph_chunk)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.ncs_setup(ctypes.byref(g), ctypes.byref(p),
@@ -285,7 +290,8 @@ class Solver:
     def info(self) -> dict:
         inf = _Info()
         _check(self.lib.ncs_get_info(self.h, ctypes.byref(inf)))
-        return {"nnz": inf.nnz, "c_r": inf.c_r, "mu_dc": inf.mu_dc, "norm_e1_sq": inf.norm_e1_sq}
+        return {"nnz": inf.nnz, "c_r": inf.c_r, "mu_dc": inf.mu_dc, "norm_e1_sq": inf.norm_e1_sq,
+                "projector": inf.projector, "projector_ms": list(inf.projector_ms)}
 
     def eigenvalues(self) -> np.ndarray:
         mu = np.empty(self.geom.n, dtype=np.float64)

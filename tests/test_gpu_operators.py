@@ -22,12 +22,13 @@ DEV = torch.device("cuda", 0)
 DT = {"f32": torch.float32, "f64": torch.float64}
 
 
-def _solver(geom, dtype, b=None, par=None, data=ncs.DATA_QUADRATIC, tv=ncs.TV_ANISO, lam=0.01, bg=None):
+def _solver(geom, dtype, b=None, par=None, data=ncs.DATA_QUADRATIC, tv=ncs.TV_ANISO, lam=0.01, bg=None,
+            projector=0):
     n, na, ns = geom
     if par is None:
         par = ct_params(n, na)
     p = ncs.Params(par.alpha, par.beta, par.gamma, lam, data_term=data, tv_term=tv,
-                   c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0)
+                   c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0, projector=projector)
     tb = None if b is None else torch.tensor(b, dtype=dtype, device=DEV)
     tbg = None if bg is None else torch.tensor(bg, dtype=dtype, device=DEV)
     return ncs.Solver(ncs.Geometry(n, na, ns), p, b=tb, bg=tbg, dtype=dtype)
@@ -40,11 +41,14 @@ def _phantom(n, seed=0):
 
 @pytest.mark.parametrize("key", ["tiny", "c1", "c4s", "c3", "c4m", "c2"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_forward_matches_oracle(key, prec):
+@pytest.mark.parametrize("projector", [1, 2])
+def test_forward_matches_oracle(key, prec, projector):
+    # both forward-projector kernels (1: LDS-staged tiles, 2: direct loads)
     geom = GEOMS[key]
-    log(f"forward parity {key} {geom} {prec}")
+    log(f"forward parity {key} {geom} {prec} projector {projector}")
     E = joseph(*geom)
-    s = _solver(geom, DT[prec])
+    s = _solver(geom, DT[prec], projector=projector)
+    assert s.info()["projector"] == projector
     for img, tol32 in ((_phantom(geom[0]), 1e-5), (np.random.default_rng(1).standard_normal(E.shape[1]), 1e-4)):
         ref = E @ img
         out = s.forward(torch.tensor(img, dtype=DT[prec], device=DEV)).double().cpu().numpy()
@@ -72,14 +76,15 @@ def test_adjoint_matches_oracle(key, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_large_slice_sampled_angles(prec):
+@pytest.mark.parametrize("proj", [1, 2])
+def test_large_slice_sampled_angles(prec, proj):
     # 512^2 with 717 x 520 (largest slice of the uneven batch): whole rows of E
     # for sampled angles, including 0, the 45-degree ties and pi/2.
     n, na, ns = 512, 717, 520
     angles = [0, 1, 179, 180, 181, 358, 359, 537, 538, 716]
-    log(f"sampled-angle parity 512 {prec}")
+    log(f"sampled-angle parity 512 {prec} projector {proj}")
     E = projector.joseph_matrix(n, na, ns, angles=angles)
-    s = _solver((n, na, ns), DT[prec])
+    s = _solver((n, na, ns), DT[prec], projector=proj)
     img = _phantom(n, 5)
     out = s.forward(torch.tensor(img, dtype=DT[prec], device=DEV)).double().cpu().numpy()
     ref = E @ img
@@ -174,4 +179,14 @@ def test_nonzero_count_matches_oracle(key):
     s = _solver(geom, torch.float32)
     ours, ref = s.info()["nnz"], joseph(*geom).nnz
     assert abs(ours - ref) <= 5e-3 * ref, (ours, ref)
+    s.close()
+
+
+def test_autotuner_times_both_projectors():
+    s = _solver(GEOMS["c2"], torch.float32)
+    inf = s.info()
+    log(f"projector autotune: LDS {inf['projector_ms'][0]:.4f} ms, direct {inf['projector_ms'][1]:.4f} ms "
+        f"-> {inf['projector']}")
+    assert all(t > 0 for t in inf["projector_ms"])
+    assert inf["projector"] == (1 if inf["projector_ms"][0] < inf["projector_ms"][1] else 2)
     s.close()
