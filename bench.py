@@ -136,7 +136,7 @@ def main() -> int:
     dominant = max(phases, key=phases.get)
     flops = 2.0 * info["nnz"]          # one multiply-add per nonzero of E
     dom_ms = phases[dominant]
-    if dominant in ("project_dataprox", "backproject"):
+    if dominant in ("project_dataprox_tv", "backproject"):
         achieved = flops / (dom_ms * 1e-3) / 1e12
         roof = {"kernel": dominant, "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,

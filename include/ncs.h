@@ -181,10 +181,10 @@ ncs_status ncs_get_info(ncs_handle* h, ncs_info* info);
 /* Per-kernel timing: run `iters` >= 1 iterations (they advance the state like
  * ncs_iterate) with a HIP event before and after every kernel on the handle's
  * stream, and return in ms_host[0..NCS_N_PHASES-1] the mean duration per
- * iteration of each phase, in the order backprojection, row DFT, column
- * DFT + multiplier, inverse row DFT + x-update, TV update, projection + data
- * prox, objective reduction.  Synchronises. */
-#define NCS_N_PHASES 7
+ * iteration of each phase, in the order backprojection (with D^T v), row DFT,
+ * column DFT + multiplier, inverse row DFT + x-update, projection + data prox
+ * + TV update, objective reduction.  Synchronises. */
+#define NCS_N_PHASES 6
 ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host);
 
 /* The eigenvalues mu of M actually used (N*N doubles, numpy FFT order,
@@ -192,6 +192,41 @@ ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host);
 ncs_status ncs_get_eigenvalues(ncs_handle* h, double* mu_host);
 
 void ncs_destroy(ncs_handle* h);
+
+/* ---- Batches: many independent slices of uneven size in shared launches ----
+ *
+ * Every phase of an iteration is one launch over the workgroups of all active
+ * slices (a workgroup -> slice map; slices are pinned to XCDs so that a
+ * slice's workgroups share one L2).  Each slice keeps its own geometry,
+ * parameters, data, state, objective history and device stop flag; the host
+ * checks every params[0].check_every iterations and drops stopped slices
+ * from the maps.  Not captured in HIP graphs (the launches are large). */
+typedef struct ncs_batch ncs_batch;
+
+/* geoms, params, b_dev: arrays of n_slices (b_dev entries non-NULL); bg_dev:
+ * NULL or an array of n_slices (entries may be NULL).  The projector is
+ * params[0].projector, or (0) the faster variant on the largest slice. */
+ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const ncs_params* params,
+                           int32_t dtype, const void* const* b_dev, const void* const* bg_dev,
+                           void* stream, ncs_batch** out);
+
+/* ncs_set_init for every slice (x0_dev NULL or an array of n_slices
+ * pointers, entries may be NULL). */
+ncs_status ncs_batch_set_init(ncs_batch* b, const void* const* x0_dev, int32_t dual_from_x0);
+
+/* Iterate every slice until its objective reaches f_target[i] (NULL or NaN:
+ * none), at most max_iters iterations.  iters_done and f_final (NULL or
+ * arrays of n_slices) receive per-slice results.  Returns NCS_OK when every
+ * slice reached its target, NCS_NOT_CONVERGED otherwise, NCS_ERR_NONFINITE
+ * if a slice produced a NaN objective. */
+ncs_status ncs_batch_solve(ncs_batch* b, int32_t max_iters, const double* f_target,
+                           int32_t* iters_done, double* f_final);
+
+/* Borrow the handle of slice i (owned by the batch; valid until
+ * ncs_batch_destroy) for ncs_get_x, ncs_get_objectives, ncs_forward, ... */
+ncs_status ncs_batch_slice(ncs_batch* b, int32_t i, ncs_handle** slice);
+
+void ncs_batch_destroy(ncs_batch* b);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* ncs_last_error(void);

@@ -1,7 +1,8 @@
 // Host side of the NCS C ABI: argument checking, double-precision setup of the
 // per-angle table, the Fourier multiplier and the twiddles, workspace
 // ownership, and the iteration driver (direct launches or a replayed HIP
-// graph of a chunk of iterations, with the stopping test on the device).
+// graph of a chunk of iterations, with the stopping test on the device), for
+// one slice or for a batch of uneven slices sharing every launch.
 #include "ncs.h"
 #include "ncs_internal.h"
 
@@ -10,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -28,17 +30,18 @@ void set_err(const char* fmt, ...) {
     g_err = buf;
 }
 
-#define NCS_HIP(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess) {                                                        \
-            set_err("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
-            return NCS_ERR_HIP;                                                        \
-        }                                                                              \
+#define NCS_HIP(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            set_err("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__);     \
+            return NCS_ERR_HIP;                                                                     \
+        }                                                                                           \
     } while (0)
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr uint64_t kStateMagic = 0x3130303331303831ull;  // blob tag
+constexpr int kXcds = 8;                                 // XCDs of an MI355X (round-robin dispatch)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -72,22 +75,42 @@ struct ncs_handle {
     void* ysc = nullptr;
     double* part_data = nullptr;
     double* part_tv = nullptr;
-    Control* ctl = nullptr;
+    Control* ctl = nullptr;     // owned, or an element of a batch's control array
     double* hist = nullptr;
+    void* dctx = nullptr;       // device copy of this slice's DevCtx<T>
 
-    const void* b = nullptr;   // caller-owned
-    const void* bg = nullptr;  // caller-owned
+    const void* b = nullptr;    // caller-owned
+    const void* bg = nullptr;   // caller-owned
 
-    std::vector<double> mu;    // eigenvalues of M, N x N, numpy FFT order
+    std::vector<double> tab;    // per-angle table (double)
+    std::vector<double> mu;     // eigenvalues of M, N x N, numpy FFT order
     double c_r = 0.0, mu_dc = 0.0, norm_e1_sq = 0.0;
-    int64_t nnz = 0;
+    int64_t nnz = -1;           // counted on request
     int projector = 2;
     double projector_ms[2] = {0.0, 0.0};
     int graph_chunk = 25;                 // <= 0: no graphs
     hipStream_t cap_stream = nullptr;     // private stream used only for graph capture
     hipGraphExec_t graph_exec = nullptr;  // graph_chunk iterations
-    int iter_host = 0;         // iteration count as last seen by the host
+    int iter_host = 0;                    // iteration count as last seen by the host
     std::vector<void*> allocs;
+};
+
+struct ncs_batch {
+    int n = 0;
+    int dtype = NCS_F32;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<ncs_handle*> slices;
+    Control* ctls = nullptr;      // device array, one per slice
+    void* dctxs = nullptr;        // device array of DevCtx<T>
+    Slot* maps[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // bp, rows, cols, proj, fin
+    size_t map_cap[5] = {0, 0, 0, 0, 0};
+    int blocks[5] = {0, 0, 0, 0, 0};
+    std::vector<int> xcd_of;      // slice -> XCD it is pinned to
+    std::vector<char> active;
+    int max_N = 0;
+    int projector = 2;
+    int check_every = 50;
 };
 
 namespace {
@@ -101,7 +124,8 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
     c.NS = h->g.n_bins;
     c.PU = h->PU;
     c.P = h->g.n_side + 4;
-    c.projector = h->projector;
+    c.nb_proj = project_blocks(c.NA, c.NS);
+    c.nb_tv = tv_blocks(c.N);
     c.ang = static_cast<const AngleT<T>*>(h->ang);
     c.axis = h->axis;
     c.x = static_cast<T*>(h->x);
@@ -133,6 +157,26 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
     return c;
 }
 
+template <class T>
+const DevCtx<T>* dctx(const ncs_handle* h) {
+    return static_cast<const DevCtx<T>*>(h->dctx);
+}
+
+template <class T>
+IterLaunch<T> single_launch(const ncs_handle* h) {
+    IterLaunch<T> L{};
+    const int N = h->g.n_side;
+    L.ctxs = dctx<T>(h);
+    L.bp = {nullptr, bp_blocks(N)};
+    L.rows = {nullptr, N / 2};
+    L.cols = {nullptr, N / 2 + 1};
+    L.proj = {nullptr, project_blocks(h->g.n_angles, h->g.n_bins) + tv_blocks(N)};
+    L.fin = {nullptr, 1};
+    L.max_N = N;
+    L.projector = h->projector;
+    return L;
+}
+
 ncs_status dev_alloc(ncs_handle* h, void** ptr, size_t bytes) {
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(ptr, bytes);
@@ -145,135 +189,106 @@ ncs_status dev_alloc(ncs_handle* h, void** ptr, size_t bytes) {
     return NCS_OK;
 }
 
-// |E 1|^2 and nnz(E) in double on the host, from the same geometry as the
-// kernels: for each ray and step, the taps floor(xi) and floor(xi) + 1 with
-// their weights 1 - f and f, kept when inside [0, N-1] and nonzero.
-void e1_stats(const ncs_geometry& g, const std::vector<double>& tab, double* norm_sq, int64_t* nnz) {
+// nnz(E) in double on the host from the same geometry as the kernels: for
+// each ray and step, the taps floor(xi) and floor(xi) + 1 with weights 1 - f
+// and f, kept when inside [0, N-1] and nonzero.
+int64_t count_nnz(const ncs_geometry& g, const std::vector<double>& tab) {
     const int N = g.n_side;
-    double total = 0.0;
     int64_t taps = 0;
     for (int a = 0; a < g.n_angles; ++a) {
         const double* t = &tab[10 * (size_t)a];
-        const double k1 = t[0], k2 = t[1], k0 = t[2], kap = t[6];
+        const double k1 = t[0], k2 = t[1], k0 = t[2];
         for (int d = 0; d < g.n_bins; ++d) {
             const double base = d * k1 + k0;
-            double s = 0.0;
             for (int st = 0; st < N; ++st) {
                 const double xi = st * k2 + base;
                 if (xi <= -1.0 || xi >= (double)N) continue;
                 const double fl = std::floor(xi);
                 const double f = xi - fl;
                 const int c0 = (int)fl;
-                if (c0 >= 0 && f != 1.0) {
-                    s += 1.0 - f;
-                    ++taps;
-                }
-                if (c0 + 1 <= N - 1 && f != 0.0) {
-                    s += f;
-                    ++taps;
-                }
+                if (c0 >= 0) ++taps;
+                if (c0 + 1 <= N - 1 && f != 0.0) ++taps;
             }
-            const double e = kap * s;
-            total += e * e;
         }
     }
-    *norm_sq = total;
-    *nnz = taps;
+    return taps;
 }
 
 template <class T>
-void convert(const std::vector<double>& src, std::vector<T>& dst) {
-    dst.resize(src.size());
-    for (size_t i = 0; i < src.size(); ++i) dst[i] = (T)src[i];
-}
-
-template <class T>
-ncs_status upload(ncs_handle* h, void* dst, const std::vector<double>& src) {
-    std::vector<T> tmp;
-    convert(src, tmp);
+ncs_status upload(void* dst, const std::vector<double>& src) {
+    std::vector<T> tmp(src.size());
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
     NCS_HIP(hipMemcpy(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
     return NCS_OK;
 }
 
-ncs_status upload_typed(ncs_handle* h, void* dst, const std::vector<double>& src) {
-    return h->dtype == NCS_F64 ? upload<double>(h, dst, src) : upload<float>(h, dst, src);
+ncs_status upload_typed(const ncs_handle* h, void* dst, const std::vector<double>& src) {
+    return h->dtype == NCS_F64 ? upload<double>(dst, src) : upload<float>(dst, src);
+}
+
+template <class T>
+ncs_status upload_ctx(ncs_handle* h) {
+    const DevCtx<T> c = make_ctx<T>(h);
+    NCS_HIP(hipMemcpy(h->dctx, &c, sizeof(c), hipMemcpyHostToDevice));
+    return NCS_OK;
+}
+
+ncs_status upload_ctx_typed(ncs_handle* h) {
+    return h->dtype == NCS_F64 ? upload_ctx<double>(h) : upload_ctx<float>(h);
 }
 
 // ---- iteration launch -----------------------------------------------------
-template <class T>
-hipError_t launch_iterations(ncs_handle* h, int k, hipStream_t st) {
-    const DevCtx<T> c = make_ctx<T>(h);
+hipError_t launch_eager(ncs_handle* h, int k, hipStream_t st) {
     for (int i = 0; i < k; ++i) {
-        hipError_t e;
-        if ((e = launch_backproject_iter<T>(c, st)) != hipSuccess) return e;
-        if ((e = launch_fft_rows_fwd<T>(c, c.w, true, st)) != hipSuccess) return e;
-        if ((e = launch_fft_cols<T>(c, T(1), true, st)) != hipSuccess) return e;
-        if ((e = launch_fft_rows_inv_update<T>(c, st)) != hipSuccess) return e;
-        if ((e = launch_tv_update<T>(c, st)) != hipSuccess) return e;
-        if ((e = launch_project_iter<T>(c, st)) != hipSuccess) return e;
-        if ((e = launch_finalize_iter<T>(c, st)) != hipSuccess) return e;
+        const hipError_t e = h->dtype == NCS_F64 ? launch_iteration<double>(single_launch<double>(h), st)
+                                                 : launch_iteration<float>(single_launch<float>(h), st);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-template <class T>
 hipError_t launch_phase(ncs_handle* h, int ph) {
-    const DevCtx<T> c = make_ctx<T>(h);
-    hipStream_t st = h->stream;
-    switch (ph) {
-        case 0: return launch_backproject_iter<T>(c, st);
-        case 1: return launch_fft_rows_fwd<T>(c, c.w, true, st);
-        case 2: return launch_fft_cols<T>(c, T(1), true, st);
-        case 3: return launch_fft_rows_inv_update<T>(c, st);
-        case 4: return launch_tv_update<T>(c, st);
-        case 5: return launch_project_iter<T>(c, st);
-        default: return launch_finalize_iter<T>(c, st);
-    }
-}
-
-hipError_t launch_eager(ncs_handle* h, int k, hipStream_t st) {
-    return h->dtype == NCS_F64 ? launch_iterations<double>(h, k, st) : launch_iterations<float>(h, k, st);
+    return h->dtype == NCS_F64 ? launch_iteration_phase<double>(single_launch<double>(h), ph, h->stream)
+                               : launch_iteration_phase<float>(single_launch<float>(h), ph, h->stream);
 }
 
 // Capture graph_chunk iterations once (on a private stream) and keep the
 // executable graph; replays then cost one launch per chunk.  Any capture
 // failure switches the handle to direct launches.
-hipError_t ensure_graph(ncs_handle* h) {
-    if (h->graph_exec || h->graph_chunk <= 0) return hipSuccess;
-    hipError_t e;
-    if (!h->cap_stream && (e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+void ensure_graph(ncs_handle* h) {
+    if (h->graph_exec || h->graph_chunk <= 0) return;
+    if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         h->graph_chunk = 0;
-        return hipSuccess;
+        return;
     }
-    if ((e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         h->graph_chunk = 0;
-        return hipSuccess;
+        return;
     }
-    hipError_t le = launch_eager(h, h->graph_chunk, h->cap_stream);
+    const hipError_t le = launch_eager(h, h->graph_chunk, h->cap_stream);
     hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(h->cap_stream, &graph);
-    if (le != hipSuccess || e != hipSuccess || !graph) {
-        if (graph) hipGraphDestroy(graph);
-        hipGetLastError();
+    const hipError_t ee = hipStreamEndCapture(h->cap_stream, &graph);
+    if (le != hipSuccess || ee != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
         h->graph_chunk = 0;
-        return hipSuccess;
+        return;
     }
-    e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (e != hipSuccess) {
+    const hipError_t ie = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
         h->graph_exec = nullptr;
-        hipGetLastError();
+        (void)hipGetLastError();
         h->graph_chunk = 0;
     }
-    return hipSuccess;
 }
 
 hipError_t launch_iters(ncs_handle* h, int k) {
     if (h->graph_chunk > 0 && k >= h->graph_chunk) {
-        hipError_t e = ensure_graph(h);
-        if (e != hipSuccess) return e;
+        ensure_graph(h);
         while (h->graph_exec && k >= h->graph_chunk) {
-            if ((e = hipGraphLaunch(h->graph_exec, h->stream)) != hipSuccess) return e;
+            const hipError_t e = hipGraphLaunch(h->graph_exec, h->stream);
+            if (e != hipSuccess) return e;
             k -= h->graph_chunk;
         }
     }
@@ -281,28 +296,27 @@ hipError_t launch_iters(ncs_handle* h, int k) {
 }
 
 // Forward-projector selection: time both variants on this geometry (plain
-// projections of the zero scratch image) and keep the faster.
+// projections of the scratch image) and keep the faster.
 template <class T>
 ncs_status autotune_projector(ncs_handle* h) {
     hipEvent_t e0, e1;
     NCS_HIP(hipEventCreate(&e0));
     NCS_HIP(hipEventCreate(&e1));
+    const DevCtx<T> c = make_ctx<T>(h);
     T* out = static_cast<T*>(h->ysc);
     const int reps = 5;
     for (int variant = 1; variant <= 2; ++variant) {
-        h->projector = variant;
-        const DevCtx<T> c = make_ctx<T>(h);
-        NCS_HIP(launch_project_plain<T>(c, out, h->stream));   // warm-up
+        NCS_HIP(launch_project_plain<T>(c, dctx<T>(h), variant, out, h->stream));   // warm-up
         NCS_HIP(hipEventRecord(e0, h->stream));
-        for (int r = 0; r < reps; ++r) NCS_HIP(launch_project_plain<T>(c, out, h->stream));
+        for (int r = 0; r < reps; ++r) NCS_HIP(launch_project_plain<T>(c, dctx<T>(h), variant, out, h->stream));
         NCS_HIP(hipEventRecord(e1, h->stream));
         NCS_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         NCS_HIP(hipEventElapsedTime(&ms, e0, e1));
         h->projector_ms[variant - 1] = ms / reps;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     h->projector = h->projector_ms[0] < h->projector_ms[1] ? 1 : 2;
     return NCS_OK;
 }
@@ -323,63 +337,54 @@ ncs_status check_handle(ncs_handle* h) {
     return NCS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* ncs_last_error(void) { return g_err.c_str(); }
-
-ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t dtype,
-                     const void* b_dev, const void* bg_dev, void* stream, ncs_handle** out) {
-    g_err.clear();
-    if (!geom || !params || !out) {
-        set_err("ncs_setup: null geometry, params or out pointer");
-        return NCS_ERR_INVALID_ARG;
-    }
-    *out = nullptr;
-    const ncs_geometry g = *geom;
-    const ncs_params p = *params;
+ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
     if (!is_pow2(g.n_side) || g.n_side < 16 || g.n_side > 1024) {
-        set_err("ncs_setup: n_side must be a power of two in [16, 1024] (got %d)", g.n_side);
+        set_err("n_side must be a power of two in [16, 1024] (got %d)", g.n_side);
         return NCS_ERR_INVALID_ARG;
     }
     if (g.n_angles < 1 || g.n_angles > (1 << 20) || g.n_bins < 2 || g.n_bins > (1 << 20)) {
-        set_err("ncs_setup: need 1 <= n_angles and 2 <= n_bins (got %d, %d)", g.n_angles, g.n_bins);
+        set_err("need 1 <= n_angles and 2 <= n_bins (got %d, %d)", g.n_angles, g.n_bins);
         return NCS_ERR_INVALID_ARG;
     }
     if (dtype != NCS_F32 && dtype != NCS_F64) {
-        set_err("ncs_setup: dtype must be NCS_F32 or NCS_F64");
+        set_err("dtype must be NCS_F32 or NCS_F64");
         return NCS_ERR_INVALID_ARG;
     }
     if (!(p.alpha > 0.0) || !(p.beta > 0.0) || !(p.gamma >= 0.0) || !(p.lambda >= 0.0) ||
         !std::isfinite(p.alpha) || !std::isfinite(p.beta) || !std::isfinite(p.gamma) ||
         !std::isfinite(p.lambda) || !std::isfinite(p.c_r) || !std::isfinite(p.mu_dc)) {
-        set_err("ncs_setup: need finite alpha > 0, beta > 0, gamma >= 0, lambda >= 0");
+        set_err("need finite alpha > 0, beta > 0, gamma >= 0, lambda >= 0");
         return NCS_ERR_INVALID_ARG;
     }
     if (p.data_term != NCS_DATA_QUADRATIC && p.data_term != NCS_DATA_POISSON) {
-        set_err("ncs_setup: unknown data_term %d", p.data_term);
+        set_err("unknown data_term %d", p.data_term);
         return NCS_ERR_INVALID_ARG;
     }
     if (p.tv_term != NCS_TV_ANISO && p.tv_term != NCS_TV_ISO) {
-        set_err("ncs_setup: unknown tv_term %d", p.tv_term);
+        set_err("unknown tv_term %d", p.tv_term);
         return NCS_ERR_INVALID_ARG;
     }
+    if (p.projector < 0 || p.projector > 2) {
+        set_err("projector must be 0 (auto), 1 (LDS) or 2 (direct)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    return NCS_OK;
+}
 
+// One slice: tables, workspace, multiplier.  ext_ctl (nullable) is a control
+// block owned by a batch; autotune = time the projector variants.
+ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype, const void* b_dev,
+                       const void* bg_dev, hipStream_t stream, Control* ext_ctl, bool autotune,
+                       ncs_handle** out) {
     ncs_handle* h = new ncs_handle();
     h->g = g;
     h->p = p;
     if (h->p.check_every <= 0) h->p.check_every = 50;
-    if (p.projector < 0 || p.projector > 2) {
-        set_err("ncs_setup: projector must be 0 (auto), 1 (LDS) or 2 (direct)");
-        delete h;
-        return NCS_ERR_INVALID_ARG;
-    }
     h->graph_chunk = p.graph_chunk == 0 ? 25 : (p.graph_chunk < 0 ? 0 : p.graph_chunk);
     h->projector = p.projector == 0 ? 2 : p.projector;
     h->dtype = dtype;
     h->esz = dtype == NCS_F64 ? 8 : 4;
-    h->stream = static_cast<hipStream_t>(stream);
+    h->stream = stream;
     h->b = b_dev;
     h->bg = bg_dev;
     const int N = g.n_side;
@@ -388,7 +393,6 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
     h->n = (size_t)N * N;
     h->m = (size_t)g.n_angles * g.n_bins;
     h->mp = (size_t)g.n_angles * h->PU;
-
     auto fail = [&](ncs_status s) {
         ncs_destroy(h);
         return s;
@@ -401,7 +405,7 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
 
     // ---- per-angle table (double) --------------------------------------
     const int NA = g.n_angles, NS = g.n_bins;
-    std::vector<double> tab(10 * (size_t)NA);
+    h->tab.assign(10 * (size_t)NA, 0.0);
     std::vector<int> axis(NA);
     const double hn = 0.5 * (N - 1), hs = 0.5 * (NS - 1);
     for (int a = 0; a < NA; ++a) {
@@ -409,7 +413,7 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
         const double ct = std::cos(th), st = std::sin(th);
         const bool rows = (4 * (long long)a <= NA) || (4 * (long long)a >= 3 * (long long)NA);
         axis[a] = rows ? 0 : 1;
-        double* t = &tab[10 * (size_t)a];
+        double* t = &h->tab[10 * (size_t)a];
         if (rows) {   // xi = column of ray d on row r
             t[0] = 1.0 / ct;
             t[1] = -st / ct;
@@ -429,10 +433,68 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
         t[9] = 0.0;
     }
 
-    // ---- multiplier (Section 4.1.1: eq. circ_R, eq. circ_D, DC entry) -----
+    // ---- workspace ---------------------------------------------------------
+    const size_t e = h->esz;
+    const int NH = N / 2 + 1;
+    const size_t padded = (size_t)N * (N + 4) * e;
+    const size_t nparts = std::max<size_t>({(size_t)project_blocks(NA, NS), (h->m + 255) / 256, (size_t)1});
+    const size_t ctx_bytes = dtype == NCS_F64 ? sizeof(DevCtx<double>) : sizeof(DevCtx<float>);
+    ncs_status s;
+    if ((s = dev_alloc(h, &h->x, h->n * e)) || (s = dev_alloc(h, &h->xbar, padded)) ||
+        (s = dev_alloc(h, &h->xbarT, padded)) || (s = dev_alloc(h, &h->xsc, padded)) ||
+        (s = dev_alloc(h, &h->xscT, padded)) || (s = dev_alloc(h, &h->u, h->mp * e)) ||
+        (s = dev_alloc(h, &h->pj, h->mp * e)) || (s = dev_alloc(h, &h->v, 2 * h->n * e)) ||
+        (s = dev_alloc(h, &h->w, h->n * e)) || (s = dev_alloc(h, &h->spec, 2 * (size_t)NH * N * e)) ||
+        (s = dev_alloc(h, &h->hh, (size_t)NH * N * e)) || (s = dev_alloc(h, &h->tw, (size_t)N * e)) ||
+        (s = dev_alloc(h, &h->ang, 10 * (size_t)NA * e)) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->axis), (size_t)NA * sizeof(int32_t))) ||
+        (s = dev_alloc(h, &h->ysc, h->mp * e)) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->part_data), nparts * sizeof(double))) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->part_tv), (size_t)tv_blocks(N) * sizeof(double))) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->hist), (size_t)kHistCap * sizeof(double))) ||
+        (s = dev_alloc(h, &h->dctx, ctx_bytes)))
+        return fail(s);
+    if (ext_ctl) {
+        h->ctl = ext_ctl;
+    } else if ((s = dev_alloc(h, reinterpret_cast<void**>(&h->ctl), sizeof(Control)))) {
+        return fail(s);
+    }
+    if ((s = upload_typed(h, h->ang, h->tab))) return fail(s);
+    Control c0{};
+    c0.f_target = std::nan("");
+    if (hipMemcpy(h->axis, axis.data(), NA * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ctl, &c0, sizeof(Control), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->x, 0, h->n * e) != hipSuccess || hipMemset(h->xbar, 0, padded) != hipSuccess ||
+        hipMemset(h->xbarT, 0, padded) != hipSuccess || hipMemset(h->xsc, 0, padded) != hipSuccess ||
+        hipMemset(h->xscT, 0, padded) != hipSuccess || hipMemset(h->u, 0, h->mp * e) != hipSuccess ||
+        hipMemset(h->pj, 0, h->mp * e) != hipSuccess || hipMemset(h->v, 0, 2 * h->n * e) != hipSuccess ||
+        hipMemset(h->ysc, 0, h->mp * e) != hipSuccess ||
+        hipMemset(h->hist, 0, (size_t)kHistCap * sizeof(double)) != hipSuccess) {
+        set_err("ncs_setup: workspace initialisation failed");
+        return fail(NCS_ERR_HIP);
+    }
+    if ((s = upload_ctx_typed(h))) return fail(s);
+
+    // ---- |E 1|^2 on the device (this handle's own projector and precision) --
     h->c_r = p.c_r > 0.0 ? p.c_r : (double)NA * N / kPi;
-    e1_stats(g, tab, &h->norm_e1_sq, &h->nnz);
-    h->mu_dc = p.mu_dc > 0.0 ? p.mu_dc : p.gamma + p.alpha * h->norm_e1_sq / (double)h->n;
+    if (p.mu_dc > 0.0) {
+        h->mu_dc = p.mu_dc;
+    } else {
+        const hipError_t le =
+            dtype == NCS_F64 ? launch_e1_norm<double>(make_ctx<double>(h), dctx<double>(h), h->projector, stream)
+                             : launch_e1_norm<float>(make_ctx<float>(h), dctx<float>(h), h->projector, stream);
+        Control cc;
+        if (le != hipSuccess ||
+            hipMemcpyAsync(&cc, h->ctl, sizeof(Control), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            set_err("ncs_setup: |E 1|^2 evaluation failed");
+            return fail(NCS_ERR_HIP);
+        }
+        h->norm_e1_sq = cc.eval_out;
+        h->mu_dc = p.gamma + p.alpha * h->norm_e1_sq / (double)h->n;
+    }
+
+    // ---- multiplier (Section 4.1.1: eq. circ_R, eq. circ_D, DC entry) -----
     h->mu.assign(h->n, 0.0);
     const double bta = p.beta * p.beta / p.alpha;
     for (int j = 0; j < N; ++j) {
@@ -448,7 +510,6 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
         }
     }
     h->mu[0] = h->mu_dc;
-    const int NH = N / 2 + 1;
     std::vector<double> hh((size_t)NH * N);
     const double scale = 1.0 / (p.alpha * (double)N * (double)N);
     for (int k = 0; k < NH; ++k)
@@ -461,65 +522,21 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
         tw[2 * k] = std::cos(2.0 * kPi * k / N);
         tw[2 * k + 1] = -std::sin(2.0 * kPi * k / N);
     }
+    if ((s = upload_typed(h, h->hh, hh)) || (s = upload_typed(h, h->tw, tw))) return fail(s);
 
-    // ---- workspace ---------------------------------------------------------
-    const size_t e = h->esz;
-    ncs_status s;
-    const size_t nparts = std::max<size_t>({(size_t)project_blocks(NA, NS), (h->m + 255) / 256, (size_t)1});
-    if ((s = dev_alloc(h, &h->x, h->n * e)) ||
-        (s = dev_alloc(h, &h->xbar, (size_t)N * (N + 4) * e)) ||
-        (s = dev_alloc(h, &h->xbarT, (size_t)N * (N + 4) * e)) ||
-        (s = dev_alloc(h, &h->xsc, (size_t)N * (N + 4) * e)) ||
-        (s = dev_alloc(h, &h->xscT, (size_t)N * (N + 4) * e)) ||
-        (s = dev_alloc(h, &h->u, h->mp * e)) ||
-        (s = dev_alloc(h, &h->pj, h->mp * e)) ||
-        (s = dev_alloc(h, &h->v, 2 * h->n * e)) ||
-        (s = dev_alloc(h, &h->w, h->n * e)) ||
-        (s = dev_alloc(h, &h->spec, 2 * (size_t)NH * N * e)) ||
-        (s = dev_alloc(h, &h->hh, (size_t)NH * N * e)) ||
-        (s = dev_alloc(h, &h->tw, (size_t)N * e)) ||
-        (s = dev_alloc(h, &h->ang, 10 * (size_t)NA * e)) ||
-        (s = dev_alloc(h, reinterpret_cast<void**>(&h->axis), (size_t)NA * sizeof(int32_t))) ||
-        (s = dev_alloc(h, &h->ysc, h->mp * e)) ||
-        (s = dev_alloc(h, reinterpret_cast<void**>(&h->part_data), nparts * sizeof(double))) ||
-        (s = dev_alloc(h, reinterpret_cast<void**>(&h->part_tv), (size_t)tv_blocks(N) * sizeof(double))) ||
-        (s = dev_alloc(h, reinterpret_cast<void**>(&h->ctl), sizeof(Control))) ||
-        (s = dev_alloc(h, reinterpret_cast<void**>(&h->hist), (size_t)kHistCap * sizeof(double))))
-        return fail(s);
-
-    if ((s = upload_typed(h, h->hh, hh)) || (s = upload_typed(h, h->tw, tw)) || (s = upload_typed(h, h->ang, tab)))
-        return fail(s);
-    if (hipMemcpy(h->axis, axis.data(), NA * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-        set_err("ncs_setup: axis upload failed");
-        return fail(NCS_ERR_HIP);
-    }
-    Control c0{};
-    c0.f_target = std::nan("");
-    if (hipMemcpy(h->ctl, &c0, sizeof(Control), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(h->x, 0, h->n * e) != hipSuccess ||
-        hipMemset(h->xbar, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
-        hipMemset(h->xbarT, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
-        hipMemset(h->xsc, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
-        hipMemset(h->xscT, 0, (size_t)N * (N + 4) * e) != hipSuccess ||
-        hipMemset(h->u, 0, h->mp * e) != hipSuccess || hipMemset(h->pj, 0, h->mp * e) != hipSuccess ||
-        hipMemset(h->v, 0, 2 * h->n * e) != hipSuccess || hipMemset(h->ysc, 0, h->mp * e) != hipSuccess ||
-        hipMemset(h->hist, 0, (size_t)kHistCap * sizeof(double)) != hipSuccess) {
-        set_err("ncs_setup: workspace initialisation failed");
-        return fail(NCS_ERR_HIP);
-    }
     if (b_dev && p.data_term == NCS_DATA_POISSON) {
-        hipError_t le = dtype == NCS_F64 ? launch_data_const<double>(make_ctx<double>(h), h->stream)
-                                         : launch_data_const<float>(make_ctx<float>(h), h->stream);
+        const hipError_t le = dtype == NCS_F64 ? launch_data_const<double>(make_ctx<double>(h), dctx<double>(h), stream)
+                                               : launch_data_const<float>(make_ctx<float>(h), dctx<float>(h), stream);
         if (le != hipSuccess) {
             set_err("ncs_setup: data constant launch failed: %s", hipGetErrorString(le));
             return fail(NCS_ERR_HIP);
         }
     }
-    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+    if (hipStreamSynchronize(stream) != hipSuccess) {
         set_err("ncs_setup: stream synchronisation failed");
         return fail(NCS_ERR_HIP);
     }
-    if (p.projector == 0) {
+    if (autotune && p.projector == 0) {
         s = dtype == NCS_F64 ? autotune_projector<double>(h) : autotune_projector<float>(h);
         if (s) return fail(s);
     }
@@ -527,13 +544,52 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
     return NCS_OK;
 }
 
+template <class T>
+ncs_status init_state(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0) {
+    const size_t e = h->esz;
+    const DevCtx<T> c = make_ctx<T>(h);
+    NCS_HIP(hipMemsetAsync(h->u, 0, h->mp * e, h->stream));
+    NCS_HIP(hipMemsetAsync(h->pj, 0, h->mp * e, h->stream));
+    NCS_HIP(hipMemsetAsync(h->v, 0, 2 * h->n * e, h->stream));
+    if (x0_dev) {
+        NCS_HIP(hipMemcpyAsync(h->x, x0_dev, h->n * e, hipMemcpyDeviceToDevice, h->stream));
+        NCS_HIP(launch_pad_image<T>(c, dctx<T>(h), c.x, h->stream));
+        NCS_HIP(launch_project_setp<T>(c, dctx<T>(h), h->projector, h->stream));
+        if (dual_from_x0) NCS_HIP(launch_dual_init<T>(c, dctx<T>(h), h->stream));
+    } else {
+        NCS_HIP(hipMemsetAsync(h->x, 0, h->n * e, h->stream));
+    }
+    NCS_HIP(launch_control(h->ctl, 0, 0, std::nan(""), h->stream));
+    h->iter_host = 0;
+    return NCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ncs_last_error(void) { return g_err.c_str(); }
+
+ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t dtype,
+                     const void* b_dev, const void* bg_dev, void* stream, ncs_handle** out) {
+    g_err.clear();
+    if (!geom || !params || !out) {
+        set_err("ncs_setup: null geometry, params or out pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    ncs_status s = validate(*geom, *params, dtype);
+    if (s) return s;
+    return setup_slice(*geom, *params, dtype, b_dev, bg_dev, static_cast<hipStream_t>(stream), nullptr, true, out);
+}
+
 void ncs_destroy(ncs_handle* h) {
     if (!h) return;
-    hipSetDevice(h->device);
-    if (h->stream) hipStreamSynchronize(h->stream);
-    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
-    for (void* ptr : h->allocs) hipFree(ptr);
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (void* ptr : h->allocs) (void)hipFree(ptr);
     delete h;
 }
 
@@ -544,30 +600,8 @@ ncs_status ncs_set_init(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0)
         set_err("ncs_set_init: dual_from_x0 needs x0 and data b");
         return NCS_ERR_INVALID_ARG;
     }
-    const size_t e = h->esz;
-    NCS_HIP(hipMemsetAsync(h->u, 0, h->mp * e, h->stream));
-    NCS_HIP(hipMemsetAsync(h->pj, 0, h->mp * e, h->stream));
-    NCS_HIP(hipMemsetAsync(h->v, 0, 2 * h->n * e, h->stream));
-    if (x0_dev) {
-        NCS_HIP(hipMemcpyAsync(h->x, x0_dev, h->n * e, hipMemcpyDeviceToDevice, h->stream));
-        if (h->dtype == NCS_F64) {
-            const DevCtx<double> c = make_ctx<double>(h);
-            NCS_HIP(launch_pad_image<double>(c, c.x, h->stream));
-            NCS_HIP(launch_project_setp<double>(c, h->stream));
-        } else {
-            const DevCtx<float> c = make_ctx<float>(h);
-            NCS_HIP(launch_pad_image<float>(c, c.x, h->stream));
-            NCS_HIP(launch_project_setp<float>(c, h->stream));
-        }
-        if (dual_from_x0)
-            NCS_HIP(h->dtype == NCS_F64 ? launch_dual_init<double>(make_ctx<double>(h), h->stream)
-                                        : launch_dual_init<float>(make_ctx<float>(h), h->stream));
-    } else {
-        NCS_HIP(hipMemsetAsync(h->x, 0, h->n * e, h->stream));
-    }
-    NCS_HIP(launch_control(h->ctl, 0, 0, std::nan(""), h->stream));
-    h->iter_host = 0;
-    return NCS_OK;
+    return h->dtype == NCS_F64 ? init_state<double>(h, x0_dev, dual_from_x0)
+                               : init_state<float>(h, x0_dev, dual_from_x0);
 }
 
 ncs_status ncs_iterate(ncs_handle* h, int32_t k, double* obj_host) {
@@ -598,8 +632,7 @@ ncs_status ncs_iterate(ncs_handle* h, int32_t k, double* obj_host) {
     const int done = c.iter - start;
     std::vector<double> hist(kHistCap);
     NCS_HIP(hipMemcpy(hist.data(), h->hist, kHistCap * sizeof(double), hipMemcpyDeviceToHost));
-    for (int i = 0; i < k; ++i)
-        obj_host[i] = i < done ? hist[(start + i) & (kHistCap - 1)] : std::nan("");
+    for (int i = 0; i < k; ++i) obj_host[i] = i < done ? hist[(start + i) & (kHistCap - 1)] : std::nan("");
     if (c.status == -4) {
         set_err("ncs_iterate: objective became NaN at iteration %d", c.iter);
         return NCS_ERR_NONFINITE;
@@ -706,9 +739,10 @@ ncs_status ncs_get_u(ncs_handle* h, void* u_out_dev) {
         set_err("ncs_get_u: null output");
         return NCS_ERR_INVALID_ARG;
     }
-    NCS_HIP(h->dtype == NCS_F64
-                ? launch_unpad_sinogram<double>(make_ctx<double>(h), (const double*)h->u, (double*)u_out_dev, h->stream)
-                : launch_unpad_sinogram<float>(make_ctx<float>(h), (const float*)h->u, (float*)u_out_dev, h->stream));
+    NCS_HIP(h->dtype == NCS_F64 ? launch_unpad_sinogram<double>(make_ctx<double>(h), dctx<double>(h),
+                                                                (const double*)h->u, (double*)u_out_dev, h->stream)
+                                : launch_unpad_sinogram<float>(make_ctx<float>(h), dctx<float>(h),
+                                                               (const float*)h->u, (float*)u_out_dev, h->stream));
     return NCS_OK;
 }
 
@@ -793,12 +827,12 @@ ncs_status ncs_forward(ncs_handle* h, const void* x_dev, void* y_dev) {
     }
     if (h->dtype == NCS_F64) {
         const DevCtx<double> c = make_ctx<double>(h);
-        NCS_HIP(launch_pad_image<double>(c, (const double*)x_dev, h->stream));
-        NCS_HIP(launch_project_plain<double>(c, (double*)y_dev, h->stream));
+        NCS_HIP(launch_pad_image<double>(c, dctx<double>(h), (const double*)x_dev, h->stream));
+        NCS_HIP(launch_project_plain<double>(c, dctx<double>(h), h->projector, (double*)y_dev, h->stream));
     } else {
         const DevCtx<float> c = make_ctx<float>(h);
-        NCS_HIP(launch_pad_image<float>(c, (const float*)x_dev, h->stream));
-        NCS_HIP(launch_project_plain<float>(c, (float*)y_dev, h->stream));
+        NCS_HIP(launch_pad_image<float>(c, dctx<float>(h), (const float*)x_dev, h->stream));
+        NCS_HIP(launch_project_plain<float>(c, dctx<float>(h), h->projector, (float*)y_dev, h->stream));
     }
     return NCS_OK;
 }
@@ -812,12 +846,12 @@ ncs_status ncs_adjoint(ncs_handle* h, const void* y_dev, void* x_dev) {
     }
     if (h->dtype == NCS_F64) {
         const DevCtx<double> c = make_ctx<double>(h);
-        NCS_HIP(launch_pad_sinogram<double>(c, (const double*)y_dev, c.ysc, h->stream));
-        NCS_HIP(launch_backproject_plain<double>(c, c.ysc, (double*)x_dev, h->stream));
+        NCS_HIP(launch_pad_sinogram<double>(c, dctx<double>(h), (const double*)y_dev, c.ysc, h->stream));
+        NCS_HIP(launch_backproject_plain<double>(c, dctx<double>(h), c.ysc, (double*)x_dev, h->stream));
     } else {
         const DevCtx<float> c = make_ctx<float>(h);
-        NCS_HIP(launch_pad_sinogram<float>(c, (const float*)y_dev, c.ysc, h->stream));
-        NCS_HIP(launch_backproject_plain<float>(c, c.ysc, (float*)x_dev, h->stream));
+        NCS_HIP(launch_pad_sinogram<float>(c, dctx<float>(h), (const float*)y_dev, c.ysc, h->stream));
+        NCS_HIP(launch_backproject_plain<float>(c, dctx<float>(h), c.ysc, (float*)x_dev, h->stream));
     }
     return NCS_OK;
 }
@@ -829,17 +863,11 @@ ncs_status ncs_apply_minv(ncs_handle* h, const void* w_dev, void* out_dev) {
         set_err("ncs_apply_minv: null pointer");
         return NCS_ERR_INVALID_ARG;
     }
-    if (h->dtype == NCS_F64) {
-        const DevCtx<double> c = make_ctx<double>(h);
-        NCS_HIP(launch_fft_rows_fwd<double>(c, (const double*)w_dev, false, h->stream));
-        NCS_HIP(launch_fft_cols<double>(c, (double)h->p.alpha, false, h->stream));
-        NCS_HIP(launch_fft_rows_inv_plain<double>(c, (double*)out_dev, h->stream));
-    } else {
-        const DevCtx<float> c = make_ctx<float>(h);
-        NCS_HIP(launch_fft_rows_fwd<float>(c, (const float*)w_dev, false, h->stream));
-        NCS_HIP(launch_fft_cols<float>(c, (float)h->p.alpha, false, h->stream));
-        NCS_HIP(launch_fft_rows_inv_plain<float>(c, (float*)out_dev, h->stream));
-    }
+    NCS_HIP(h->dtype == NCS_F64
+                ? launch_apply_minv<double>(make_ctx<double>(h), dctx<double>(h), (const double*)w_dev,
+                                            (double*)out_dev, (double)h->p.alpha, h->stream)
+                : launch_apply_minv<float>(make_ctx<float>(h), dctx<float>(h), (const float*)w_dev,
+                                           (float*)out_dev, (float)h->p.alpha, h->stream));
     return NCS_OK;
 }
 
@@ -854,8 +882,10 @@ ncs_status ncs_objective(ncs_handle* h, const void* x_dev, double* f) {
         set_err("ncs_objective: handle has no data (b_dev was NULL)");
         return NCS_ERR_INVALID_ARG;
     }
-    NCS_HIP(h->dtype == NCS_F64 ? launch_eval_objective<double>(make_ctx<double>(h), (const double*)x_dev, h->stream)
-                                : launch_eval_objective<float>(make_ctx<float>(h), (const float*)x_dev, h->stream));
+    NCS_HIP(h->dtype == NCS_F64 ? launch_eval_objective<double>(make_ctx<double>(h), dctx<double>(h), h->projector,
+                                                                (const double*)x_dev, h->stream)
+                                : launch_eval_objective<float>(make_ctx<float>(h), dctx<float>(h), h->projector,
+                                                               (const float*)x_dev, h->stream));
     Control c;
     if ((s = read_control(h, &c))) return s;
     *f = c.eval_out;
@@ -880,9 +910,9 @@ ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host) {
     for (int i = 0; i < iters && le == hipSuccess; ++i) {
         for (int ph = 0; ph < NCS_N_PHASES && le == hipSuccess; ++ph) {
             const size_t k = 2 * ((size_t)i * NCS_N_PHASES + ph);
-            hipEventRecord(ev[k], h->stream);
-            le = h->dtype == NCS_F64 ? launch_phase<double>(h, ph) : launch_phase<float>(h, ph);
-            hipEventRecord(ev[k + 1], h->stream);
+            (void)hipEventRecord(ev[k], h->stream);
+            le = launch_phase(h, ph);
+            (void)hipEventRecord(ev[k + 1], h->stream);
         }
     }
     hipError_t se = hipStreamSynchronize(h->stream);
@@ -892,11 +922,11 @@ ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host) {
             for (int ph = 0; ph < NCS_N_PHASES; ++ph) {
                 const size_t k = 2 * ((size_t)i * NCS_N_PHASES + ph);
                 float ms = 0.f;
-                hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+                (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
                 ms_host[ph] += ms / iters;
             }
     }
-    for (auto& e : ev) hipEventDestroy(e);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     NCS_HIP(le);
     NCS_HIP(se);
     Control c;
@@ -908,6 +938,7 @@ ncs_status ncs_get_info(ncs_handle* h, ncs_info* info) {
         set_err("ncs_get_info: null pointer");
         return NCS_ERR_INVALID_ARG;
     }
+    if (h->nnz < 0) h->nnz = count_nnz(h->g, h->tab);
     info->nnz = h->nnz;
     info->c_r = h->c_r;
     info->mu_dc = h->mu_dc;
@@ -925,6 +956,269 @@ ncs_status ncs_get_eigenvalues(ncs_handle* h, double* mu_host) {
         return NCS_ERR_INVALID_ARG;
     }
     std::memcpy(mu_host, h->mu.data(), h->mu.size() * sizeof(double));
+    return NCS_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches of slices
+// ===========================================================================
+namespace {
+
+// Rebuild the workgroup maps of the active slices.  Slices are pinned to XCDs
+// (longest-processing-time assignment by projector workgroups); workgroup b
+// of a launch is dispatched to XCD b mod 8, so the map interleaves the eight
+// per-XCD lists and each slice's workgroups share one XCD's L2.
+ncs_status build_maps(ncs_batch* B) {
+    const int nphase = 5;
+    std::vector<std::vector<Slot>> lists[5];
+    for (int ph = 0; ph < nphase; ++ph) lists[ph].assign(kXcds, {});
+    for (int i = 0; i < B->n; ++i) {
+        if (!B->active[i]) continue;
+        const ncs_handle* h = B->slices[i];
+        const int N = h->g.n_side;
+        const int cnt[5] = {bp_blocks(N), N / 2, N / 2 + 1,
+                            project_blocks(h->g.n_angles, h->g.n_bins) + tv_blocks(N), 1};
+        const int x = B->xcd_of[i];
+        for (int ph = 0; ph < nphase; ++ph)
+            for (int l = 0; l < cnt[ph]; ++l) lists[ph][x].push_back(Slot{i, l});
+    }
+    for (int ph = 0; ph < nphase; ++ph) {
+        std::vector<Slot> flat;
+        size_t longest = 0;
+        for (auto& l : lists[ph]) longest = std::max(longest, l.size());
+        for (size_t r = 0; r < longest; ++r)
+            for (int x = 0; x < kXcds; ++x)
+                if (r < lists[ph][x].size()) flat.push_back(lists[ph][x][r]);
+        B->blocks[ph] = (int)flat.size();
+        if (flat.empty()) continue;
+        if (flat.size() > B->map_cap[ph]) {
+            if (B->maps[ph]) (void)hipFree(B->maps[ph]);
+            B->maps[ph] = nullptr;
+            B->map_cap[ph] = 0;
+            NCS_HIP(hipMalloc(reinterpret_cast<void**>(&B->maps[ph]), flat.size() * sizeof(Slot)));
+            B->map_cap[ph] = flat.size();
+        }
+        NCS_HIP(hipMemcpy(B->maps[ph], flat.data(), flat.size() * sizeof(Slot), hipMemcpyHostToDevice));
+    }
+    return NCS_OK;
+}
+
+template <class T>
+hipError_t batch_iterate(ncs_batch* B, int k) {
+    if (B->blocks[3] == 0) return hipSuccess;
+    IterLaunch<T> L{};
+    L.ctxs = static_cast<const DevCtx<T>*>(B->dctxs);
+    L.bp = {B->maps[0], B->blocks[0]};
+    L.rows = {B->maps[1], B->blocks[1]};
+    L.cols = {B->maps[2], B->blocks[2]};
+    L.proj = {B->maps[3], B->blocks[3]};
+    L.fin = {B->maps[4], B->blocks[4]};
+    L.max_N = B->max_N;
+    L.projector = B->projector;
+    for (int i = 0; i < k; ++i) {
+        const hipError_t e = launch_iteration<T>(L, B->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <class T>
+ncs_status batch_upload_ctxs(ncs_batch* B) {
+    std::vector<DevCtx<T>> all(B->n);
+    for (int i = 0; i < B->n; ++i) all[i] = make_ctx<T>(B->slices[i]);
+    NCS_HIP(hipMemcpy(B->dctxs, all.data(), all.size() * sizeof(DevCtx<T>), hipMemcpyHostToDevice));
+    return NCS_OK;
+}
+
+ncs_status check_batch(ncs_batch* B) {
+    if (!B) {
+        set_err("null batch");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(hipSetDevice(B->device));
+    return NCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const ncs_params* params, int32_t dtype,
+                           const void* const* b_dev, const void* const* bg_dev, void* stream, ncs_batch** out) {
+    g_err.clear();
+    if (!out || !geoms || !params || !b_dev || n_slices < 1) {
+        set_err("ncs_batch_setup: need n_slices >= 1 and non-null geometry, params, data and out");
+        return NCS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    for (int i = 0; i < n_slices; ++i) {
+        ncs_status s = validate(geoms[i], params[i], dtype);
+        if (s) {
+            const std::string msg = g_err;
+            set_err("ncs_batch_setup: slice %d: %s", i, msg.c_str());
+            return s;
+        }
+        if (!b_dev[i]) {
+            set_err("ncs_batch_setup: slice %d has no data", i);
+            return NCS_ERR_INVALID_ARG;
+        }
+    }
+    ncs_batch* B = new ncs_batch();
+    B->n = n_slices;
+    B->dtype = dtype;
+    B->stream = static_cast<hipStream_t>(stream);
+    B->check_every = params[0].check_every > 0 ? params[0].check_every : 50;
+    auto fail = [&](ncs_status s) {
+        ncs_batch_destroy(B);
+        return s;
+    };
+    if (hipGetDevice(&B->device) != hipSuccess) {
+        set_err("ncs_batch_setup: hipGetDevice failed");
+        delete B;
+        return NCS_ERR_HIP;
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&B->ctls), (size_t)n_slices * sizeof(Control)) != hipSuccess) {
+        set_err("ncs_batch_setup: control array allocation failed");
+        B->ctls = nullptr;
+        return fail(NCS_ERR_OOM);
+    }
+    const size_t ctx_bytes = dtype == NCS_F64 ? sizeof(DevCtx<double>) : sizeof(DevCtx<float>);
+    if (hipMalloc(&B->dctxs, (size_t)n_slices * ctx_bytes) != hipSuccess) {
+        set_err("ncs_batch_setup: descriptor array allocation failed");
+        B->dctxs = nullptr;
+        return fail(NCS_ERR_OOM);
+    }
+    // projector choice: params[0].projector, or (0) timed on the largest slice
+    int largest = 0;
+    for (int i = 1; i < n_slices; ++i)
+        if ((long long)geoms[i].n_side * geoms[i].n_angles > (long long)geoms[largest].n_side * geoms[largest].n_angles)
+            largest = i;
+    B->slices.assign(n_slices, nullptr);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < n_slices; ++i) {
+            if ((pass == 0) != (i == largest)) continue;
+            ncs_params p = params[i];
+            p.graph_chunk = -1;
+            if (pass == 1) p.projector = B->projector;
+            ncs_status s = setup_slice(geoms[i], p, dtype, b_dev[i], bg_dev ? bg_dev[i] : nullptr, B->stream,
+                                       B->ctls + i, pass == 0 && params[i].projector == 0, &B->slices[i]);
+            if (s) {
+                const std::string msg = g_err;
+                set_err("ncs_batch_setup: slice %d: %s", i, msg.c_str());
+                return fail(s);
+            }
+            if (pass == 0) B->projector = B->slices[i]->projector;
+            B->max_N = std::max(B->max_N, geoms[i].n_side);
+        }
+    }
+    // LPT assignment of slices to XCDs by projector workgroups x image side
+    std::vector<int> order(n_slices);
+    std::iota(order.begin(), order.end(), 0);
+    auto cost = [&](int i) {
+        const ncs_handle* h = B->slices[i];
+        return (double)project_blocks(h->g.n_angles, h->g.n_bins) * h->g.n_side;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<double> load(kXcds, 0.0);
+    B->xcd_of.assign(n_slices, 0);
+    for (int i : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        B->xcd_of[i] = x;
+        load[x] += cost(i);
+    }
+    B->active.assign(n_slices, 1);
+    ncs_status s = dtype == NCS_F64 ? batch_upload_ctxs<double>(B) : batch_upload_ctxs<float>(B);
+    if (s) return fail(s);
+    if ((s = build_maps(B))) return fail(s);
+    *out = B;
+    return NCS_OK;
+}
+
+void ncs_batch_destroy(ncs_batch* B) {
+    if (!B) return;
+    (void)hipSetDevice(B->device);
+    (void)hipStreamSynchronize(B->stream);
+    for (ncs_handle* h : B->slices) ncs_destroy(h);
+    for (Slot* m : B->maps)
+        if (m) (void)hipFree(m);
+    if (B->dctxs) (void)hipFree(B->dctxs);
+    if (B->ctls) (void)hipFree(B->ctls);
+    delete B;
+}
+
+ncs_status ncs_batch_set_init(ncs_batch* B, const void* const* x0_dev, int32_t dual_from_x0) {
+    ncs_status s = check_batch(B);
+    if (s) return s;
+    for (int i = 0; i < B->n; ++i) {
+        if ((s = ncs_set_init(B->slices[i], x0_dev ? x0_dev[i] : nullptr, dual_from_x0))) return s;
+        B->active[i] = 1;
+    }
+    return build_maps(B);
+}
+
+ncs_status ncs_batch_solve(ncs_batch* B, int32_t max_iters, const double* f_target, int32_t* iters_done,
+                           double* f_final) {
+    ncs_status s = check_batch(B);
+    if (s) return s;
+    if (max_iters < 0) {
+        set_err("ncs_batch_solve: max_iters must be >= 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    std::vector<int> start(B->n);
+    for (int i = 0; i < B->n; ++i) {
+        NCS_HIP(launch_control(B->ctls + i, 1, 0, f_target ? f_target[i] : std::nan(""), B->stream));
+        B->active[i] = 1;
+    }
+    std::vector<Control> c(B->n);
+    NCS_HIP(hipMemcpyAsync(c.data(), B->ctls, B->n * sizeof(Control), hipMemcpyDeviceToHost, B->stream));
+    NCS_HIP(hipStreamSynchronize(B->stream));
+    for (int i = 0; i < B->n; ++i) start[i] = c[i].iter;
+    if ((s = build_maps(B))) return s;
+    int remaining = max_iters;
+    bool any_nan = false;
+    while (remaining > 0) {
+        const int chunk = std::min(remaining, B->check_every);
+        NCS_HIP(B->dtype == NCS_F64 ? batch_iterate<double>(B, chunk) : batch_iterate<float>(B, chunk));
+        remaining -= chunk;
+        NCS_HIP(hipMemcpyAsync(c.data(), B->ctls, B->n * sizeof(Control), hipMemcpyDeviceToHost, B->stream));
+        NCS_HIP(hipStreamSynchronize(B->stream));
+        bool changed = false;
+        int left = 0;
+        for (int i = 0; i < B->n; ++i) {
+            if (B->active[i] && c[i].stop) {
+                B->active[i] = 0;
+                changed = true;
+                any_nan |= c[i].status == -4;
+            }
+            left += B->active[i];
+        }
+        if (left == 0) break;
+        if (changed && (s = build_maps(B))) return s;
+    }
+    bool all_reached = true;
+    for (int i = 0; i < B->n; ++i) {
+        if (iters_done) iters_done[i] = c[i].iter - start[i];
+        if (f_final) f_final[i] = c[i].f_last;
+        all_reached &= c[i].status == 1;
+        B->slices[i]->iter_host = c[i].iter;
+    }
+    if (any_nan) {
+        set_err("ncs_batch_solve: a slice's objective became NaN");
+        return NCS_ERR_NONFINITE;
+    }
+    return all_reached ? NCS_OK : NCS_NOT_CONVERGED;
+}
+
+ncs_status ncs_batch_slice(ncs_batch* B, int32_t i, ncs_handle** slice) {
+    ncs_status s = check_batch(B);
+    if (s) return s;
+    if (i < 0 || i >= B->n || !slice) {
+        set_err("ncs_batch_slice: index %d outside [0, %d)", i, B->n);
+        return NCS_ERR_INVALID_ARG;
+    }
+    *slice = B->slices[i];
     return NCS_OK;
 }
 

@@ -5,6 +5,16 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+// Pointers inside descriptors that kernels read from device memory are marked
+// global in the device pass of the kernel source, so that loads through them
+// are global (uniform ones scalar) rather than flat; everywhere else they are
+// plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(NCS_KERNEL_SOURCE)
+#define NCS_G __attribute__((address_space(1)))
+#else
+#define NCS_G
+#endif
+
 namespace ncs {
 
 // Per-angle geometry, precomputed in double on the host and stored in T.
@@ -24,9 +34,9 @@ struct AngleT {
     T pad;
 };
 
-// Device control block of one solver.
+// Device control block of one slice.
 struct Control {
-    int32_t stop;        // 1: iteration kernels return immediately
+    int32_t stop;        // 1: iteration kernels of this slice return immediately
     int32_t status;      // 0 running, 1 target reached, -4 NaN objective
     int32_t iter;        // iterations completed since the last init
     int32_t pad0;
@@ -41,59 +51,81 @@ constexpr int kHistCap = 65536;   // objective history ring (doubles)
 enum { DATA_QUAD = 0, DATA_POISSON = 1 };
 enum { TV_ANISO = 0, TV_ISO = 1 };
 
-// Raw device pointers and scalars handed to every kernel by value.
+// Device pointers and scalars of one slice.  Kernels read it from a device
+// array indexed by slice, so one launch can serve many slices.
 template <class T>
 struct DevCtx {
     int N, log2N, NA, NS, PU;        // PU: padded sinogram pitch = NS + 3 (entry d at a*PU + 1 + d)
     int P;                           // padded image pitch = N + 4 (pixel c of a row at offset c + 2)
-    int projector;                   // 1: LDS-staged tiles, 2: direct coalesced loads
-    const AngleT<T>* ang;
-    const int32_t* axis;
-    T* x;        // N*N current image
-    T* xbar;     // N*P padded extrapolated image 2x+ - x (two zero columns each side)
-    T* xbarT;    // N*P padded transpose of xbar (row c holds column c)
-    T* xsc;      // N*P padded scratch image (plain projections)
-    T* xscT;     // N*P padded scratch transpose
-    T* u;        // NA*PU padded data dual
-    T* p;        // NA*PU padded projection E x (kept by recurrence)
-    T* v;        // 2*N*N TV dual (horizontal plane, vertical plane)
-    T* w;        // N*N backprojection + divergence
-    T* spec;     // (N/2+1)*N complex, transposed half spectrum: spec[2*(k*N + j) + {0,1}]
-    const T* hh; // (N/2+1)*N real multiplier h/(alpha N^2), transposed like spec
-    const T* tw; // N/2 complex twiddles exp(-2 pi i k / N)
-    const T* b;  // NA*NS data (caller-owned)
-    const T* bg; // NA*NS PET background or nullptr
-    T* ysc;      // NA*PU padded scratch sinogram
-    double* part_data;
-    double* part_tv;
-    Control* ctl;
-    double* hist;
+    int nb_proj, nb_tv;              // projection and TV workgroups of this slice
+    const NCS_G AngleT<T>* ang;
+    const NCS_G int32_t* axis;
+    NCS_G T* x;        // N*N current image
+    NCS_G T* xbar;     // N*P padded extrapolated image 2x+ - x (two zero columns each side)
+    NCS_G T* xbarT;    // N*P padded transpose of xbar (row c holds column c)
+    NCS_G T* xsc;      // N*P padded scratch image (plain projections)
+    NCS_G T* xscT;     // N*P padded scratch transpose
+    NCS_G T* u;        // NA*PU padded data dual
+    NCS_G T* p;        // NA*PU padded projection E x (kept by recurrence)
+    NCS_G T* v;        // 2*N*N TV dual (horizontal plane, vertical plane)
+    NCS_G T* w;        // N*N backprojection + divergence
+    NCS_G T* spec;     // (N/2+1)*N complex, transposed half spectrum: spec[2*(k*N + j) + {0,1}]
+    const NCS_G T* hh; // (N/2+1)*N real multiplier h/(alpha N^2), transposed like spec
+    const NCS_G T* tw; // N/2 complex twiddles exp(-2 pi i k / N)
+    const NCS_G T* b;  // NA*NS data (caller-owned)
+    const NCS_G T* bg; // NA*NS PET background or nullptr
+    NCS_G T* ysc;      // NA*PU padded scratch sinogram
+    NCS_G double* part_data;   // nb_proj partial data terms (also reused by evaluations)
+    NCS_G double* part_tv;     // nb_tv partial TV terms
+    NCS_G Control* ctl;
+    NCS_G double* hist;
     T alpha, beta, s_tv, inv1pa;
     double lambda;
     int data_term, tv_term;
 };
 
-// Launch helpers (ncs_kernels.hip).  All enqueue on `st` and return the
-// launch status.
-template <class T> hipError_t launch_backproject_iter(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_backproject_plain(const DevCtx<T>& c, const T* y_padded, T* out, hipStream_t st);
-template <class T> hipError_t launch_fft_rows_fwd(const DevCtx<T>& c, const T* src, bool iter, hipStream_t st);
-template <class T> hipError_t launch_fft_cols(const DevCtx<T>& c, T scale, bool iter, hipStream_t st);
-template <class T> hipError_t launch_fft_rows_inv_update(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_fft_rows_inv_plain(const DevCtx<T>& c, T* out, hipStream_t st);
-template <class T> hipError_t launch_tv_update(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_project_iter(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_pad_image(const DevCtx<T>& c, const T* img, hipStream_t st);
-// Plain projections read the padded scratch pair (xsc, xscT): call
-// launch_pad_image first.
-template <class T> hipError_t launch_project_plain(const DevCtx<T>& c, T* out, hipStream_t st);
-template <class T> hipError_t launch_project_setp(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_finalize_iter(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_eval_objective(const DevCtx<T>& c, const T* img, hipStream_t st);   // pads img itself
-template <class T> hipError_t launch_pad_sinogram(const DevCtx<T>& c, const T* y, T* y_padded, hipStream_t st);
-template <class T> hipError_t launch_unpad_sinogram(const DevCtx<T>& c, const T* y_padded, T* y, hipStream_t st);
-template <class T> hipError_t launch_data_const(const DevCtx<T>& c, hipStream_t st);
-template <class T> hipError_t launch_dual_init(const DevCtx<T>& c, hipStream_t st);
+// Workgroup -> (slice, workgroup within the slice) for batched launches; a
+// null map means one slice and local workgroup = blockIdx.x.
+struct Slot {
+    int32_t slice, local;
+};
+
+// One phase of a batched iteration launch.
+struct PhaseGrid {
+    const Slot* map;   // device array or nullptr (single slice)
+    int blocks;        // total workgroups
+};
+
+// Everything one (batched) NCS iteration needs.
+template <class T>
+struct IterLaunch {
+    const DevCtx<T>* ctxs;   // device array of slice descriptors
+    PhaseGrid bp, rows, cols, proj, fin;   // rows is shared by the forward and inverse row DFTs
+    int max_N;               // largest image side (dynamic LDS of the DFT kernels)
+    int projector;           // 1: LDS-staged tiles, 2: direct coalesced loads
+};
+
+constexpr int kNumPhases = 6;   // backprojection, row DFT, column DFT, inverse row DFT + x-update,
+                                // projection + data prox + TV update, objective
+
+template <class T> hipError_t launch_iteration(const IterLaunch<T>& L, hipStream_t st);
+template <class T> hipError_t launch_iteration_phase(const IterLaunch<T>& L, int phase, hipStream_t st);
+
+// Single-slice operators.  `hc` is the host copy of the descriptor (launch
+// sizes), `dc` its device copy.
+template <class T> hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y_padded, T* out, hipStream_t st);
+template <class T> hipError_t launch_apply_minv(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* w, T* out, T scale, hipStream_t st);
+template <class T> hipError_t launch_pad_image(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st);
+// Plain projections read the padded scratch pair (xsc, xscT): pad first.
+template <class T> hipError_t launch_project_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, T* out, hipStream_t st);
+template <class T> hipError_t launch_project_setp(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, hipStream_t st);
+template <class T> hipError_t launch_eval_objective(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, const T* img, hipStream_t st);
+template <class T> hipError_t launch_pad_sinogram(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y, T* y_padded, hipStream_t st);
+template <class T> hipError_t launch_unpad_sinogram(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y_padded, T* y, hipStream_t st);
+template <class T> hipError_t launch_data_const(const DevCtx<T>& hc, const DevCtx<T>* dc, hipStream_t st);
+template <class T> hipError_t launch_dual_init(const DevCtx<T>& hc, const DevCtx<T>* dc, hipStream_t st);
+// |E 1|^2 into ctl->eval_out (projection of the ones image, double sum)
+template <class T> hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, hipStream_t st);
 
 // Control block updates queued on the stream (no memset nodes, capturable):
 //   op 0: reset  (iter = 0, stop = 0, status = 0, f_target)
@@ -103,5 +135,6 @@ hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target,
 
 int project_blocks(int NA, int NS);
 int tv_blocks(int N);
+int bp_blocks(int N);
 
 }  // namespace ncs

@@ -1,21 +1,25 @@
 // HIP kernels of the NCS iteration for gfx950 (CDNA4), templated on the
 // iterate precision T (float or double).  One NCS iteration (Section 4.1 /
-// Section 4.2 of the paper) is
+// Section 4.2 of the paper) is six launches:
 //
-//   k_backproject  w  = alpha E^T u + beta D^T v            (pixel-driven gather)
+//   k_backproject     w = alpha E^T u + beta D^T v          (pixel-driven gather)
 //   k_fft_rows_fwd    row DFTs of w, two real rows per complex transform
 //   k_fft_cols        column DFT, multiply by h/(alpha N^2), inverse column DFT
 //   k_fft_rows_inv    inverse row DFTs; x+ = x - Delta, xbar = 2x+ - x (padded
 //                     row-major copy and padded transposed copy)
-//   k_tv              v+ = Pi(v + beta D xbar), TV of x+ (double partial sums)
-//   k_project_direct  q = E xbar (ray-driven, coalesced loads from the copy
-//   / k_project_lds   whose rows run along the sampled axis, or LDS-staged
-//                     tiles); u+ = prox(u + ...), p+ = (q + p)/2 = E x+, data
-//                     term of x+ (double partials)
-//   k_finalize        f(x+) = data + lambda TV, history, device stop flag
+//   k_project         q = E xbar (ray-driven; direct coalesced loads or
+//                     LDS-staged tiles); u+ = prox(u + ...), p+ = (q + p)/2 =
+//                     E x+, data term of x+.  Extra workgroups of the same
+//                     launch do v+ = Pi(v + beta D xbar) and the TV term of
+//                     x+ (double partial sums)
+//   k_finalize_iter   f(x+) = partial sums added in a fixed order, history,
+//                     the slice's stop flag
 //
-// Every iteration kernel returns at once when the device stop flag is set, so a
-// queued or captured batch of iterations ends cleanly after the stopping test.
+// Every kernel reads its slice's descriptor from a device array, through a
+// workgroup -> (slice, local workgroup) map when several slices share one
+// launch.  Iteration kernels of a slice whose stop flag is set return at
+// once, so queued or replayed iterations end cleanly after the stopping test.
+#define NCS_KERNEL_SOURCE 1
 #include "ncs_internal.h"
 
 #include <cmath>
@@ -25,9 +29,23 @@ namespace ncs {
 namespace {
 
 constexpr int kRays = 64;      // rays per projector workgroup (one per lane)
-constexpr int kWaves = 4;      // waves per workgroup
-constexpr int kSeg = 64;       // steps per LDS segment of the projector
+constexpr int kWaves = 4;      // waves per projector / TV workgroup
+constexpr int kSeg = 64;       // steps per LDS segment (LDS-staged projector)
 constexpr int kPitch = 161;    // LDS row pitch: >= 63*sqrt(2) + 63 + 5, odd
+constexpr int kBpWaves = 8;    // backprojector: angle groups per 8 x 8 pixel tile
+constexpr int kFftThreads = 256;
+
+template <class T>
+__device__ inline const DevCtx<T>& slot_ctx(const DevCtx<T>* __restrict__ ctxs, const Slot* __restrict__ map,
+                                            int& local) {
+    if (map) {
+        const Slot s = map[blockIdx.x];
+        local = s.local;
+        return ctxs[s.slice];
+    }
+    local = blockIdx.x;
+    return ctxs[0];
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -67,10 +85,17 @@ __device__ inline int sat_int(T v) {
     return (int)fmin(fmax(v, T(-1.0e9)), T(1.0e9));
 }
 
+template <class T>
+__device__ inline T med3(T v, T lo, T hi);
+template <>
+__device__ inline float med3<float>(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
+template <>
+__device__ inline double med3<double>(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
+
 // Radix-2 decimation-in-time transform in LDS: input in bit-reversed order,
 // output in natural order.  tw[2k], tw[2k+1] = cos, -sin of 2 pi k / N.
 template <class T>
-__device__ void fft_dit(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
+__device__ void fft_dit(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int logN, bool inverse,
                         int tid, int nthr) {
     for (int ls = 0; ls < logN; ++ls) {
         const int half = 1 << ls;
@@ -98,7 +123,7 @@ __device__ void fft_dit(T* re, T* im, const T* __restrict__ tw, int N, int logN,
 // Radix-2 decimation-in-frequency transform in LDS: input natural, output in
 // bit-reversed order.
 template <class T>
-__device__ void fft_dif(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
+__device__ void fft_dif(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int logN, bool inverse,
                         int tid, int nthr) {
     for (int ls = logN - 1; ls >= 0; --ls) {
         const int half = 1 << ls;
@@ -123,17 +148,22 @@ __device__ void fft_dif(T* re, T* im, const T* __restrict__ tw, int N, int logN,
 
 // ---------------------------------------------------------------------------
 // Backprojection (pixel-driven gather, matched to the ray-driven projector).
-// Workgroup: an 8 x 8 pixel tile; each of the 4 waves takes every 4th angle;
-// the 4 partial sums are added in a fixed order.
+// Workgroup: an 8 x 8 pixel tile; each of the 8 waves takes every 8th angle;
+// the partial sums are added in a fixed order.
 // ---------------------------------------------------------------------------
 template <class T, bool ITER>
-__global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __restrict__ ysrc,
-                                                     T* __restrict__ out) {
+__global__ __launch_bounds__(kBpWaves * 64) void k_backproject(const DevCtx<T>* __restrict__ ctxs,
+                                                               const Slot* __restrict__ map,
+                                                               const T* __restrict__ ysrc_plain,
+                                                               T* __restrict__ out) {
+    int local;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, local);
     if (ITER && c.ctl->stop) return;
-    __shared__ T red[kWaves * 64];
+    __shared__ T red[kBpWaves * 64];
+    const T* ysrc = ITER ? c.u : ysrc_plain;
     const int N = c.N;
     const int tiles_x = N >> 3;
-    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int tx = local % tiles_x, ty = local / tiles_x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = tx * 8 + (lane & 7);
@@ -141,16 +171,18 @@ __global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __res
     const T fc = (T)col, fr = (T)row;
     const T tmax = (T)c.NS;
     const int PU = c.PU;
+    const int NA = c.NA;
+    const AngleT<T>* ang = c.ang;
     T acc = T(0);
 #pragma unroll 4
-    for (int a = wave; a < c.NA; a += kWaves) {
-        const AngleT<T> A = c.ang[a];
-        T t = fma(fc, A.q1, fma(fr, A.q2, A.q0));
-        t = fmin(fmax(t, T(-1)), tmax);   // outside the detector: both taps land on zero pads
+    for (int a = wave; a < NA; a += kBpWaves) {
+        const AngleT<T> A = ang[a];
+        // outside the detector both taps land on the zero pads at d = -1, N_s, N_s + 1
+        const T t = med3(fma(fc, A.q1, fma(fr, A.q2, A.q0)), T(-1), tmax);
         const T fl = floor(t);
         const T f = t - fl;
-        const int d0 = (int)fl;
-        const Pair<T> y = load_pair(ysrc + (size_t)a * PU + 1 + d0);
+        const unsigned off = (unsigned)((int)fl + 1);
+        const Pair<T> y = load_pair(ysrc + (size_t)a * PU + off);
         const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
         const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
         acc = fma(w0, y.a, acc);
@@ -159,7 +191,9 @@ __global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __res
     red[wave * 64 + lane] = acc;
     __syncthreads();
     if (wave != 0) return;
-    const T bp = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+    T bp = red[lane];
+#pragma unroll
+    for (int w = 1; w < kBpWaves; ++w) bp += red[w * 64 + lane];
     const size_t pix = (size_t)row * N + col;
     if (!ITER) {
         out[pix] = bp;
@@ -177,26 +211,23 @@ __global__ __launch_bounds__(256) void k_backproject(DevCtx<T> c, const T* __res
 }
 
 // ---------------------------------------------------------------------------
-// Forward projection (Joseph, ray-driven).  Workgroup: one angle and 64
-// consecutive rays (one per lane).  The stepping axis is cut into segments of
-// 64 steps; for each segment the bounding box of the sampled coordinates of
-// all 64 rays is staged in LDS with coalesced loads (transposed on the fly for
-// column-stepping angles), then each wave marches 16 steps of every ray.
+// Forward projection (Joseph, ray-driven) with the data prox, fused with the
+// TV update and the objective reduction in iteration mode.
 // ---------------------------------------------------------------------------
 enum { PMODE_PLAIN = 0, PMODE_SETP = 1, PMODE_ITER = 2 };
 
-// Epilogue shared by both projector variants: q is the ray sum of lane's ray.
+// Ray sum -> output / state update.  Returns this lane's data term (ITER).
 template <class T, int MODE>
-__device__ inline void project_epilogue(const DevCtx<T>& c, int a, int d, int lane, T q, T* __restrict__ out) {
+__device__ inline double project_epilogue(const DevCtx<T>& c, int a, int d, T q, T* __restrict__ out) {
     const int NS = c.NS;
     const bool valid = d < NS;
     if (MODE == PMODE_PLAIN) {
         if (valid) out[(size_t)a * NS + d] = q;
-        return;
+        return 0.0;
     }
     if (MODE == PMODE_SETP) {
         if (valid) c.p[(size_t)a * c.PU + 1 + d] = q;
-        return;
+        return 0.0;
     }
     double dterm = 0.0;
     if (valid) {
@@ -227,26 +258,59 @@ __device__ inline void project_epilogue(const DevCtx<T>& c, int a, int d, int la
         c.u[ip] = un;
         c.p[ip] = pn;
     }
-    dterm = wave_sum(dterm);
-    if (lane == 0) c.part_data[blockIdx.x] = dterm;
+    return dterm;
 }
 
-template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_project_lds(DevCtx<T> c, const T* __restrict__ img,
-                                                     const T* __restrict__ imgT, T* __restrict__ out) {
-    (void)imgT;
-    if (MODE == PMODE_ITER && c.ctl->stop) return;
-    __shared__ T tile[kSeg * kPitch];
-    __shared__ T red[kWaves * kRays];
-    const int N = c.N, NS = c.NS;
-    const int nb = (NS + kRays - 1) / kRays;
-    const int a = blockIdx.x / nb;
-    const int d0 = (blockIdx.x - a * nb) * kRays;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const AngleT<T> A = c.ang[a];
-    const int axis = c.axis[a];
-    const int d = d0 + lane;
+// Ray sum of lane's ray by the direct method: one lane per ray, the 4 waves
+// split the steps.  Column-stepping angles read the transposed copy so that
+// every angle walks along contiguous rows; two zero columns on each side of
+// a row absorb taps that fall off the image, so the clamped tap index needs
+// no per-step test.
+template <class T>
+__device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
+                                   const AngleT<T>& A, int axis, int d0, int d, int wave) {
+    const int N = c.N, P = c.P;
+    const T* src = axis == 0 ? img : imgT;
+    const T base = fma((T)d, A.k1, A.k0);
+    // Steps where some ray of the block has xi in [-2, N+1] (all rays of an
+    // angle share the slope k2 in s, so the block's xi at step s spans
+    // [blo, bhi] + s k2); the margin keeps the range conservative.
+    const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
+    const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
+    const T lo_x = T(-2), hi_x = T(N + 1);
+    const int SW = N / kWaves;
+    int s_begin = wave * SW, s_end = s_begin + SW;
+    if (A.k2 > T(0)) {
+        s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
+    } else if (A.k2 < T(0)) {
+        s_begin = max(s_begin, sat_int(floor((hi_x - blo) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
+    } else if (bhi < lo_x || blo > hi_x) {
+        s_end = s_begin;
+    }
+    T acc = T(0);
+    const T cmax = (T)N;
+#pragma unroll 4
+    for (int s = s_begin; s < s_end; ++s) {
+        const T xi = fma((T)s, A.k2, base);
+        const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
+        const T f = xi - fl;
+        const unsigned off = (unsigned)((int)fl + 2);
+        const Pair<T> v = load_pair(src + (size_t)s * P + off);
+        acc += fma(f, v.b - v.a, v.a);
+    }
+    return acc;
+}
+
+// Ray sum by LDS-staged tiles: the stepping axis is cut into segments of 64
+// steps; for each segment the bounding box of the sampled coordinates of all
+// 64 rays is staged in LDS with coalesced loads (transposed on the fly for
+// column-stepping angles), then each wave marches 16 steps of every ray.
+template <class T>
+__device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, const AngleT<T>& A, int axis,
+                                int d0, int d, int lane, int wave, T* tile) {
+    const int N = c.N;
     const T base = fma((T)d, A.k1, A.k0);
     const T bA = fma((T)d0, A.k1, A.k0);
     const T bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
@@ -294,64 +358,112 @@ __global__ __launch_bounds__(256) void k_project_lds(DevCtx<T> c, const T* __res
             acc += fma(f, v1 - v0, v0);
         }
     }
-    red[wave * kRays + lane] = acc;
-    __syncthreads();
-    if (wave != 0) return;
-    const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
-    project_epilogue<T, MODE>(c, a, d, lane, q, out);
+    return acc;
 }
 
-// Direct variant: one lane per ray, the 4 waves split the steps.  Column-
-// stepping angles read the transposed copy so that every angle walks along
-// contiguous rows; two zero columns on each side of a row absorb taps that
-// fall off the image, so the clamped tap index needs no per-step test.
-template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_project_direct(DevCtx<T> c, const T* __restrict__ img,
-                                                        const T* __restrict__ imgT, T* __restrict__ out) {
+// TV dual update of one 256-pixel tile and the TV term of x+ (ITER only).
+template <class T>
+__device__ inline double tv_tile(const DevCtx<T>& c, int tile) {
+    const int N = c.N;
+    const size_t NN = (size_t)N * N;
+    const size_t pix = (size_t)tile * 256 + threadIdx.x;
+    if (pix >= NN) return 0.0;
+    const int r = (int)(pix >> c.log2N);
+    const int col = (int)(pix & (size_t)(N - 1));
+    const bool hx = col < N - 1, hy = r < N - 1;
+    const T* xbp = c.xbar + (size_t)r * c.P + col + 2;
+    const T xb = xbp[0];
+    const T dh = hx ? xb - xbp[1] : T(0);
+    const T dv = hy ? xb - xbp[c.P] : T(0);
+    T* vh = c.v;
+    T* vv = c.v + NN;
+    const T gh = fma(c.beta, dh, vh[pix]);
+    const T gv = fma(c.beta, dv, vv[pix]);
+    const T s = c.s_tv;
+    if (c.tv_term == TV_ANISO) {
+        vh[pix] = fmin(fmax(gh, -s), s);
+        vv[pix] = fmin(fmax(gv, -s), s);
+    } else {
+        const T nrm = sqrt(fma(gh, gh, gv * gv));
+        const T sc = nrm > s ? s / nrm : T(1);
+        vh[pix] = gh * sc;
+        vv[pix] = gv * sc;
+    }
+    const double xx = (double)c.x[pix];
+    const double th = hx ? xx - (double)c.x[pix + 1] : 0.0;
+    const double tw = hy ? xx - (double)c.x[pix + N] : 0.0;
+    return c.tv_term == TV_ANISO ? fabs(th) + fabs(tw) : sqrt(th * th + tw * tw);
+}
+
+// Objective of a slice after an iteration: the partial sums of the projection
+// launch added in a fixed order (double), the history entry and the stop
+// test.  One workgroup per slice; the kernel boundary orders it after every
+// workgroup of the projection launch.
+template <class T>
+__global__ __launch_bounds__(256) void k_finalize_iter(const DevCtx<T>* __restrict__ ctxs,
+                                                       const Slot* __restrict__ map) {
+    int local;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, local);
+    if (c.ctl->stop) return;
+    __shared__ double sh[kWaves];
+    double sd = 0.0, st = 0.0;
+    for (int i = threadIdx.x; i < c.nb_proj; i += 256) sd += c.part_data[i];
+    for (int i = threadIdx.x; i < c.nb_tv; i += 256) st += c.part_tv[i];
+    sd = block_sum256(sd, sh);
+    __syncthreads();
+    st = block_sum256(st, sh);
+    if (threadIdx.x != 0) return;
+    NCS_G Control* k = c.ctl;
+    const double f = (sd + k->data_const) + c.lambda * st;
+    const int it = k->iter;
+    c.hist[it & (kHistCap - 1)] = f;
+    k->iter = it + 1;
+    k->f_last = f;
+    if (f != f) {
+        k->status = -4;
+        k->stop = 1;
+    } else if (f <= k->f_target) {
+        k->status = 1;
+        k->stop = 1;
+    }
+}
+
+template <class T, int MODE, int VARIANT>
+__global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ ctxs, const Slot* __restrict__ map,
+                                                 T* __restrict__ out) {
+    int local;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, local);
     if (MODE == PMODE_ITER && c.ctl->stop) return;
     __shared__ T red[kWaves * kRays];
-    const int N = c.N, NS = c.NS, P = c.P;
-    const int nb = (NS + kRays - 1) / kRays;
-    const int a = blockIdx.x / nb;
-    const int d0 = (blockIdx.x - a * nb) * kRays;
+    __shared__ double shd[kWaves];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const AngleT<T> A = c.ang[a];
-    const T* src = c.axis[a] == 0 ? img : imgT;
-    const int d = d0 + lane;
-    const T base = fma((T)d, A.k1, A.k0);
-    // Steps where some ray of the block has xi in [-2, N+1] (all rays of an
-    // angle share the slope k2 in s, so the block's xi at step s spans
-    // [blo, bhi] + s k2); the margin keeps the range conservative.
-    const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
-    const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
-    const T lo_x = T(-2), hi_x = T(N + 1);
-    const int SW = N / kWaves;
-    int s_begin = wave * SW, s_end = s_begin + SW;
-    if (A.k2 > T(0)) {
-        s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
-        s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
-    } else if (A.k2 < T(0)) {
-        s_begin = max(s_begin, sat_int(floor((hi_x - blo) / A.k2)) - 1);
-        s_end = min(s_end, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
-    } else if (bhi < lo_x || blo > hi_x) {
-        s_end = s_begin;
+    const T* img = MODE == PMODE_ITER ? c.xbar : c.xsc;
+    const T* imgT = MODE == PMODE_ITER ? c.xbarT : c.xscT;
+    if (MODE == PMODE_ITER && local >= c.nb_proj) {
+        const double tv = block_sum256(tv_tile(c, local - c.nb_proj), shd);
+        if (threadIdx.x == 0) c.part_tv[local - c.nb_proj] = tv;
+        return;
     }
-    T acc = T(0);
-#pragma unroll 4
-    for (int s = s_begin; s < s_end; ++s) {
-        const T xi = fma((T)s, A.k2, base);
-        const T fl = floor(xi);
-        const T f = xi - fl;
-        const int cc = min(max((int)fl, -2), N);
-        const Pair<T> v = load_pair(src + (size_t)s * P + cc + 2);
-        acc += fma(f, v.b - v.a, v.a);
+    const int nb = (c.NS + kRays - 1) / kRays;
+    const int a = local / nb;
+    const int d0 = (local - a * nb) * kRays;
+    const int d = d0 + lane;
+    const AngleT<T> A = c.ang[a];
+    const int axis = c.axis[a];
+    T acc;
+    if (VARIANT == 1) {
+        __shared__ T tile[kSeg * kPitch];
+        acc = ray_sum_lds(c, img, A, axis, d0, d, lane, wave, tile);
+    } else {
+        acc = ray_sum_direct(c, img, imgT, A, axis, d0, d, wave);
     }
     red[wave * kRays + lane] = acc;
     __syncthreads();
     if (wave != 0) return;
     const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
-    project_epilogue<T, MODE>(c, a, d, lane, q, out);
+    const double dterm = wave_sum(project_epilogue<T, MODE>(c, a, d, q, out));
+    if (MODE == PMODE_ITER && lane == 0) c.part_data[local] = dterm;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,13 +471,17 @@ __global__ __launch_bounds__(256) void k_project_direct(DevCtx<T> c, const T* __
 // complex transform), column transforms with the multiplier, inverse rows.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256) void k_fft_rows_fwd(DevCtx<T> c, const T* __restrict__ src, int check_stop) {
-    if (check_stop && c.ctl->stop) return;
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const DevCtx<T>* __restrict__ ctxs,
+                                                              const Slot* __restrict__ map,
+                                                              const T* __restrict__ src_plain, int iter) {
+    int pr;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, pr);
+    if (iter && c.ctl->stop) return;
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
     const int N = c.N, logN = c.log2N;
-    const int pr = blockIdx.x;
+    const T* src = iter ? c.w : src_plain;
     const T* ra = src + (size_t)(2 * pr) * N;
     const T* rb = ra + N;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
@@ -386,13 +502,15 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(DevCtx<T> c, const T* __re
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_fft_cols(DevCtx<T> c, T scale, int check_stop) {
-    if (check_stop && c.ctl->stop) return;
+__global__ __launch_bounds__(kFftThreads) void k_fft_cols(const DevCtx<T>* __restrict__ ctxs,
+                                                          const Slot* __restrict__ map, T scale, int iter) {
+    int k;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, k);
+    if (iter && c.ctl->stop) return;
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
     const int N = c.N, logN = c.log2N;
-    const int k = blockIdx.x;
     T* colp = c.spec + 2 * (size_t)k * N;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
         const int i = bitrev(n, logN);
@@ -415,13 +533,15 @@ __global__ __launch_bounds__(256) void k_fft_cols(DevCtx<T> c, T scale, int chec
 }
 
 template <class T, bool ITER>
-__global__ __launch_bounds__(256) void k_fft_rows_inv(DevCtx<T> c, T* __restrict__ out) {
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* __restrict__ ctxs,
+                                                              const Slot* __restrict__ map, T* __restrict__ out) {
+    int pr;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, pr);
     if (ITER && c.ctl->stop) return;
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
     const int N = c.N, logN = c.log2N;
-    const int pr = blockIdx.x;
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const int kk = k <= (N >> 1) ? k : N - k;
         const T* s = c.spec + 2 * ((size_t)kk * N + 2 * pr);
@@ -456,50 +576,11 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(DevCtx<T> c, T* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// TV dual update and TV term of x+ (double partial sums).
+// Single-slice helpers: objective evaluation, padding, duals, data constant.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256) void k_tv(DevCtx<T> c) {
-    if (c.ctl->stop) return;
-    __shared__ double sh[kWaves];
-    const int N = c.N;
-    const size_t NN = (size_t)N * N;
-    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
-    double tvv = 0.0;
-    if (pix < NN) {
-        const int r = (int)(pix >> c.log2N);
-        const int col = (int)(pix & (size_t)(N - 1));
-        const bool hx = col < N - 1, hy = r < N - 1;
-        const T* xbp = c.xbar + (size_t)r * c.P + col + 2;
-        const T xb = xbp[0];
-        const T dh = hx ? xb - xbp[1] : T(0);
-        const T dv = hy ? xb - xbp[c.P] : T(0);
-        T* vh = c.v;
-        T* vv = c.v + NN;
-        const T gh = fma(c.beta, dh, vh[pix]);
-        const T gv = fma(c.beta, dv, vv[pix]);
-        const T s = c.s_tv;
-        if (c.tv_term == TV_ANISO) {
-            vh[pix] = fmin(fmax(gh, -s), s);
-            vv[pix] = fmin(fmax(gv, -s), s);
-        } else {
-            const T nrm = sqrt(fma(gh, gh, gv * gv));
-            const T sc = nrm > s ? s / nrm : T(1);
-            vh[pix] = gh * sc;
-            vv[pix] = gv * sc;
-        }
-        const double xx = (double)c.x[pix];
-        const double th = hx ? xx - (double)c.x[pix + 1] : 0.0;
-        const double tw = hy ? xx - (double)c.x[pix + N] : 0.0;
-        tvv = c.tv_term == TV_ANISO ? fabs(th) + fabs(tw) : sqrt(th * th + tw * tw);
-    }
-    const double tot = block_sum256(tvv, sh);
-    if (threadIdx.x == 0) c.part_tv[blockIdx.x] = tot;
-}
-
-// TV term of an arbitrary image (objective evaluation).
-template <class T>
-__global__ __launch_bounds__(256) void k_tv_eval(DevCtx<T> c, const T* __restrict__ img) {
+__global__ __launch_bounds__(256) void k_tv_eval(const DevCtx<T>* __restrict__ ctxs, const T* __restrict__ img) {
+    const DevCtx<T>& c = ctxs[0];
     __shared__ double sh[kWaves];
     const int N = c.N;
     const size_t NN = (size_t)N * N;
@@ -519,7 +600,8 @@ __global__ __launch_bounds__(256) void k_tv_eval(DevCtx<T> c, const T* __restric
 
 // Data term of a projected image q (unpadded, NA*NS) (objective evaluation).
 template <class T>
-__global__ __launch_bounds__(256) void k_data_eval(DevCtx<T> c, const T* __restrict__ q) {
+__global__ __launch_bounds__(256) void k_data_eval(const DevCtx<T>* __restrict__ ctxs, const T* __restrict__ q) {
+    const DevCtx<T>& c = ctxs[0];
     __shared__ double sh[kWaves];
     const size_t m = (size_t)c.NA * c.NS;
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -533,7 +615,7 @@ __global__ __launch_bounds__(256) void k_data_eval(DevCtx<T> c, const T* __restr
         } else {
             const double y = y0 + (c.bg ? (double)c.bg[i] : 0.0);
             if (bd > 0.0) dterm = y > 0.0 ? y - bd * log(y) : INFINITY;
-            else dterm = y;   // zero counts: l = y (indicator not reported)
+            else dterm = y;
         }
     }
     const double tot = block_sum256(dterm, sh);
@@ -542,7 +624,8 @@ __global__ __launch_bounds__(256) void k_data_eval(DevCtx<T> c, const T* __restr
 
 // PET constant sum_i log Gamma(b_i + 1).
 template <class T>
-__global__ __launch_bounds__(256) void k_lgamma_part(DevCtx<T> c) {
+__global__ __launch_bounds__(256) void k_lgamma_part(const DevCtx<T>* __restrict__ ctxs) {
+    const DevCtx<T>& c = ctxs[0];
     __shared__ double sh[kWaves];
     const size_t m = (size_t)c.NA * c.NS;
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -552,11 +635,40 @@ __global__ __launch_bounds__(256) void k_lgamma_part(DevCtx<T> c) {
     if (threadIdx.x == 0) c.part_data[blockIdx.x] = tot;
 }
 
-// which: 0 = iteration (history, stop test), 1 = evaluation (eval_out),
-//        2 = data constant (data_const = sum of data partials).
+// Sum of squares of a sinogram (|E 1|^2 at setup).
 template <class T>
-__global__ __launch_bounds__(256) void k_finalize(DevCtx<T> c, int nd, int nt, int which) {
-    if (which == 0 && c.ctl->stop) return;
+__global__ __launch_bounds__(256) void k_sumsq(const DevCtx<T>* __restrict__ ctxs, const T* __restrict__ q) {
+    const DevCtx<T>& c = ctxs[0];
+    __shared__ double sh[kWaves];
+    const size_t m = (size_t)c.NA * c.NS;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (i < m) {
+        const double y = (double)q[i];
+        v = y * y;
+    }
+    const double tot = block_sum256(v, sh);
+    if (threadIdx.x == 0) c.part_data[blockIdx.x] = tot;
+}
+
+// Fill the interior of the padded scratch pair with ones.
+template <class T>
+__global__ __launch_bounds__(256) void k_ones_image(const DevCtx<T>* __restrict__ ctxs) {
+    const DevCtx<T>& c = ctxs[0];
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (pix >= (size_t)c.N * c.N) return;
+    const int r = (int)(pix >> c.log2N);
+    const int col = (int)(pix & (size_t)(c.N - 1));
+    c.xsc[(size_t)r * c.P + col + 2] = T(1);
+    c.xscT[(size_t)col * c.P + r + 2] = T(1);
+}
+
+// which: 1 = evaluation (eval_out = data + constant + lambda TV),
+//        2 = data constant (data_const = sum of data partials),
+//        3 = plain sum (eval_out = sum of data partials).
+template <class T>
+__global__ __launch_bounds__(256) void k_finalize(const DevCtx<T>* __restrict__ ctxs, int nd, int nt, int which) {
+    const DevCtx<T>& c = ctxs[0];
     __shared__ double sh[kWaves];
     double sd = 0.0, st = 0.0;
     for (int i = threadIdx.x; i < nd; i += 256) sd += c.part_data[i];
@@ -570,26 +682,17 @@ __global__ __launch_bounds__(256) void k_finalize(DevCtx<T> c, int nd, int nt, i
         k->data_const = sd;
         return;
     }
-    const double f = (sd + k->data_const) + c.lambda * st;
-    if (which == 1) {
-        k->eval_out = f;
+    if (which == 3) {
+        k->eval_out = sd;
         return;
     }
-    const int it = k->iter;
-    c.hist[it & (kHistCap - 1)] = f;
-    k->iter = it + 1;
-    k->f_last = f;
-    if (f != f) {
-        k->status = -4;
-        k->stop = 1;
-    } else if (f <= k->f_target) {
-        k->status = 1;
-        k->stop = 1;
-    }
+    k->eval_out = (sd + k->data_const) + c.lambda * st;
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_pad(DevCtx<T> c, const T* __restrict__ y, T* __restrict__ yp) {
+__global__ __launch_bounds__(256) void k_pad(const DevCtx<T>* __restrict__ ctxs, const T* __restrict__ y,
+                                             T* __restrict__ yp) {
+    const DevCtx<T>& c = ctxs[0];
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     const size_t tot = (size_t)c.NA * c.PU;
     if (i >= tot) return;
@@ -599,7 +702,9 @@ __global__ __launch_bounds__(256) void k_pad(DevCtx<T> c, const T* __restrict__ 
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_unpad(DevCtx<T> c, const T* __restrict__ yp, T* __restrict__ y) {
+__global__ __launch_bounds__(256) void k_unpad(const DevCtx<T>* __restrict__ ctxs, const T* __restrict__ yp,
+                                               T* __restrict__ y) {
+    const DevCtx<T>& c = ctxs[0];
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     const size_t tot = (size_t)c.NA * c.NS;
     if (i >= tot) return;
@@ -610,7 +715,8 @@ __global__ __launch_bounds__(256) void k_unpad(DevCtx<T> c, const T* __restrict_
 
 // Write an image into the padded scratch pair (row-major and transposed).
 template <class T>
-__global__ __launch_bounds__(256) void k_pad_image(DevCtx<T> c, const T* __restrict__ img) {
+__global__ __launch_bounds__(256) void k_pad_image(const DevCtx<T>* __restrict__ ctxs, const T* __restrict__ img) {
+    const DevCtx<T>& c = ctxs[0];
     const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
     const size_t NN = (size_t)c.N * c.N;
     if (pix >= NN) return;
@@ -624,7 +730,8 @@ __global__ __launch_bounds__(256) void k_pad_image(DevCtx<T> c, const T* __restr
 // Dual initialisation from x0 (fixed-point relations of the optimality
 // conditions): u = grad g_data(E x0) from p = E x0; v from D x0.
 template <class T>
-__global__ __launch_bounds__(256) void k_dual_init_u(DevCtx<T> c) {
+__global__ __launch_bounds__(256) void k_dual_init_u(const DevCtx<T>* __restrict__ ctxs) {
+    const DevCtx<T>& c = ctxs[0];
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     const size_t m = (size_t)c.NA * c.NS;
     if (i >= m) return;
@@ -638,14 +745,16 @@ __global__ __launch_bounds__(256) void k_dual_init_u(DevCtx<T> c) {
         un = pp - bb;
     } else {
         const T y = pp + (c.bg ? c.bg[i] : T(0));
-        // grad of l(y; b) = 1 - b/y on the domain; clamp to the closure of dom l*
-        un = y > T(0) ? T(1) - bb / y : (bb > T(0) ? T(-1e30) : T(1));
+        // grad of l(y; b) = 1 - b/y on the domain; the dual of a ray outside
+        // the domain is left at 0
+        un = y > T(0) ? T(1) - bb / y : T(0);
     }
     c.u[ip] = un;
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_dual_init_v(DevCtx<T> c) {
+__global__ __launch_bounds__(256) void k_dual_init_v(const DevCtx<T>* __restrict__ ctxs) {
+    const DevCtx<T>& c = ctxs[0];
     const int N = c.N;
     const size_t NN = (size_t)N * N;
     const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -669,16 +778,6 @@ __global__ __launch_bounds__(256) void k_dual_init_v(DevCtx<T> c) {
     c.v[pix + NN] = vv;
 }
 
-template <class T>
-inline int fft_threads(const DevCtx<T>& c) {
-    int t = c.N / 2;
-    if (t < 64) t = 64;
-    if (t > 256) t = 256;
-    return t;
-}
-
-inline unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
-
 __global__ void k_control(Control* ctl, int op, int iter_value, double f_target) {
     if (threadIdx.x != 0) return;
     if (op == 0) ctl->iter = 0;
@@ -688,161 +787,173 @@ __global__ void k_control(Control* ctl, int op, int iter_value, double f_target)
     ctl->f_target = f_target;
 }
 
+inline unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
+
+template <class T>
+inline size_t fft_lds(int N) { return 2 * (size_t)N * sizeof(T); }
+
+template <class T, int MODE>
+hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, int projector, T* out,
+                          hipStream_t st) {
+    if (projector == 1)
+        hipLaunchKernelGGL((k_project<T, MODE, 1>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
+    else
+        hipLaunchKernelGGL((k_project<T, MODE, 2>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
+int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
+int bp_blocks(int N) { return (N / 8) * (N / 8); }
 
 hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target, hipStream_t st) {
     hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, st, ctl, op, iter_value, f_target);
     return hipGetLastError();
 }
 
-int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
-int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
-
 template <class T>
-hipError_t launch_backproject_iter(const DevCtx<T>& c, hipStream_t st) {
-    const int nb = (c.N / 8) * (c.N / 8);
-    hipLaunchKernelGGL((k_backproject<T, true>), dim3(nb), dim3(256), 0, st, c, (const T*)c.u, (T*)nullptr);
+hipError_t launch_iteration_phase(const IterLaunch<T>& L, int phase, hipStream_t st) {
+    const size_t sm = fft_lds<T>(L.max_N);
+    switch (phase) {
+        case 0:
+            hipLaunchKernelGGL((k_backproject<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
+                               L.bp.map, (const T*)nullptr, (T*)nullptr);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(L.rows.blocks), dim3(kFftThreads), sm, st, L.ctxs,
+                               L.rows.map, (const T*)nullptr, 1);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_fft_cols<T>), dim3(L.cols.blocks), dim3(kFftThreads), sm, st, L.ctxs, L.cols.map,
+                               T(1), 1);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_fft_rows_inv<T, true>), dim3(L.rows.blocks), dim3(kFftThreads), sm, st, L.ctxs,
+                               L.rows.map, (T*)nullptr);
+            break;
+        case 4:
+            return launch_project<T, PMODE_ITER>(L.ctxs, L.proj.map, L.proj.blocks, L.projector, (T*)nullptr, st);
+        default:
+            hipLaunchKernelGGL((k_finalize_iter<T>), dim3(L.fin.blocks), dim3(256), 0, st, L.ctxs, L.fin.map);
+            break;
+    }
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_backproject_plain(const DevCtx<T>& c, const T* y_padded, T* out, hipStream_t st) {
-    const int nb = (c.N / 8) * (c.N / 8);
-    hipLaunchKernelGGL((k_backproject<T, false>), dim3(nb), dim3(256), 0, st, c, y_padded, out);
+hipError_t launch_iteration(const IterLaunch<T>& L, hipStream_t st) {
+    for (int ph = 0; ph < kNumPhases; ++ph) {
+        const hipError_t e = launch_iteration_phase<T>(L, ph, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <class T>
+hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y_padded, T* out,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL((k_backproject<T, false>), dim3(bp_blocks(hc.N)), dim3(kBpWaves * 64), 0, st, dc,
+                       (const Slot*)nullptr, y_padded, out);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fft_rows_fwd(const DevCtx<T>& c, const T* src, bool iter, hipStream_t st) {
-    const size_t sm = 2 * (size_t)c.N * sizeof(T);
-    hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(c.N / 2), dim3(fft_threads(c)), sm, st, c, src, iter ? 1 : 0);
+hipError_t launch_apply_minv(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* w, T* out, T scale,
+                             hipStream_t st) {
+    const size_t sm = fft_lds<T>(hc.N);
+    hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, w, 0);
+    hipLaunchKernelGGL((k_fft_cols<T>), dim3(hc.N / 2 + 1), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, scale, 0);
+    hipLaunchKernelGGL((k_fft_rows_inv<T, false>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, out);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fft_cols(const DevCtx<T>& c, T scale, bool iter, hipStream_t st) {
-    const size_t sm = 2 * (size_t)c.N * sizeof(T);
-    hipLaunchKernelGGL((k_fft_cols<T>), dim3(c.N / 2 + 1), dim3(fft_threads(c)), sm, st, c, scale, iter ? 1 : 0);
+hipError_t launch_pad_image(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st) {
+    hipLaunchKernelGGL((k_pad_image<T>), dim3(tv_blocks(hc.N)), dim3(256), 0, st, dc, img);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fft_rows_inv_update(const DevCtx<T>& c, hipStream_t st) {
-    const size_t sm = 2 * (size_t)c.N * sizeof(T);
-    hipLaunchKernelGGL((k_fft_rows_inv<T, true>), dim3(c.N / 2), dim3(fft_threads(c)), sm, st, c, (T*)nullptr);
-    return hipGetLastError();
+hipError_t launch_project_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, T* out, hipStream_t st) {
+    return launch_project<T, PMODE_PLAIN>(dc, nullptr, project_blocks(hc.NA, hc.NS), projector, out, st);
 }
 
 template <class T>
-hipError_t launch_fft_rows_inv_plain(const DevCtx<T>& c, T* out, hipStream_t st) {
-    const size_t sm = 2 * (size_t)c.N * sizeof(T);
-    hipLaunchKernelGGL((k_fft_rows_inv<T, false>), dim3(c.N / 2), dim3(fft_threads(c)), sm, st, c, out);
-    return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_tv_update(const DevCtx<T>& c, hipStream_t st) {
-    hipLaunchKernelGGL((k_tv<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c);
-    return hipGetLastError();
-}
-
-template <class T, int MODE>
-hipError_t launch_project(const DevCtx<T>& c, const T* img, const T* imgT, T* out, hipStream_t st) {
-    const dim3 grid(project_blocks(c.NA, c.NS)), block(256);
-    if (c.projector == 1)
-        hipLaunchKernelGGL((k_project_lds<T, MODE>), grid, block, 0, st, c, img, imgT, out);
-    else
-        hipLaunchKernelGGL((k_project_direct<T, MODE>), grid, block, 0, st, c, img, imgT, out);
-    return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_project_iter(const DevCtx<T>& c, hipStream_t st) {
-    return launch_project<T, PMODE_ITER>(c, c.xbar, c.xbarT, (T*)nullptr, st);
-}
-
-template <class T>
-hipError_t launch_pad_image(const DevCtx<T>& c, const T* img, hipStream_t st) {
-    hipLaunchKernelGGL((k_pad_image<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c, img);
-    return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_project_plain(const DevCtx<T>& c, T* out, hipStream_t st) {
-    return launch_project<T, PMODE_PLAIN>(c, c.xsc, c.xscT, out, st);
-}
-
-template <class T>
-hipError_t launch_project_setp(const DevCtx<T>& c, hipStream_t st) {
-    return launch_project<T, PMODE_SETP>(c, c.xsc, c.xscT, (T*)nullptr, st);
-}
-
-template <class T>
-hipError_t launch_finalize_iter(const DevCtx<T>& c, hipStream_t st) {
-    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, c, project_blocks(c.NA, c.NS), tv_blocks(c.N), 0);
-    return hipGetLastError();
+hipError_t launch_project_setp(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, hipStream_t st) {
+    return launch_project<T, PMODE_SETP>(dc, nullptr, project_blocks(hc.NA, hc.NS), projector, (T*)nullptr, st);
 }
 
 // f(img): project into the scratch sinogram (unpadded view), data and TV
 // partials, then reduce into ctl->eval_out.
 template <class T>
-hipError_t launch_eval_objective(const DevCtx<T>& c, const T* img, hipStream_t st) {
-    const size_t m = (size_t)c.NA * c.NS;
+hipError_t launch_eval_objective(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, const T* img,
+                                 hipStream_t st) {
+    const size_t m = (size_t)hc.NA * hc.NS;
     hipError_t e;
-    if ((e = launch_pad_image<T>(c, img, st)) != hipSuccess) return e;
-    if ((e = launch_project<T, PMODE_PLAIN>(c, c.xsc, c.xscT, c.ysc, st)) != hipSuccess) return e;
+    if ((e = launch_pad_image<T>(hc, dc, img, st)) != hipSuccess) return e;
+    if ((e = launch_project_plain<T>(hc, dc, projector, hc.ysc, st)) != hipSuccess) return e;
     const unsigned nd = blocks_for(m);
-    hipLaunchKernelGGL((k_data_eval<T>), dim3(nd), dim3(256), 0, st, c, (const T*)c.ysc);
-    hipLaunchKernelGGL((k_tv_eval<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c, img);
-    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, c, (int)nd, tv_blocks(c.N), 1);
+    hipLaunchKernelGGL((k_data_eval<T>), dim3(nd), dim3(256), 0, st, dc, (const T*)hc.ysc);
+    hipLaunchKernelGGL((k_tv_eval<T>), dim3(tv_blocks(hc.N)), dim3(256), 0, st, dc, img);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, dc, (int)nd, tv_blocks(hc.N), 1);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_pad_sinogram(const DevCtx<T>& c, const T* y, T* y_padded, hipStream_t st) {
-    hipLaunchKernelGGL((k_pad<T>), dim3(blocks_for((size_t)c.NA * c.PU)), dim3(256), 0, st, c, y, y_padded);
+hipError_t launch_pad_sinogram(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y, T* y_padded, hipStream_t st) {
+    hipLaunchKernelGGL((k_pad<T>), dim3(blocks_for((size_t)hc.NA * hc.PU)), dim3(256), 0, st, dc, y, y_padded);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_unpad_sinogram(const DevCtx<T>& c, const T* y_padded, T* y, hipStream_t st) {
-    hipLaunchKernelGGL((k_unpad<T>), dim3(blocks_for((size_t)c.NA * c.NS)), dim3(256), 0, st, c, y_padded, y);
+hipError_t launch_unpad_sinogram(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y_padded, T* y,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL((k_unpad<T>), dim3(blocks_for((size_t)hc.NA * hc.NS)), dim3(256), 0, st, dc, y_padded, y);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_data_const(const DevCtx<T>& c, hipStream_t st) {
-    const unsigned nd = blocks_for((size_t)c.NA * c.NS);
-    hipLaunchKernelGGL((k_lgamma_part<T>), dim3(nd), dim3(256), 0, st, c);
-    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, c, (int)nd, 0, 2);
+hipError_t launch_data_const(const DevCtx<T>& hc, const DevCtx<T>* dc, hipStream_t st) {
+    const unsigned nd = blocks_for((size_t)hc.NA * hc.NS);
+    hipLaunchKernelGGL((k_lgamma_part<T>), dim3(nd), dim3(256), 0, st, dc);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, dc, (int)nd, 0, 2);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_dual_init(const DevCtx<T>& c, hipStream_t st) {
-    hipLaunchKernelGGL((k_dual_init_u<T>), dim3(blocks_for((size_t)c.NA * c.NS)), dim3(256), 0, st, c);
-    hipLaunchKernelGGL((k_dual_init_v<T>), dim3(tv_blocks(c.N)), dim3(256), 0, st, c);
+hipError_t launch_dual_init(const DevCtx<T>& hc, const DevCtx<T>* dc, hipStream_t st) {
+    hipLaunchKernelGGL((k_dual_init_u<T>), dim3(blocks_for((size_t)hc.NA * hc.NS)), dim3(256), 0, st, dc);
+    hipLaunchKernelGGL((k_dual_init_v<T>), dim3(tv_blocks(hc.N)), dim3(256), 0, st, dc);
     return hipGetLastError();
 }
 
-#define NCS_INSTANTIATE(T)                                                                       \
-    template hipError_t launch_backproject_iter<T>(const DevCtx<T>&, hipStream_t);               \
-    template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const T*, T*, hipStream_t); \
-    template hipError_t launch_fft_rows_fwd<T>(const DevCtx<T>&, const T*, bool, hipStream_t);   \
-    template hipError_t launch_fft_cols<T>(const DevCtx<T>&, T, bool, hipStream_t);              \
-    template hipError_t launch_fft_rows_inv_update<T>(const DevCtx<T>&, hipStream_t);            \
-    template hipError_t launch_fft_rows_inv_plain<T>(const DevCtx<T>&, T*, hipStream_t);         \
-    template hipError_t launch_tv_update<T>(const DevCtx<T>&, hipStream_t);                      \
-    template hipError_t launch_project_iter<T>(const DevCtx<T>&, hipStream_t);                   \
-    template hipError_t launch_project_plain<T>(const DevCtx<T>&, T*, hipStream_t);              \
-    template hipError_t launch_project_setp<T>(const DevCtx<T>&, hipStream_t);                   \
-    template hipError_t launch_pad_image<T>(const DevCtx<T>&, const T*, hipStream_t);            \
-    template hipError_t launch_finalize_iter<T>(const DevCtx<T>&, hipStream_t);                  \
-    template hipError_t launch_eval_objective<T>(const DevCtx<T>&, const T*, hipStream_t);       \
-    template hipError_t launch_pad_sinogram<T>(const DevCtx<T>&, const T*, T*, hipStream_t);     \
-    template hipError_t launch_unpad_sinogram<T>(const DevCtx<T>&, const T*, T*, hipStream_t);   \
-    template hipError_t launch_data_const<T>(const DevCtx<T>&, hipStream_t);                     \
-    template hipError_t launch_dual_init<T>(const DevCtx<T>&, hipStream_t);
+template <class T>
+hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, hipStream_t st) {
+    const unsigned nd = blocks_for((size_t)hc.NA * hc.NS);
+    hipLaunchKernelGGL((k_ones_image<T>), dim3(tv_blocks(hc.N)), dim3(256), 0, st, dc);
+    hipError_t e;
+    if ((e = launch_project_plain<T>(hc, dc, projector, hc.ysc, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sumsq<T>), dim3(nd), dim3(256), 0, st, dc, (const T*)hc.ysc);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(1), dim3(256), 0, st, dc, (int)nd, 0, 3);
+    return hipGetLastError();
+}
+
+#define NCS_INSTANTIATE(T)                                                                                        \
+    template hipError_t launch_iteration<T>(const IterLaunch<T>&, hipStream_t);                                  \
+    template hipError_t launch_iteration_phase<T>(const IterLaunch<T>&, int, hipStream_t);                       \
+    template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t); \
+    template hipError_t launch_apply_minv<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, T, hipStream_t);  \
+    template hipError_t launch_pad_image<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, hipStream_t);          \
+    template hipError_t launch_project_plain<T>(const DevCtx<T>&, const DevCtx<T>*, int, T*, hipStream_t);       \
+    template hipError_t launch_project_setp<T>(const DevCtx<T>&, const DevCtx<T>*, int, hipStream_t);            \
+    template hipError_t launch_eval_objective<T>(const DevCtx<T>&, const DevCtx<T>*, int, const T*, hipStream_t); \
+    template hipError_t launch_pad_sinogram<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t);   \
+    template hipError_t launch_unpad_sinogram<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t); \
+    template hipError_t launch_data_const<T>(const DevCtx<T>&, const DevCtx<T>*, hipStream_t);                   \
+    template hipError_t launch_dual_init<T>(const DevCtx<T>&, const DevCtx<T>*, hipStream_t);                   \
+    template hipError_t launch_e1_norm<T>(const DevCtx<T>&, const DevCtx<T>*, int, hipStream_t);
 
 NCS_INSTANTIATE(float)
 NCS_INSTANTIATE(double)

@@ -45,9 +45,10 @@ EXPORTED = [
     "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_state", "ncs_set_state",
     "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_get_eigenvalues",
     "ncs_time_phases", "ncs_get_info", "ncs_destroy", "ncs_last_error",
+    "ncs_batch_setup", "ncs_batch_set_init", "ncs_batch_solve", "ncs_batch_slice", "ncs_batch_destroy",
 ]
-PHASES = ["backproject", "fft_rows", "fft_cols_multiplier", "fft_rows_inv_update", "tv_update",
-          "project_dataprox", "objective_reduce"]
+PHASES = ["backproject", "fft_rows", "fft_cols_multiplier", "fft_rows_inv_update",
+          "project_dataprox_tv", "objective_reduce"]
 
 
 class NcsError(RuntimeError):
@@ -109,6 +110,12 @@ def load_library() -> ctypes.CDLL:
         "ncs_time_phases": ([vp, i32, pdbl], i32),
         "ncs_get_info": ([vp, ctypes.POINTER(_Info)], i32),
         "ncs_destroy": ([vp], None),
+        "ncs_batch_setup": ([i32, ctypes.POINTER(_Geometry), ctypes.POINTER(_Params), i32,
+                             ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(vp)], i32),
+        "ncs_batch_set_init": ([vp, ctypes.POINTER(vp), i32], i32),
+        "ncs_batch_solve": ([vp, i32, pdbl, pi32, pdbl], i32),
+        "ncs_batch_slice": ([vp, i32, ctypes.POINTER(vp)], i32),
+        "ncs_batch_destroy": ([vp], None),
         "ncs_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sigs.items():
@@ -301,6 +308,94 @@ class Solver:
     def close(self) -> None:
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.ncs_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _SliceView(Solver):
+    """A slice of a Batch: the Solver interface on a handle the batch owns."""
+
+    def __init__(self, batch: "Batch", i: int, geom: Geometry, params: Params):
+        self.lib = batch.lib
+        self.geom = geom
+        self.params = params
+        self.dtype = batch.dtype
+        self.device = batch.device
+        self._b = batch._b[i]
+        self._bg = None
+        self.stream = batch.stream
+        h = ctypes.c_void_p()
+        _check(self.lib.ncs_batch_slice(batch.h, i, ctypes.byref(h)))
+        self.h = h
+
+    def close(self) -> None:   # owned by the batch
+        self.h = ctypes.c_void_p()
+
+
+class Batch:
+    """Many independent slices of uneven size solved by shared launches."""
+
+    def __init__(self, geoms: list, params: list, bs: list, bgs: list | None = None,
+                 dtype: torch.dtype = torch.float32):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the NCS library needs a GPU; none is visible")
+        n = len(geoms)
+        if not (n == len(params) == len(bs)) or n == 0:
+            raise ValueError("geoms, params and bs must have the same non-zero length")
+        self.lib = load_library()
+        self.dtype = dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.geoms, self.params = list(geoms), list(params)
+        for g, b in zip(geoms, bs):
+            if b.device != self.device or b.dtype != dtype or b.numel() != g.m or not b.is_contiguous():
+                raise ValueError("each b must be a contiguous tensor of n_angles*n_bins elements on the device")
+        self._b = list(bs)
+        self._bg = list(bgs) if bgs is not None else None
+        G = (_Geometry * n)(*[_Geometry(g.n_side, g.n_angles, g.n_bins) for g in geoms])
+        P = (_Params * n)(*[_Params(p.alpha, p.beta, p.gamma, p.lam, p.c_r, p.mu_dc, p.data_term, p.tv_term,
+                                    p.check_every, p.diverge_checks, p.projector, p.graph_chunk) for p in params])
+        B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        BG = None
+        if bgs is not None:
+            BG = (ctypes.c_void_p * n)(*[None if t is None else t.data_ptr() for t in bgs])
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.ncs_batch_setup(n, G, P, NCS_F64 if dtype == torch.float64 else NCS_F32, B, BG,
+                                        self.stream.cuda_stream, ctypes.byref(h)))
+        self.h = h
+        self.n = n
+
+    def set_init(self, x0s: list | None = None, dual_from_x0: bool = False) -> None:
+        arr = None
+        if x0s is not None:
+            self._x0_keep = list(x0s)
+            arr = (ctypes.c_void_p * self.n)(*[None if t is None else t.data_ptr() for t in x0s])
+        _check(self.lib.ncs_batch_set_init(self.h, arr, int(dual_from_x0)))
+
+    def solve(self, max_iters: int, f_targets=None):
+        """Returns (status, iterations per slice, last objective per slice)."""
+        ft = None
+        if f_targets is not None:
+            ft = np.ascontiguousarray(f_targets, dtype=np.float64)
+        it = np.zeros(self.n, dtype=np.int32)
+        f = np.zeros(self.n, dtype=np.float64)
+        st = _check(self.lib.ncs_batch_solve(
+            self.h, max_iters, None if ft is None else ft.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+            allow=(NCS_OK, NCS_NOT_CONVERGED))
+        return st, it, f
+
+    def slice(self, i: int) -> Solver:
+        return _SliceView(self, i, self.geoms[i], self.params[i])
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.ncs_batch_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):

@@ -124,7 +124,10 @@ def test_circulant_solve_matches_oracle(key, prec):
     par = ct_params(geom[0], geom[1])
     s = _solver(geom, DT[prec], b=prob.b, par=par, lam=prob.lam)
     mu_ref = problems.eigenvalues(prob, par)
-    np.testing.assert_allclose(s.eigenvalues(), mu_ref, rtol=1e-12)
+    # the DC entry uses |E 1|^2 from the handle's own projector in its own
+    # precision (FP32: ~1e-7 relative); every other entry is host double
+    np.testing.assert_allclose(s.eigenvalues(), mu_ref, rtol=1e-12 if prec == "f64" else 1e-6)
+    np.testing.assert_allclose(s.eigenvalues().ravel()[1:], mu_ref.ravel()[1:], rtol=1e-13)
     h = problems.multiplier(prob, par)
     w = np.random.default_rng(4).standard_normal(geom[0] ** 2)
     ref = operators.apply_circulant(h, w.reshape(geom[0], geom[0])).ravel()
