@@ -17,6 +17,13 @@ Recipe (same for every consumer):
 * the uneven 512-slice batch: 205 slices of 128^2, 205 of 256^2, 102 of 512^2,
   shuffled with ``default_rng(4242)``; angles = round(1.4 * side), bins =
   side + side // 64.
+* warm-start network: initial parameters from ``default_rng([seed, 3])``,
+  He-normal weights (std sqrt(2 / (9 C_in))) rounded to float32, zero biases,
+  the last layer scaled by ``scale_last`` (0: the network starts as the
+  identity map of its input); training slices use seeds 1,000,000 + i,
+  validation 2,000,000 + i, evaluation 0..31.
+* bfloat16-exact test tensors: k 2^-e with integer |k| <= 255, so every value
+  is exactly representable in bfloat16 and float32.
 """
 from __future__ import annotations
 
@@ -29,7 +36,13 @@ __all__ = [
     "poisson_counts",
     "batch_sides",
     "batch_geometry",
+    "cnn_init",
+    "bf16_exact",
+    "CNN_LAYERS",
 ]
+
+# (C_in, C_out) of the six 3x3 layers of the warm-start network
+CNN_LAYERS = [(1, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]
 
 
 def ellipse_params(seed: int) -> np.ndarray:
@@ -85,3 +98,23 @@ def batch_sides(n_small: int = 205, n_mid: int = 205, n_large: int = 102) -> np.
 def batch_geometry(side: int) -> tuple[int, int, int]:
     """(n_side, n_angles, n_bins) of one slice of the uneven batch."""
     return int(side), int(round(1.4 * side)), int(side + side // 64)
+
+
+def cnn_init(seed: int, scale_last: float = 0.0) -> np.ndarray:
+    """Initial flat parameter vector of the warm-start network (float64 holding
+    float32 values): per layer the weights [9, C_out, C_in], then the biases."""
+    rng = np.random.default_rng([seed, 3])
+    parts = []
+    for l, (ci, co) in enumerate(CNN_LAYERS):
+        w = rng.standard_normal(9 * co * ci) * np.sqrt(2.0 / (9 * ci))
+        if l == len(CNN_LAYERS) - 1:
+            w = w * scale_last
+        parts += [w, np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
+
+
+def bf16_exact(seed: int, shape, exponent: int = 8, positive: bool = False) -> np.ndarray:
+    """Random values k * 2^-exponent with integer |k| <= 255 (k >= 0 if positive)."""
+    rng = np.random.default_rng([seed, 4])
+    k = rng.integers(0 if positive else -255, 256, size=shape)
+    return k.astype(np.float64) * 2.0 ** -exponent
