@@ -165,6 +165,14 @@ ncs_status ncs_adjoint(ncs_handle* h, const void* y_dev, void* x_dev);
 ncs_status ncs_apply_minv(ncs_handle* h, const void* w_dev, void* out_dev);
 ncs_status ncs_objective(ncs_handle* h, const void* x_dev, double* f);
 
+/* Filtered backprojection with the method's own circulant inverse:
+ * x = alpha M^+ E^T y (N*N values from N_theta*N_s).  Since E^T E is close to
+ * the circulant of eq. (circ_R), this approximates the least-squares image
+ * (E^T E)^-1 E^T y with the regularisation that M adds; it is also (1 + alpha)
+ * times the second CT iterate of NCS started from zero.  It is the input of
+ * the learned warm start (ncs_cnn.h). */
+ncs_status ncs_prefilter(ncs_handle* h, const void* y_dev, void* x_dev);
+
 /* Facts about a handle, computed in double on the host at setup. */
 typedef struct {
     int64_t nnz;       /* nonzero entries of E (Joseph taps with weight != 0 inside the image) */

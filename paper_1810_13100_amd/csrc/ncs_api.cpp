@@ -30,6 +30,13 @@ void set_err(const char* fmt, ...) {
     g_err = buf;
 }
 
+}  // namespace
+
+// Error message for ncs_last_error(), shared with the network's host code.
+void ncs::set_error_message(const char* msg) { g_err = msg; }
+
+namespace {
+
 #define NCS_HIP(expr)                                                                               \
     do {                                                                                            \
         hipError_t e_ = (expr);                                                                     \
@@ -868,6 +875,31 @@ ncs_status ncs_apply_minv(ncs_handle* h, const void* w_dev, void* out_dev) {
                                             (double*)out_dev, (double)h->p.alpha, h->stream)
                 : launch_apply_minv<float>(make_ctx<float>(h), dctx<float>(h), (const float*)w_dev,
                                            (float*)out_dev, (float)h->p.alpha, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_prefilter(ncs_handle* h, const void* y_dev, void* x_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!x_dev || !y_dev) {
+        set_err("ncs_prefilter: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    // E^T y into the handle's backprojection buffer (not live between
+    // iterations), then alpha M^+: the column pass scales h/(alpha N^2) by alpha^2
+    if (h->dtype == NCS_F64) {
+        const DevCtx<double> c = make_ctx<double>(h);
+        const double a = h->p.alpha;
+        NCS_HIP(launch_pad_sinogram<double>(c, dctx<double>(h), (const double*)y_dev, c.ysc, h->stream));
+        NCS_HIP(launch_backproject_plain<double>(c, dctx<double>(h), c.ysc, c.w, h->stream));
+        NCS_HIP(launch_apply_minv<double>(c, dctx<double>(h), c.w, (double*)x_dev, a * a, h->stream));
+    } else {
+        const DevCtx<float> c = make_ctx<float>(h);
+        const float a2 = (float)(h->p.alpha * h->p.alpha);
+        NCS_HIP(launch_pad_sinogram<float>(c, dctx<float>(h), (const float*)y_dev, c.ysc, h->stream));
+        NCS_HIP(launch_backproject_plain<float>(c, dctx<float>(h), c.ysc, c.w, h->stream));
+        NCS_HIP(launch_apply_minv<float>(c, dctx<float>(h), c.w, (float*)x_dev, a2, h->stream));
+    }
     return NCS_OK;
 }
 

@@ -133,6 +133,9 @@ template <class T> hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T
 //   op 2: set    (iter = iter_value, stop = 0, status = 0, f_target)
 hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target, hipStream_t st);
 
+// Sets the message returned by ncs_last_error() on this thread.
+void set_error_message(const char* msg);
+
 int project_blocks(int NA, int NS);
 int tv_blocks(int N);
 int bp_blocks(int N);

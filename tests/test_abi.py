@@ -1,25 +1,29 @@
-"""The C-ABI library loads and exports every function that include/ncs.h declares
+"""The C-ABI library loads and exports every function that include/*.h declares
 (no GPU needed; no compute call is made)."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ncs.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(ROOT, "paper_1810_13100_amd", "libncs.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ncs_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(ncs_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_api():
     names = declared_functions()
-    for n in ("ncs_setup", "ncs_iterate", "ncs_solve", "ncs_destroy", "ncs_last_error"):
+    for n in ("ncs_setup", "ncs_iterate", "ncs_solve", "ncs_destroy", "ncs_last_error", "ncs_prefilter",
+              "ncs_cnn_create", "ncs_cnn_forward", "ncs_cnn_train_step", "ncs_conv3x3_bf16"):
         assert n in names
 
 
@@ -29,8 +33,8 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    from paper_1810_13100_amd import ncs
-    assert sorted(ncs.EXPORTED) == declared_functions()
+    from paper_1810_13100_amd import cnn, ncs
+    assert sorted(ncs.EXPORTED + cnn.EXPORTED) == declared_functions()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libncs.so not built")
