@@ -96,6 +96,10 @@ typedef struct {
                           faster, 1 = LDS-staged image tiles, 2 = direct coalesced loads */
     int32_t graph_chunk; /* iterations per replayed HIP graph; 0 selects 25, < 0 disables
                             graphs (every kernel launched directly) */
+    double dual_ramp;    /* ncs_set_init with dual_from_x0: width tau of the ramp of the TV
+                            dual, v = s clamp(D x0 / tau, -1, 1) (anisotropic) or
+                            s (D x0)_p / max(|(D x0)_p|, tau) (isotropic); <= 0 gives the
+                            sign, v = s sign(D x0) */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;
@@ -116,7 +120,10 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
  * are taken from the fixed-point relations of the optimality conditions
  * (Section 3.2, Fact on fixed points): u = grad g_data(E x0) and
  * v = s sign(D x0) (anisotropic) or s (D x0)/|(D x0)_p| (isotropic) where the
- * difference is nonzero, 0 elsewhere, with s = lambda alpha / beta. */
+ * difference is nonzero, 0 elsewhere, with s = lambda alpha / beta.  With
+ * params.dual_ramp = tau > 0 the sign is replaced by the ramp
+ * clamp(D x0 / tau, -1, 1), so that near-flat regions of x0 (where the
+ * optimal v is strictly inside [-s, s]) start near v = 0. */
 ncs_status ncs_set_init(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0);
 
 /* Run exactly k >= 0 iterations (each: one x-update, one (u, v)-update, one
@@ -148,6 +155,10 @@ ncs_status ncs_get_x(ncs_handle* h, void* x_out_dev);
 
 /* Copy the current data dual u (N_theta*N_s values) to u_out_dev. */
 ncs_status ncs_get_u(ncs_handle* h, void* u_out_dev);
+
+/* Copy the current TV dual v (2*N*N values: the horizontal-difference plane,
+ * then the vertical one, each row-major) to v_out_dev. */
+ncs_status ncs_get_v(ncs_handle* h, void* v_out_dev);
 
 /* Checkpoint: the full state (x, u, v, E x, iteration count) as an opaque
  * host blob.  With host_buf NULL, *bytes receives the size needed.  Resuming

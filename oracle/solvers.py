@@ -170,3 +170,31 @@ def admm_classic(prob: Problem, par: Params, iters: int, x0, lam0, ata_pinv_solv
         lm = lm + z - A(x) + btil
         xs.append(x)
     return xs, y1
+
+
+def fixed_point_duals(prob: Problem, par: Params, x0: np.ndarray, tau: float = 0.0):
+    """Duals (u, v) of a warm start at x0 from the fixed-point relations
+    (Section 3.2, lemma on fixed points): at a fixed point u is the gradient of
+    the data term at E x (CT: E x - b; PET: 1 - b / (E x + r)), and v lies in
+    the subdifferential of s |.|_1 (anisotropic) or s |.|_2 per pixel
+    (isotropic) at D x, s = lambda alpha / beta.  Reading: where that
+    subdifferential is an interval (D x = 0) v = 0; with tau > 0 the sign is
+    replaced by the ramp clamp(D x / tau, -1, 1) (isotropic: D x / max(|D x|, tau)).
+    A PET ray outside the domain (E x + r <= 0) gets u = 0."""
+    n = prob.n
+    y = prob.E @ x0
+    if prob.kind == "ct":
+        u = y - prob.b
+    else:
+        yy = y + prob.bg
+        u = np.where(yy > 0, 1.0 - prob.b / np.where(yy > 0, yy, 1.0), 0.0)
+    g = prob.D @ x0
+    s = prob.lam * par.alpha / par.beta
+    if prob.tv == "aniso":
+        v = s * (np.clip(g / tau, -1.0, 1.0) if tau > 0 else np.sign(g))
+    else:
+        gh, gv = g[:n], g[n:]
+        den = np.maximum(np.sqrt(gh * gh + gv * gv), tau)
+        safe = np.where(den > 0, den, 1.0)
+        v = np.concatenate([np.where(den > 0, s * gh / safe, 0.0), np.where(den > 0, s * gv / safe, 0.0)])
+    return u, v

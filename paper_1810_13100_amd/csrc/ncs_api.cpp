@@ -157,6 +157,7 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
     c.alpha = (T)h->p.alpha;
     c.beta = (T)h->p.beta;
     c.s_tv = (T)(h->p.lambda * h->p.alpha / h->p.beta);
+    c.dual_ramp = (T)(h->p.dual_ramp > 0.0 ? h->p.dual_ramp : 0.0);
     c.inv1pa = (T)(1.0 / (1.0 + h->p.alpha));
     c.lambda = h->p.lambda;
     c.data_term = h->p.data_term;
@@ -359,7 +360,7 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
     }
     if (!(p.alpha > 0.0) || !(p.beta > 0.0) || !(p.gamma >= 0.0) || !(p.lambda >= 0.0) ||
         !std::isfinite(p.alpha) || !std::isfinite(p.beta) || !std::isfinite(p.gamma) ||
-        !std::isfinite(p.lambda) || !std::isfinite(p.c_r) || !std::isfinite(p.mu_dc)) {
+        !std::isfinite(p.lambda) || !std::isfinite(p.c_r) || !std::isfinite(p.mu_dc) || !std::isfinite(p.dual_ramp)) {
         set_err("need finite alpha > 0, beta > 0, gamma >= 0, lambda >= 0");
         return NCS_ERR_INVALID_ARG;
     }
@@ -750,6 +751,17 @@ ncs_status ncs_get_u(ncs_handle* h, void* u_out_dev) {
                                                                 (const double*)h->u, (double*)u_out_dev, h->stream)
                                 : launch_unpad_sinogram<float>(make_ctx<float>(h), dctx<float>(h),
                                                                (const float*)h->u, (float*)u_out_dev, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_get_v(ncs_handle* h, void* v_out_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!v_out_dev) {
+        set_err("ncs_get_v: null output");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(hipMemcpyAsync(v_out_dev, h->v, 2 * h->n * h->esz, hipMemcpyDeviceToDevice, h->stream));
     return NCS_OK;
 }
 

@@ -80,6 +80,7 @@ struct DevCtx {
     NCS_G Control* ctl;
     NCS_G double* hist;
     T alpha, beta, s_tv, inv1pa;
+    T dual_ramp;                     // TV-dual ramp width of the warm start (<= 0: sign)
     double lambda;
     int data_term, tv_term;
 };

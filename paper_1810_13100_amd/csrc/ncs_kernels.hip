@@ -30,9 +30,9 @@ namespace {
 
 constexpr int kRays = 64;      // rays per projector workgroup (one per lane)
 constexpr int kWaves = 4;      // waves per projector / TV workgroup
-constexpr int kSeg = 64;       // steps per LDS segment (LDS-staged projector)
-constexpr int kPitch = 161;    // LDS row pitch: >= 63*sqrt(2) + 63 + 5, odd
-constexpr int kBpWaves = 8;    // backprojector: angle groups per 8 x 8 pixel tile
+constexpr int kRowWin = 100;   // LDS-staged projector: padded-row elements staged per step
+constexpr int kStageRows = 16; // LDS-staged projector: steps staged at a time by one wave
+constexpr int kBpWaves = 8;    // backprojector: waves per 16 x 16 pixel tile
 constexpr int kFftThreads = 256;
 
 template <class T>
@@ -147,10 +147,21 @@ __device__ void fft_dif(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int
 }
 
 // ---------------------------------------------------------------------------
-// Backprojection (pixel-driven gather, matched to the ray-driven projector).
-// Workgroup: an 8 x 8 pixel tile; each of the 8 waves takes every 8th angle;
-// the partial sums are added in a fixed order.
+// Backprojection (pixel-driven gather, matched to the ray-driven projector)
+// with LDS-staged detector windows.  Workgroup: a 16 x 16 pixel tile.  For
+// each angle the tile's pixels touch at most kBpWin consecutive detector bins
+// (the tile spans 15 (|cos| + |sin|) <= 21.3 bins, plus the second tap and a
+// rounding margin); those windows are staged in LDS for a chunk of angles
+// with coalesced loads, so the per-tap reads go to LDS rather than through
+// the vector-memory address path.  Waves 0-3 take the first half of each
+// chunk's angles, waves 4-7 the second half, 64 pixels (4 rows) per wave;
+// the two halves are added in a fixed order.
 // ---------------------------------------------------------------------------
+constexpr int kBpTile = 16;
+constexpr int kBpWin = 26;
+template <class T>
+constexpr int bp_chunk() { return sizeof(T) == 4 ? 384 : 192; }
+
 template <class T, bool ITER>
 __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(const DevCtx<T>* __restrict__ ctxs,
                                                                const Slot* __restrict__ map,
@@ -159,41 +170,65 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(const DevCtx<T>* 
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
     if (ITER && c.ctl->stop) return;
-    __shared__ T red[kBpWaves * 64];
+    constexpr int CH = bp_chunk<T>();
+    __shared__ T win[CH * kBpWin];
+    __shared__ int wbase[CH];
+    __shared__ T red[4 * 64];
     const T* ysrc = ITER ? c.u : ysrc_plain;
     const int N = c.N;
-    const int tiles_x = N >> 3;
+    const int tiles_x = N / kBpTile;
     const int tx = local % tiles_x, ty = local / tiles_x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int col = tx * 8 + (lane & 7);
-    const int row = ty * 8 + (lane >> 3);
+    const int g = wave & 3, half = wave >> 2;
+    const int col = tx * kBpTile + (lane & 15);
+    const int row = ty * kBpTile + g * 4 + (lane >> 4);
     const T fc = (T)col, fr = (T)row;
     const T tmax = (T)c.NS;
-    const int PU = c.PU;
-    const int NA = c.NA;
+    const int PU = c.PU, NA = c.NA, NS = c.NS;
+    const T c0 = (T)(tx * kBpTile), r0 = (T)(ty * kBpTile), span = (T)(kBpTile - 1);
     const AngleT<T>* ang = c.ang;
     T acc = T(0);
+    for (int a0 = 0; a0 < NA; a0 += CH) {
+        const int nch = min(CH, NA - a0);
+        __syncthreads();   // the previous chunk has been consumed
+        // window of angle a: bins wbase .. wbase + kBpWin - 1, starting one below
+        // the smallest clamped detector coordinate of the tile
+        for (int k = threadIdx.x; k < nch; k += kBpWaves * 64) {
+            const AngleT<T> A = ang[a0 + k];
+            const T tmin = fma(c0, A.q1, fma(r0, A.q2, A.q0)) + span * (fmin(A.q1, T(0)) + fmin(A.q2, T(0)));
+            wbase[k] = (int)floor(med3(tmin, T(-1), tmax)) - 1;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nch * kBpWin; e += kBpWaves * 64) {
+            const int k = e / kBpWin, j = e - k * kBpWin;
+            const int d = wbase[k] + j;   // bins -1, NS and NS + 1 are the zero pads of the row
+            win[e] = (d >= -1 && d <= NS + 1) ? ysrc[(size_t)(a0 + k) * PU + 1 + d] : T(0);
+        }
+        __syncthreads();
+        const int kmid = (nch + 1) >> 1;
+        const int kbeg = half ? kmid : 0, kend = half ? nch : kmid;
 #pragma unroll 4
-    for (int a = wave; a < NA; a += kBpWaves) {
-        const AngleT<T> A = ang[a];
-        // outside the detector both taps land on the zero pads at d = -1, N_s, N_s + 1
-        const T t = med3(fma(fc, A.q1, fma(fr, A.q2, A.q0)), T(-1), tmax);
-        const T fl = floor(t);
-        const T f = t - fl;
-        const unsigned off = (unsigned)((int)fl + 1);
-        const Pair<T> y = load_pair(ysrc + (size_t)a * PU + off);
-        const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
-        const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
-        acc = fma(w0, y.a, acc);
-        acc = fma(w1, y.b, acc);
+        for (int k = kbeg; k < kend; ++k) {
+            const AngleT<T> A = ang[a0 + k];
+            // outside the detector both taps land on the zero pads
+            const T t = med3(fma(fc, A.q1, fma(fr, A.q2, A.q0)), T(-1), tmax);
+            const T fl = floor(t);
+            const T f = t - fl;
+            int j = (int)fl - wbase[k];
+            j = min(max(j, 0), kBpWin - 2);
+            const T* wp = win + k * kBpWin + j;
+            const T y0 = wp[0], y1 = wp[1];
+            const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
+            const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
+            acc = fma(w0, y0, acc);
+            acc = fma(w1, y1, acc);
+        }
     }
-    red[wave * 64 + lane] = acc;
+    if (half) red[g * 64 + lane] = acc;
     __syncthreads();
-    if (wave != 0) return;
-    T bp = red[lane];
-#pragma unroll
-    for (int w = 1; w < kBpWaves; ++w) bp += red[w * 64 + lane];
+    if (half) return;
+    const T bp = acc + red[g * 64 + lane];
     const size_t pix = (size_t)row * N + col;
     if (!ITER) {
         out[pix] = bp;
@@ -303,57 +338,77 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
     return acc;
 }
 
-// Ray sum by LDS-staged tiles: the stepping axis is cut into segments of 64
-// steps; for each segment the bounding box of the sampled coordinates of all
-// 64 rays is staged in LDS with coalesced loads (transposed on the fly for
-// column-stepping angles), then each wave marches 16 steps of every ray.
+// Ray sum with LDS-staged row windows.  For each step s the 64 rays of the
+// block read padded-row elements in [lo, lo + 95] (the block spans
+// 63 |k1| <= 89.1 columns), lo from the clamped smallest coordinate of the
+// block; each wave stages those 100-element windows (16-byte aligned) for
+// kStageRows of its steps at a time with 16-byte loads into a region of LDS
+// only it uses, then marches the steps reading both taps from LDS.  The
+// arithmetic of every tap is that of the direct method.
 template <class T>
-__device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, const AngleT<T>& A, int axis,
-                                int d0, int d, int lane, int wave, T* tile) {
-    const int N = c.N;
+struct alignas(16) Quad {
+    T v[4];
+};
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T>
+__device__ inline int row_window_base(const AngleT<T>& A, int s, T blo, T cmax) {
+    // element index (column + 2) of the column left of the clamped smallest coordinate
+    const int lo = (int)med3(floor(fma((T)s, A.k2, blo)), T(-2), cmax) + 1;
+    return lo & ~3;
+}
+
+template <class T>
+__device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
+                                const AngleT<T>& A, int axis, int d0, int d, int lane, int wave, T* stage,
+                                int* rbase) {
+    const int N = c.N, P = c.P;
+    const T* src = axis == 0 ? img : imgT;
     const T base = fma((T)d, A.k1, A.k0);
-    const T bA = fma((T)d0, A.k1, A.k0);
-    const T bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
-    const int SL = N < kSeg ? N : kSeg;
-    const int SW = SL / kWaves;
+    const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
+    const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
+    const T lo_x = T(-2), hi_x = T(N + 1);
+    const int SW = N / kWaves;
+    int s_begin = wave * SW, s_end = s_begin + SW;
+    if (A.k2 > T(0)) {
+        s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
+    } else if (A.k2 < T(0)) {
+        s_begin = max(s_begin, sat_int(floor((hi_x - blo) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
+    } else if (bhi < lo_x || blo > hi_x) {
+        s_end = s_begin;
+    }
+    const T cmax = (T)N;
+    constexpr int NQ = kRowWin / 4;
     T acc = T(0);
-    for (int s0 = 0; s0 < N; s0 += SL) {
-        const T sA = (T)s0, sB = (T)(s0 + SL - 1);
-        const T e0 = fma(sA, A.k2, bA), e1 = fma(sB, A.k2, bA);
-        const T e2 = fma(sA, A.k2, bB), e3 = fma(sB, A.k2, bB);
-        const T mn = fmin(fmin(e0, e1), fmin(e2, e3));
-        const T mx = fmax(fmax(e0, e1), fmax(e2, e3));
-        const int lo = (int)floor(mn) - 1;
-        const int hi = (int)floor(mx) + 2;
-        if (hi < 0 || lo > N - 1) continue;   // the whole ray block misses the image here
-        int W = hi - lo + 1;
-        W = W > kPitch ? kPitch : W;
-        __syncthreads();
-        if (axis == 0) {
-            for (int sl = wave; sl < SL; sl += kWaves) {
-                const T* rowp = img + (size_t)(s0 + sl) * c.P + 2;
-                for (int j = lane; j < W; j += 64) {
-                    const int cc = lo + j;
-                    tile[sl * kPitch + j] = (cc >= 0 && cc < N) ? rowp[cc] : T(0);
-                }
-            }
-        } else {
-            for (int j = wave; j < W; j += kWaves) {
-                const int rr = lo + j;
-                const bool ok = rr >= 0 && rr < N;
-                const T* rowp = img + (size_t)(ok ? rr : 0) * c.P + 2 + s0;
-                for (int sl = lane; sl < SL; sl += 64) tile[sl * kPitch + j] = ok ? rowp[sl] : T(0);
-            }
+    for (int s0 = s_begin; s0 < s_end; s0 += kStageRows) {
+        const int ns = min(kStageRows, s_end - s0);
+        wave_lds_sync();   // the previous rows have been read
+        if (lane < ns) rbase[lane] = row_window_base(A, s0 + lane, blo, cmax);
+        for (int qi = lane; qi < ns * NQ; qi += 64) {
+            const int i = qi / NQ, q = qi - i * NQ;
+            const int e = row_window_base(A, s0 + i, blo, cmax) + 4 * q;
+            Quad<T> v;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v.v[k] = T(0);
+            // P and e are multiples of 4: a quad is wholly inside the padded row or wholly outside
+            if (e >= 0 && e < P) v = *reinterpret_cast<const Quad<T>*>(src + (size_t)(s0 + i) * P + e);
+            *reinterpret_cast<Quad<T>*>(stage + i * kRowWin + 4 * q) = v;
         }
-        __syncthreads();
-        const int sb = wave * SW;
-        for (int sl = sb; sl < sb + SW; ++sl) {
-            const T xi = fma((T)(s0 + sl), A.k2, base);
-            const T fl = floor(xi);
+        wave_lds_sync();
+        for (int i = 0; i < ns; ++i) {
+            const T xi = fma((T)(s0 + i), A.k2, base);
+            const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
             const T f = xi - fl;
-            int j = (int)fl - lo;
-            j = min(max(j, 0), W - 2);
-            const T* tp = tile + sl * kPitch + j;
+            int j = (int)fl + 2 - rbase[i];
+            j = min(max(j, 0), kRowWin - 2);
+            const T* tp = stage + i * kRowWin + j;
             const T v0 = tp[0], v1 = tp[1];
             acc += fma(f, v1 - v0, v0);
         }
@@ -453,8 +508,10 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     const int axis = c.axis[a];
     T acc;
     if (VARIANT == 1) {
-        __shared__ T tile[kSeg * kPitch];
-        acc = ray_sum_lds(c, img, A, axis, d0, d, lane, wave, tile);
+        __shared__ __attribute__((aligned(16))) T stage[kWaves * kStageRows * kRowWin];
+        __shared__ int rbase[kWaves * kStageRows];
+        acc = ray_sum_lds(c, img, imgT, A, axis, d0, d, lane, wave, stage + wave * kStageRows * kRowWin,
+                          rbase + wave * kStageRows);
     } else {
         acc = ray_sum_direct(c, img, imgT, A, axis, d0, d, wave);
     }
@@ -765,14 +822,21 @@ __global__ __launch_bounds__(256) void k_dual_init_v(const DevCtx<T>* __restrict
     const T dh = col < N - 1 ? xx - c.x[pix + 1] : T(0);
     const T dv = r < N - 1 ? xx - c.x[pix + N] : T(0);
     const T s = c.s_tv;
+    const T tau = c.dual_ramp;
     T vh, vv;
     if (c.tv_term == TV_ANISO) {
-        vh = dh > T(0) ? s : (dh < T(0) ? -s : T(0));
-        vv = dv > T(0) ? s : (dv < T(0) ? -s : T(0));
+        if (tau > T(0)) {
+            vh = s * fmin(fmax(dh / tau, T(-1)), T(1));
+            vv = s * fmin(fmax(dv / tau, T(-1)), T(1));
+        } else {
+            vh = dh > T(0) ? s : (dh < T(0) ? -s : T(0));
+            vv = dv > T(0) ? s : (dv < T(0) ? -s : T(0));
+        }
     } else {
         const T nrm = sqrt(fma(dh, dh, dv * dv));
-        vh = nrm > T(0) ? s * dh / nrm : T(0);
-        vv = nrm > T(0) ? s * dv / nrm : T(0);
+        const T den = fmax(nrm, tau);
+        vh = den > T(0) ? s * dh / den : T(0);
+        vv = den > T(0) ? s * dv / den : T(0);
     }
     c.v[pix] = vh;
     c.v[pix + NN] = vv;
@@ -806,7 +870,7 @@ hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, in
 
 int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
 int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
-int bp_blocks(int N) { return (N / 8) * (N / 8); }
+int bp_blocks(int N) { return (N / kBpTile) * (N / kBpTile); }
 
 hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target, hipStream_t st) {
     hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, st, ctl, op, iter_value, f_target);

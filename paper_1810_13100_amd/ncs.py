@@ -42,7 +42,7 @@ _STATUS_NAMES = {
 
 EXPORTED = [
     "ncs_setup", "ncs_set_init", "ncs_iterate", "ncs_solve", "ncs_get_objectives",
-    "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_state", "ncs_set_state",
+    "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_v", "ncs_get_state", "ncs_set_state",
     "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_prefilter", "ncs_get_eigenvalues",
     "ncs_time_phases", "ncs_get_info", "ncs_destroy", "ncs_last_error",
     "ncs_batch_setup", "ncs_batch_set_init", "ncs_batch_solve", "ncs_batch_slice", "ncs_batch_destroy",
@@ -68,6 +68,7 @@ class _Params(ctypes.Structure):
         ("data_term", ctypes.c_int32), ("tv_term", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("diverge_checks", ctypes.c_int32),
         ("projector", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
+        ("dual_ramp", ctypes.c_double),
     ]
 
 
@@ -100,6 +101,7 @@ def load_library() -> ctypes.CDLL:
         "ncs_get_iteration": ([vp, pi32], i32),
         "ncs_get_x": ([vp, vp], i32),
         "ncs_get_u": ([vp, vp], i32),
+        "ncs_get_v": ([vp, vp], i32),
         "ncs_get_state": ([vp, vp, psz], i32),
         "ncs_set_state": ([vp, vp, ctypes.c_size_t], i32),
         "ncs_forward": ([vp, vp, vp], i32),
@@ -163,6 +165,7 @@ class Params:
     diverge_checks: int = 0
     projector: int = 0        # 0: autotune at setup, 1: LDS-staged, 2: direct
     graph_chunk: int = 0      # 0: 25 iterations per HIP graph, < 0: no graphs
+    dual_ramp: float = 0.0    # TV-dual ramp width of the warm start (0: sign)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -188,7 +191,7 @@ class Solver:
         g = _Geometry(geom.n_side, geom.n_angles, geom.n_bins)
         p = _Params(params.alpha, params.beta, params.gamma, params.lam, params.c_r, params.mu_dc,
                     params.data_term, params.tv_term, params.check_every, params.diverge_checks,
-                    params.projector, params.graph_chunk)
+                    params.projector, params.graph_chunk, params.dual_ramp)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.ncs_setup(ctypes.byref(g), ctypes.byref(p),
@@ -255,6 +258,11 @@ class Solver:
     def u(self) -> torch.Tensor:
         out = torch.empty(self.geom.m, dtype=self.dtype, device=self.device)
         _check(self.lib.ncs_get_u(self.h, out.data_ptr()))
+        return out
+
+    def v(self) -> torch.Tensor:
+        out = torch.empty(2 * self.geom.n, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_get_v(self.h, out.data_ptr()))
         return out
 
     def get_state(self) -> bytes:
@@ -365,7 +373,8 @@ class Batch:
         self._bg = list(bgs) if bgs is not None else None
         G = (_Geometry * n)(*[_Geometry(g.n_side, g.n_angles, g.n_bins) for g in geoms])
         P = (_Params * n)(*[_Params(p.alpha, p.beta, p.gamma, p.lam, p.c_r, p.mu_dc, p.data_term, p.tv_term,
-                                    p.check_every, p.diverge_checks, p.projector, p.graph_chunk) for p in params])
+                                    p.check_every, p.diverge_checks, p.projector, p.graph_chunk, p.dual_ramp)
+                              for p in params])
         B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
         BG = None
         if bgs is not None:

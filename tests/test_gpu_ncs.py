@@ -12,8 +12,9 @@ import numpy as np
 import pytest
 import torch
 
+import ncs_inputs
 from gpu_common import GEOMS, ct_params, ct_problem, joseph, log, oracle_ncs, pet_problem, rel_l2
-from oracle import problems
+from oracle import problems, solvers
 from paper_1810_13100_amd import ncs
 
 pytestmark = pytest.mark.gpu
@@ -22,12 +23,12 @@ DT = {"f32": torch.float32, "f64": torch.float64}
 TOL = {"f64": (1e-10, 1e-10), "f32": (1e-4, 1e-5)}
 
 
-def make_solver(prob, par, dtype, check_every=50, diverge_checks=0, projector=0, graph_chunk=0):
+def make_solver(prob, par, dtype, check_every=50, diverge_checks=0, projector=0, graph_chunk=0, dual_ramp=0.0):
     data = ncs.DATA_POISSON if prob.kind == "pet" else ncs.DATA_QUADRATIC
     tv = ncs.TV_ISO if prob.tv == "iso" else ncs.TV_ANISO
     p = ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0,
                    data_term=data, tv_term=tv, check_every=check_every, diverge_checks=diverge_checks,
-                   projector=projector, graph_chunk=graph_chunk)
+                   projector=projector, graph_chunk=graph_chunk, dual_ramp=dual_ramp)
     b = torch.tensor(prob.b, dtype=dtype, device=DEV)
     bg = torch.tensor(prob.bg, dtype=dtype, device=DEV) if prob.kind == "pet" else None
     return ncs.Solver(ncs.Geometry(prob.n_side, prob.n_angles, prob.n_bins), p, b=b, bg=bg, dtype=dtype)
@@ -233,3 +234,25 @@ def test_a3_violation_is_reported_as_divergence():
         s.solve(5000)
     assert e.value.status in (ncs.NCS_ERR_DIVERGED, ncs.NCS_ERR_NONFINITE)
     s.close()
+
+
+@pytest.mark.parametrize("kind", ["ct", "ct_iso", "pet"])
+@pytest.mark.parametrize("tau", [0.0, 0.05])
+def test_fixed_point_dual_init(kind, tau):
+    # ncs_set_init with dual_from_x0 against the oracle's fixed-point duals
+    if kind == "pet":
+        prob, par = pet_problem("c3"), pet_params(128, 180)
+    else:
+        prob = ct_problem("c1") if kind == "ct" else ct_problem("c1", seed=2, lam=0.5, tv="iso")
+        par = ct_params(64, 90)
+    x0 = ncs_inputs.phantom(prob.n_side, 7).ravel()
+    u_ref, v_ref = solvers.fixed_point_duals(prob, par, x0, tau)
+    s = make_solver(prob, par, torch.float64, dual_ramp=tau)
+    s.set_init(torch.tensor(x0, dtype=torch.float64, device=DEV), dual_from_x0=True)
+    u = s.u().cpu().numpy()
+    v = s.v().cpu().numpy()
+    s.close()
+    eu = np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref))
+    ev = np.max(np.abs(v - v_ref)) / max(np.max(np.abs(v_ref)), 1e-300)
+    log(f"dual init {kind} tau {tau}: max rel err u {eu:.1e}, v {ev:.1e}")
+    assert eu <= 1e-10 and ev <= 1e-12

@@ -180,3 +180,22 @@ def test_tv_of_step_image():
     dot[5, 5] = 1.0                           # pixel (5,5) pairs (1, 1); (5,4) and (4,5) one unit each
     assert objective.tv(prob, dot.ravel()) == pytest.approx(4.0)
     assert objective.tv(prob_iso, dot.ravel()) == pytest.approx(2.0 + np.sqrt(2.0))
+
+
+def test_fixed_point_duals_match_the_ncs_limit():
+    # At the limit of NCS the duals are determined where the image has an edge:
+    # u* = E x* - b everywhere (CT), v* = s sign(D x*) where |D x*| is not small.
+    prob = problems.ct_problem(16, 12, 23, 0, 0.05)
+    par = problems.Params(0.05, 0.15, 0.3 * 0.05 * 12 * 16 / np.pi)
+    traj = solvers.ncs(prob, par, 20000, record=False)
+    u0, v0 = solvers.fixed_point_duals(prob, par, traj.x)
+    np.testing.assert_allclose(u0, traj.u, rtol=0, atol=1e-8 * np.abs(traj.u).max())
+    edge = np.abs(prob.D @ traj.x) > 1e-3
+    assert edge.sum() > 50
+    np.testing.assert_allclose(v0[edge], traj.v[edge], rtol=1e-8, atol=1e-10)
+    # the ramp agrees with the sign wherever |D x| >= tau
+    tau = 1e-2
+    _, vr = solvers.fixed_point_duals(prob, par, traj.x, tau)
+    big = np.abs(prob.D @ traj.x) >= tau
+    np.testing.assert_array_equal(vr[big], v0[big])
+    assert np.all(np.abs(vr) <= np.abs(v0) + 1e-15)
