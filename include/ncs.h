@@ -184,6 +184,13 @@ ncs_status ncs_objective(ncs_handle* h, const void* x_dev, double* f);
  * the learned warm start (ncs_cnn.h). */
 ncs_status ncs_prefilter(ncs_handle* h, const void* y_dev, void* x_dev);
 
+/* Filtered backprojection x = (pi / N_theta) E^T (h * y): each projection is
+ * convolved over the detector with the Shepp-Logan filter for unit bin
+ * spacing, h(n) = -2 / (pi^2 (4 n^2 - 1)) (zero outside the detector), then
+ * backprojected.  It approximates the image whose line integrals are y, and
+ * is the input of the learned warm start (ncs_cnn.h).  At most 4096 bins. */
+ncs_status ncs_fbp(ncs_handle* h, const void* y_dev, void* x_dev);
+
 /* Facts about a handle, computed in double on the host at setup. */
 typedef struct {
     int64_t nnz;       /* nonzero entries of E (Joseph taps with weight != 0 inside the image) */

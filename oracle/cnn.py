@@ -158,3 +158,20 @@ def prefilter(E, h: np.ndarray, alpha: float, y: np.ndarray) -> np.ndarray:
     from .operators import apply_circulant
     n = h.shape[0]
     return alpha * apply_circulant(h, (E.T @ y).reshape(n, n))
+
+
+def shepp_logan(n_bins: int) -> np.ndarray:
+    """Shepp-Logan filter taps h(n) = -2 / (pi^2 (4 n^2 - 1)) for unit spacing,
+    n = -(n_bins - 1) .. n_bins - 1 (Shepp and Logan, 1974)."""
+    n = np.arange(-(n_bins - 1), n_bins, dtype=np.float64)
+    return -2.0 / (np.pi ** 2 * (4.0 * n * n - 1.0))
+
+
+def fbp(E, n_angles: int, n_bins: int, y: np.ndarray) -> np.ndarray:
+    """Filtered backprojection (pi / N_theta) E^T q with q[a] the linear
+    convolution of projection a with the Shepp-Logan filter, kept on the
+    detector's n_bins samples (zero outside the detector)."""
+    h = shepp_logan(n_bins)
+    ys = np.asarray(y, dtype=np.float64).reshape(n_angles, n_bins)
+    q = np.stack([np.convolve(row, h, mode="full")[n_bins - 1:2 * n_bins - 1] for row in ys])
+    return (np.pi / n_angles) * (E.T @ q.ravel())

@@ -915,6 +915,23 @@ ncs_status ncs_prefilter(ncs_handle* h, const void* y_dev, void* x_dev) {
     return NCS_OK;
 }
 
+ncs_status ncs_fbp(ncs_handle* h, const void* y_dev, void* x_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!x_dev || !y_dev) {
+        set_err("ncs_fbp: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (h->g.n_bins > 4096) {
+        set_err("ncs_fbp: at most 4096 detector bins (got %d)", h->g.n_bins);
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(h->dtype == NCS_F64
+                ? launch_fbp<double>(make_ctx<double>(h), dctx<double>(h), (const double*)y_dev, (double*)x_dev, h->stream)
+                : launch_fbp<float>(make_ctx<float>(h), dctx<float>(h), (const float*)y_dev, (float*)x_dev, h->stream));
+    return NCS_OK;
+}
+
 ncs_status ncs_objective(ncs_handle* h, const void* x_dev, double* f) {
     ncs_status s = check_handle(h);
     if (s) return s;

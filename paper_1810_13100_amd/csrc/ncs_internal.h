@@ -115,6 +115,9 @@ template <class T> hipError_t launch_iteration_phase(const IterLaunch<T>& L, int
 // Single-slice operators.  `hc` is the host copy of the descriptor (launch
 // sizes), `dc` its device copy.
 template <class T> hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y_padded, T* out, hipStream_t st);
+// Filtered backprojection: Shepp-Logan filter per projection (into the padded
+// scratch sinogram), then the backprojection; out = N*N image.
+template <class T> hipError_t launch_fbp(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y, T* out, hipStream_t st);
 template <class T> hipError_t launch_apply_minv(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* w, T* out, T scale, hipStream_t st);
 template <class T> hipError_t launch_pad_image(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st);
 // Plain projections read the padded scratch pair (xsc, xscT): pad first.

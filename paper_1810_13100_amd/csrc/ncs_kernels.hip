@@ -842,6 +842,43 @@ __global__ __launch_bounds__(256) void k_dual_init_v(const DevCtx<T>* __restrict
     c.v[pix + NN] = vv;
 }
 
+// Shepp-Logan filtering of each projection (filtered backprojection): with
+// unit bin spacing the filter is h(n) = -2 / (pi^2 (4 n^2 - 1)), applied as a
+// linear convolution over the detector (zero outside it).  The output goes to
+// the padded sinogram, scaled by pi / N_theta so that one backprojection gives
+// the FBP image.  One workgroup per angle; the projection and the filter taps
+// are staged in LDS.
+constexpr int kFbpMaxBins = 4096;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fbp_filter(const DevCtx<T>* __restrict__ ctxs, const T* __restrict__ y,
+                                                    T* __restrict__ ypad) {
+    const DevCtx<T>& c = ctxs[0];
+    extern __shared__ unsigned char fbp_smem[];
+    T* yl = reinterpret_cast<T*>(fbp_smem);
+    T* hl = yl + c.NS;
+    const int a = blockIdx.x, NS = c.NS;
+    const double pi = 3.14159265358979323846;
+    for (int k = threadIdx.x; k < NS; k += 256) {
+        yl[k] = y[(size_t)a * NS + k];
+        const double nn = (double)k;
+        hl[k] = (T)(-2.0 / (pi * pi * (4.0 * nn * nn - 1.0)));
+    }
+    __syncthreads();
+    const T scale = (T)(pi / (double)c.NA);
+    T* out = ypad + (size_t)a * c.PU;
+    for (int d = threadIdx.x; d < NS; d += 256) {
+        T acc = T(0);
+        for (int k = 0; k < NS; ++k) acc = fma(hl[d > k ? d - k : k - d], yl[k], acc);
+        out[1 + d] = acc * scale;
+    }
+    if (threadIdx.x == 0) {
+        out[0] = T(0);
+        out[NS + 1] = T(0);
+        out[NS + 2] = T(0);
+    }
+}
+
 __global__ void k_control(Control* ctl, int op, int iter_value, double f_target) {
     if (threadIdx.x != 0) return;
     if (op == 0) ctl->iter = 0;
@@ -921,6 +958,16 @@ hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, co
     hipLaunchKernelGGL((k_backproject<T, false>), dim3(bp_blocks(hc.N)), dim3(kBpWaves * 64), 0, st, dc,
                        (const Slot*)nullptr, y_padded, out);
     return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fbp(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y, T* out, hipStream_t st) {
+    if (hc.NS > kFbpMaxBins) return hipErrorInvalidValue;
+    const size_t sm = 2 * (size_t)hc.NS * sizeof(T);
+    hipLaunchKernelGGL((k_fbp_filter<T>), dim3(hc.NA), dim3(256), sm, st, dc, y, hc.ysc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_backproject_plain<T>(hc, dc, hc.ysc, out, st);
 }
 
 template <class T>
@@ -1009,6 +1056,7 @@ hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projecto
     template hipError_t launch_iteration_phase<T>(const IterLaunch<T>&, int, hipStream_t);                       \
     template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t); \
     template hipError_t launch_apply_minv<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, T, hipStream_t);  \
+    template hipError_t launch_fbp<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t);            \
     template hipError_t launch_pad_image<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, hipStream_t);          \
     template hipError_t launch_project_plain<T>(const DevCtx<T>&, const DevCtx<T>*, int, T*, hipStream_t);       \
     template hipError_t launch_project_setp<T>(const DevCtx<T>&, const DevCtx<T>*, int, hipStream_t);            \

@@ -43,7 +43,7 @@ _STATUS_NAMES = {
 EXPORTED = [
     "ncs_setup", "ncs_set_init", "ncs_iterate", "ncs_solve", "ncs_get_objectives",
     "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_v", "ncs_get_state", "ncs_set_state",
-    "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_prefilter", "ncs_get_eigenvalues",
+    "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_prefilter", "ncs_fbp", "ncs_get_eigenvalues",
     "ncs_time_phases", "ncs_get_info", "ncs_destroy", "ncs_last_error",
     "ncs_batch_setup", "ncs_batch_set_init", "ncs_batch_solve", "ncs_batch_slice", "ncs_batch_destroy",
 ]
@@ -108,6 +108,7 @@ def load_library() -> ctypes.CDLL:
         "ncs_adjoint": ([vp, vp, vp], i32),
         "ncs_apply_minv": ([vp, vp, vp], i32),
         "ncs_prefilter": ([vp, vp, vp], i32),
+        "ncs_fbp": ([vp, vp, vp], i32),
         "ncs_objective": ([vp, vp, pdbl], i32),
         "ncs_get_eigenvalues": ([vp, pdbl], i32),
         "ncs_time_phases": ([vp, i32, pdbl], i32),
@@ -296,6 +297,12 @@ class Solver:
         """alpha M^+ E^T y: the filtered backprojection that feeds the warm-start network."""
         out = torch.empty(self.geom.n, dtype=self.dtype, device=self.device)
         _check(self.lib.ncs_prefilter(self.h, self._sino(y, "y").data_ptr(), out.data_ptr()))
+        return out
+
+    def fbp(self, y: torch.Tensor) -> torch.Tensor:
+        """Filtered backprojection (pi / N_theta) E^T (h * y) with the Shepp-Logan filter."""
+        out = torch.empty(self.geom.n, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_fbp(self.h, self._sino(y, "y").data_ptr(), out.data_ptr()))
         return out
 
     def objective(self, x: torch.Tensor) -> float:

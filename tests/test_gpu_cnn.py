@@ -192,3 +192,20 @@ def test_prefilter_matches_oracle(prec):
     log(f"prefilter {prec}: rel-L2 {e:.2e}")
     assert e <= (1e-11 if prec == "f64" else 1e-5)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("key", ["c1", "tiny"])
+def test_fbp_matches_oracle(prec, key):
+    from gpu_common import GEOMS, joseph
+    n, na, ns = GEOMS[key]
+    E = joseph(n, na, ns)
+    y = np.random.default_rng(12).standard_normal(na * ns) + E @ ncs_inputs.phantom(n, 3).ravel()
+    ref = ocnn.fbp(E, na, ns, y)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    s = ncs.Solver(ncs.Geometry(n, na, ns), ncs.Params(0.01, 0.03, 1.0, 0.01), dtype=dt)
+    out = s.fbp(torch.tensor(y, dtype=dt, device=DEV)).double().cpu().numpy()
+    e = rel_l2(out, ref)
+    log(f"fbp {key} {prec}: rel-L2 {e:.2e}")
+    assert e <= (1e-11 if prec == "f64" else 2e-5)
+    s.close()

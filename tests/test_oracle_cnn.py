@@ -127,3 +127,24 @@ def test_prefilter_is_scaled_second_ncs_iterate():
     z = cnn.prefilter(prob.E, h, par.alpha, prob.b)
     x2 = solvers.ncs(prob, par, 2, record=False).x
     np.testing.assert_allclose(z.ravel(), (1 + par.alpha) * x2, rtol=1e-12, atol=1e-14)
+
+
+def test_shepp_logan_frequency_response():
+    # sum_n h(n) e^{-i w n} = |sin(w / 2)| / pi: the ramp |w| / (2 pi) times sinc(w / (2 pi))
+    h = cnn.shepp_logan(100001)
+    n = np.arange(-100000, 100001)
+    for w in (0.05, 0.3, 1.0, 2.0, 2.9, np.pi):
+        assert abs(np.sum(h * np.cos(w * n)) - abs(np.sin(w / 2)) / np.pi) < 1e-9
+
+
+def test_fbp_reconstructs_a_smooth_image():
+    # FBP inverts the projector on a smooth image up to discretisation error
+    from oracle import projector
+    N, NA, NS = 64, 180, 92
+    E = projector.joseph_matrix(N, NA, NS)
+    c = np.arange(N) - (N - 1) / 2
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    img = np.exp(-((xx - 5) ** 2 + (yy + 3) ** 2) / (2 * 8.0 ** 2)) + 0.5 * np.exp(-((xx + 10) ** 2 + yy ** 2) / (2 * 4.0 ** 2))
+    rec = cnn.fbp(E, NA, NS, E @ img.ravel())
+    err = np.linalg.norm(rec - img.ravel()) / np.linalg.norm(img)
+    assert err < 0.05, err
