@@ -26,6 +26,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -94,6 +96,128 @@ def calibration_copy(torch, dev) -> None:
     del src, dst
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1810_13100_amd", "weights", "warmstart_ct256.npy")
+
+
+def time_to_gap(ncs, torch, dev, geom, args) -> dict:
+    """Plain NCS from zero and the learned warm start, each run on its own
+    evaluation slice (seeds 0..n-1) to f <= f* (1 + 1e-4), f* the smallest
+    objective of a long double-precision run of the same slice.  Wall time
+    from "b on the device, setup done" to the stopping iteration."""
+    from paper_1810_13100_amd import warmstart
+    seeds = list(range(args.gap_seeds))
+    op = ncs.Solver(geom, params(ncs))
+    bs = [warmstart.ct_sinogram(op, s) for s in seeds]
+    op.close()
+    progress(f"f*: {args.fstar_iters} double-precision iterations on {len(seeds)} slices")
+    ref = ncs.Batch([geom] * len(seeds), [params(ncs)] * len(seeds), [b.double() for b in bs], dtype=torch.float64)
+    ref.set_init()
+    fstar = np.full(len(seeds), np.inf)
+    done = 0
+    while done < args.fstar_iters:
+        k = min(2000, args.fstar_iters - done)
+        _, _, f = ref.solve(k)
+        fstar = np.minimum(fstar, f)
+        done += k
+    tail = [float(abs(ref.slice(i).objectives(done - 1, 1)[0] - ref.slice(i).objectives(done - 1000, 1)[0])
+                  / abs(fstar[i])) for i in range(len(seeds))]
+    ref.close()
+    net, meta = None, None
+    if os.path.exists(WEIGHTS):
+        from paper_1810_13100_amd import cnn
+        net = cnn.WarmStartNet(1, N_SIDE, N_SIDE)
+        net.set_params(warmstart.load_params(WEIGHTS))
+        meta_path = os.path.splitext(WEIGHTS)[0] + ".json"
+        if os.path.exists(meta_path):
+            with open(meta_path) as f:
+                meta = json.load(f)
+    k0 = int(meta["k0"]) if meta else 300
+    plain_t, plain_it, warm_t, warm_it = [], [], [], []
+    for i, b in enumerate(bs):
+        target = fstar[i] * (1.0 + GAP)
+        s = ncs.Solver(geom, params(ncs), b=b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_init()
+        st, it, _ = s.solve(50000, target)
+        torch.cuda.synchronize()
+        plain_t.append(time.perf_counter() - t0)
+        plain_it.append(it if st == ncs.NCS_OK else None)
+        if net is not None:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it, _ = warmstart.warm_solve(s, net, k0, 50000, target)
+            torch.cuda.synchronize()
+            warm_t.append(time.perf_counter() - t0)
+            warm_it.append(it if st == ncs.NCS_OK else None)
+        s.close()
+        progress(f"  slice {i}: plain {plain_it[-1]} it {plain_t[-1]:.3f} s" +
+                 (f", warm {warm_it[-1]} it {warm_t[-1]:.3f} s" if net is not None else ""))
+    med = lambda v: float(np.median(v)) if v and all(x is not None for x in v) else None
+    out = {"seeds": seeds, "rel_gap": GAP, "f_star": fstar.tolist(),
+           "f_star_source": f"min f over {args.fstar_iters} FP64 iterations of each slice",
+           "f_star_rel_change_last_1000": tail,
+           "plain": {"seconds_median": med(plain_t), "iterations_median": med(plain_it),
+                     "seconds": plain_t, "iterations": plain_it}}
+    if net is not None:
+        out["warm"] = {"seconds_median": med(warm_t), "iterations_median": med(warm_it), "seconds": warm_t,
+                       "iterations": warm_it, "k0": k0, "weights": os.path.relpath(WEIGHTS, ROOT),
+                       "training": meta,
+                       "description": f"{k0} plain iterations, x <- x + N(x) by the network, NCS continued "
+                                      f"with its own duals"}
+        net.close()
+    else:
+        out["warm"] = None
+    return out
+
+
+def batch_throughput(ncs, torch, dev, iters: int) -> dict:
+    """The uneven batch: 205 slices of 128^2, 205 of 256^2 and 102 of 512^2
+    (angles round(1.4 side), bins side + side/64), shuffled; every slice has its
+    own seeded phantom and noise.  Timed: `iters` batch iterations of all 512
+    slices in shared launches (replayed graphs, objective every iteration)."""
+    import ncs_inputs
+    sides = ncs_inputs.batch_sides()
+    ops, geoms, pars, bs = {}, [], [], []
+    progress(f"batch: preparing {len(sides)} slices")
+    for i, side in enumerate(sides):
+        n, na, nb = ncs_inputs.batch_geometry(int(side))
+        g = ncs.Geometry(n, na, nb)
+        c_r = na * n / math.pi
+        alpha = 0.01 * (64.0 / n) ** 2      # the 64^2 and 256^2 tunings, alpha ~ 1/n
+        p = ncs.Params(alpha, BETA_RATIO * alpha, GAMMA_FRAC * alpha * c_r, LAMBDA)
+        if n not in ops:
+            ops[n] = ncs.Solver(g, p)
+        seed = 10_000 + i
+        x = torch.tensor(ncs_inputs.phantom(n, seed).ravel(), dtype=torch.float32, device=dev)
+        clean = ops[n].forward(x)
+        eps = torch.tensor(ncs_inputs.gaussian_noise(seed, g.m), dtype=torch.float32, device=dev)
+        bs.append((clean + 0.01 * float(clean.max()) * eps).contiguous())
+        geoms.append(g)
+        pars.append(p)
+    for o in ops.values():
+        o.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bat = ncs.Batch(geoms, pars, bs)
+    setup_s = time.perf_counter() - t0
+    bat.set_init()
+    bat.solve(5)
+    torch.cuda.synchronize()
+    progress(f"batch: timing {iters} iterations of {len(sides)} slices")
+    t0 = time.perf_counter()
+    _, it, _ = bat.solve(iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bat.close()
+    taps = sum(1.8 * g.n_side * (g.n_side + 1) * g.n_angles for g in geoms)   # nnz(E) estimate per slice
+    return {"slices": len(sides), "mix": {"128": int((sides == 128).sum()), "256": int((sides == 256).sum()),
+                                           "512": int((sides == 512).sum())},
+            "iterations": iters, "seconds": dt, "slice_iterations_per_s": len(sides) * iters / dt,
+            "ms_per_batch_iteration": dt / iters * 1e3, "est_taps_per_s": 2 * taps * iters / dt,
+            "setup_s": setup_s, "alpha": "0.01 (64/N)^2, beta = 3 alpha, gamma = 0.3 alpha C_R"}
+
+
 def cpu_baseline(iters: int) -> dict:
     """The FP64 oracle on the same workload, timed on the host (assembly excluded)."""
     from oracle import problems, solvers
@@ -130,7 +254,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline (0: skip)")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap measurement")
-    ap.add_argument("--fstar-iters", type=int, default=20000)
+    ap.add_argument("--fstar-iters", type=int, default=12000)
+    ap.add_argument("--gap-seeds", type=int, default=8, help="evaluation slices of the time-to-gap measurement")
+    ap.add_argument("--batch-iters", type=int, default=40, help="iterations of the uneven 512-slice batch (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -182,31 +308,9 @@ def main() -> int:
 
     gap = None
     if not args.no_gap:
-        progress(f"f*: {args.fstar_iters} double-precision iterations")
-        s64 = ncs.Solver(geom, params(ncs), b=b.double(), dtype=torch.float64)
-        s64.set_init()
-        chunk = 5000
-        done = 0
-        fmin = math.inf
-        while done < args.fstar_iters:
-            k = min(chunk, args.fstar_iters - done)
-            obj = s64.iterate(k, record=True)
-            fmin = min(fmin, float(obj.min()))
-            done += k
-            progress(f"  f* run: {done} iterations, f = {obj[-1]:.10g}")
-        tail_change = float(abs(obj[-1] - obj[-1000]) / abs(obj[-1])) if len(obj) >= 1000 else None
-        s64.close()
-        target = fmin * (1.0 + GAP)
-        progress("time to gap (plain, x0 = 0)")
-        s.set_init()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st, iters, f = s.solve(50000, target)
-        t_gap = time.perf_counter() - t0
-        gap = {"plain": {"seconds": t_gap, "iterations": iters, "reached": st == ncs.NCS_OK, "f": f},
-               "warm": None, "f_star": fmin, "f_star_rel_change_last_1000": tail_change,
-               "rel_gap": GAP, "f_star_source": f"min f over {args.fstar_iters} FP64 iterations"}
+        gap = time_to_gap(ncs, torch, dev, geom, args)
 
+    batch = batch_throughput(ncs, torch, dev, args.batch_iters) if args.batch_iters > 0 else None
     cpu = cpu_baseline(args.cpu_iters) if args.cpu_iters > 0 else None
     s.close()
     out = {
@@ -218,7 +322,7 @@ def main() -> int:
                    "n_side": N_SIDE, "n_angles": N_ANGLES, "n_bins": N_BINS, "alpha": ALPHA,
                    "beta": BETA_RATIO * ALPHA, "gamma": GAMMA_FRAC * ALPHA * N_ANGLES * N_SIDE / math.pi,
                    "nnz_E": info["nnz"]},
-        "wall_s_timed": wall, "phases_ms": phases, "roofline": roof, "time_to_gap": gap,
+        "wall_s_timed": wall, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "batch": batch,
         "cpu_baseline": cpu, "host": platform.node(),
     }
     print(json.dumps(out), flush=True)

@@ -93,13 +93,16 @@ typedef struct {
     int32_t diverge_checks; /* ncs_solve: stop with NCS_ERR_DIVERGED after this many
                                consecutive checks with a growing objective; <= 0 disables */
     int32_t projector; /* forward-projector kernel: 0 = time both at setup and keep the
-                          faster, 1 = LDS-staged image tiles, 2 = direct coalesced loads */
+                          faster, 1 = LDS-staged row windows, 2 = direct coalesced loads */
     int32_t graph_chunk; /* iterations per replayed HIP graph; 0 selects 25, < 0 disables
                             graphs (every kernel launched directly) */
     double dual_ramp;    /* ncs_set_init with dual_from_x0: width tau of the ramp of the TV
                             dual, v = s clamp(D x0 / tau, -1, 1) (anisotropic) or
                             s (D x0)_p / max(|(D x0)_p|, tau) (isotropic); <= 0 gives the
                             sign, v = s sign(D x0) */
+    int32_t backprojector; /* backprojector kernel: 0 = time both at setup and keep the faster,
+                              1 = LDS-staged detector windows (16 x 16 pixel tiles),
+                              2 = direct global loads (8 x 8 pixel tiles) */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;
@@ -125,6 +128,12 @@ ncs_status ncs_setup(const ncs_geometry* geom, const ncs_params* params, int32_t
  * clamp(D x0 / tau, -1, 1), so that near-flat regions of x0 (where the
  * optimal v is strictly inside [-s, s]) start near v = 0. */
 ncs_status ncs_set_init(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0);
+
+/* Replace the iterate x by x_dev (N*N values) and recompute E x; the duals
+ * u, v and the iteration count are kept.  This is the restart point of the
+ * learned warm start (ncs_cnn.h): a few plain iterations, a corrected x,
+ * then NCS continues with its own duals. */
+ncs_status ncs_set_x(ncs_handle* h, const void* x_dev);
 
 /* Run exactly k >= 0 iterations (each: one x-update, one (u, v)-update, one
  * objective f(x^{k+1}) in double).  obj_host (length k, may be NULL) receives
@@ -197,9 +206,10 @@ typedef struct {
     double c_r;        /* C_R in use */
     double mu_dc;      /* DC eigenvalue of M in use */
     double norm_e1_sq; /* |E 1|^2 */
-    int32_t projector; /* forward-projector kernel in use (1 or 2) */
-    int32_t pad;
-    double projector_ms[2]; /* setup timing of the two variants (0 when not timed) */
+    int32_t projector;     /* forward-projector kernel in use (1 or 2) */
+    int32_t backprojector; /* backprojector kernel in use (1 or 2) */
+    double projector_ms[2];     /* setup timing of the two variants (0 when not timed) */
+    double backprojector_ms[2]; /* setup timing of the two variants (0 when not timed) */
 } ncs_info;
 
 ncs_status ncs_get_info(ncs_handle* h, ncs_info* info);

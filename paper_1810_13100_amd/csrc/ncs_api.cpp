@@ -95,6 +95,8 @@ struct ncs_handle {
     int64_t nnz = -1;           // counted on request
     int projector = 2;
     double projector_ms[2] = {0.0, 0.0};
+    int backprojector = 2;
+    double backprojector_ms[2] = {0.0, 0.0};
     int graph_chunk = 25;                 // <= 0: no graphs
     hipStream_t cap_stream = nullptr;     // private stream used only for graph capture
     hipGraphExec_t graph_exec = nullptr;  // graph_chunk iterations
@@ -117,6 +119,7 @@ struct ncs_batch {
     std::vector<char> active;
     int max_N = 0;
     int projector = 2;
+    int backprojector = 2;
     int check_every = 50;
 };
 
@@ -175,13 +178,14 @@ IterLaunch<T> single_launch(const ncs_handle* h) {
     IterLaunch<T> L{};
     const int N = h->g.n_side;
     L.ctxs = dctx<T>(h);
-    L.bp = {nullptr, bp_blocks(N)};
+    L.bp = {nullptr, bp_blocks(N, h->backprojector)};
     L.rows = {nullptr, N / 2};
     L.cols = {nullptr, N / 2 + 1};
     L.proj = {nullptr, project_blocks(h->g.n_angles, h->g.n_bins) + tv_blocks(N)};
     L.fin = {nullptr, 1};
     L.max_N = N;
     L.projector = h->projector;
+    L.backprojector = h->backprojector;
     return L;
 }
 
@@ -329,6 +333,33 @@ ncs_status autotune_projector(ncs_handle* h) {
     return NCS_OK;
 }
 
+// Backprojector selection: time both variants on this geometry (plain
+// backprojections of the scratch sinogram) and keep the faster.
+template <class T>
+ncs_status autotune_backprojector(ncs_handle* h) {
+    hipEvent_t e0, e1;
+    NCS_HIP(hipEventCreate(&e0));
+    NCS_HIP(hipEventCreate(&e1));
+    const DevCtx<T> c = make_ctx<T>(h);
+    const T* src = static_cast<const T*>(h->ysc);
+    T* out = static_cast<T*>(h->w);
+    const int reps = 5;
+    for (int variant = 1; variant <= 2; ++variant) {
+        NCS_HIP(launch_backproject_plain<T>(c, dctx<T>(h), variant, src, out, h->stream));   // warm-up
+        NCS_HIP(hipEventRecord(e0, h->stream));
+        for (int r = 0; r < reps; ++r) NCS_HIP(launch_backproject_plain<T>(c, dctx<T>(h), variant, src, out, h->stream));
+        NCS_HIP(hipEventRecord(e1, h->stream));
+        NCS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        NCS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        h->backprojector_ms[variant - 1] = ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->backprojector = h->backprojector_ms[0] < h->backprojector_ms[1] ? 1 : 2;
+    return NCS_OK;
+}
+
 ncs_status read_control(ncs_handle* h, Control* out) {
     NCS_HIP(hipMemcpyAsync(out, h->ctl, sizeof(Control), hipMemcpyDeviceToHost, h->stream));
     NCS_HIP(hipStreamSynchronize(h->stream));
@@ -372,6 +403,10 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("unknown tv_term %d", p.tv_term);
         return NCS_ERR_INVALID_ARG;
     }
+    if (p.backprojector < 0 || p.backprojector > 2) {
+        set_err("backprojector must be 0 (auto), 1 (LDS) or 2 (direct)");
+        return NCS_ERR_INVALID_ARG;
+    }
     if (p.projector < 0 || p.projector > 2) {
         set_err("projector must be 0 (auto), 1 (LDS) or 2 (direct)");
         return NCS_ERR_INVALID_ARG;
@@ -390,6 +425,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
     if (h->p.check_every <= 0) h->p.check_every = 50;
     h->graph_chunk = p.graph_chunk == 0 ? 25 : (p.graph_chunk < 0 ? 0 : p.graph_chunk);
     h->projector = p.projector == 0 ? 2 : p.projector;
+    h->backprojector = p.backprojector == 0 ? 2 : p.backprojector;
     h->dtype = dtype;
     h->esz = dtype == NCS_F64 ? 8 : 4;
     h->stream = stream;
@@ -548,6 +584,10 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         s = dtype == NCS_F64 ? autotune_projector<double>(h) : autotune_projector<float>(h);
         if (s) return fail(s);
     }
+    if (autotune && p.backprojector == 0) {
+        s = dtype == NCS_F64 ? autotune_backprojector<double>(h) : autotune_backprojector<float>(h);
+        if (s) return fail(s);
+    }
     *out = h;
     return NCS_OK;
 }
@@ -610,6 +650,28 @@ ncs_status ncs_set_init(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0)
     }
     return h->dtype == NCS_F64 ? init_state<double>(h, x0_dev, dual_from_x0)
                                : init_state<float>(h, x0_dev, dual_from_x0);
+}
+
+ncs_status ncs_set_x(ncs_handle* h, const void* x_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!x_dev) {
+        set_err("ncs_set_x: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    // x = x_dev and p = E x; the duals and the iteration count are kept
+    NCS_HIP(hipMemcpyAsync(h->x, x_dev, h->n * h->esz, hipMemcpyDeviceToDevice, h->stream));
+    if (h->dtype == NCS_F64) {
+        const DevCtx<double> c = make_ctx<double>(h);
+        NCS_HIP(launch_pad_image<double>(c, dctx<double>(h), c.x, h->stream));
+        NCS_HIP(launch_project_setp<double>(c, dctx<double>(h), h->projector, h->stream));
+    } else {
+        const DevCtx<float> c = make_ctx<float>(h);
+        NCS_HIP(launch_pad_image<float>(c, dctx<float>(h), c.x, h->stream));
+        NCS_HIP(launch_project_setp<float>(c, dctx<float>(h), h->projector, h->stream));
+    }
+    NCS_HIP(launch_control(h->ctl, 1, 0, std::nan(""), h->stream));
+    return NCS_OK;
 }
 
 ncs_status ncs_iterate(ncs_handle* h, int32_t k, double* obj_host) {
@@ -866,11 +928,11 @@ ncs_status ncs_adjoint(ncs_handle* h, const void* y_dev, void* x_dev) {
     if (h->dtype == NCS_F64) {
         const DevCtx<double> c = make_ctx<double>(h);
         NCS_HIP(launch_pad_sinogram<double>(c, dctx<double>(h), (const double*)y_dev, c.ysc, h->stream));
-        NCS_HIP(launch_backproject_plain<double>(c, dctx<double>(h), c.ysc, (double*)x_dev, h->stream));
+        NCS_HIP(launch_backproject_plain<double>(c, dctx<double>(h), h->backprojector, c.ysc, (double*)x_dev, h->stream));
     } else {
         const DevCtx<float> c = make_ctx<float>(h);
         NCS_HIP(launch_pad_sinogram<float>(c, dctx<float>(h), (const float*)y_dev, c.ysc, h->stream));
-        NCS_HIP(launch_backproject_plain<float>(c, dctx<float>(h), c.ysc, (float*)x_dev, h->stream));
+        NCS_HIP(launch_backproject_plain<float>(c, dctx<float>(h), h->backprojector, c.ysc, (float*)x_dev, h->stream));
     }
     return NCS_OK;
 }
@@ -903,13 +965,13 @@ ncs_status ncs_prefilter(ncs_handle* h, const void* y_dev, void* x_dev) {
         const DevCtx<double> c = make_ctx<double>(h);
         const double a = h->p.alpha;
         NCS_HIP(launch_pad_sinogram<double>(c, dctx<double>(h), (const double*)y_dev, c.ysc, h->stream));
-        NCS_HIP(launch_backproject_plain<double>(c, dctx<double>(h), c.ysc, c.w, h->stream));
+        NCS_HIP(launch_backproject_plain<double>(c, dctx<double>(h), h->backprojector, c.ysc, c.w, h->stream));
         NCS_HIP(launch_apply_minv<double>(c, dctx<double>(h), c.w, (double*)x_dev, a * a, h->stream));
     } else {
         const DevCtx<float> c = make_ctx<float>(h);
         const float a2 = (float)(h->p.alpha * h->p.alpha);
         NCS_HIP(launch_pad_sinogram<float>(c, dctx<float>(h), (const float*)y_dev, c.ysc, h->stream));
-        NCS_HIP(launch_backproject_plain<float>(c, dctx<float>(h), c.ysc, c.w, h->stream));
+        NCS_HIP(launch_backproject_plain<float>(c, dctx<float>(h), h->backprojector, c.ysc, c.w, h->stream));
         NCS_HIP(launch_apply_minv<float>(c, dctx<float>(h), c.w, (float*)x_dev, a2, h->stream));
     }
     return NCS_OK;
@@ -927,8 +989,8 @@ ncs_status ncs_fbp(ncs_handle* h, const void* y_dev, void* x_dev) {
         return NCS_ERR_INVALID_ARG;
     }
     NCS_HIP(h->dtype == NCS_F64
-                ? launch_fbp<double>(make_ctx<double>(h), dctx<double>(h), (const double*)y_dev, (double*)x_dev, h->stream)
-                : launch_fbp<float>(make_ctx<float>(h), dctx<float>(h), (const float*)y_dev, (float*)x_dev, h->stream));
+                ? launch_fbp<double>(make_ctx<double>(h), dctx<double>(h), h->backprojector, (const double*)y_dev, (double*)x_dev, h->stream)
+                : launch_fbp<float>(make_ctx<float>(h), dctx<float>(h), h->backprojector, (const float*)y_dev, (float*)x_dev, h->stream));
     return NCS_OK;
 }
 
@@ -1005,9 +1067,11 @@ ncs_status ncs_get_info(ncs_handle* h, ncs_info* info) {
     info->mu_dc = h->mu_dc;
     info->norm_e1_sq = h->norm_e1_sq;
     info->projector = h->projector;
-    info->pad = 0;
+    info->backprojector = h->backprojector;
     info->projector_ms[0] = h->projector_ms[0];
     info->projector_ms[1] = h->projector_ms[1];
+    info->backprojector_ms[0] = h->backprojector_ms[0];
+    info->backprojector_ms[1] = h->backprojector_ms[1];
     return NCS_OK;
 }
 
@@ -1039,7 +1103,7 @@ ncs_status build_maps(ncs_batch* B) {
         if (!B->active[i]) continue;
         const ncs_handle* h = B->slices[i];
         const int N = h->g.n_side;
-        const int cnt[5] = {bp_blocks(N), N / 2, N / 2 + 1,
+        const int cnt[5] = {bp_blocks(N, B->backprojector), N / 2, N / 2 + 1,
                             project_blocks(h->g.n_angles, h->g.n_bins) + tv_blocks(N), 1};
         const int x = B->xcd_of[i];
         for (int ph = 0; ph < nphase; ++ph)
@@ -1078,11 +1142,62 @@ hipError_t batch_iterate(ncs_batch* B, int k) {
     L.fin = {B->maps[4], B->blocks[4]};
     L.max_N = B->max_N;
     L.projector = B->projector;
+    L.backprojector = B->backprojector;
     for (int i = 0; i < k; ++i) {
         const hipError_t e = launch_iteration<T>(L, B->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+
+// Kernel selection for a batch: time a few batched iterations of every
+// candidate (projector, backprojector) pair on the zeroed state of all
+// slices and keep the fastest (the whole batch loads the GPU differently from
+// the single-slice timing done at slice setup).
+template <class T>
+ncs_status autotune_batch(ncs_batch* B, bool tune_p, bool tune_b) {
+    for (ncs_handle* h : B->slices) {
+        ncs_status s = init_state<T>(h, nullptr, 0);
+        if (s) return s;
+    }
+    const int p0 = B->projector, b0 = B->backprojector;
+    hipEvent_t e0, e1;
+    NCS_HIP(hipEventCreate(&e0));
+    NCS_HIP(hipEventCreate(&e1));
+    float best = -1.f;
+    int bp = p0, bb = b0;
+    for (int pv = 1; pv <= 2; ++pv) {
+        if (!tune_p && pv != p0) continue;
+        for (int bv = 1; bv <= 2; ++bv) {
+            if (!tune_b && bv != b0) continue;
+            B->projector = pv;
+            B->backprojector = bv;
+            ncs_status s = build_maps(B);
+            if (s) return s;
+            NCS_HIP(batch_iterate<T>(B, 1));
+            NCS_HIP(hipEventRecord(e0, B->stream));
+            NCS_HIP(batch_iterate<T>(B, 3));
+            NCS_HIP(hipEventRecord(e1, B->stream));
+            NCS_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            NCS_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (best < 0.f || ms < best) {
+                best = ms;
+                bp = pv;
+                bb = bv;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B->projector = bp;
+    B->backprojector = bb;
+    for (ncs_handle* h : B->slices) {
+        h->projector = bp;
+        h->backprojector = bb;
+    }
+    return build_maps(B);
 }
 
 template <class T>
@@ -1162,15 +1277,21 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
             if ((pass == 0) != (i == largest)) continue;
             ncs_params p = params[i];
             p.graph_chunk = -1;
-            if (pass == 1) p.projector = B->projector;
+            if (pass == 1) {
+                p.projector = B->projector;
+                p.backprojector = B->backprojector;
+            }
             ncs_status s = setup_slice(geoms[i], p, dtype, b_dev[i], bg_dev ? bg_dev[i] : nullptr, B->stream,
-                                       B->ctls + i, pass == 0 && params[i].projector == 0, &B->slices[i]);
+                                       B->ctls + i, pass == 0, &B->slices[i]);
             if (s) {
                 const std::string msg = g_err;
                 set_err("ncs_batch_setup: slice %d: %s", i, msg.c_str());
                 return fail(s);
             }
-            if (pass == 0) B->projector = B->slices[i]->projector;
+            if (pass == 0) {
+                B->projector = B->slices[i]->projector;
+                B->backprojector = B->slices[i]->backprojector;
+            }
             B->max_N = std::max(B->max_N, geoms[i].n_side);
         }
     }
@@ -1193,6 +1314,11 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
     ncs_status s = dtype == NCS_F64 ? batch_upload_ctxs<double>(B) : batch_upload_ctxs<float>(B);
     if (s) return fail(s);
     if ((s = build_maps(B))) return fail(s);
+    const bool tune_p = params[0].projector == 0, tune_b = params[0].backprojector == 0;
+    if (tune_p || tune_b) {
+        s = dtype == NCS_F64 ? autotune_batch<double>(B, tune_p, tune_b) : autotune_batch<float>(B, tune_p, tune_b);
+        if (s) return fail(s);
+    }
     *out = B;
     return NCS_OK;
 }

@@ -103,7 +103,8 @@ struct IterLaunch {
     const DevCtx<T>* ctxs;   // device array of slice descriptors
     PhaseGrid bp, rows, cols, proj, fin;   // rows is shared by the forward and inverse row DFTs
     int max_N;               // largest image side (dynamic LDS of the DFT kernels)
-    int projector;           // 1: LDS-staged tiles, 2: direct coalesced loads
+    int projector;           // 1: LDS-staged row windows, 2: direct coalesced loads
+    int backprojector;       // 1: LDS-staged detector windows (16 x 16 tiles), 2: direct (8 x 8 tiles)
 };
 
 constexpr int kNumPhases = 6;   // backprojection, row DFT, column DFT, inverse row DFT + x-update,
@@ -114,10 +115,10 @@ template <class T> hipError_t launch_iteration_phase(const IterLaunch<T>& L, int
 
 // Single-slice operators.  `hc` is the host copy of the descriptor (launch
 // sizes), `dc` its device copy.
-template <class T> hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y_padded, T* out, hipStream_t st);
+template <class T> hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int variant, const T* y_padded, T* out, hipStream_t st);
 // Filtered backprojection: Shepp-Logan filter per projection (into the padded
 // scratch sinogram), then the backprojection; out = N*N image.
-template <class T> hipError_t launch_fbp(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y, T* out, hipStream_t st);
+template <class T> hipError_t launch_fbp(const DevCtx<T>& hc, const DevCtx<T>* dc, int backprojector, const T* y, T* out, hipStream_t st);
 template <class T> hipError_t launch_apply_minv(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* w, T* out, T scale, hipStream_t st);
 template <class T> hipError_t launch_pad_image(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st);
 // Plain projections read the padded scratch pair (xsc, xscT): pad first.
@@ -142,6 +143,6 @@ void set_error_message(const char* msg);
 
 int project_blocks(int NA, int NS);
 int tv_blocks(int N);
-int bp_blocks(int N);
+int bp_blocks(int N, int variant);
 
 }  // namespace ncs

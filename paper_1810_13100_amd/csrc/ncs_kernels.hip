@@ -147,8 +147,77 @@ __device__ void fft_dif(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int
 }
 
 // ---------------------------------------------------------------------------
-// Backprojection (pixel-driven gather, matched to the ray-driven projector)
-// with LDS-staged detector windows.  Workgroup: a 16 x 16 pixel tile.  For
+// Backprojection (pixel-driven gather, matched to the ray-driven projector).
+// Two kernels compute the same taps: the direct one reads every tap pair from
+// the sinogram in global memory; the LDS one stages detector windows.  The
+// setup timing keeps the faster for a geometry (and, for a batch, for the
+// whole batch).
+//
+// Direct: an 8 x 8 pixel tile per workgroup; each of the 8 waves takes every
+// 8th angle; the partial sums are added in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kBpTileD = 8;
+
+template <class T, bool ITER>
+__global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevCtx<T>* __restrict__ ctxs,
+                                                                      const Slot* __restrict__ map,
+                                                                      const T* __restrict__ ysrc_plain,
+                                                                      T* __restrict__ out) {
+    int local;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, local);
+    if (ITER && c.ctl->stop) return;
+    __shared__ T red[kBpWaves * 64];
+    const T* ysrc = ITER ? c.u : ysrc_plain;
+    const int N = c.N;
+    const int tiles_x = N / kBpTileD;
+    const int tx = local % tiles_x, ty = local / tiles_x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = tx * kBpTileD + (lane & 7);
+    const int row = ty * kBpTileD + (lane >> 3);
+    const T fc = (T)col, fr = (T)row;
+    const T tmax = (T)c.NS;
+    const int PU = c.PU;
+    const int NA = c.NA;
+    const AngleT<T>* ang = c.ang;
+    T acc = T(0);
+#pragma unroll 4
+    for (int a = wave; a < NA; a += kBpWaves) {
+        const AngleT<T> A = ang[a];
+        // outside the detector both taps land on the zero pads at d = -1, N_s, N_s + 1
+        const T t = med3(fma(fc, A.q1, fma(fr, A.q2, A.q0)), T(-1), tmax);
+        const T fl = floor(t);
+        const T f = t - fl;
+        const unsigned off = (unsigned)((int)fl + 1);
+        const Pair<T> y = load_pair(ysrc + (size_t)a * PU + off);
+        const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
+        const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
+        acc = fma(w0, y.a, acc);
+        acc = fma(w1, y.b, acc);
+    }
+    red[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    T bp = red[lane];
+#pragma unroll
+    for (int w = 1; w < kBpWaves; ++w) bp += red[w * 64 + lane];
+    const size_t pix = (size_t)row * N + col;
+    if (!ITER) {
+        out[pix] = bp;
+        return;
+    }
+    // D^T v with D of Section 2 (rows [1, -1]) on each axis, padded planes.
+    const T* vh = c.v;
+    const T* vv = c.v + (size_t)N * N;
+    T dtv = T(0);
+    if (col < N - 1) dtv += vh[pix];
+    if (col > 0) dtv -= vh[pix - 1];
+    if (row < N - 1) dtv += vv[pix];
+    if (row > 0) dtv -= vv[pix - N];
+    c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
+}
+
+// LDS: a 16 x 16 pixel tile per workgroup.  For
 // each angle the tile's pixels touch at most kBpWin consecutive detector bins
 // (the tile spans 15 (|cos| + |sin|) <= 21.3 bins, plus the second tap and a
 // rounding margin); those windows are staged in LDS for a chunk of angles
@@ -163,10 +232,10 @@ template <class T>
 constexpr int bp_chunk() { return sizeof(T) == 4 ? 384 : 192; }
 
 template <class T, bool ITER>
-__global__ __launch_bounds__(kBpWaves * 64) void k_backproject(const DevCtx<T>* __restrict__ ctxs,
-                                                               const Slot* __restrict__ map,
-                                                               const T* __restrict__ ysrc_plain,
-                                                               T* __restrict__ out) {
+__global__ __launch_bounds__(kBpWaves * 64) void k_backproject_lds(const DevCtx<T>* __restrict__ ctxs,
+                                                                   const Slot* __restrict__ map,
+                                                                   const T* __restrict__ ysrc_plain,
+                                                                   T* __restrict__ out) {
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
     if (ITER && c.ctl->stop) return;
@@ -200,10 +269,23 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(const DevCtx<T>* 
             wbase[k] = (int)floor(med3(tmin, T(-1), tmax)) - 1;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < nch * kBpWin; e += kBpWaves * 64) {
-            const int k = e / kBpWin, j = e - k * kBpWin;
-            const int d = wbase[k] + j;   // bins -1, NS and NS + 1 are the zero pads of the row
-            win[e] = (d >= -1 && d <= NS + 1) ? ysrc[(size_t)(a0 + k) * PU + 1 + d] : T(0);
+        {
+            // every load of this thread is issued before any is stored, so the
+            // staging costs one memory latency
+            constexpr int R = (CH * kBpWin + kBpWaves * 64 - 1) / (kBpWaves * 64);
+            T vals[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = threadIdx.x + r * kBpWaves * 64;
+                const int k = e / kBpWin, j = e - k * kBpWin;
+                const int d = e < nch * kBpWin ? wbase[k] + j : -2;   // bins -1, NS, NS + 1: zero pads
+                vals[r] = (d >= -1 && d <= NS + 1) ? ysrc[(size_t)(a0 + k) * PU + 1 + d] : T(0);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = threadIdx.x + r * kBpWaves * 64;
+                if (e < nch * kBpWin) win[e] = vals[r];
+            }
         }
         __syncthreads();
         const int kmid = (nch + 1) >> 1;
@@ -391,15 +473,28 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
         const int ns = min(kStageRows, s_end - s0);
         wave_lds_sync();   // the previous rows have been read
         if (lane < ns) rbase[lane] = row_window_base(A, s0 + lane, blo, cmax);
-        for (int qi = lane; qi < ns * NQ; qi += 64) {
-            const int i = qi / NQ, q = qi - i * NQ;
-            const int e = row_window_base(A, s0 + i, blo, cmax) + 4 * q;
-            Quad<T> v;
+        {
+            // all loads of the lane in flight before the stores
+            constexpr int R = (kStageRows * NQ + 63) / 64;
+            Quad<T> v[R];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v.v[k] = T(0);
-            // P and e are multiples of 4: a quad is wholly inside the padded row or wholly outside
-            if (e >= 0 && e < P) v = *reinterpret_cast<const Quad<T>*>(src + (size_t)(s0 + i) * P + e);
-            *reinterpret_cast<Quad<T>*>(stage + i * kRowWin + 4 * q) = v;
+            for (int r = 0; r < R; ++r) {
+                const int qi = lane + 64 * r;
+                const int i = qi / NQ, q = qi - i * NQ;
+                const int e = qi < ns * NQ ? row_window_base(A, s0 + i, blo, cmax) + 4 * q : -4;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[r].v[k] = T(0);
+                // P and e are multiples of 4: a quad is wholly inside the padded row or wholly outside
+                if (e >= 0 && e < P) v[r] = *reinterpret_cast<const Quad<T>*>(src + (size_t)(s0 + i) * P + e);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int qi = lane + 64 * r;
+                if (qi < ns * NQ) {
+                    const int i = qi / NQ, q = qi - i * NQ;
+                    *reinterpret_cast<Quad<T>*>(stage + i * kRowWin + 4 * q) = v[r];
+                }
+            }
         }
         wave_lds_sync();
         for (int i = 0; i < ns; ++i) {
@@ -907,7 +1002,10 @@ hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, in
 
 int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
 int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
-int bp_blocks(int N) { return (N / kBpTile) * (N / kBpTile); }
+int bp_blocks(int N, int variant) {
+    const int t = variant == 1 ? kBpTile : kBpTileD;
+    return (N / t) * (N / t);
+}
 
 hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target, hipStream_t st) {
     hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, st, ctl, op, iter_value, f_target);
@@ -919,8 +1017,12 @@ hipError_t launch_iteration_phase(const IterLaunch<T>& L, int phase, hipStream_t
     const size_t sm = fft_lds<T>(L.max_N);
     switch (phase) {
         case 0:
-            hipLaunchKernelGGL((k_backproject<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
-                               L.bp.map, (const T*)nullptr, (T*)nullptr);
+            if (L.backprojector == 1)
+                hipLaunchKernelGGL((k_backproject_lds<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st,
+                                   L.ctxs, L.bp.map, (const T*)nullptr, (T*)nullptr);
+            else
+                hipLaunchKernelGGL((k_backproject_direct<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st,
+                                   L.ctxs, L.bp.map, (const T*)nullptr, (T*)nullptr);
             break;
         case 1:
             hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(L.rows.blocks), dim3(kFftThreads), sm, st, L.ctxs,
@@ -953,21 +1055,26 @@ hipError_t launch_iteration(const IterLaunch<T>& L, hipStream_t st) {
 }
 
 template <class T>
-hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y_padded, T* out,
-                                    hipStream_t st) {
-    hipLaunchKernelGGL((k_backproject<T, false>), dim3(bp_blocks(hc.N)), dim3(kBpWaves * 64), 0, st, dc,
-                       (const Slot*)nullptr, y_padded, out);
+hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int variant, const T* y_padded,
+                                    T* out, hipStream_t st) {
+    if (variant == 1)
+        hipLaunchKernelGGL((k_backproject_lds<T, false>), dim3(bp_blocks(hc.N, 1)), dim3(kBpWaves * 64), 0, st, dc,
+                           (const Slot*)nullptr, y_padded, out);
+    else
+        hipLaunchKernelGGL((k_backproject_direct<T, false>), dim3(bp_blocks(hc.N, 2)), dim3(kBpWaves * 64), 0, st,
+                           dc, (const Slot*)nullptr, y_padded, out);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fbp(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* y, T* out, hipStream_t st) {
+hipError_t launch_fbp(const DevCtx<T>& hc, const DevCtx<T>* dc, int backprojector, const T* y, T* out,
+                      hipStream_t st) {
     if (hc.NS > kFbpMaxBins) return hipErrorInvalidValue;
     const size_t sm = 2 * (size_t)hc.NS * sizeof(T);
     hipLaunchKernelGGL((k_fbp_filter<T>), dim3(hc.NA), dim3(256), sm, st, dc, y, hc.ysc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_backproject_plain<T>(hc, dc, hc.ysc, out, st);
+    return launch_backproject_plain<T>(hc, dc, backprojector, hc.ysc, out, st);
 }
 
 template <class T>
@@ -1054,9 +1161,9 @@ hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projecto
 #define NCS_INSTANTIATE(T)                                                                                        \
     template hipError_t launch_iteration<T>(const IterLaunch<T>&, hipStream_t);                                  \
     template hipError_t launch_iteration_phase<T>(const IterLaunch<T>&, int, hipStream_t);                       \
-    template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t); \
+    template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const DevCtx<T>*, int, const T*, T*, hipStream_t); \
     template hipError_t launch_apply_minv<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, T, hipStream_t);  \
-    template hipError_t launch_fbp<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t);            \
+    template hipError_t launch_fbp<T>(const DevCtx<T>&, const DevCtx<T>*, int, const T*, T*, hipStream_t);       \
     template hipError_t launch_pad_image<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, hipStream_t);          \
     template hipError_t launch_project_plain<T>(const DevCtx<T>&, const DevCtx<T>*, int, T*, hipStream_t);       \
     template hipError_t launch_project_setp<T>(const DevCtx<T>&, const DevCtx<T>*, int, hipStream_t);            \

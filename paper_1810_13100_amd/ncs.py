@@ -41,7 +41,7 @@ _STATUS_NAMES = {
 }
 
 EXPORTED = [
-    "ncs_setup", "ncs_set_init", "ncs_iterate", "ncs_solve", "ncs_get_objectives",
+    "ncs_setup", "ncs_set_init", "ncs_set_x", "ncs_iterate", "ncs_solve", "ncs_get_objectives",
     "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_v", "ncs_get_state", "ncs_set_state",
     "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_prefilter", "ncs_fbp", "ncs_get_eigenvalues",
     "ncs_time_phases", "ncs_get_info", "ncs_destroy", "ncs_last_error",
@@ -68,14 +68,14 @@ class _Params(ctypes.Structure):
         ("data_term", ctypes.c_int32), ("tv_term", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("diverge_checks", ctypes.c_int32),
         ("projector", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
-        ("dual_ramp", ctypes.c_double),
+        ("dual_ramp", ctypes.c_double), ("backprojector", ctypes.c_int32),
     ]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("nnz", ctypes.c_int64), ("c_r", ctypes.c_double), ("mu_dc", ctypes.c_double),
-                ("norm_e1_sq", ctypes.c_double), ("projector", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("projector_ms", ctypes.c_double * 2)]
+                ("norm_e1_sq", ctypes.c_double), ("projector", ctypes.c_int32), ("backprojector", ctypes.c_int32),
+                ("projector_ms", ctypes.c_double * 2), ("backprojector_ms", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -95,6 +95,7 @@ def load_library() -> ctypes.CDLL:
         "ncs_setup": ([ctypes.POINTER(_Geometry), ctypes.POINTER(_Params), i32, vp, vp, vp,
                        ctypes.POINTER(vp)], i32),
         "ncs_set_init": ([vp, vp, i32], i32),
+        "ncs_set_x": ([vp, vp], i32),
         "ncs_iterate": ([vp, i32, pdbl], i32),
         "ncs_solve": ([vp, i32, dbl, pi32, pdbl], i32),
         "ncs_get_objectives": ([vp, i32, i32, pdbl], i32),
@@ -167,6 +168,7 @@ class Params:
     projector: int = 0        # 0: autotune at setup, 1: LDS-staged, 2: direct
     graph_chunk: int = 0      # 0: 25 iterations per HIP graph, < 0: no graphs
     dual_ramp: float = 0.0    # TV-dual ramp width of the warm start (0: sign)
+    backprojector: int = 0    # 0: autotune at setup, 1: LDS-staged windows, 2: direct
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -192,7 +194,7 @@ class Solver:
         g = _Geometry(geom.n_side, geom.n_angles, geom.n_bins)
         p = _Params(params.alpha, params.beta, params.gamma, params.lam, params.c_r, params.mu_dc,
                     params.data_term, params.tv_term, params.check_every, params.diverge_checks,
-                    params.projector, params.graph_chunk, params.dual_ramp)
+                    params.projector, params.graph_chunk, params.dual_ramp, params.backprojector)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.ncs_setup(ctypes.byref(g), ctypes.byref(p),
@@ -223,6 +225,11 @@ class Solver:
         x0p = _ptr(self._img(x0, "x0")) if x0 is not None else None
         self._x0_keep = x0
         _check(self.lib.ncs_set_init(self.h, x0p, int(dual_from_x0)))
+
+    def set_x(self, x: torch.Tensor) -> None:
+        """Replace the iterate (E x recomputed); duals and iteration count are kept."""
+        self._x_keep = self._img(x, "x")
+        _check(self.lib.ncs_set_x(self.h, self._x_keep.data_ptr()))
 
     def iterate(self, k: int, record: bool = False) -> np.ndarray | None:
         if record:
@@ -320,7 +327,8 @@ class Solver:
         inf = _Info()
         _check(self.lib.ncs_get_info(self.h, ctypes.byref(inf)))
         return {"nnz": inf.nnz, "c_r": inf.c_r, "mu_dc": inf.mu_dc, "norm_e1_sq": inf.norm_e1_sq,
-                "projector": inf.projector, "projector_ms": list(inf.projector_ms)}
+                "projector": inf.projector, "projector_ms": list(inf.projector_ms),
+                "backprojector": inf.backprojector, "backprojector_ms": list(inf.backprojector_ms)}
 
     def eigenvalues(self) -> np.ndarray:
         mu = np.empty(self.geom.n, dtype=np.float64)
@@ -380,7 +388,8 @@ class Batch:
         self._bg = list(bgs) if bgs is not None else None
         G = (_Geometry * n)(*[_Geometry(g.n_side, g.n_angles, g.n_bins) for g in geoms])
         P = (_Params * n)(*[_Params(p.alpha, p.beta, p.gamma, p.lam, p.c_r, p.mu_dc, p.data_term, p.tv_term,
-                                    p.check_every, p.diverge_checks, p.projector, p.graph_chunk, p.dual_ramp)
+                                    p.check_every, p.diverge_checks, p.projector, p.graph_chunk, p.dual_ramp,
+                                    p.backprojector)
                               for p in params])
         B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
         BG = None

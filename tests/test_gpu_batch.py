@@ -31,9 +31,10 @@ def _params(prob, projector=2):
     if prob.kind == "pet":
         par = ct_params(prob.n_side, prob.n_angles, alpha=1.0, ratio=3.0, g=1.0)
         return par, ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, data_term=ncs.DATA_POISSON,
-                               tv_term=ncs.TV_ISO, projector=projector, check_every=10)
+                               tv_term=ncs.TV_ISO, projector=projector, backprojector=projector, check_every=10)
     par = ct_params(prob.n_side, prob.n_angles)
-    return par, ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, projector=projector, check_every=10)
+    return par, ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, projector=projector, backprojector=projector,
+                           check_every=10)
 
 
 def _batch(probs, dtype, projector=2):
@@ -105,3 +106,21 @@ def test_batch_rejects_bad_slices():
         ncs.Batch([ncs.Geometry(64, 90, 92), ncs.Geometry(48, 90, 92)], [good, good], [b, b])
     assert e.value.status == ncs.NCS_ERR_INVALID_ARG
     assert "slice 1" in str(e.value)
+
+
+def test_batch_autotuned_kernels():
+    # kernels chosen by timing batched iterations; every slice uses the batch's choice
+    probs = [_problem(*s) for s in SLICES if s[4] == "ct"]
+    K = 40
+    bt, _, _ = _batch(probs, torch.float32, projector=0)
+    bt.set_init()
+    st, iters, f = bt.solve(K)
+    assert list(iters) == [K] * len(probs)
+    infos = [bt.slice(i).info() for i in range(len(probs))]
+    log(f"batch kernels: projector {infos[0]['projector']}, backprojector {infos[0]['backprojector']}")
+    assert len({(i["projector"], i["backprojector"]) for i in infos}) == 1
+    for i, prob in enumerate(probs):
+        ref = oracle_ncs(prob, _params(prob)[0], K)
+        ex = rel_l2(bt.slice(i).x().double().cpu().numpy(), ref.x)
+        assert ex <= 1e-4, ex
+    bt.close()

@@ -23,12 +23,13 @@ DT = {"f32": torch.float32, "f64": torch.float64}
 TOL = {"f64": (1e-10, 1e-10), "f32": (1e-4, 1e-5)}
 
 
-def make_solver(prob, par, dtype, check_every=50, diverge_checks=0, projector=0, graph_chunk=0, dual_ramp=0.0):
+def make_solver(prob, par, dtype, check_every=50, diverge_checks=0, projector=0, graph_chunk=0, dual_ramp=0.0,
+                backprojector=0):
     data = ncs.DATA_POISSON if prob.kind == "pet" else ncs.DATA_QUADRATIC
     tv = ncs.TV_ISO if prob.tv == "iso" else ncs.TV_ANISO
     p = ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0,
                    data_term=data, tv_term=tv, check_every=check_every, diverge_checks=diverge_checks,
-                   projector=projector, graph_chunk=graph_chunk, dual_ramp=dual_ramp)
+                   projector=projector, graph_chunk=graph_chunk, dual_ramp=dual_ramp, backprojector=backprojector)
     b = torch.tensor(prob.b, dtype=dtype, device=DEV)
     bg = torch.tensor(prob.bg, dtype=dtype, device=DEV) if prob.kind == "pet" else None
     return ncs.Solver(ncs.Geometry(prob.n_side, prob.n_angles, prob.n_bins), p, b=b, bg=bg, dtype=dtype)
@@ -59,13 +60,15 @@ def check_trajectory(prob, par, iters, prec, **kw):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("projector,graph_chunk", [(1, -1), (2, -1), (0, 0), (2, 7)])
-def test_ct_64_200_iterations(prec, projector, graph_chunk):
-    # both projector kernels, direct launches and replayed HIP graphs (a chunk
-    # of 7 leaves a remainder of direct launches)
+@pytest.mark.parametrize("projector,backprojector,graph_chunk", [(1, 1, -1), (2, 2, -1), (0, 0, 0), (2, 1, 7)])
+def test_ct_64_200_iterations(prec, projector, backprojector, graph_chunk):
+    # both projector and backprojector kernels, direct launches and replayed
+    # HIP graphs (a chunk of 7 leaves a remainder of direct launches)
     prob = ct_problem("c1")
-    log(f"NCS parity 64^2 CT, 200 iterations, {prec}, projector {projector}, graph chunk {graph_chunk}")
-    check_trajectory(prob, ct_params(64, 90), 200, prec, projector=projector, graph_chunk=graph_chunk)
+    log(f"NCS parity 64^2 CT, 200 iterations, {prec}, projector {projector}, backprojector {backprojector}, "
+        f"graph chunk {graph_chunk}")
+    check_trajectory(prob, ct_params(64, 90), 200, prec, projector=projector, backprojector=backprojector,
+                     graph_chunk=graph_chunk)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -23,12 +23,12 @@ DT = {"f32": torch.float32, "f64": torch.float64}
 
 
 def _solver(geom, dtype, b=None, par=None, data=ncs.DATA_QUADRATIC, tv=ncs.TV_ANISO, lam=0.01, bg=None,
-            projector=0):
+            projector=0, backprojector=0):
     n, na, ns = geom
     if par is None:
         par = ct_params(n, na)
     p = ncs.Params(par.alpha, par.beta, par.gamma, lam, data_term=data, tv_term=tv,
-                   c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0, projector=projector)
+                   c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0, projector=projector, backprojector=backprojector)
     tb = None if b is None else torch.tensor(b, dtype=dtype, device=DEV)
     tbg = None if bg is None else torch.tensor(bg, dtype=dtype, device=DEV)
     return ncs.Solver(ncs.Geometry(n, na, ns), p, b=tb, bg=tbg, dtype=dtype)
@@ -60,11 +60,14 @@ def test_forward_matches_oracle(key, prec, projector):
 
 @pytest.mark.parametrize("key", ["tiny", "c1", "c4s", "c3", "c4m", "c2"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_adjoint_matches_oracle(key, prec):
+@pytest.mark.parametrize("bproj", [1, 2])
+def test_adjoint_matches_oracle(key, prec, bproj):
+    # both backprojector kernels (1: LDS-staged detector windows, 2: direct loads)
     geom = GEOMS[key]
-    log(f"adjoint parity {key} {geom} {prec}")
+    log(f"adjoint parity {key} {geom} {prec} backprojector {bproj}")
     E = joseph(*geom)
-    s = _solver(geom, DT[prec])
+    s = _solver(geom, DT[prec], backprojector=bproj)
+    assert s.info()["backprojector"] == bproj
     rng = np.random.default_rng(2)
     for y, tol32 in ((E @ _phantom(geom[0], 3), 1e-5), (rng.standard_normal(E.shape[0]), 1e-4)):
         ref = E.T @ y
@@ -84,7 +87,7 @@ def test_large_slice_sampled_angles(prec, proj):
     angles = [0, 1, 179, 180, 181, 358, 359, 537, 538, 716]
     log(f"sampled-angle parity 512 {prec} projector {proj}")
     E = projector.joseph_matrix(n, na, ns, angles=angles)
-    s = _solver((n, na, ns), DT[prec], projector=proj)
+    s = _solver((n, na, ns), DT[prec], projector=proj, backprojector=proj)
     img = _phantom(n, 5)
     out = s.forward(torch.tensor(img, dtype=DT[prec], device=DEV)).double().cpu().numpy()
     ref = E @ img
@@ -192,4 +195,8 @@ def test_autotuner_times_both_projectors():
         f"-> {inf['projector']}")
     assert all(t > 0 for t in inf["projector_ms"])
     assert inf["projector"] == (1 if inf["projector_ms"][0] < inf["projector_ms"][1] else 2)
+    log(f"backprojector autotune: LDS {inf['backprojector_ms'][0]:.4f} ms, direct {inf['backprojector_ms'][1]:.4f} ms "
+        f"-> {inf['backprojector']}")
+    assert all(t > 0 for t in inf["backprojector_ms"])
+    assert inf["backprojector"] == (1 if inf["backprojector_ms"][0] < inf["backprojector_ms"][1] else 2)
     s.close()
