@@ -251,12 +251,8 @@ ncs_status upload_ctx_typed(ncs_handle* h) {
 
 // ---- iteration launch -----------------------------------------------------
 hipError_t launch_eager(ncs_handle* h, int k, hipStream_t st) {
-    for (int i = 0; i < k; ++i) {
-        const hipError_t e = h->dtype == NCS_F64 ? launch_iteration<double>(single_launch<double>(h), st)
-                                                 : launch_iteration<float>(single_launch<float>(h), st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return h->dtype == NCS_F64 ? launch_iterations<double>(single_launch<double>(h), k, st)
+                               : launch_iterations<float>(single_launch<float>(h), k, st);
 }
 
 hipError_t launch_phase(ncs_handle* h, int ph) {
@@ -1143,11 +1139,7 @@ hipError_t batch_iterate(ncs_batch* B, int k) {
     L.max_N = B->max_N;
     L.projector = B->projector;
     L.backprojector = B->backprojector;
-    for (int i = 0; i < k; ++i) {
-        const hipError_t e = launch_iteration<T>(L, B->stream);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return launch_iterations<T>(L, k, B->stream);
 }
 
 

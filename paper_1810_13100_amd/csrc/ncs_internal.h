@@ -110,7 +110,10 @@ struct IterLaunch {
 constexpr int kNumPhases = 6;   // backprojection, row DFT, column DFT, inverse row DFT + x-update,
                                 // projection + data prox + TV update, objective
 
-template <class T> hipError_t launch_iteration(const IterLaunch<T>& L, hipStream_t st);
+// k iterations (five launches each plus one finalize at the end).
+template <class T> hipError_t launch_iterations(const IterLaunch<T>& L, int k, hipStream_t st);
+// One phase of an iteration, unfused (phase 0 does not reduce the previous
+// objective; phase 5 is the finalize launch): used for per-kernel timing.
 template <class T> hipError_t launch_iteration_phase(const IterLaunch<T>& L, int phase, hipStream_t st);
 
 // Single-slice operators.  `hc` is the host copy of the descriptor (launch

@@ -95,7 +95,7 @@ __device__ inline double med3<double>(double v, double lo, double hi) { return f
 // Radix-2 decimation-in-time transform in LDS: input in bit-reversed order,
 // output in natural order.  tw[2k], tw[2k+1] = cos, -sin of 2 pi k / N.
 template <class T>
-__device__ void fft_dit(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int logN, bool inverse,
+__device__ void fft_dit(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
                         int tid, int nthr) {
     for (int ls = 0; ls < logN; ++ls) {
         const int half = 1 << ls;
@@ -123,7 +123,7 @@ __device__ void fft_dit(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int
 // Radix-2 decimation-in-frequency transform in LDS: input natural, output in
 // bit-reversed order.
 template <class T>
-__device__ void fft_dif(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int logN, bool inverse,
+__device__ void fft_dif(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
                         int tid, int nthr) {
     for (int ls = logN - 1; ls >= 0; --ls) {
         const int half = 1 << ls;
@@ -146,6 +146,56 @@ __device__ void fft_dif(T* re, T* im, const NCS_G T* __restrict__ tw, int N, int
     __syncthreads();
 }
 
+// The N/2 complex twiddles copied to LDS (after the data area), so that no
+// butterfly stage waits on a global load.
+template <class T>
+__device__ inline T* stage_twiddles(const DevCtx<T>& c, T* lds_after_data) {
+    for (int i = threadIdx.x; i < c.N; i += blockDim.x) lds_after_data[i] = c.tw[i];
+    return lds_after_data;
+}
+
+// Objective of a slice after an iteration: the partial sums of the projection
+// launch added in a fixed order (double) by the first 256 threads of the
+// calling workgroup, the history entry and the stop test.  Every thread of
+// the workgroup calls it (it synchronises).  It runs either as its own
+// kernel after the last iteration of a launch sequence or at the start of
+// the next iteration's backprojection; the kernel boundary orders it after
+// every workgroup of the projection launch either way.
+template <class T>
+__device__ inline void finalize_slice(const DevCtx<T>& c, double* sh) {
+    double sd = 0.0, st = 0.0;
+    if (threadIdx.x < 256) {
+        for (int i = threadIdx.x; i < c.nb_proj; i += 256) sd += c.part_data[i];
+        for (int i = threadIdx.x; i < c.nb_tv; i += 256) st += c.part_tv[i];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    sd = wave_sum(sd);
+    st = wave_sum(st);
+    if (lane == 0 && wave < 4) {
+        sh[wave] = sd;
+        sh[4 + wave] = st;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sd = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        st = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+        NCS_G Control* k = c.ctl;
+        const double f = (sd + k->data_const) + c.lambda * st;
+        const int it = k->iter;
+        c.hist[it & (kHistCap - 1)] = f;
+        k->iter = it + 1;
+        k->f_last = f;
+        if (f != f) {
+            k->status = -4;
+            k->stop = 1;
+        } else if (f <= k->f_target) {
+            k->status = 1;
+            k->stop = 1;
+        }
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Backprojection (pixel-driven gather, matched to the ray-driven projector).
 // Two kernels compute the same taps: the direct one reads every tap pair from
@@ -162,11 +212,18 @@ template <class T, bool ITER>
 __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevCtx<T>* __restrict__ ctxs,
                                                                       const Slot* __restrict__ map,
                                                                       const T* __restrict__ ysrc_plain,
-                                                                      T* __restrict__ out) {
+                                                                      T* __restrict__ out, int fin_prev) {
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
-    if (ITER && c.ctl->stop) return;
     __shared__ T red[kBpWaves * 64];
+    if (ITER) {
+        __shared__ int stop_sh;
+        __shared__ double fin_sh[8];
+        if (threadIdx.x == 0) stop_sh = c.ctl->stop;   // one read per workgroup: the flag may change below
+        __syncthreads();
+        if (stop_sh) return;
+        if (fin_prev && local == 0) finalize_slice(c, fin_sh);   // objective of the previous iteration
+    }
     const T* ysrc = ITER ? c.u : ysrc_plain;
     const int N = c.N;
     const int tiles_x = N / kBpTileD;
@@ -235,10 +292,17 @@ template <class T, bool ITER>
 __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_lds(const DevCtx<T>* __restrict__ ctxs,
                                                                    const Slot* __restrict__ map,
                                                                    const T* __restrict__ ysrc_plain,
-                                                                   T* __restrict__ out) {
+                                                                   T* __restrict__ out, int fin_prev) {
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
-    if (ITER && c.ctl->stop) return;
+    if (ITER) {
+        __shared__ int stop_sh;
+        __shared__ double fin_sh[8];
+        if (threadIdx.x == 0) stop_sh = c.ctl->stop;   // one read per workgroup: the flag may change below
+        __syncthreads();
+        if (stop_sh) return;
+        if (fin_prev && local == 0) finalize_slice(c, fin_sh);   // objective of the previous iteration
+    }
     constexpr int CH = bp_chunk<T>();
     __shared__ T win[CH * kBpWin];
     __shared__ int wbase[CH];
@@ -545,37 +609,14 @@ __device__ inline double tv_tile(const DevCtx<T>& c, int tile) {
     return c.tv_term == TV_ANISO ? fabs(th) + fabs(tw) : sqrt(th * th + tw * tw);
 }
 
-// Objective of a slice after an iteration: the partial sums of the projection
-// launch added in a fixed order (double), the history entry and the stop
-// test.  One workgroup per slice; the kernel boundary orders it after every
-// workgroup of the projection launch.
 template <class T>
 __global__ __launch_bounds__(256) void k_finalize_iter(const DevCtx<T>* __restrict__ ctxs,
                                                        const Slot* __restrict__ map) {
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
     if (c.ctl->stop) return;
-    __shared__ double sh[kWaves];
-    double sd = 0.0, st = 0.0;
-    for (int i = threadIdx.x; i < c.nb_proj; i += 256) sd += c.part_data[i];
-    for (int i = threadIdx.x; i < c.nb_tv; i += 256) st += c.part_tv[i];
-    sd = block_sum256(sd, sh);
-    __syncthreads();
-    st = block_sum256(st, sh);
-    if (threadIdx.x != 0) return;
-    NCS_G Control* k = c.ctl;
-    const double f = (sd + k->data_const) + c.lambda * st;
-    const int it = k->iter;
-    c.hist[it & (kHistCap - 1)] = f;
-    k->iter = it + 1;
-    k->f_last = f;
-    if (f != f) {
-        k->status = -4;
-        k->stop = 1;
-    } else if (f <= k->f_target) {
-        k->status = 1;
-        k->stop = 1;
-    }
+    __shared__ double sh[8];
+    finalize_slice(c, sh);
 }
 
 template <class T, int MODE, int VARIANT>
@@ -632,6 +673,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const DevCtx<T>* _
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
+    const T* tw = stage_twiddles(c, im + c.N);
     const int N = c.N, logN = c.log2N;
     const T* src = iter ? c.w : src_plain;
     const T* ra = src + (size_t)(2 * pr) * N;
@@ -641,7 +683,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const DevCtx<T>* _
         re[i] = ra[n];
         im[i] = rb[n];
     }
-    fft_dit(re, im, c.tw, N, logN, false, threadIdx.x, blockDim.x);
+    fft_dit(re, im, tw, N, logN, false, threadIdx.x, blockDim.x);
     for (int k = threadIdx.x; k <= (N >> 1); k += blockDim.x) {
         const int m = (N - k) & (N - 1);
         const T zr = re[k], zi = im[k], mr = re[m], mi = im[m];
@@ -662,6 +704,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(const DevCtx<T>* __res
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
+    const T* tw = stage_twiddles(c, im + c.N);
     const int N = c.N, logN = c.log2N;
     T* colp = c.spec + 2 * (size_t)k * N;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
@@ -669,14 +712,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(const DevCtx<T>* __res
         re[i] = colp[2 * n];
         im[i] = colp[2 * n + 1];
     }
-    fft_dit(re, im, c.tw, N, logN, false, threadIdx.x, blockDim.x);
+    fft_dit(re, im, tw, N, logN, false, threadIdx.x, blockDim.x);
     const T* hk = c.hh + (size_t)k * N;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         const T hv = hk[j] * scale;
         re[j] *= hv;
         im[j] *= hv;
     }
-    fft_dif(re, im, c.tw, N, logN, true, threadIdx.x, blockDim.x);
+    fft_dif(re, im, tw, N, logN, true, threadIdx.x, blockDim.x);
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
         const int i = bitrev(n, logN);
         colp[2 * n] = re[i];
@@ -693,6 +736,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
+    const T* tw = stage_twiddles(c, im + c.N);
     const int N = c.N, logN = c.log2N;
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const int kk = k <= (N >> 1) ? k : N - k;
@@ -706,7 +750,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
         re[k] = ar - bi;      // Z = Ya + i Yb
         im[k] = ai + br;
     }
-    fft_dif(re, im, c.tw, N, logN, true, threadIdx.x, blockDim.x);
+    fft_dif(re, im, tw, N, logN, true, threadIdx.x, blockDim.x);
     const size_t ra = (size_t)(2 * pr) * N, rb = ra + N;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
         const int i = bitrev(n, logN);
@@ -986,7 +1030,7 @@ __global__ void k_control(Control* ctl, int op, int iter_value, double f_target)
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
 template <class T>
-inline size_t fft_lds(int N) { return 2 * (size_t)N * sizeof(T); }
+inline size_t fft_lds(int N) { return 3 * (size_t)N * sizeof(T); }   // re, im, twiddles
 
 template <class T, int MODE>
 hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, int projector, T* out,
@@ -1013,17 +1057,22 @@ hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target,
 }
 
 template <class T>
+hipError_t launch_bp_iter(const IterLaunch<T>& L, int fin_prev, hipStream_t st) {
+    if (L.backprojector == 1)
+        hipLaunchKernelGGL((k_backproject_lds<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
+                           L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
+    else
+        hipLaunchKernelGGL((k_backproject_direct<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
+                           L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
+    return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_iteration_phase(const IterLaunch<T>& L, int phase, hipStream_t st) {
     const size_t sm = fft_lds<T>(L.max_N);
     switch (phase) {
         case 0:
-            if (L.backprojector == 1)
-                hipLaunchKernelGGL((k_backproject_lds<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st,
-                                   L.ctxs, L.bp.map, (const T*)nullptr, (T*)nullptr);
-            else
-                hipLaunchKernelGGL((k_backproject_direct<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st,
-                                   L.ctxs, L.bp.map, (const T*)nullptr, (T*)nullptr);
-            break;
+            return launch_bp_iter<T>(L, 0, st);
         case 1:
             hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(L.rows.blocks), dim3(kFftThreads), sm, st, L.ctxs,
                                L.rows.map, (const T*)nullptr, 1);
@@ -1045,13 +1094,17 @@ hipError_t launch_iteration_phase(const IterLaunch<T>& L, int phase, hipStream_t
     return hipGetLastError();
 }
 
+// k iterations: the objective of iteration i is reduced at the start of
+// iteration i + 1's backprojection, and that of the last by one finalize
+// launch, so each iteration is five launches.
 template <class T>
-hipError_t launch_iteration(const IterLaunch<T>& L, hipStream_t st) {
-    for (int ph = 0; ph < kNumPhases; ++ph) {
-        const hipError_t e = launch_iteration_phase<T>(L, ph, st);
+hipError_t launch_iterations(const IterLaunch<T>& L, int k, hipStream_t st) {
+    for (int i = 0; i < k; ++i) {
+        hipError_t e = launch_bp_iter<T>(L, i > 0 ? 1 : 0, st);
+        for (int ph = 1; ph < kNumPhases - 1 && e == hipSuccess; ++ph) e = launch_iteration_phase<T>(L, ph, st);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return k > 0 ? launch_iteration_phase<T>(L, kNumPhases - 1, st) : hipSuccess;
 }
 
 template <class T>
@@ -1059,10 +1112,10 @@ hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, in
                                     T* out, hipStream_t st) {
     if (variant == 1)
         hipLaunchKernelGGL((k_backproject_lds<T, false>), dim3(bp_blocks(hc.N, 1)), dim3(kBpWaves * 64), 0, st, dc,
-                           (const Slot*)nullptr, y_padded, out);
+                           (const Slot*)nullptr, y_padded, out, 0);
     else
         hipLaunchKernelGGL((k_backproject_direct<T, false>), dim3(bp_blocks(hc.N, 2)), dim3(kBpWaves * 64), 0, st,
-                           dc, (const Slot*)nullptr, y_padded, out);
+                           dc, (const Slot*)nullptr, y_padded, out, 0);
     return hipGetLastError();
 }
 
@@ -1159,7 +1212,7 @@ hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projecto
 }
 
 #define NCS_INSTANTIATE(T)                                                                                        \
-    template hipError_t launch_iteration<T>(const IterLaunch<T>&, hipStream_t);                                  \
+    template hipError_t launch_iterations<T>(const IterLaunch<T>&, int, hipStream_t);                            \
     template hipError_t launch_iteration_phase<T>(const IterLaunch<T>&, int, hipStream_t);                       \
     template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const DevCtx<T>*, int, const T*, T*, hipStream_t); \
     template hipError_t launch_apply_minv<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, T, hipStream_t);  \
