@@ -92,17 +92,19 @@ typedef struct {
     int32_t check_every;    /* ncs_solve: iterations between host checks; <= 0 selects 50 */
     int32_t diverge_checks; /* ncs_solve: stop with NCS_ERR_DIVERGED after this many
                                consecutive checks with a growing objective; <= 0 disables */
-    int32_t projector; /* forward-projector kernel: 0 = time both at setup and keep the
-                          faster, 1 = LDS-staged row windows, 2 = direct coalesced loads */
+    int32_t projector; /* forward-projector kernel: 0 = time all at setup and keep the
+                          fastest, 1 = LDS-staged row windows, 2 = direct coalesced loads,
+                          3 = two adjacent rays per lane, one 16-byte load per step */
     int32_t graph_chunk; /* iterations per replayed HIP graph; 0 selects 25, < 0 disables
                             graphs (every kernel launched directly) */
     double dual_ramp;    /* ncs_set_init with dual_from_x0: width tau of the ramp of the TV
                             dual, v = s clamp(D x0 / tau, -1, 1) (anisotropic) or
                             s (D x0)_p / max(|(D x0)_p|, tau) (isotropic); <= 0 gives the
                             sign, v = s sign(D x0) */
-    int32_t backprojector; /* backprojector kernel: 0 = time both at setup and keep the faster,
+    int32_t backprojector; /* backprojector kernel: 0 = time all at setup and keep the fastest,
                               1 = LDS-staged detector windows (16 x 16 pixel tiles),
-                              2 = direct global loads (8 x 8 pixel tiles) */
+                              2 = direct global loads (8 x 8 pixel tiles),
+                              3 = 2 x 2 pixels per lane, one 16-byte load per angle */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;
@@ -206,10 +208,10 @@ typedef struct {
     double c_r;        /* C_R in use */
     double mu_dc;      /* DC eigenvalue of M in use */
     double norm_e1_sq; /* |E 1|^2 */
-    int32_t projector;     /* forward-projector kernel in use (1 or 2) */
-    int32_t backprojector; /* backprojector kernel in use (1 or 2) */
-    double projector_ms[2];     /* setup timing of the two variants (0 when not timed) */
-    double backprojector_ms[2]; /* setup timing of the two variants (0 when not timed) */
+    int32_t projector;     /* forward-projector kernel in use (1, 2 or 3) */
+    int32_t backprojector; /* backprojector kernel in use (1, 2 or 3) */
+    double projector_ms[3];     /* setup timing of the three variants (0 when not timed) */
+    double backprojector_ms[3]; /* setup timing of the three variants (0 when not timed) */
 } ncs_info;
 
 ncs_status ncs_get_info(ncs_handle* h, ncs_info* info);

@@ -94,9 +94,9 @@ struct ncs_handle {
     double c_r = 0.0, mu_dc = 0.0, norm_e1_sq = 0.0;
     int64_t nnz = -1;           // counted on request
     int projector = 2;
-    double projector_ms[2] = {0.0, 0.0};
+    double projector_ms[3] = {0.0, 0.0, 0.0};
     int backprojector = 2;
-    double backprojector_ms[2] = {0.0, 0.0};
+    double backprojector_ms[3] = {0.0, 0.0, 0.0};
     int graph_chunk = 25;                 // <= 0: no graphs
     hipStream_t cap_stream = nullptr;     // private stream used only for graph capture
     hipGraphExec_t graph_exec = nullptr;  // graph_chunk iterations
@@ -313,7 +313,7 @@ ncs_status autotune_projector(ncs_handle* h) {
     const DevCtx<T> c = make_ctx<T>(h);
     T* out = static_cast<T*>(h->ysc);
     const int reps = 5;
-    for (int variant = 1; variant <= 2; ++variant) {
+    for (int variant = 1; variant <= 3; ++variant) {
         NCS_HIP(launch_project_plain<T>(c, dctx<T>(h), variant, out, h->stream));   // warm-up
         NCS_HIP(hipEventRecord(e0, h->stream));
         for (int r = 0; r < reps; ++r) NCS_HIP(launch_project_plain<T>(c, dctx<T>(h), variant, out, h->stream));
@@ -325,7 +325,10 @@ ncs_status autotune_projector(ncs_handle* h) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    h->projector = h->projector_ms[0] < h->projector_ms[1] ? 1 : 2;
+    int best = 1;
+    for (int v = 2; v <= 3; ++v)
+        if (h->projector_ms[v - 1] < h->projector_ms[best - 1]) best = v;
+    h->projector = best;
     return NCS_OK;
 }
 
@@ -340,7 +343,7 @@ ncs_status autotune_backprojector(ncs_handle* h) {
     const T* src = static_cast<const T*>(h->ysc);
     T* out = static_cast<T*>(h->w);
     const int reps = 5;
-    for (int variant = 1; variant <= 2; ++variant) {
+    for (int variant = 1; variant <= 3; ++variant) {
         NCS_HIP(launch_backproject_plain<T>(c, dctx<T>(h), variant, src, out, h->stream));   // warm-up
         NCS_HIP(hipEventRecord(e0, h->stream));
         for (int r = 0; r < reps; ++r) NCS_HIP(launch_backproject_plain<T>(c, dctx<T>(h), variant, src, out, h->stream));
@@ -352,7 +355,10 @@ ncs_status autotune_backprojector(ncs_handle* h) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    h->backprojector = h->backprojector_ms[0] < h->backprojector_ms[1] ? 1 : 2;
+    int best = 1;
+    for (int v = 2; v <= 3; ++v)
+        if (h->backprojector_ms[v - 1] < h->backprojector_ms[best - 1]) best = v;
+    h->backprojector = best;
     return NCS_OK;
 }
 
@@ -399,12 +405,12 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("unknown tv_term %d", p.tv_term);
         return NCS_ERR_INVALID_ARG;
     }
-    if (p.backprojector < 0 || p.backprojector > 2) {
-        set_err("backprojector must be 0 (auto), 1 (LDS) or 2 (direct)");
+    if (p.backprojector < 0 || p.backprojector > 3) {
+        set_err("backprojector must be 0 (auto), 1 (LDS), 2 (direct) or 3 (quad)");
         return NCS_ERR_INVALID_ARG;
     }
-    if (p.projector < 0 || p.projector > 2) {
-        set_err("projector must be 0 (auto), 1 (LDS) or 2 (direct)");
+    if (p.projector < 0 || p.projector > 3) {
+        set_err("projector must be 0 (auto), 1 (LDS), 2 (direct) or 3 (ray pairs)");
         return NCS_ERR_INVALID_ARG;
     }
     return NCS_OK;
@@ -1066,8 +1072,10 @@ ncs_status ncs_get_info(ncs_handle* h, ncs_info* info) {
     info->backprojector = h->backprojector;
     info->projector_ms[0] = h->projector_ms[0];
     info->projector_ms[1] = h->projector_ms[1];
+    info->projector_ms[2] = h->projector_ms[2];
     info->backprojector_ms[0] = h->backprojector_ms[0];
     info->backprojector_ms[1] = h->backprojector_ms[1];
+    info->backprojector_ms[2] = h->backprojector_ms[2];
     return NCS_OK;
 }
 
@@ -1159,9 +1167,9 @@ ncs_status autotune_batch(ncs_batch* B, bool tune_p, bool tune_b) {
     NCS_HIP(hipEventCreate(&e1));
     float best = -1.f;
     int bp = p0, bb = b0;
-    for (int pv = 1; pv <= 2; ++pv) {
+    for (int pv = 1; pv <= 3; ++pv) {
         if (!tune_p && pv != p0) continue;
-        for (int bv = 1; bv <= 2; ++bv) {
+        for (int bv = 1; bv <= 3; ++bv) {
             if (!tune_b && bv != b0) continue;
             B->projector = pv;
             B->backprojector = bv;

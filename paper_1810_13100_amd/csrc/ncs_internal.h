@@ -103,8 +103,9 @@ struct IterLaunch {
     const DevCtx<T>* ctxs;   // device array of slice descriptors
     PhaseGrid bp, rows, cols, proj, fin;   // rows is shared by the forward and inverse row DFTs
     int max_N;               // largest image side (dynamic LDS of the DFT kernels)
-    int projector;           // 1: LDS-staged row windows, 2: direct coalesced loads
-    int backprojector;       // 1: LDS-staged detector windows (16 x 16 tiles), 2: direct (8 x 8 tiles)
+    int projector;           // 1: LDS-staged row windows, 2: direct coalesced loads, 3: ray pairs
+    int backprojector;       // 1: LDS-staged detector windows (16 x 16 tiles), 2: direct (8 x 8 tiles),
+                             // 3: 2 x 2 pixels per lane with 16-byte loads (16 x 16 tiles)
 };
 
 constexpr int kNumPhases = 6;   // backprojection, row DFT, column DFT, inverse row DFT + x-update,

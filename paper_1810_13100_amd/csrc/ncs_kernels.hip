@@ -28,6 +28,20 @@ namespace ncs {
 
 namespace {
 
+// Unroll factors of the tap loops (loads in flight per wave).
+#ifndef NCS_UNROLL_BP
+#define NCS_UNROLL_BP 4
+#endif
+#ifndef NCS_UNROLL_BPQ
+#define NCS_UNROLL_BPQ 2
+#endif
+#ifndef NCS_UNROLL_PROJ
+#define NCS_UNROLL_PROJ 4
+#endif
+#ifndef NCS_UNROLL_PAIR
+#define NCS_UNROLL_PAIR 4
+#endif
+
 constexpr int kRays = 64;      // rays per projector workgroup (one per lane)
 constexpr int kWaves = 4;      // waves per projector / TV workgroup
 constexpr int kRowWin = 100;   // LDS-staged projector: padded-row elements staged per step
@@ -206,7 +220,8 @@ __device__ inline void finalize_slice(const DevCtx<T>& c, double* sh) {
 // Direct: an 8 x 8 pixel tile per workgroup; each of the 8 waves takes every
 // 8th angle; the partial sums are added in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kBpTileD = 8;
+constexpr int kBpTileD = 8;   // direct kernel's tile side
+constexpr int kBpTile = 16;   // LDS and quad kernels' tile side
 
 template <class T, bool ITER>
 __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevCtx<T>* __restrict__ ctxs,
@@ -238,7 +253,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevC
     const int NA = c.NA;
     const AngleT<T>* ang = c.ang;
     T acc = T(0);
-#pragma unroll 4
+#pragma unroll NCS_UNROLL_BP
     for (int a = wave; a < NA; a += kBpWaves) {
         const AngleT<T> A = ang[a];
         // outside the detector both taps land on the zero pads at d = -1, N_s, N_s + 1
@@ -274,6 +289,112 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevC
     c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
 }
 
+// Quad: a 16 x 16 pixel tile per workgroup of 16 waves; each lane takes a
+// 2 x 2 pixel block and each wave every 16th angle.  The detector coordinates
+// of a 2 x 2 block span |q1| + |q2| <= sqrt(2) < 2 bins, so the eight taps of
+// an angle lie in 4 consecutive bins, read with one 16-byte load.  Each
+// pixel's coordinate and taps are computed exactly as in the direct kernel;
+// the per-pixel sums over the 16 angle groups are added in a fixed order.
+constexpr int kBpQuadWaves = 16;
+
+template <class T>
+struct alignas(sizeof(T)) Four {
+    T a, b, c, d;
+};
+
+template <class T>
+__device__ inline T pick(int j, T v0, T v1, T v2) {
+    return j == 0 ? v0 : (j == 1 ? v1 : v2);
+}
+
+template <class T, bool ITER>
+__global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_quad(const DevCtx<T>* __restrict__ ctxs,
+                                                                        const Slot* __restrict__ map,
+                                                                        const T* __restrict__ ysrc_plain,
+                                                                        T* __restrict__ out, int fin_prev) {
+    int local;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, local);
+    if (ITER) {
+        __shared__ int stop_sh;
+        __shared__ double fin_sh[8];
+        if (threadIdx.x == 0) stop_sh = c.ctl->stop;   // one read per workgroup: the flag may change below
+        __syncthreads();
+        if (stop_sh) return;
+        if (fin_prev && local == 0) finalize_slice(c, fin_sh);   // objective of the previous iteration
+    }
+    __shared__ T red[kBpQuadWaves * kBpTile * kBpTile];
+    const T* ysrc = ITER ? c.u : ysrc_plain;
+    const int N = c.N;
+    const int tiles_x = N / kBpTile;
+    const int tx = local % tiles_x, ty = local / tiles_x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lc = 2 * (lane & 7), lr = 2 * (lane >> 3);          // block corner within the tile
+    const T fc0 = (T)(tx * kBpTile + lc), fc1 = fc0 + T(1);
+    const T fr0 = (T)(ty * kBpTile + lr), fr1 = fr0 + T(1);
+    const T tmax = (T)c.NS;
+    const int PU = c.PU, NA = c.NA, NS = c.NS;
+    const AngleT<T>* ang = c.ang;
+    T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
+#pragma unroll NCS_UNROLL_BPQ
+    for (int a = wave; a < NA; a += kBpQuadWaves) {
+        const AngleT<T> A = ang[a];
+        // the direct kernel's coordinate of each pixel; outside the detector the
+        // taps land on the zero pads at d = -1, N_s, N_s + 1
+        const T t00 = med3(fma(fc0, A.q1, fma(fr0, A.q2, A.q0)), T(-1), tmax);
+        const T t01 = med3(fma(fc1, A.q1, fma(fr0, A.q2, A.q0)), T(-1), tmax);
+        const T t10 = med3(fma(fc0, A.q1, fma(fr1, A.q2, A.q0)), T(-1), tmax);
+        const T t11 = med3(fma(fc1, A.q1, fma(fr1, A.q2, A.q0)), T(-1), tmax);
+        const T l00 = floor(t00), l01 = floor(t01), l10 = floor(t10), l11 = floor(t11);
+        // window start: the smallest bin, kept <= N_s - 2 so that the 4 bins stay
+        // inside the padded row (bins -1 .. N_s + 1)
+        const int base = min((int)fmin(fmin(l00, l01), fmin(l10, l11)), NS - 2);
+        const Four<T> y = *reinterpret_cast<const Four<T>*>(ysrc + (size_t)a * PU + 1 + base);
+        const T fb = (T)base;
+#define NCS_BP_TAP(acc, t, l)                                                              \
+        {                                                                                  \
+            const T f = t - l;                                                             \
+            const int j = min(max((int)(l - fb), 0), 2);                                   \
+            const T y0 = pick(j, y.a, y.b, y.c), y1 = pick(j, y.b, y.c, y.d);              \
+            const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));                           \
+            const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));                               \
+            acc = fma(w0, y0, acc);                                                        \
+            acc = fma(w1, y1, acc);                                                        \
+        }
+        NCS_BP_TAP(a00, t00, l00)
+        NCS_BP_TAP(a01, t01, l01)
+        NCS_BP_TAP(a10, t10, l10)
+        NCS_BP_TAP(a11, t11, l11)
+#undef NCS_BP_TAP
+    }
+    T* rw = red + wave * (kBpTile * kBpTile);
+    rw[lr * kBpTile + lc] = a00;
+    rw[lr * kBpTile + lc + 1] = a01;
+    rw[(lr + 1) * kBpTile + lc] = a10;
+    rw[(lr + 1) * kBpTile + lc + 1] = a11;
+    __syncthreads();
+    if (threadIdx.x >= kBpTile * kBpTile) return;
+    const int p = threadIdx.x;
+    T bp = red[p];
+#pragma unroll
+    for (int w = 1; w < kBpQuadWaves; ++w) bp += red[w * (kBpTile * kBpTile) + p];
+    const int col = tx * kBpTile + (p & (kBpTile - 1)), row = ty * kBpTile + p / kBpTile;
+    const size_t pix = (size_t)row * N + col;
+    if (!ITER) {
+        out[pix] = bp;
+        return;
+    }
+    // D^T v with D of Section 2 (rows [1, -1]) on each axis, padded planes.
+    const T* vh = c.v;
+    const T* vv = c.v + (size_t)N * N;
+    T dtv = T(0);
+    if (col < N - 1) dtv += vh[pix];
+    if (col > 0) dtv -= vh[pix - 1];
+    if (row < N - 1) dtv += vv[pix];
+    if (row > 0) dtv -= vv[pix - N];
+    c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
+}
+
 // LDS: a 16 x 16 pixel tile per workgroup.  For
 // each angle the tile's pixels touch at most kBpWin consecutive detector bins
 // (the tile spans 15 (|cos| + |sin|) <= 21.3 bins, plus the second tap and a
@@ -283,7 +404,6 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevC
 // chunk's angles, waves 4-7 the second half, 64 pixels (4 rows) per wave;
 // the two halves are added in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kBpTile = 16;
 constexpr int kBpWin = 26;
 template <class T>
 constexpr int bp_chunk() { return sizeof(T) == 4 ? 384 : 192; }
@@ -472,7 +592,7 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
     }
     T acc = T(0);
     const T cmax = (T)N;
-#pragma unroll 4
+#pragma unroll NCS_UNROLL_PROJ
     for (int s = s_begin; s < s_end; ++s) {
         const T xi = fma((T)s, A.k2, base);
         const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
@@ -482,6 +602,57 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
         acc += fma(f, v.b - v.a, v.a);
     }
     return acc;
+}
+
+// Ray sums of two adjacent rays per lane: lane (h, p) of a wave takes rays
+// d0 + 2p and d0 + 2p + 1 over step range 2 wave + h of 8.  The two rays'
+// coordinates at a step differ by |k1| <= sqrt(2) < 2 columns, so their four
+// taps lie in 4 consecutive padded-row elements, read with one 16-byte load;
+// each tap's arithmetic is that of the direct method.  Partial sums of the 8
+// step ranges go to red[range * 64 + ray].
+template <class T>
+__device__ inline void ray_sum_pair(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
+                                    const AngleT<T>& A, int axis, int d0, int lane, int wave, T* red) {
+    const int N = c.N, P = c.P;
+    const T* src = axis == 0 ? img : imgT;
+    const int h = lane >> 5, pr = lane & 31;
+    const int da = d0 + 2 * pr;
+    const T base0 = fma((T)da, A.k1, A.k0);
+    const T base1 = fma((T)(da + 1), A.k1, A.k0);
+    const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
+    const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
+    const T lo_x = T(-2), hi_x = T(N + 1);
+    const int range = 2 * wave + h;
+    const int SW = N / (2 * kWaves);
+    int s_begin = range * SW, s_end = s_begin + SW;
+    if (A.k2 > T(0)) {
+        s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
+    } else if (A.k2 < T(0)) {
+        s_begin = max(s_begin, sat_int(floor((hi_x - blo) / A.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
+    } else if (bhi < lo_x || blo > hi_x) {
+        s_end = s_begin;
+    }
+    const T cmax = (T)N;
+    T acc0 = T(0), acc1 = T(0);
+#pragma unroll NCS_UNROLL_PAIR
+    for (int s = s_begin; s < s_end; ++s) {
+        const T x0 = fma((T)s, A.k2, base0), x1 = fma((T)s, A.k2, base1);
+        const T l0 = med3(floor(x0), T(-2), cmax), l1 = med3(floor(x1), T(-2), cmax);   // zero columns off the image
+        // the 4 elements from the smaller tap, kept inside the padded row
+        const int base = min((int)fmin(l0, l1), N - 2);
+        const Four<T> v = *reinterpret_cast<const Four<T>*>(src + (size_t)s * P + base + 2);
+        const T fb = (T)base;
+        const int j0 = min(max((int)(l0 - fb), 0), 2), j1 = min(max((int)(l1 - fb), 0), 2);
+        const T f0 = x0 - l0, f1 = x1 - l1;
+        const T u0 = pick(j0, v.a, v.b, v.c), w0 = pick(j0, v.b, v.c, v.d);
+        const T u1 = pick(j1, v.a, v.b, v.c), w1 = pick(j1, v.b, v.c, v.d);
+        acc0 += fma(f0, w0 - u0, u0);
+        acc1 += fma(f1, w1 - u1, u1);
+    }
+    red[range * kRays + 2 * pr] = acc0;
+    red[range * kRays + 2 * pr + 1] = acc1;
 }
 
 // Ray sum with LDS-staged row windows.  For each step s the 64 rays of the
@@ -625,7 +796,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
     if (MODE == PMODE_ITER && c.ctl->stop) return;
-    __shared__ T red[kWaves * kRays];
+    __shared__ T red[2 * kWaves * kRays];
     __shared__ double shd[kWaves];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -642,6 +813,18 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     const int d = d0 + lane;
     const AngleT<T> A = c.ang[a];
     const int axis = c.axis[a];
+    if (VARIANT == 3) {
+        ray_sum_pair(c, img, imgT, A, axis, d0, lane, wave, red);
+        __syncthreads();
+        if (wave != 0) return;
+        T sum = red[lane];
+#pragma unroll
+        for (int r = 1; r < 2 * kWaves; ++r) sum += red[r * kRays + lane];
+        const T q = sum * A.kappa;
+        const double dterm = wave_sum(project_epilogue<T, MODE>(c, a, d, q, out));
+        if (MODE == PMODE_ITER && lane == 0) c.part_data[local] = dterm;
+        return;
+    }
     T acc;
     if (VARIANT == 1) {
         __shared__ __attribute__((aligned(16))) T stage[kWaves * kStageRows * kRowWin];
@@ -1037,6 +1220,8 @@ hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, in
                           hipStream_t st) {
     if (projector == 1)
         hipLaunchKernelGGL((k_project<T, MODE, 1>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
+    else if (projector == 3)
+        hipLaunchKernelGGL((k_project<T, MODE, 3>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
     else
         hipLaunchKernelGGL((k_project<T, MODE, 2>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
     return hipGetLastError();
@@ -1047,7 +1232,7 @@ hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, in
 int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
 int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
 int bp_blocks(int N, int variant) {
-    const int t = variant == 1 ? kBpTile : kBpTileD;
+    const int t = variant == 2 ? kBpTileD : kBpTile;
     return (N / t) * (N / t);
 }
 
@@ -1058,7 +1243,10 @@ hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target,
 
 template <class T>
 hipError_t launch_bp_iter(const IterLaunch<T>& L, int fin_prev, hipStream_t st) {
-    if (L.backprojector == 1)
+    if (L.backprojector == 3)
+        hipLaunchKernelGGL((k_backproject_quad<T, true>), dim3(L.bp.blocks), dim3(kBpQuadWaves * 64), 0, st, L.ctxs,
+                           L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
+    else if (L.backprojector == 1)
         hipLaunchKernelGGL((k_backproject_lds<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
                            L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
     else
@@ -1110,7 +1298,10 @@ hipError_t launch_iterations(const IterLaunch<T>& L, int k, hipStream_t st) {
 template <class T>
 hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int variant, const T* y_padded,
                                     T* out, hipStream_t st) {
-    if (variant == 1)
+    if (variant == 3)
+        hipLaunchKernelGGL((k_backproject_quad<T, false>), dim3(bp_blocks(hc.N, 3)), dim3(kBpQuadWaves * 64), 0, st,
+                           dc, (const Slot*)nullptr, y_padded, out, 0);
+    else if (variant == 1)
         hipLaunchKernelGGL((k_backproject_lds<T, false>), dim3(bp_blocks(hc.N, 1)), dim3(kBpWaves * 64), 0, st, dc,
                            (const Slot*)nullptr, y_padded, out, 0);
     else

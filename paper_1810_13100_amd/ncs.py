@@ -75,7 +75,7 @@ class _Params(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("nnz", ctypes.c_int64), ("c_r", ctypes.c_double), ("mu_dc", ctypes.c_double),
                 ("norm_e1_sq", ctypes.c_double), ("projector", ctypes.c_int32), ("backprojector", ctypes.c_int32),
-                ("projector_ms", ctypes.c_double * 2), ("backprojector_ms", ctypes.c_double * 2)]
+                ("projector_ms", ctypes.c_double * 3), ("backprojector_ms", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -165,10 +165,10 @@ class Params:
     tv_term: int = TV_ANISO
     check_every: int = 50
     diverge_checks: int = 0
-    projector: int = 0        # 0: autotune at setup, 1: LDS-staged, 2: direct
+    projector: int = 0        # 0: autotune at setup, 1: LDS-staged, 2: direct, 3: ray pairs
     graph_chunk: int = 0      # 0: 25 iterations per HIP graph, < 0: no graphs
     dual_ramp: float = 0.0    # TV-dual ramp width of the warm start (0: sign)
-    backprojector: int = 0    # 0: autotune at setup, 1: LDS-staged windows, 2: direct
+    backprojector: int = 0    # 0: autotune at setup, 1: LDS-staged windows, 2: direct, 3: 2x2 per lane
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:

@@ -41,9 +41,10 @@ def _phantom(n, seed=0):
 
 @pytest.mark.parametrize("key", ["tiny", "c1", "c4s", "c3", "c4m", "c2"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("projector", [1, 2])
+@pytest.mark.parametrize("projector", [1, 2, 3])
 def test_forward_matches_oracle(key, prec, projector):
-    # both forward-projector kernels (1: LDS-staged tiles, 2: direct loads)
+    # the three forward-projector kernels (1: LDS-staged row windows, 2: direct
+    # loads, 3: two rays per lane with 16-byte loads)
     geom = GEOMS[key]
     log(f"forward parity {key} {geom} {prec} projector {projector}")
     E = joseph(*geom)
@@ -60,9 +61,10 @@ def test_forward_matches_oracle(key, prec, projector):
 
 @pytest.mark.parametrize("key", ["tiny", "c1", "c4s", "c3", "c4m", "c2"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("bproj", [1, 2])
+@pytest.mark.parametrize("bproj", [1, 2, 3])
 def test_adjoint_matches_oracle(key, prec, bproj):
-    # both backprojector kernels (1: LDS-staged detector windows, 2: direct loads)
+    # the three backprojector kernels (1: LDS-staged detector windows, 2: direct
+    # loads, 3: 2 x 2 pixels per lane with 16-byte loads)
     geom = GEOMS[key]
     log(f"adjoint parity {key} {geom} {prec} backprojector {bproj}")
     E = joseph(*geom)
@@ -79,7 +81,7 @@ def test_adjoint_matches_oracle(key, prec, bproj):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("proj", [1, 2])
+@pytest.mark.parametrize("proj", [1, 2, 3])
 def test_large_slice_sampled_angles(prec, proj):
     # 512^2 with 717 x 520 (largest slice of the uneven batch): whole rows of E
     # for sampled angles, including 0, the 45-degree ties and pi/2.
@@ -191,12 +193,14 @@ def test_nonzero_count_matches_oracle(key):
 def test_autotuner_times_both_projectors():
     s = _solver(GEOMS["c2"], torch.float32)
     inf = s.info()
-    log(f"projector autotune: LDS {inf['projector_ms'][0]:.4f} ms, direct {inf['projector_ms'][1]:.4f} ms "
+    pms = inf["projector_ms"]
+    log(f"projector autotune: LDS {pms[0]:.4f} ms, direct {pms[1]:.4f} ms, pairs {pms[2]:.4f} ms "
         f"-> {inf['projector']}")
-    assert all(t > 0 for t in inf["projector_ms"])
-    assert inf["projector"] == (1 if inf["projector_ms"][0] < inf["projector_ms"][1] else 2)
-    log(f"backprojector autotune: LDS {inf['backprojector_ms'][0]:.4f} ms, direct {inf['backprojector_ms'][1]:.4f} ms "
+    assert all(t > 0 for t in pms)
+    assert inf["projector"] == 1 + int(np.argmin(pms))
+    bms = inf["backprojector_ms"]
+    log(f"backprojector autotune: LDS {bms[0]:.4f} ms, direct {bms[1]:.4f} ms, quad {bms[2]:.4f} ms "
         f"-> {inf['backprojector']}")
-    assert all(t > 0 for t in inf["backprojector_ms"])
-    assert inf["backprojector"] == (1 if inf["backprojector_ms"][0] < inf["backprojector_ms"][1] else 2)
+    assert all(t > 0 for t in bms)
+    assert inf["backprojector"] == 1 + int(np.argmin(bms))
     s.close()
