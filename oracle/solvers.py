@@ -198,3 +198,47 @@ def fixed_point_duals(prob: Problem, par: Params, x0: np.ndarray, tau: float = 0
         safe = np.where(den > 0, den, 1.0)
         v = np.concatenate([np.where(den > 0, s * gh / safe, 0.0), np.where(den > 0, s * gv / safe, 0.0)])
     return u, v
+
+
+def pcg(apply_a, rhs: np.ndarray, iters: int, precond=None) -> np.ndarray:
+    """Exactly `iters` steps of (preconditioned) conjugate gradients for
+    A d = rhs from d = 0 (Hestenes and Stiefel).  A step whose curvature p.A p
+    is zero leaves d unchanged (a zero right-hand side gives d = 0)."""
+    d = np.zeros_like(rhs)
+    r = rhs.copy()
+    z = precond(r) if precond is not None else r.copy()
+    p = z.copy()
+    rz = float(r @ z)
+    for _ in range(iters):
+        q = apply_a(p)
+        pq = float(p @ q)
+        a = rz / pq if pq != 0.0 else 0.0
+        d = d + a * p
+        r = r - a * q
+        z = precond(r) if precond is not None else r.copy()
+        rz_new = float(r @ z)
+        b = rz_new / rz if rz != 0.0 else 0.0
+        p = z + b * p
+        rz = rz_new
+    return d
+
+
+def admm_cg(prob: Problem, par: Params, iters: int, cg_iters: int, precondition: bool = True, **kw):
+    """ADMM (eq. DRS/ADMM in the form x+ = x - alpha^-1 (A^T A)^+ A^T y) with the
+    linear system solved approximately by cg_iters CG steps from zero, the
+    comparison method of Section 5 (Ramani and Fessler use CG for these
+    systems).  With precondition, CG is preconditioned by alpha M^+, the
+    method's own circulant (alpha M^+ ~ (A^T A)^-1)."""
+    N = prob.n_side
+    ratio = par.beta / par.alpha
+    h = multiplier(prob, par)
+
+    def apply_a(p):
+        return prob.Et @ (prob.E @ p) + ratio * ratio * (prob.Dt @ (prob.D @ p))
+
+    precond = None
+    if precondition:
+        def precond(r):
+            return par.alpha * operators.apply_circulant(h, r.reshape(N, N)).ravel()
+
+    return ncs_generic(prob, par, lambda z: pcg(apply_a, z, cg_iters, precond) / par.alpha, iters, **kw)

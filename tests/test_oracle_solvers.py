@@ -199,3 +199,42 @@ def test_fixed_point_duals_match_the_ncs_limit():
     big = np.abs(prob.D @ traj.x) >= tau
     np.testing.assert_array_equal(vr[big], v0[big])
     assert np.all(np.abs(vr) <= np.abs(v0) + 1e-15)
+
+
+def test_pcg_solves_spd_systems():
+    # CG reaches the solution in n steps on an n x n SPD system (exact arithmetic),
+    # with or without an SPD preconditioner
+    rng = np.random.default_rng(12)
+    n = 40
+    q = rng.standard_normal((n, n))
+    a = q @ q.T + n * np.eye(n)
+    rhs = rng.standard_normal(n)
+    ref = np.linalg.solve(a, rhs)
+    d = solvers.pcg(lambda v: a @ v, rhs, n)
+    np.testing.assert_allclose(d, ref, rtol=1e-9, atol=1e-12)
+    pinv = np.diag(1.0 / np.diag(a))
+    d = solvers.pcg(lambda v: a @ v, rhs, n, precond=lambda v: pinv @ v)
+    np.testing.assert_allclose(d, ref, rtol=1e-9, atol=1e-12)
+    assert np.array_equal(solvers.pcg(lambda v: a @ v, np.zeros(n), 5), np.zeros(n))
+
+
+@pytest.mark.parametrize("precondition", [True, False])
+def test_admm_cg_converged_inner_solves_equal_admm(precondition):
+    # with the inner systems solved to convergence ADMM-CG is exact-solve ADMM
+    prob = problems.ct_problem(16, 12, 23, 0, 0.05)
+    par = problems.Params(0.05, 0.15, 0.3 * 0.05 * 12 * 16 / np.pi)
+    x_ref, y_ref, obj_ref = solvers.admm(prob, par, 20)
+    x, y, obj = solvers.admm_cg(prob, par, 20, 400, precondition=precondition)
+    np.testing.assert_allclose(x, x_ref, rtol=0, atol=1e-8 * np.abs(x_ref).max())
+    np.testing.assert_allclose(obj, obj_ref, rtol=1e-9)
+
+
+def test_preconditioned_cg_needs_fewer_steps():
+    # the circulant preconditioner reduces the inner residual faster (Section 4.1:
+    # alpha M^+ approximates (A^T A)^-1)
+    prob = problems.ct_problem(32, 45, 48, 0, 0.01)
+    par = problems.Params(0.01, 0.03, 0.3 * 0.01 * 45 * 32 / np.pi)
+    x_ref, _, _ = solvers.admm(prob, par, 30)
+    e_pc = np.linalg.norm(solvers.admm_cg(prob, par, 30, 5, True)[0] - x_ref)
+    e_cg = np.linalg.norm(solvers.admm_cg(prob, par, 30, 5, False)[0] - x_ref)
+    assert e_pc < e_cg
