@@ -153,12 +153,52 @@ def time_to_gap(ncs, torch, dev, geom, args) -> dict:
         s.close()
         progress(f"  slice {i}: plain {plain_it[-1]} it {plain_t[-1]:.3f} s" +
                  (f", warm {warm_it[-1]} it {warm_t[-1]:.3f} s" if net is not None else ""))
+    # PDHG (eq. PDHG) on the same kernels and the first slice: M = gamma_P I with
+    # gamma_P = 1.05 alpha lambda_max(A^T A); lambda_max(E^T E) by power iteration,
+    # plus (beta/alpha)^2 * 8 for D^T D (its largest eigenvalue is below 8)
+    progress("PDHG: power iteration for lambda_max(E^T E)")
+    op = ncs.Solver(geom, params(ncs))
+    g = torch.Generator(device="cpu").manual_seed(3)
+    v = torch.randn(geom.n, generator=g, dtype=torch.float32).to(dev)
+    lam_e = 0.0
+    for _ in range(60):
+        w = op.adjoint(op.forward(v / torch.linalg.norm(v)))
+        lam_e = float(torch.linalg.norm(w))
+        v = w
+    op.close()
+    gamma_p = 1.05 * ALPHA * (lam_e + (BETA_RATIO ** 2) * 8.0)
+    pp = ncs.Params(ALPHA, BETA_RATIO * ALPHA, gamma_p, LAMBDA, method=ncs.METHOD_PDHG)
+    s = ncs.Solver(geom, pp, b=bs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_init()
+    st, it_p, f_p = s.solve(args.pdhg_iters, fstar[0] * (1.0 + GAP))
+    torch.cuda.synchronize()
+    pdhg = {"slice": 0, "gamma_p": gamma_p, "lambda_max_EtE": lam_e, "seconds": time.perf_counter() - t0,
+            "iterations": it_p, "reached": st == ncs.NCS_OK, "rel_gap_at_end": (f_p - fstar[0]) / abs(fstar[0]),
+            "ncs_iterations_same_slice": plain_it[0]}
+    s.close()
+    progress(f"PDHG: {it_p} iterations, reached {st == ncs.NCS_OK} (NCS: {plain_it[0]})")
+    # ADMM with 10 preconditioned CG steps per linear solve on the same slice
+    pa = ncs.Params(ALPHA, BETA_RATIO * ALPHA, GAMMA_FRAC * ALPHA * N_ANGLES * N_SIDE / math.pi, LAMBDA,
+                    method=ncs.METHOD_ADMM_CG, cg_iters=10, cg_precondition=1)
+    s = ncs.Solver(geom, pa, b=bs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_init()
+    st, it_a, f_a = s.solve(args.admm_iters, fstar[0] * (1.0 + GAP))
+    torch.cuda.synchronize()
+    admm = {"slice": 0, "cg_iters": 10, "preconditioner": "alpha M^+ (the NCS circulant)",
+            "seconds": time.perf_counter() - t0, "iterations": it_a, "reached": st == ncs.NCS_OK,
+            "rel_gap_at_end": (f_a - fstar[0]) / abs(fstar[0])}
+    s.close()
+    progress(f"ADMM-CG: {it_a} iterations, reached {st == ncs.NCS_OK}")
     med = lambda v: float(np.median(v)) if v and all(x is not None for x in v) else None
     out = {"seeds": seeds, "rel_gap": GAP, "f_star": fstar.tolist(),
            "f_star_source": f"min f over {args.fstar_iters} FP64 iterations of each slice",
            "f_star_rel_change_last_1000": tail,
            "plain": {"seconds_median": med(plain_t), "iterations_median": med(plain_it),
-                     "seconds": plain_t, "iterations": plain_it}}
+                     "seconds": plain_t, "iterations": plain_it}, "pdhg": pdhg, "admm_cg": admm}
     if net is not None:
         out["warm"] = {"seconds_median": med(warm_t), "iterations_median": med(warm_it), "seconds": warm_t,
                        "iterations": warm_it, "k0": k0, "weights": os.path.relpath(WEIGHTS, ROOT),
@@ -297,6 +337,8 @@ def main() -> int:
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap measurement")
     ap.add_argument("--fstar-iters", type=int, default=12000)
     ap.add_argument("--gap-seeds", type=int, default=8, help="evaluation slices of the time-to-gap measurement")
+    ap.add_argument("--pdhg-iters", type=int, default=100000, help="iteration budget of the PDHG comparison")
+    ap.add_argument("--admm-iters", type=int, default=5000, help="iteration budget of the ADMM-CG comparison")
     ap.add_argument("--batch-iters", type=int, default=40, help="iterations of the uneven 512-slice batch (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:

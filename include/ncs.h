@@ -79,6 +79,13 @@ typedef struct {
     int32_t n_bins;    /* N_s */
 } ncs_geometry;
 
+/* The splitting: NCS with the circulant M of Section 4.1.1; PDHG (eq. PDHG,
+ * Section 1), the same iteration with M = gamma I; or ADMM (eq. DRS/ADMM),
+ * M = alpha A^T A, with each linear system solved by cg_iters conjugate-
+ * gradient steps from zero (Section 5's comparison method), optionally
+ * preconditioned by alpha M^+ with the NCS circulant M (single slices only). */
+typedef enum { NCS_METHOD_NCS = 0, NCS_METHOD_PDHG = 1, NCS_METHOD_ADMM_CG = 2 } ncs_method;
+
 typedef struct {
     double alpha;      /* > 0: dual step alpha of eq. (NCS) */
     double beta;       /* > 0: TV block scaling, A = [E; (beta/alpha) D] (Section 4.1) */
@@ -105,6 +112,10 @@ typedef struct {
                               1 = LDS-staged detector windows (16 x 16 pixel tiles),
                               2 = direct global loads (8 x 8 pixel tiles),
                               3 = 2 x 2 pixels per lane, one 16-byte load per angle */
+    int32_t method;        /* ncs_method: NCS (M circulant), PDHG (M = gamma I; needs
+                              gamma > alpha lambda_max(A^T A) to converge) or ADMM-CG */
+    int32_t cg_iters;      /* ADMM-CG: CG steps per linear solve; 0 selects 10 */
+    int32_t cg_precondition; /* ADMM-CG: 1 = precondition CG with alpha M^+, 0 = plain CG */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;

@@ -85,6 +85,11 @@ struct ncs_handle {
     Control* ctl = nullptr;     // owned, or an element of a batch's control array
     double* hist = nullptr;
     void* dctx = nullptr;       // device copy of this slice's DevCtx<T>
+    // ADMM with CG inner solves (method NCS_METHOD_ADMM_CG) only
+    void* cg_vec = nullptr;     // d, r, z, p, q: 5 N*N vectors
+    void* cg_y = nullptr;       // unpadded sinogram scratch
+    double* cg_part = nullptr;  // dot-product partials
+    double* cg_s = nullptr;     // CG scalars
 
     const void* b = nullptr;    // caller-owned
     const void* bg = nullptr;   // caller-owned
@@ -157,6 +162,17 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
     c.part_tv = h->part_tv;
     c.ctl = h->ctl;
     c.hist = h->hist;
+    if (h->cg_vec) {
+        T* v = static_cast<T*>(h->cg_vec);
+        c.cg_d = v;
+        c.cg_r = v + h->n;
+        c.cg_z = v + 2 * h->n;
+        c.cg_p = v + 3 * h->n;
+        c.cg_q = v + 4 * h->n;
+        c.cg_y = static_cast<T*>(h->cg_y);
+        c.cg_part = h->cg_part;
+        c.cg_s = h->cg_s;
+    }
     c.alpha = (T)h->p.alpha;
     c.beta = (T)h->p.beta;
     c.s_tv = (T)(h->p.lambda * h->p.alpha / h->p.beta);
@@ -251,6 +267,14 @@ ncs_status upload_ctx_typed(ncs_handle* h) {
 
 // ---- iteration launch -----------------------------------------------------
 hipError_t launch_eager(ncs_handle* h, int k, hipStream_t st) {
+    if (h->p.method == NCS_METHOD_ADMM_CG) {
+        const int cg = h->p.cg_iters > 0 ? h->p.cg_iters : 10;
+        return h->dtype == NCS_F64
+                   ? launch_admm_iterations<double>(single_launch<double>(h), make_ctx<double>(h), k, cg,
+                                                    h->p.cg_precondition, st)
+                   : launch_admm_iterations<float>(single_launch<float>(h), make_ctx<float>(h), k, cg,
+                                                   h->p.cg_precondition, st);
+    }
     return h->dtype == NCS_F64 ? launch_iterations<double>(single_launch<double>(h), k, st)
                                : launch_iterations<float>(single_launch<float>(h), k, st);
 }
@@ -405,6 +429,19 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("unknown tv_term %d", p.tv_term);
         return NCS_ERR_INVALID_ARG;
     }
+    if (p.method != NCS_METHOD_NCS && p.method != NCS_METHOD_PDHG && p.method != NCS_METHOD_ADMM_CG) {
+        set_err("method must be NCS_METHOD_NCS (0), NCS_METHOD_PDHG (1) or NCS_METHOD_ADMM_CG (2)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.method == NCS_METHOD_ADMM_CG && (p.cg_iters < 0 || p.cg_iters > 1000 || p.cg_precondition < 0 ||
+                                           p.cg_precondition > 1)) {
+        set_err("ADMM-CG needs 0 <= cg_iters <= 1000 (0 selects 10) and cg_precondition 0 or 1");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.method == NCS_METHOD_PDHG && !(p.gamma > 0.0)) {
+        set_err("PDHG needs gamma > 0 (the step is 1/gamma)");
+        return NCS_ERR_INVALID_ARG;
+    }
     if (p.backprojector < 0 || p.backprojector > 3) {
         set_err("backprojector must be 0 (auto), 1 (LDS), 2 (direct) or 3 (quad)");
         return NCS_ERR_INVALID_ARG;
@@ -426,6 +463,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
     h->p = p;
     if (h->p.check_every <= 0) h->p.check_every = 50;
     h->graph_chunk = p.graph_chunk == 0 ? 25 : (p.graph_chunk < 0 ? 0 : p.graph_chunk);
+    if (p.method == NCS_METHOD_ADMM_CG && h->graph_chunk > 2) h->graph_chunk = 2;   // ~15 launches per CG step
     h->projector = p.projector == 0 ? 2 : p.projector;
     h->backprojector = p.backprojector == 0 ? 2 : p.backprojector;
     h->dtype = dtype;
@@ -500,6 +538,11 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         (s = dev_alloc(h, reinterpret_cast<void**>(&h->hist), (size_t)kHistCap * sizeof(double))) ||
         (s = dev_alloc(h, &h->dctx, ctx_bytes)))
         return fail(s);
+    if (p.method == NCS_METHOD_ADMM_CG &&
+        ((s = dev_alloc(h, &h->cg_vec, 5 * h->n * e)) || (s = dev_alloc(h, &h->cg_y, h->m * e)) ||
+         (s = dev_alloc(h, reinterpret_cast<void**>(&h->cg_part), (size_t)cg_blocks(N) * sizeof(double))) ||
+         (s = dev_alloc(h, reinterpret_cast<void**>(&h->cg_s), 4 * sizeof(double)))))
+        return fail(s);
     if (ext_ctl) {
         h->ctl = ext_ctl;
     } else if ((s = dev_alloc(h, reinterpret_cast<void**>(&h->ctl), sizeof(Control)))) {
@@ -556,6 +599,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         }
     }
     h->mu[0] = h->mu_dc;
+    if (p.method == NCS_METHOD_PDHG) std::fill(h->mu.begin(), h->mu.end(), p.gamma);   // M = gamma I (eq. PDHG)
     std::vector<double> hh((size_t)NH * N);
     const double scale = 1.0 / (p.alpha * (double)N * (double)N);
     for (int k = 0; k < NH; ++k)
@@ -1028,6 +1072,10 @@ ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host) {
         set_err("ncs_time_phases: handle has no data (b_dev was NULL)");
         return NCS_ERR_INVALID_ARG;
     }
+    if (h->p.method == NCS_METHOD_ADMM_CG) {
+        set_err("ncs_time_phases: the phases are those of NCS and PDHG, not of ADMM-CG");
+        return NCS_ERR_INVALID_ARG;
+    }
     NCS_HIP(launch_control(h->ctl, 1, 0, std::nan(""), h->stream));
     std::vector<hipEvent_t> ev(2 * NCS_N_PHASES * (size_t)iters);
     for (auto& e : ev) NCS_HIP(hipEventCreate(&e));
@@ -1238,6 +1286,10 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
         }
         if (!b_dev[i]) {
             set_err("ncs_batch_setup: slice %d has no data", i);
+            return NCS_ERR_INVALID_ARG;
+        }
+        if (params[i].method == NCS_METHOD_ADMM_CG) {
+            set_err("ncs_batch_setup: slice %d: batches run NCS or PDHG, not ADMM-CG", i);
             return NCS_ERR_INVALID_ARG;
         }
     }

@@ -79,6 +79,17 @@ struct DevCtx {
     NCS_G double* part_tv;     // nb_tv partial TV terms
     NCS_G Control* ctl;
     NCS_G double* hist;
+    // ADMM with CG inner solves only (null otherwise): CG vectors (N*N), an
+    // unpadded sinogram scratch, per-block dot-product partials and the CG
+    // scalars [r.z, p.q, a, b]
+    NCS_G T* cg_d;
+    NCS_G T* cg_r;
+    NCS_G T* cg_z;
+    NCS_G T* cg_p;
+    NCS_G T* cg_q;
+    NCS_G T* cg_y;
+    NCS_G double* cg_part;
+    NCS_G double* cg_s;
     T alpha, beta, s_tv, inv1pa;
     T dual_ramp;                     // TV-dual ramp width of the warm start (<= 0: sign)
     double lambda;
@@ -110,6 +121,17 @@ struct IterLaunch {
 
 constexpr int kNumPhases = 6;   // backprojection, row DFT, column DFT, inverse row DFT + x-update,
                                 // projection + data prox + TV update, objective
+
+// The backprojection launch of an iteration (fin_prev: reduce the previous
+// iteration's objective first).
+template <class T> hipError_t launch_bp_iter(const IterLaunch<T>& L, int fin_prev, hipStream_t st);
+
+// k iterations of ADMM with cg_iters conjugate-gradient steps per linear
+// solve (precond: circulant alpha M^+ preconditioner); hc is the host copy
+// of the single slice's descriptor.
+template <class T> hipError_t launch_admm_iterations(const IterLaunch<T>& L, const DevCtx<T>& hc, int k, int cg_iters,
+                                                     int precond, hipStream_t st);
+int cg_blocks(int N);
 
 // k iterations (five launches each plus one finalize at the end).
 template <class T> hipError_t launch_iterations(const IterLaunch<T>& L, int k, hipStream_t st);

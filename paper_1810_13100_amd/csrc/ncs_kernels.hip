@@ -1201,6 +1201,124 @@ __global__ __launch_bounds__(256) void k_fbp_filter(const DevCtx<T>* __restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// ADMM with conjugate-gradient inner solves (the comparison method of
+// Section 5): x+ = x - d / alpha with d ~ (A^T A)^-1 g, g = E^T u + (beta/alpha)
+// D^T v = w / alpha, by a fixed number of (preconditioned) CG steps from
+// d = 0.  Dot products use per-block partial sums added in a fixed order;
+// the CG scalars stay in device memory (cg_s: r.z, p.q, a, b).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_start(const DevCtx<T>* __restrict__ ctxs, int precond) {
+    const DevCtx<T>& c = ctxs[0];
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (pix >= (size_t)c.N * c.N) return;
+    const T r = c.w[pix] / c.alpha;
+    c.cg_d[pix] = T(0);
+    c.cg_r[pix] = r;
+    if (!precond) c.cg_z[pix] = r;
+}
+
+// part[block] = sum over the block's pixels of a * b
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_dot(const DevCtx<T>* __restrict__ ctxs, int which) {
+    const DevCtx<T>& c = ctxs[0];
+    __shared__ double sh[kWaves];
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (pix < (size_t)c.N * c.N) v = which == 0 ? (double)c.cg_r[pix] * (double)c.cg_z[pix] : 0.0;
+    v = block_sum256(v, sh);
+    if (threadIdx.x == 0) c.cg_part[blockIdx.x] = v;
+}
+
+// q += (beta/alpha)^2 D^T D p (q holds E^T E p), and part[block] = p . q
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_normal(const DevCtx<T>* __restrict__ ctxs, T ratio2) {
+    const DevCtx<T>& c = ctxs[0];
+    __shared__ double sh[kWaves];
+    const int N = c.N;
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (pix < (size_t)N * N) {
+        const int r = (int)(pix >> c.log2N), col = (int)(pix & (size_t)(N - 1));
+        const T* p = c.cg_p;
+        // D of Section 2 on each axis: (D p)_h = p(r, c) - p(r, c + 1), zero in the last column
+        auto dh = [&](size_t i, int cc) { return cc < N - 1 ? p[i] - p[i + 1] : T(0); };
+        auto dv = [&](size_t i, int rr) { return rr < N - 1 ? p[i] - p[i + N] : T(0); };
+        T dtd = dh(pix, col) + dv(pix, r);
+        if (col > 0) dtd -= dh(pix - 1, col - 1);
+        if (r > 0) dtd -= dv(pix - N, r - 1);
+        const T q = fma(ratio2, dtd, c.cg_q[pix]);
+        c.cg_q[pix] = q;
+        v = (double)p[pix] * (double)q;
+    }
+    v = block_sum256(v, sh);
+    if (threadIdx.x == 0) c.cg_part[blockIdx.x] = v;
+}
+
+// One workgroup: the sum of the partials and the scalar update.
+//   op 0: r.z;  op 1: p.q and a = r.z / p.q;  op 2: b = r.z' / r.z and r.z = r.z'
+// A zero denominator gives a zero step (the oracle's convention).
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_scalar(const DevCtx<T>* __restrict__ ctxs, int nb, int op) {
+    const DevCtx<T>& c = ctxs[0];
+    __shared__ double sh[kWaves];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) v += c.cg_part[i];
+    v = block_sum256(v, sh);
+    if (threadIdx.x != 0) return;
+    NCS_G double* s = c.cg_s;
+    if (op == 0) {
+        s[0] = v;
+    } else if (op == 1) {
+        s[1] = v;
+        s[2] = v != 0.0 ? s[0] / v : 0.0;
+    } else {
+        s[3] = s[0] != 0.0 ? v / s[0] : 0.0;
+        s[0] = v;
+    }
+}
+
+// d += a p, r -= a q (and z = r without a preconditioner)
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_step(const DevCtx<T>* __restrict__ ctxs, int precond) {
+    const DevCtx<T>& c = ctxs[0];
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (pix >= (size_t)c.N * c.N) return;
+    const T a = (T)c.cg_s[2];
+    c.cg_d[pix] = fma(a, c.cg_p[pix], c.cg_d[pix]);
+    const T r = fma(-a, c.cg_q[pix], c.cg_r[pix]);
+    c.cg_r[pix] = r;
+    if (!precond) c.cg_z[pix] = r;
+}
+
+// p = z (first direction) or p = z + b p
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_dir(const DevCtx<T>* __restrict__ ctxs, int first) {
+    const DevCtx<T>& c = ctxs[0];
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (pix >= (size_t)c.N * c.N) return;
+    c.cg_p[pix] = first ? c.cg_z[pix] : fma((T)c.cg_s[3], c.cg_p[pix], c.cg_z[pix]);
+}
+
+// x+ = x - d / alpha, xbar = 2 x+ - x (padded row-major and padded transpose);
+// an iteration after the stopping one leaves the state alone
+template <class T>
+__global__ __launch_bounds__(256) void k_admm_update(const DevCtx<T>* __restrict__ ctxs) {
+    const DevCtx<T>& c = ctxs[0];
+    if (c.ctl->stop) return;
+    const int N = c.N;
+    const size_t pix = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (pix >= (size_t)N * N) return;
+    const int r = (int)(pix >> c.log2N), col = (int)(pix & (size_t)(N - 1));
+    const T x = c.x[pix];
+    const T xn = x - c.cg_d[pix] / c.alpha;
+    c.x[pix] = xn;
+    const T xb = fma(T(2), xn, -x);
+    c.xbar[(size_t)r * c.P + col + 2] = xb;
+    c.xbarT[(size_t)col * c.P + r + 2] = xb;
+}
+
 __global__ void k_control(Control* ctl, int op, int iter_value, double f_target) {
     if (threadIdx.x != 0) return;
     if (op == 0) ctl->iter = 0;
@@ -1231,6 +1349,8 @@ hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, in
 
 int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
 int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
+int cg_blocks(int N) { return (int)blocks_for((size_t)N * N); }
+
 int bp_blocks(int N, int variant) {
     const int t = variant == 2 ? kBpTileD : kBpTile;
     return (N / t) * (N / t);
@@ -1291,6 +1411,53 @@ hipError_t launch_iterations(const IterLaunch<T>& L, int k, hipStream_t st) {
         hipError_t e = launch_bp_iter<T>(L, i > 0 ? 1 : 0, st);
         for (int ph = 1; ph < kNumPhases - 1 && e == hipSuccess; ++ph) e = launch_iteration_phase<T>(L, ph, st);
         if (e != hipSuccess) return e;
+    }
+    return k > 0 ? launch_iteration_phase<T>(L, kNumPhases - 1, st) : hipSuccess;
+}
+
+template <class T>
+hipError_t launch_admm_iterations(const IterLaunch<T>& L, const DevCtx<T>& hc, int k, int cg_iters, int precond,
+                                  hipStream_t st) {
+    const DevCtx<T>* dc = L.ctxs;
+    const int nb = cg_blocks(hc.N);
+    const T ratio2 = (hc.beta / hc.alpha) * (hc.beta / hc.alpha);
+    const T a2 = hc.alpha * hc.alpha;   // the column pass scales h/(alpha N^2): alpha^2 gives alpha M^+
+    const size_t sm = fft_lds<T>(hc.N);
+    auto precondition = [&]() {
+        hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr,
+                           (const T*)hc.cg_r, 0);
+        hipLaunchKernelGGL((k_fft_cols<T>), dim3(hc.N / 2 + 1), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, a2, 0);
+        hipLaunchKernelGGL((k_fft_rows_inv<T, false>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc,
+                           (const Slot*)nullptr, (T*)hc.cg_z);
+    };
+    for (int i = 0; i < k; ++i) {
+        hipError_t e = launch_bp_iter<T>(L, i > 0 ? 1 : 0, st);   // w = alpha E^T u + beta D^T v
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_cg_start<T>), dim3(nb), dim3(256), 0, st, dc, precond);
+        if (precond) precondition();
+        hipLaunchKernelGGL((k_cg_dot<T>), dim3(nb), dim3(256), 0, st, dc, 0);
+        hipLaunchKernelGGL((k_cg_scalar<T>), dim3(1), dim3(256), 0, st, dc, nb, 0);
+        hipLaunchKernelGGL((k_cg_dir<T>), dim3(nb), dim3(256), 0, st, dc, 1);
+        for (int j = 0; j < cg_iters; ++j) {
+            // q = A^T A p = E^T E p + (beta/alpha)^2 D^T D p
+            hipLaunchKernelGGL((k_pad_image<T>), dim3(tv_blocks(hc.N)), dim3(256), 0, st, dc, (const T*)hc.cg_p);
+            if ((e = launch_project<T, PMODE_PLAIN>(dc, nullptr, project_blocks(hc.NA, hc.NS), L.projector,
+                                                    (T*)hc.cg_y, st)) != hipSuccess)
+                return e;
+            if ((e = launch_pad_sinogram<T>(hc, dc, (const T*)hc.cg_y, hc.ysc, st)) != hipSuccess) return e;
+            if ((e = launch_backproject_plain<T>(hc, dc, L.backprojector, hc.ysc, hc.cg_q, st)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL((k_cg_normal<T>), dim3(nb), dim3(256), 0, st, dc, ratio2);
+            hipLaunchKernelGGL((k_cg_scalar<T>), dim3(1), dim3(256), 0, st, dc, nb, 1);
+            hipLaunchKernelGGL((k_cg_step<T>), dim3(nb), dim3(256), 0, st, dc, precond);
+            if (precond) precondition();
+            hipLaunchKernelGGL((k_cg_dot<T>), dim3(nb), dim3(256), 0, st, dc, 0);
+            hipLaunchKernelGGL((k_cg_scalar<T>), dim3(1), dim3(256), 0, st, dc, nb, 2);
+            hipLaunchKernelGGL((k_cg_dir<T>), dim3(nb), dim3(256), 0, st, dc, 0);
+        }
+        hipLaunchKernelGGL((k_admm_update<T>), dim3(nb), dim3(256), 0, st, dc);
+        if ((e = launch_iteration_phase<T>(L, 4, st)) != hipSuccess) return e;   // projection, duals, TV, partials
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return k > 0 ? launch_iteration_phase<T>(L, kNumPhases - 1, st) : hipSuccess;
 }
@@ -1404,6 +1571,8 @@ hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projecto
 
 #define NCS_INSTANTIATE(T)                                                                                        \
     template hipError_t launch_iterations<T>(const IterLaunch<T>&, int, hipStream_t);                            \
+    template hipError_t launch_bp_iter<T>(const IterLaunch<T>&, int, hipStream_t);                                \
+    template hipError_t launch_admm_iterations<T>(const IterLaunch<T>&, const DevCtx<T>&, int, int, int, hipStream_t); \
     template hipError_t launch_iteration_phase<T>(const IterLaunch<T>&, int, hipStream_t);                       \
     template hipError_t launch_backproject_plain<T>(const DevCtx<T>&, const DevCtx<T>*, int, const T*, T*, hipStream_t); \
     template hipError_t launch_apply_minv<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, T, hipStream_t);  \

@@ -28,6 +28,9 @@ NCS_ERR_DIVERGED = -5
 
 NCS_F32 = 0
 NCS_F64 = 1
+METHOD_NCS = 0
+METHOD_PDHG = 1
+METHOD_ADMM_CG = 2
 DATA_QUADRATIC = 0
 DATA_POISSON = 1
 TV_ANISO = 0
@@ -68,7 +71,8 @@ class _Params(ctypes.Structure):
         ("data_term", ctypes.c_int32), ("tv_term", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("diverge_checks", ctypes.c_int32),
         ("projector", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
-        ("dual_ramp", ctypes.c_double), ("backprojector", ctypes.c_int32),
+        ("dual_ramp", ctypes.c_double), ("backprojector", ctypes.c_int32), ("method", ctypes.c_int32),
+        ("cg_iters", ctypes.c_int32), ("cg_precondition", ctypes.c_int32),
     ]
 
 
@@ -169,6 +173,9 @@ class Params:
     graph_chunk: int = 0      # 0: 25 iterations per HIP graph, < 0: no graphs
     dual_ramp: float = 0.0    # TV-dual ramp width of the warm start (0: sign)
     backprojector: int = 0    # 0: autotune at setup, 1: LDS-staged windows, 2: direct, 3: 2x2 per lane
+    method: int = 0           # METHOD_NCS, METHOD_PDHG (M = gamma I) or METHOD_ADMM_CG
+    cg_iters: int = 0         # ADMM-CG: CG steps per linear solve (0: 10)
+    cg_precondition: int = 1  # ADMM-CG: precondition CG with alpha M^+
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -194,7 +201,8 @@ class Solver:
         g = _Geometry(geom.n_side, geom.n_angles, geom.n_bins)
         p = _Params(params.alpha, params.beta, params.gamma, params.lam, params.c_r, params.mu_dc,
                     params.data_term, params.tv_term, params.check_every, params.diverge_checks,
-                    params.projector, params.graph_chunk, params.dual_ramp, params.backprojector)
+                    params.projector, params.graph_chunk, params.dual_ramp, params.backprojector, params.method,
+                    params.cg_iters, params.cg_precondition)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.ncs_setup(ctypes.byref(g), ctypes.byref(p),
@@ -389,7 +397,7 @@ class Batch:
         G = (_Geometry * n)(*[_Geometry(g.n_side, g.n_angles, g.n_bins) for g in geoms])
         P = (_Params * n)(*[_Params(p.alpha, p.beta, p.gamma, p.lam, p.c_r, p.mu_dc, p.data_term, p.tv_term,
                                     p.check_every, p.diverge_checks, p.projector, p.graph_chunk, p.dual_ramp,
-                                    p.backprojector)
+                                    p.backprojector, p.method, p.cg_iters, p.cg_precondition)
                               for p in params])
         B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
         BG = None

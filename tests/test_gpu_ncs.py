@@ -260,3 +260,68 @@ def test_fixed_point_dual_init(kind, tau):
     ev = np.max(np.abs(v - v_ref)) / max(np.max(np.abs(v_ref)), 1e-300)
     log(f"dual init {kind} tau {tau}: max rel err u {eu:.1e}, v {ev:.1e}")
     assert eu <= 1e-10 and ev <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pdhg_matches_oracle(prec):
+    # method = PDHG runs the same kernels with M = gamma I (eq. PDHG)
+    import scipy.sparse.linalg as sla
+    prob = ct_problem("c1")
+    par0 = ct_params(64, 90)
+    ata = sla.LinearOperator((prob.n, prob.n), dtype=np.float64,
+                             matvec=lambda x: prob.Et @ (prob.E @ x) + (par0.beta / par0.alpha) ** 2 * (prob.Dt @ (prob.D @ x)))
+    lmax = float(sla.eigsh(ata, k=1, which="LA", tol=1e-10, return_eigenvectors=False)[0])
+    gp = 1.01 * par0.alpha * lmax
+    K = 200
+    x_ref, y_ref, obj_ref = solvers.pdhg(prob, par0, gp, K)
+    p = ncs.Params(par0.alpha, par0.beta, gp, prob.lam, method=ncs.METHOD_PDHG)
+    dt = DT[prec]
+    s = ncs.Solver(ncs.Geometry(64, 90, 92), p, b=torch.tensor(prob.b, dtype=dt, device=DEV), dtype=dt)
+    s.set_init()
+    obj = s.iterate(K, record=True)
+    x = s.x().double().cpu().numpy()
+    s.close()
+    ex = rel_l2(x, x_ref)
+    ef = float(np.max(np.abs(obj - obj_ref) / np.abs(obj_ref)))
+    log(f"PDHG parity {prec}: rel-L2 x {ex:.2e}, max rel f {ef:.2e}")
+    tx, tf = TOL[prec]
+    assert ex <= tx and ef <= tf
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("precondition", [1, 0])
+def test_admm_cg_matches_oracle(prec, precondition):
+    # method = ADMM_CG: cg_iters CG steps per linear solve, the same number as the oracle
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    K, CG = 30, 5
+    x_ref, _, obj_ref = solvers.admm_cg(prob, par, K, CG, precondition=bool(precondition))
+    p = ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, c_r=par.c_r or 0.0, mu_dc=par.mu_dc or 0.0,
+                   method=ncs.METHOD_ADMM_CG, cg_iters=CG, cg_precondition=precondition)
+    dt = DT[prec]
+    s = ncs.Solver(ncs.Geometry(64, 90, 92), p, b=torch.tensor(prob.b, dtype=dt, device=DEV), dtype=dt)
+    s.set_init()
+    obj = s.iterate(K, record=True)
+    x = s.x().double().cpu().numpy()
+    s.close()
+    ex = rel_l2(x, x_ref)
+    ef = float(np.max(np.abs(obj - obj_ref) / np.abs(obj_ref)))
+    log(f"ADMM-CG parity {prec} precondition {precondition}: rel-L2 x {ex:.2e}, max rel f {ef:.2e}")
+    # FP64 equals the oracle's arithmetic; in FP32, CG without a preconditioner
+    # amplifies rounding by roughly the condition number of A^T A (~1e4 here,
+    # times the FP32 unit roundoff 6e-8), hence its wider gate
+    if prec == "f64":
+        tx, tf = 1e-9, 1e-10
+    else:
+        tx, tf = (1e-3, 1e-5) if precondition else (2e-3, 1e-3)
+    assert ex <= tx and ef <= tf
+
+
+def test_admm_cg_rejected_in_batches():
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    p = ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, method=ncs.METHOD_ADMM_CG)
+    b = torch.tensor(prob.b, dtype=torch.float32, device=DEV)
+    with pytest.raises(ncs.NcsError) as e:
+        ncs.Batch([ncs.Geometry(64, 90, 92)], [p], [b])
+    assert e.value.status == ncs.NCS_ERR_INVALID_ARG
