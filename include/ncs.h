@@ -109,7 +109,8 @@ typedef struct {
                             s (D x0)_p / max(|(D x0)_p|, tau) (isotropic); <= 0 gives the
                             sign, v = s sign(D x0) */
     int32_t backprojector; /* backprojector kernel: 0 = time all at setup and keep the fastest,
-                              1 = LDS-staged detector windows (16 x 16 pixel tiles),
+                              1 = LDS-staged detector windows (16 x 16 pixel tiles,
+                                  2 x 2 pixels per lane),
                               2 = direct global loads (8 x 8 pixel tiles),
                               3 = 2 x 2 pixels per lane, one 16-byte load per angle */
     int32_t method;        /* ncs_method: NCS (M circulant), PDHG (M = gamma I; needs

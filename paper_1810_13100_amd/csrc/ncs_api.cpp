@@ -356,8 +356,8 @@ ncs_status autotune_projector(ncs_handle* h) {
     return NCS_OK;
 }
 
-// Backprojector selection: time both variants on this geometry (plain
-// backprojections of the scratch sinogram) and keep the faster.
+// Backprojector selection: time every variant on this geometry (plain
+// backprojections of the scratch sinogram) and keep the fastest.
 template <class T>
 ncs_status autotune_backprojector(ncs_handle* h) {
     hipEvent_t e0, e1;
@@ -367,7 +367,7 @@ ncs_status autotune_backprojector(ncs_handle* h) {
     const T* src = static_cast<const T*>(h->ysc);
     T* out = static_cast<T*>(h->w);
     const int reps = 5;
-    for (int variant = 1; variant <= 3; ++variant) {
+    for (int variant = 1; variant <= kNumBackprojectors; ++variant) {
         NCS_HIP(launch_backproject_plain<T>(c, dctx<T>(h), variant, src, out, h->stream));   // warm-up
         NCS_HIP(hipEventRecord(e0, h->stream));
         for (int r = 0; r < reps; ++r) NCS_HIP(launch_backproject_plain<T>(c, dctx<T>(h), variant, src, out, h->stream));
@@ -380,7 +380,7 @@ ncs_status autotune_backprojector(ncs_handle* h) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     int best = 1;
-    for (int v = 2; v <= 3; ++v)
+    for (int v = 2; v <= kNumBackprojectors; ++v)
         if (h->backprojector_ms[v - 1] < h->backprojector_ms[best - 1]) best = v;
     h->backprojector = best;
     return NCS_OK;
@@ -442,7 +442,7 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("PDHG needs gamma > 0 (the step is 1/gamma)");
         return NCS_ERR_INVALID_ARG;
     }
-    if (p.backprojector < 0 || p.backprojector > 3) {
+    if (p.backprojector < 0 || p.backprojector > kNumBackprojectors) {
         set_err("backprojector must be 0 (auto), 1 (LDS), 2 (direct) or 3 (quad)");
         return NCS_ERR_INVALID_ARG;
     }
@@ -514,7 +514,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         t[5] = hs - hn * (ct + st);
         t[7] = t[6] * t[6];
         t[8] = t[6] - t[7];
-        t[9] = 0.0;
+        t[9] = 1.0 - t[6];
     }
 
     // ---- workspace ---------------------------------------------------------
@@ -1217,7 +1217,7 @@ ncs_status autotune_batch(ncs_batch* B, bool tune_p, bool tune_b) {
     int bp = p0, bb = b0;
     for (int pv = 1; pv <= 3; ++pv) {
         if (!tune_p && pv != p0) continue;
-        for (int bv = 1; bv <= 3; ++bv) {
+        for (int bv = 1; bv <= kNumBackprojectors; ++bv) {
             if (!tune_b && bv != b0) continue;
             B->projector = pv;
             B->backprojector = bv;

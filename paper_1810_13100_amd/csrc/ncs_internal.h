@@ -31,7 +31,7 @@ struct AngleT {
     T k1, k2, k0;
     T q1, q2, q0;
     T kappa, kappa2, kd;   // kd = kappa - kappa2
-    T pad;
+    T omk;                 // 1 - kappa
 };
 
 // Device control block of one slice.
@@ -115,9 +115,12 @@ struct IterLaunch {
     PhaseGrid bp, rows, cols, proj, fin;   // rows is shared by the forward and inverse row DFTs
     int max_N;               // largest image side (dynamic LDS of the DFT kernels)
     int projector;           // 1: LDS-staged row windows, 2: direct coalesced loads, 3: ray pairs
-    int backprojector;       // 1: LDS-staged detector windows (16 x 16 tiles), 2: direct (8 x 8 tiles),
-                             // 3: 2 x 2 pixels per lane with 16-byte loads (16 x 16 tiles)
+    int backprojector;       // 1: LDS-staged detector windows, 2 x 2 pixels per lane (16 x 16 tiles),
+                             // 2: direct (8 x 8 tiles), 3: 2 x 2 pixels per lane with 16-byte loads
+                             // (16 x 16 tiles)
 };
+
+constexpr int kNumBackprojectors = 3;
 
 constexpr int kNumPhases = 6;   // backprojection, row DFT, column DFT, inverse row DFT + x-update,
                                 // projection + data prox + TV update, objective

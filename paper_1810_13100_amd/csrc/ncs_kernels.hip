@@ -1,14 +1,19 @@
 // HIP kernels of the NCS iteration for gfx950 (CDNA4), templated on the
 // iterate precision T (float or double).  One NCS iteration (Section 4.1 /
-// Section 4.2 of the paper) is six launches:
+// Section 4.2 of the paper) is the six phases below; in a sequence of
+// iterations the objective of iteration i is reduced by the first workgroup of
+// iteration i + 1's backprojection, so only the last iteration launches
+// k_finalize_iter and an iteration is five launches.
 //
-//   k_backproject     w = alpha E^T u + beta D^T v          (pixel-driven gather)
+//   k_backproject     w = alpha E^T u + beta D^T v          (pixel-driven gather;
+//                     LDS-staged detector windows, direct loads or 16-byte
+//                     windows per 2 x 2 pixel block)
 //   k_fft_rows_fwd    row DFTs of w, two real rows per complex transform
 //   k_fft_cols        column DFT, multiply by h/(alpha N^2), inverse column DFT
 //   k_fft_rows_inv    inverse row DFTs; x+ = x - Delta, xbar = 2x+ - x (padded
 //                     row-major copy and padded transposed copy)
-//   k_project         q = E xbar (ray-driven; direct coalesced loads or
-//                     LDS-staged tiles); u+ = prox(u + ...), p+ = (q + p)/2 =
+//   k_project         q = E xbar (ray-driven; direct coalesced loads,
+//                     LDS-staged row windows or ray pairs); u+ = prox(u + ...), p+ = (q + p)/2 =
 //                     E x+, data term of x+.  Extra workgroups of the same
 //                     launch do v+ = Pi(v + beta D xbar) and the TV term of
 //                     x+ (double partial sums)
@@ -46,8 +51,9 @@ constexpr int kRays = 64;      // rays per projector workgroup (one per lane)
 constexpr int kWaves = 4;      // waves per projector / TV workgroup
 constexpr int kRowWin = 100;   // LDS-staged projector: padded-row elements staged per step
 constexpr int kStageRows = 16; // LDS-staged projector: steps staged at a time by one wave
-constexpr int kBpWaves = 8;    // backprojector: waves per 16 x 16 pixel tile
+constexpr int kBpWaves = 8;    // direct backprojector: waves per 8 x 8 pixel tile
 constexpr int kFftThreads = 256;
+constexpr int kFinGroup = 8;  // objective partials loaded per thread before they are added
 
 template <class T>
 __device__ inline const DevCtx<T>& slot_ctx(const DevCtx<T>* __restrict__ ctxs, const Slot* __restrict__ map,
@@ -179,8 +185,23 @@ template <class T>
 __device__ inline void finalize_slice(const DevCtx<T>& c, double* sh) {
     double sd = 0.0, st = 0.0;
     if (threadIdx.x < 256) {
-        for (int i = threadIdx.x; i < c.nb_proj; i += 256) sd += c.part_data[i];
-        for (int i = threadIdx.x; i < c.nb_tv; i += 256) st += c.part_tv[i];
+        // each thread adds its partials in increasing index order; the loads of
+        // a group of kFinGroup are issued before the first add so that the
+        // group costs one memory round trip
+        for (int i0 = threadIdx.x; i0 < c.nb_proj; i0 += 256 * kFinGroup) {
+            double v[kFinGroup];
+#pragma unroll
+            for (int u = 0; u < kFinGroup; ++u) v[u] = i0 + 256 * u < c.nb_proj ? c.part_data[i0 + 256 * u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kFinGroup; ++u) sd += v[u];
+        }
+        for (int i0 = threadIdx.x; i0 < c.nb_tv; i0 += 256 * kFinGroup) {
+            double v[kFinGroup];
+#pragma unroll
+            for (int u = 0; u < kFinGroup; ++u) v[u] = i0 + 256 * u < c.nb_tv ? c.part_tv[i0 + 256 * u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kFinGroup; ++u) st += v[u];
+        }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     sd = wave_sum(sd);
@@ -212,9 +233,10 @@ __device__ inline void finalize_slice(const DevCtx<T>& c, double* sh) {
 
 // ---------------------------------------------------------------------------
 // Backprojection (pixel-driven gather, matched to the ray-driven projector).
-// Two kernels compute the same taps: the direct one reads every tap pair from
-// the sinogram in global memory; the LDS one stages detector windows.  The
-// setup timing keeps the faster for a geometry (and, for a batch, for the
+// Three kernels compute the same taps: the direct one reads every tap pair
+// from the sinogram in global memory, the quad one reads one 16-byte window
+// per 2 x 2 pixel block, and the LDS one stages detector windows.  The
+// setup timing keeps the fastest for a geometry (and, for a batch, for the
 // whole batch).
 //
 // Direct: an 8 x 8 pixel tile per workgroup; each of the 8 waves takes every
@@ -395,24 +417,51 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_quad(const De
     c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
 }
 
-// LDS: a 16 x 16 pixel tile per workgroup.  For
-// each angle the tile's pixels touch at most kBpWin consecutive detector bins
-// (the tile spans 15 (|cos| + |sin|) <= 21.3 bins, plus the second tap and a
-// rounding margin); those windows are staged in LDS for a chunk of angles
-// with coalesced loads, so the per-tap reads go to LDS rather than through
-// the vector-memory address path.  Waves 0-3 take the first half of each
-// chunk's angles, waves 4-7 the second half, 64 pixels (4 rows) per wave;
-// the two halves are added in a fixed order.
+// Hat weights clamped to [0, 1] (the clamp folds into the multiply-add).
+template <class T>
+__device__ inline T clamp01(T v);
+template <>
+__device__ inline float clamp01<float>(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
+template <>
+__device__ inline double clamp01<double>(double v) { return fmin(fmax(v, 0.0), 1.0); }
+
+// LDS: a 16 x 16 pixel tile per workgroup of 16 waves, a 2 x 2 pixel block
+// per lane and every 16th angle per wave (the quad kernel's layout), with the
+// taps read from LDS.  For each angle the tile's detector coordinates span
+// 15 (|q1| + |q2|) <= 21.3 bins, so both taps of every pixel lie in the
+// kBpWin bins starting one below the floor of the tile's smallest coordinate
+// (a bin of rounding margin on each side).  Those windows are staged for a
+// chunk of angles with zeros for bins outside the detector, which gives the
+// direct kernel's result for pixels whose coordinate is clamped there, so the
+// compute loop needs no clamp.  Per pixel and angle it is the coordinate, the
+// floor, the fraction, one LDS address, one two-element LDS read and the hat
+// weights kappa clamp01(1 - kappa f) and kappa clamp01(1 - kappa + kappa f):
+// the direct kernel's max(0, kappa - kappa^2 f) and
+// max(0, kappa - kappa^2 + kappa^2 f) up to rounding, with kappa applied once
+// per pixel and angle (about 12 vector instructions against the quad
+// kernel's 21).
 // ---------------------------------------------------------------------------
 constexpr int kBpWin = 26;
 template <class T>
 constexpr int bp_chunk() { return sizeof(T) == 4 ? 384 : 192; }
 
+// woffb: LDS byte offset, relative to win, of detector bin 0 in this angle's window
+template <class T>
+__device__ inline void bp_window_tap(T& acc, T tc, const T* __restrict__ win, int woffb, const AngleT<T>& A) {
+    const T fl = floor(tc);
+    const T f = tc - fl;
+    const T* wp = reinterpret_cast<const T*>(reinterpret_cast<const char*>(win) + (int)fl * (int)sizeof(T) + woffb);
+    const T y0 = wp[0], y1 = wp[1];
+    const T w0 = clamp01(fma(-A.kappa, f, T(1)));
+    const T w1 = clamp01(fma(A.kappa, f, A.omk));
+    acc = fma(A.kappa, fma(w1, y1, w0 * y0), acc);
+}
+
 template <class T, bool ITER>
-__global__ __launch_bounds__(kBpWaves * 64) void k_backproject_lds(const DevCtx<T>* __restrict__ ctxs,
-                                                                   const Slot* __restrict__ map,
-                                                                   const T* __restrict__ ysrc_plain,
-                                                                   T* __restrict__ out, int fin_prev) {
+__global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const DevCtx<T>* __restrict__ ctxs,
+                                                                       const Slot* __restrict__ map,
+                                                                       const T* __restrict__ ysrc_plain,
+                                                                       T* __restrict__ out, int fin_prev) {
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
     if (ITER) {
@@ -424,77 +473,77 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_lds(const DevCtx<
         if (fin_prev && local == 0) finalize_slice(c, fin_sh);   // objective of the previous iteration
     }
     constexpr int CH = bp_chunk<T>();
+    constexpr int NT = kBpQuadWaves * 64;
     __shared__ T win[CH * kBpWin];
     __shared__ int wbase[CH];
-    __shared__ T red[4 * 64];
+    __shared__ T red[kBpQuadWaves * kBpTile * kBpTile];
     const T* ysrc = ITER ? c.u : ysrc_plain;
     const int N = c.N;
     const int tiles_x = N / kBpTile;
     const int tx = local % tiles_x, ty = local / tiles_x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = wave & 3, half = wave >> 2;
-    const int col = tx * kBpTile + (lane & 15);
-    const int row = ty * kBpTile + g * 4 + (lane >> 4);
-    const T fc = (T)col, fr = (T)row;
-    const T tmax = (T)c.NS;
+    const int lc = 2 * (lane & 7), lr = 2 * (lane >> 3);          // block corner within the tile
+    const T fc0 = (T)(tx * kBpTile + lc), fc1 = fc0 + T(1);
+    const T fr0 = (T)(ty * kBpTile + lr), fr1 = fr0 + T(1);
     const int PU = c.PU, NA = c.NA, NS = c.NS;
     const T c0 = (T)(tx * kBpTile), r0 = (T)(ty * kBpTile), span = (T)(kBpTile - 1);
     const AngleT<T>* ang = c.ang;
-    T acc = T(0);
+    T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
     for (int a0 = 0; a0 < NA; a0 += CH) {
         const int nch = min(CH, NA - a0);
         __syncthreads();   // the previous chunk has been consumed
-        // window of angle a: bins wbase .. wbase + kBpWin - 1, starting one below
-        // the smallest clamped detector coordinate of the tile
-        for (int k = threadIdx.x; k < nch; k += kBpWaves * 64) {
+        // window of angle a: bins wbase .. wbase + kBpWin - 1 from one below the
+        // floor of the smallest (unclamped) coordinate of the tile
+        for (int k = threadIdx.x; k < nch; k += NT) {
             const AngleT<T> A = ang[a0 + k];
             const T tmin = fma(c0, A.q1, fma(r0, A.q2, A.q0)) + span * (fmin(A.q1, T(0)) + fmin(A.q2, T(0)));
-            wbase[k] = (int)floor(med3(tmin, T(-1), tmax)) - 1;
+            wbase[k] = (int)floor(tmin) - 1;
         }
         __syncthreads();
         {
             // every load of this thread is issued before any is stored, so the
-            // staging costs one memory latency
-            constexpr int R = (CH * kBpWin + kBpWaves * 64 - 1) / (kBpWaves * 64);
+            // staging costs one memory latency; bins off the detector are zero
+            constexpr int R = (CH * kBpWin + NT - 1) / NT;
             T vals[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int e = threadIdx.x + r * kBpWaves * 64;
+                const int e = threadIdx.x + r * NT;
                 const int k = e / kBpWin, j = e - k * kBpWin;
-                const int d = e < nch * kBpWin ? wbase[k] + j : -2;   // bins -1, NS, NS + 1: zero pads
-                vals[r] = (d >= -1 && d <= NS + 1) ? ysrc[(size_t)(a0 + k) * PU + 1 + d] : T(0);
+                const int d = e < nch * kBpWin ? wbase[k] + j : -1;
+                vals[r] = (d >= 0 && d < NS) ? ysrc[(size_t)(a0 + k) * PU + 1 + d] : T(0);
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int e = threadIdx.x + r * kBpWaves * 64;
+                const int e = threadIdx.x + r * NT;
                 if (e < nch * kBpWin) win[e] = vals[r];
             }
         }
         __syncthreads();
-        const int kmid = (nch + 1) >> 1;
-        const int kbeg = half ? kmid : 0, kend = half ? nch : kmid;
-#pragma unroll 4
-        for (int k = kbeg; k < kend; ++k) {
+        for (int k = wave; k < nch; k += kBpQuadWaves) {
             const AngleT<T> A = ang[a0 + k];
-            // outside the detector both taps land on the zero pads
-            const T t = med3(fma(fc, A.q1, fma(fr, A.q2, A.q0)), T(-1), tmax);
-            const T fl = floor(t);
-            const T f = t - fl;
-            int j = (int)fl - wbase[k];
-            j = min(max(j, 0), kBpWin - 2);
-            const T* wp = win + k * kBpWin + j;
-            const T y0 = wp[0], y1 = wp[1];
-            const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
-            const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
-            acc = fma(w0, y0, acc);
-            acc = fma(w1, y1, acc);
+            // angle k's window starts at bin wbase[k] (a wave-uniform offset, so
+            // that each pixel's address is one shift-and-add)
+            const int woffb = __builtin_amdgcn_readfirstlane((k * kBpWin - wbase[k]) * (int)sizeof(T));
+            const T q0r0 = fma(fr0, A.q2, A.q0), q0r1 = fma(fr1, A.q2, A.q0);
+            bp_window_tap(a00, fma(fc0, A.q1, q0r0), win, woffb, A);
+            bp_window_tap(a01, fma(fc1, A.q1, q0r0), win, woffb, A);
+            bp_window_tap(a10, fma(fc0, A.q1, q0r1), win, woffb, A);
+            bp_window_tap(a11, fma(fc1, A.q1, q0r1), win, woffb, A);
         }
     }
-    if (half) red[g * 64 + lane] = acc;
+    T* rw = red + wave * (kBpTile * kBpTile);
+    rw[lr * kBpTile + lc] = a00;
+    rw[lr * kBpTile + lc + 1] = a01;
+    rw[(lr + 1) * kBpTile + lc] = a10;
+    rw[(lr + 1) * kBpTile + lc + 1] = a11;
     __syncthreads();
-    if (half) return;
-    const T bp = acc + red[g * 64 + lane];
+    if (threadIdx.x >= kBpTile * kBpTile) return;
+    const int p = threadIdx.x;
+    T bp = red[p];
+#pragma unroll
+    for (int w = 1; w < kBpQuadWaves; ++w) bp += red[w * (kBpTile * kBpTile) + p];
+    const int col = tx * kBpTile + (p & (kBpTile - 1)), row = ty * kBpTile + p / kBpTile;
     const size_t pix = (size_t)row * N + col;
     if (!ITER) {
         out[pix] = bp;
@@ -1367,7 +1416,7 @@ hipError_t launch_bp_iter(const IterLaunch<T>& L, int fin_prev, hipStream_t st) 
         hipLaunchKernelGGL((k_backproject_quad<T, true>), dim3(L.bp.blocks), dim3(kBpQuadWaves * 64), 0, st, L.ctxs,
                            L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
     else if (L.backprojector == 1)
-        hipLaunchKernelGGL((k_backproject_lds<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
+        hipLaunchKernelGGL((k_backproject_lds<T, true>), dim3(L.bp.blocks), dim3(kBpQuadWaves * 64), 0, st, L.ctxs,
                            L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
     else
         hipLaunchKernelGGL((k_backproject_direct<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
@@ -1469,7 +1518,7 @@ hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, in
         hipLaunchKernelGGL((k_backproject_quad<T, false>), dim3(bp_blocks(hc.N, 3)), dim3(kBpQuadWaves * 64), 0, st,
                            dc, (const Slot*)nullptr, y_padded, out, 0);
     else if (variant == 1)
-        hipLaunchKernelGGL((k_backproject_lds<T, false>), dim3(bp_blocks(hc.N, 1)), dim3(kBpWaves * 64), 0, st, dc,
+        hipLaunchKernelGGL((k_backproject_lds<T, false>), dim3(bp_blocks(hc.N, 1)), dim3(kBpQuadWaves * 64), 0, st, dc,
                            (const Slot*)nullptr, y_padded, out, 0);
     else
         hipLaunchKernelGGL((k_backproject_direct<T, false>), dim3(bp_blocks(hc.N, 2)), dim3(kBpWaves * 64), 0, st,

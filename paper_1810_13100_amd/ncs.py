@@ -173,6 +173,7 @@ class Params:
     graph_chunk: int = 0      # 0: 25 iterations per HIP graph, < 0: no graphs
     dual_ramp: float = 0.0    # TV-dual ramp width of the warm start (0: sign)
     backprojector: int = 0    # 0: autotune at setup, 1: LDS-staged windows, 2: direct, 3: 2x2 per lane
+                              # with 16-byte windows
     method: int = 0           # METHOD_NCS, METHOD_PDHG (M = gamma I) or METHOD_ADMM_CG
     cg_iters: int = 0         # ADMM-CG: CG steps per linear solve (0: 10)
     cg_precondition: int = 1  # ADMM-CG: precondition CG with alpha M^+

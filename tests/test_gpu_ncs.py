@@ -60,8 +60,8 @@ def check_trajectory(prob, par, iters, prec, **kw):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("projector,backprojector,graph_chunk", [(1, 1, -1), (2, 2, -1), (3, 3, -1), (0, 0, 0),
-                                                                 (2, 1, 7), (3, 2, 7)])
+@pytest.mark.parametrize("projector,backprojector,graph_chunk", [(1, 1, -1), (2, 2, -1), (3, 3, -1), (2, 1, -1),
+                                                                 (0, 0, 0), (2, 1, 7), (3, 2, 7), (3, 1, 7)])
 def test_ct_64_200_iterations(prec, projector, backprojector, graph_chunk):
     # both projector and backprojector kernels, direct launches and replayed
     # HIP graphs (a chunk of 7 leaves a remainder of direct launches)
