@@ -55,28 +55,34 @@ def objective(prob: Problem, x: np.ndarray) -> float:
     return data_term(prob, prob.E @ x) + prob.lam * tv(prob, x)
 
 
-def stacked_A(prob: Problem, par: Params):
+def stacked_A(prob: Problem, par: Params, positivity: bool = False):
     """Callables for A = [E; (beta/alpha) D] and A^T, and the offset b~ = [b; 0] (CT)
-    or [-r; 0] (PET, where the data block is l(. + r) with zero offset)."""
+    or [-r; 0] (PET, where the data block is l(. + r) with zero offset).  With
+    ``positivity`` A gains the rows I of the constraint x >= 0 (remark in
+    Section 4.2) and b~ a zero block."""
     ratio = par.beta / par.alpha
-    m = prob.m
+    m, n = prob.m, prob.n
 
     def A(x):
-        return np.concatenate([prob.E @ x, ratio * (prob.D @ x)])
+        parts = [prob.E @ x, ratio * (prob.D @ x)]
+        if positivity:
+            parts.append(x)
+        return np.concatenate(parts)
 
     def At(y):
-        return prob.Et @ y[:m] + ratio * (prob.Dt @ y[m:])
+        z = prob.Et @ y[:m] + ratio * (prob.Dt @ y[m:m + 2 * n])
+        return z + y[m + 2 * n:] if positivity else z
 
-    if prob.kind == "ct":
-        btil = np.concatenate([prob.b, np.zeros(2 * prob.n)])
-    else:
-        btil = np.concatenate([-prob.bg, np.zeros(2 * prob.n)])
+    head = prob.b if prob.kind == "ct" else -prob.bg
+    btil = np.concatenate([head, np.zeros((3 if positivity else 2) * n)])
     return A, At, btil
 
 
-def prox_conj(prob: Problem, par: Params):
+def prox_conj(prob: Problem, par: Params, positivity: bool = False):
     """prox_{alpha g*} for the stacked g, derived by the Moreau identity
-    (Section 2, eq. Moreau) from the primal proximal maps of g."""
+    (Section 2, eq. Moreau) from the primal proximal maps of g (with
+    ``positivity``, the indicator of x >= 0 on the third block, whose primal
+    prox is max(., 0))."""
     a = par.alpha
     m, n = prob.m, prob.n
     s_tv = prob.lam * par.alpha / par.beta   # weight of |z| in g after scaling D by beta/alpha
@@ -95,8 +101,10 @@ def prox_conj(prob: Problem, par: Params):
         return np.concatenate([zh * shrink, zv * shrink])
 
     def pc(w):
-        return np.concatenate([prox.moreau_conj(data_prox, w[:m], a),
-                               prox.moreau_conj(tv_prox, w[m:], a)])
+        parts = [prox.moreau_conj(data_prox, w[:m], a), prox.moreau_conj(tv_prox, w[m:m + 2 * n], a)]
+        if positivity:
+            parts.append(prox.moreau_conj(lambda z, t: np.maximum(z, 0.0), w[m + 2 * n:], a))
+        return np.concatenate(parts)
 
     return pc
 

@@ -81,16 +81,22 @@ def resolved_mu_dc(prob: Problem, par: Params) -> float:
     return par.gamma + par.alpha * float(e1 @ e1) / prob.n
 
 
-def multiplier(prob: Problem, par: Params) -> np.ndarray:
-    """h (N x N) for this problem and parameters."""
-    return operators.ncs_multiplier(prob.n_side, par.alpha, par.beta, par.gamma,
-                                    resolved_c_r(prob, par), resolved_mu_dc(prob, par))
+def multiplier(prob: Problem, par: Params, positivity: bool = False) -> np.ndarray:
+    """h (N x N) for this problem and parameters (see ``eigenvalues``)."""
+    return operators.pseudo_inverse_diag(eigenvalues(prob, par, positivity))
 
 
-def eigenvalues(prob: Problem, par: Params) -> np.ndarray:
-    """mu = eig(M) (N x N)."""
-    return operators.ncs_eigenvalues(prob.n_side, par.alpha, par.beta, par.gamma,
-                                     resolved_c_r(prob, par), resolved_mu_dc(prob, par))
+def eigenvalues(prob: Problem, par: Params, positivity: bool = False) -> np.ndarray:
+    """mu = eig(M) (N x N).
+
+    With the positivity block of the remark in Section 4.2, A gains the rows
+    I (the block (delta/alpha) I with delta = alpha, scaled like the data
+    block), so alpha A^T A gains alpha I and so does M: every eigenvalue,
+    mu_DC included, is raised by alpha.
+    """
+    mu = operators.ncs_eigenvalues(prob.n_side, par.alpha, par.beta, par.gamma,
+                                   resolved_c_r(prob, par), resolved_mu_dc(prob, par))
+    return mu + par.alpha if positivity else mu
 
 
 def ct_problem(n_side: int, n_angles: int, n_bins: int, seed: int, lam: float,

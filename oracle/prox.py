@@ -15,6 +15,9 @@ Maps on the dual side (what the iterations call):
   which uses anisotropic TV; required by the PET workload).
 * ``poisson_s``: S(u; c) = 1 + (u - 1 - sqrt((u-1)^2 + 4c))/2 of Section 4.2,
   which is prox_{a l*}(u) for l(y) = y - b log y with c = a b.
+* ``nonpositive``: g = indicator of the nonnegative orthant (the positivity
+  block of the remark in Section 4.2); its conjugate is the indicator of the
+  nonpositive orthant, so prox_{a g*} = min(., 0) for every a > 0.
 
 Maps on the primal side (used only by the classic-ADMM cross-check of the
 appendix): ``prox_quadratic``, ``soft_threshold``, ``prox_poisson``.
@@ -45,6 +48,10 @@ def l2_ball(wh: np.ndarray, wv: np.ndarray, s: float) -> tuple[np.ndarray, np.nd
 def poisson_s(u: np.ndarray, c: np.ndarray) -> np.ndarray:
     """S(u; c) exactly as printed in Section 4.2."""
     return 1.0 + (u - 1.0 - np.sqrt((u - 1.0) ** 2 + 4.0 * c)) / 2.0
+
+
+def nonpositive(w: np.ndarray) -> np.ndarray:
+    return np.minimum(w, 0.0)
 
 
 def prox_quadratic(z: np.ndarray, t: float) -> np.ndarray:

@@ -9,7 +9,16 @@
 
   (the isotropic variant replaces Pi by the per-pixel l2-ball projection).
   One iteration is one x-update followed by one (u, v)-update; the objective
-  recorded at iteration k is f(x^k).
+  recorded at iteration k is f(x^k).  With ``positivity`` the constraint
+  x >= 0 of the remark in Section 4.2 enters as a third block of A (rows I,
+  the indicator of the nonnegative orthant in g) with its own dual t:
+
+      x+ = x - (1/alpha) F^-1 diag(h') F (alpha E^T u + beta D^T v + alpha t)
+      t+ = min(t + alpha (2x+ - x), 0)
+
+  where h' inverts the eigenvalues of M raised by alpha (``problems.eigenvalues``).
+  The reported objective leaves out the indicator of x >= 0, which the
+  iterates satisfy only in the limit.
 * ``ncs_generic``: eq. (NCS) for any M^+ given as a callable, on the stacked
   dual y = [u; v], A = [E; (beta/alpha) D] and prox_{alpha g*} obtained from the
   Moreau identity.  With M^+ = (1/gamma) I it is eq. (PDHG) (``pdhg``); with
@@ -41,22 +50,27 @@ class Trajectory:
     v: np.ndarray
     obj: np.ndarray          # obj[k] = f(x^{k+1}), k = 0..iters-1
     x_prev: np.ndarray       # x^{K-1}
+    t: np.ndarray | None = None   # positivity dual (positivity runs only)
 
 
 def ncs(prob: Problem, par: Params, iters: int, x0=None, u0=None, v0=None,
-        h: np.ndarray | None = None, record: bool = True) -> Trajectory:
+        h: np.ndarray | None = None, record: bool = True, positivity: bool = False,
+        t0=None) -> Trajectory:
     n, m, N = prob.n, prob.m, prob.n_side
     a, be = par.alpha, par.beta
     s = prob.lam * a / be
     if h is None:
-        h = multiplier(prob, par)
+        h = multiplier(prob, par, positivity)
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     u = np.zeros(m) if u0 is None else np.array(u0, dtype=np.float64)
     v = np.zeros(2 * n) if v0 is None else np.array(v0, dtype=np.float64)
+    t = (np.zeros(n) if t0 is None else np.array(t0, dtype=np.float64)) if positivity else None
     obj = np.full(iters, np.nan)
     x_prev = x
     for k in range(iters):
         w = a * (prob.Et @ u) + be * (prob.Dt @ v)
+        if positivity:
+            w = w + a * t
         x_new = x - operators.apply_circulant(h, w.reshape(N, N)).ravel() / a
         xbar = 2.0 * x_new - x
         q = prob.E @ xbar
@@ -70,19 +84,21 @@ def ncs(prob: Problem, par: Params, iters: int, x0=None, u0=None, v0=None,
         else:
             vh, vv = prox.l2_ball(g[:n], g[n:], s)
             v = np.concatenate([vh, vv])
+        if positivity:
+            t = prox.nonpositive(t + a * xbar)
         x_prev, x = x, x_new
         if record:
             obj[k] = objective(prob, x)
-    return Trajectory(x, u, v, obj, x_prev)
+    return Trajectory(x, u, v, obj, x_prev, t)
 
 
 def ncs_generic(prob: Problem, par: Params, apply_minv, iters: int, x0=None, y0=None,
-                record: bool = True):
+                record: bool = True, positivity: bool = False):
     """eq. (NCS): x+ = x - M^+ A^T y; y+ = prox_{alpha g*}(y + alpha(A(2x+ - x) - b~))."""
-    A, At, btil = stacked_A(prob, par)
-    pc = prox_conj(prob, par)
+    A, At, btil = stacked_A(prob, par, positivity)
+    pc = prox_conj(prob, par, positivity)
     x = np.zeros(prob.n) if x0 is None else np.array(x0, dtype=np.float64)
-    y = np.zeros(prob.m + 2 * prob.n) if y0 is None else np.array(y0, dtype=np.float64)
+    y = np.zeros(btil.size) if y0 is None else np.array(y0, dtype=np.float64)
     obj = np.full(iters, np.nan)
     for k in range(iters):
         x_new = x - apply_minv(At(y))

@@ -5,6 +5,7 @@ residuals, and the monotone / summable lemmas of Section 3.2 under A3.
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 from oracle import objective, operators, problems, solvers
 
@@ -238,3 +239,123 @@ def test_preconditioned_cg_needs_fewer_steps():
     e_pc = np.linalg.norm(solvers.admm_cg(prob, par, 30, 5, True)[0] - x_ref)
     e_cg = np.linalg.norm(solvers.admm_cg(prob, par, 30, 5, False)[0] - x_ref)
     assert e_pc < e_cg
+
+
+# ---------------------------------------------------------------------------
+# Positivity constraint x >= 0 (the remark in Section 4.2): a third block of A
+# (rows I) with the indicator of the nonnegative orthant in g.
+
+
+def _chambolle_pock_nonneg(prob, iters):
+    """An independent solver of the constrained problem: the primal-dual method
+    of Chambolle and Pock with the constraint on the primal side,
+    x+ = max(x - tau K^T p+, 0), K = [E; D], and the conjugate prox of the data
+    and TV terms on p; no circulant and no third dual block."""
+    K = sp.vstack([prob.E, prob.D]).tocsr()
+    Kt = K.T.tocsr()
+    tau = sigma = 0.99 / np.sqrt(np.linalg.eigvalsh((Kt @ K).toarray())[-1])
+    m, n = prob.m, prob.n
+    x = np.zeros(n)
+    xb = x.copy()
+    p = np.zeros(m + 2 * n)
+    for _ in range(iters):
+        w = p + sigma * (K @ xb)
+        if prob.kind == "ct":   # conjugate of 1/2 |y - b|^2
+            p1 = (w[:m] - sigma * prob.b) / (1.0 + sigma)
+        else:                   # conjugate of sum l(y + r; b): S(w + sigma r; sigma b)
+            z = w[:m] + sigma * prob.bg - 1.0
+            p1 = 1.0 + (z - np.sqrt(z * z + 4.0 * sigma * prob.b)) / 2.0
+        if prob.tv == "aniso":
+            p2 = np.clip(w[m:], -prob.lam, prob.lam)
+        else:
+            h, v = w[m:m + n], w[m + n:]
+            sc = np.maximum(1.0, np.sqrt(h * h + v * v) / prob.lam)
+            p2 = np.concatenate([h / sc, v / sc])
+        p = np.concatenate([p1, p2])
+        xn = np.maximum(x - tau * (Kt @ p), 0.0)
+        xb = 2.0 * xn - x
+        x = xn
+    return x
+
+
+@pytest.mark.parametrize("kind", ["ct", "pet"])
+def test_positivity_limit_is_the_constrained_minimiser(kind):
+    prob = _ct() if kind == "ct" else _pet()
+    par = _a3_params(prob)
+    free = solvers.ncs(prob, par, 3000, record=False).x
+    pos = solvers.ncs(prob, par, 20000, record=False, positivity=True)
+    ref = _chambolle_pock_nonneg(prob, 20000)
+    assert free.min() < -1e-2 * free.max()                # the constraint is active
+    assert pos.x.min() >= -1e-6 * pos.x.max()
+    assert np.linalg.norm(pos.x - ref) <= 1e-6 * np.linalg.norm(ref)
+    assert np.all(pos.t <= 0.0)
+    # complementarity of the limit: t < 0 only where x = 0
+    assert np.max(np.abs(pos.t) * np.maximum(pos.x, 0.0)) <= 1e-6 * np.abs(pos.t).max() * pos.x.max()
+    assert objective.objective(prob, pos.x) >= objective.objective(prob, free) - 1e-9
+
+
+@pytest.mark.parametrize("kind", ["ct_aniso", "pet_iso"])
+def test_positivity_form_is_general_ncs(kind):
+    # the third dual block and its coupling: the specialised iteration equals
+    # eq. (NCS) on A' = [E; (beta/alpha) D; I] with prox_{alpha g*} from the
+    # Moreau identity and M'^+ = F^-1 diag(h') F
+    prob = _ct() if kind == "ct_aniso" else _pet()
+    par = problems.Params(0.03, 0.09, 20.0)
+    h = problems.multiplier(prob, par, positivity=True)
+    tr = solvers.ncs(prob, par, 40, positivity=True)
+    x, y, _ = solvers.ncs_generic(prob, par, lambda z: operators.apply_circulant(h, z.reshape(N, N)).ravel(), 40,
+                                  positivity=True)
+    m, n = prob.m, prob.n
+    assert np.abs(tr.t).max() > 0
+    np.testing.assert_allclose(tr.x, x, rtol=0, atol=1e-10 * np.abs(x).max())
+    np.testing.assert_allclose(tr.u, y[:m], rtol=0, atol=1e-10 * np.abs(y[:m]).max())
+    np.testing.assert_allclose(tr.t, y[m + 2 * n:], rtol=0, atol=1e-10 * np.abs(y[m + 2 * n:]).max())
+
+
+def test_positivity_multiplier_meets_the_convergence_condition():
+    # NCS converges for M >= alpha A^T A (Section 3): with gamma at the A3
+    # threshold of the unconstrained system, M' = M + alpha I meets the
+    # condition for A' = [E; (beta/alpha) D; I] and M alone does not.
+    prob = _ct("aniso")
+    par0 = problems.Params(0.05, 0.1, 0.0)
+    par = problems.Params(0.05, 0.1, _gamma_a3(prob, par0) * (1 + 1e-9) + 1e-12)
+    ext = par.alpha * (solvers.normal_matrix(prob, par) + np.eye(prob.n))
+    gap = np.linalg.eigvalsh(_dense_circulant(problems.eigenvalues(prob, par, positivity=True)) - ext)[0]
+    gap0 = np.linalg.eigvalsh(_dense_circulant(problems.eigenvalues(prob, par)) - ext)[0]
+    scale = np.abs(ext).max()
+    assert gap >= -1e-9 * scale
+    assert gap0 < -0.5 * par.alpha
+
+
+def _d_sq_extended(prob, par, mu, dx, dy):
+    """D-seminorm of Section 3.2 for A' = [E; (beta/alpha) D; I] and M with eigenvalues mu."""
+    a = par.alpha
+    adx = np.concatenate([prob.E @ dx, (par.beta / a) * (prob.D @ dx), dx])
+    r = dy - a * adx
+    return float(r @ r) + a * objective.quad_M(mu, dx) - a * a * float(adx @ adx)
+
+
+def test_positivity_iteration_is_monotone_in_the_extended_seminorm():
+    # Lemma (monotone) and Lemma (summable) of Section 3.2 for NCS on the
+    # extended system; they need M' >= alpha A'^T A', which holds because M' = M + alpha I.
+    prob = _ct("aniso")
+    par = _a3_params(prob)
+    mu = problems.eigenvalues(prob, par, positivity=True)
+    K = 150
+    x, u, v, t = np.zeros(prob.n), np.zeros(prob.m), np.zeros(2 * prob.n), np.zeros(prob.n)
+    xs, ys = [x], [np.concatenate([u, v, t])]
+    for _ in range(K):
+        tr = solvers.ncs(prob, par, 1, x0=x, u0=u, v0=v, t0=t, record=False, positivity=True)
+        x, u, v, t = tr.x, tr.u, tr.v, tr.t
+        xs.append(x)
+        ys.append(np.concatenate([u, v, t]))
+    star = solvers.ncs(prob, par, 8000, record=False, positivity=True)
+    ystar = np.concatenate([star.u, star.v, star.t])
+    d_step = [_d_sq_extended(prob, par, mu, xs[k + 1] - xs[k], ys[k + 1] - ys[k]) for k in range(K)]
+    d_star = [_d_sq_extended(prob, par, mu, xs[k] - star.x, ys[k] - ystar) for k in range(K)]
+    assert min(d_step) >= -1e-9 * max(d_step)
+    for k in range(K - 1):
+        assert d_step[k + 1] <= d_step[k] * (1 + 1e-9) + 1e-12
+        assert d_star[k + 1] <= d_star[k] * (1 + 1e-9) + 1e-12
+    for k in range(K):
+        assert d_step[k] <= d_star[0] / (k + 1) * (1 + 1e-6) + 1e-12
