@@ -117,6 +117,13 @@ typedef struct {
                               gamma > alpha lambda_max(A^T A) to converge) or ADMM-CG */
     int32_t cg_iters;      /* ADMM-CG: CG steps per linear solve; 0 selects 10 */
     int32_t cg_precondition; /* ADMM-CG: 1 = precondition CG with alpha M^+, 0 = plain CG */
+    int32_t positivity;    /* 1: constrain x >= 0 (remark in Section 4.2): A gains the rows I with
+                              the indicator of the nonnegative orthant in g, a dual t (N*N,
+                              zero at ncs_set_init) updated as t = min(t + alpha xbar, 0), the
+                              backprojection gains alpha t and, for NCS, every eigenvalue of M
+                              is raised by alpha (for PDHG, gamma must cover the extra rows).
+                              The reported objective leaves out the indicator.  Not with
+                              ADMM-CG. */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;
@@ -183,7 +190,11 @@ ncs_status ncs_get_u(ncs_handle* h, void* u_out_dev);
  * then the vertical one, each row-major) to v_out_dev. */
 ncs_status ncs_get_v(ncs_handle* h, void* v_out_dev);
 
-/* Checkpoint: the full state (x, u, v, E x, iteration count) as an opaque
+/* Copy the positivity dual t (N*N values, row-major; params.positivity = 1
+ * only, NCS_ERR_INVALID_ARG otherwise) to t_out_dev. */
+ncs_status ncs_get_t(ncs_handle* h, void* t_out_dev);
+
+/* Checkpoint: the full state (x, u, v, E x, t, iteration count) as an opaque
  * host blob.  With host_buf NULL, *bytes receives the size needed.  Resuming
  * from a saved state reproduces the uninterrupted run bit for bit. */
 ncs_status ncs_get_state(ncs_handle* h, void* host_buf, size_t* bytes);

@@ -90,6 +90,7 @@ struct ncs_handle {
     void* cg_y = nullptr;       // unpadded sinogram scratch
     double* cg_part = nullptr;  // dot-product partials
     double* cg_s = nullptr;     // CG scalars
+    void* tpos = nullptr;       // positivity dual t (params.positivity only)
 
     const void* b = nullptr;    // caller-owned
     const void* bg = nullptr;   // caller-owned
@@ -173,6 +174,7 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
         c.cg_part = h->cg_part;
         c.cg_s = h->cg_s;
     }
+    c.tpos = static_cast<T*>(h->tpos);
     c.alpha = (T)h->p.alpha;
     c.beta = (T)h->p.beta;
     c.s_tv = (T)(h->p.lambda * h->p.alpha / h->p.beta);
@@ -438,6 +440,14 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("ADMM-CG needs 0 <= cg_iters <= 1000 (0 selects 10) and cg_precondition 0 or 1");
         return NCS_ERR_INVALID_ARG;
     }
+    if (p.positivity != 0 && p.positivity != 1) {
+        set_err("positivity must be 0 or 1");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.positivity && p.method == NCS_METHOD_ADMM_CG) {
+        set_err("the positivity constraint runs with NCS or PDHG, not ADMM-CG");
+        return NCS_ERR_INVALID_ARG;
+    }
     if (p.method == NCS_METHOD_PDHG && !(p.gamma > 0.0)) {
         set_err("PDHG needs gamma > 0 (the step is 1/gamma)");
         return NCS_ERR_INVALID_ARG;
@@ -543,6 +553,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
          (s = dev_alloc(h, reinterpret_cast<void**>(&h->cg_part), (size_t)cg_blocks(N) * sizeof(double))) ||
          (s = dev_alloc(h, reinterpret_cast<void**>(&h->cg_s), 4 * sizeof(double)))))
         return fail(s);
+    if (p.positivity && (s = dev_alloc(h, &h->tpos, h->n * e))) return fail(s);
     if (ext_ctl) {
         h->ctl = ext_ctl;
     } else if ((s = dev_alloc(h, reinterpret_cast<void**>(&h->ctl), sizeof(Control)))) {
@@ -599,6 +610,9 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         }
     }
     h->mu[0] = h->mu_dc;
+    // x >= 0 (remark in Section 4.2): A gains the rows I, so alpha A^T A and M gain alpha I
+    if (p.positivity)
+        for (double& m : h->mu) m += p.alpha;
     if (p.method == NCS_METHOD_PDHG) std::fill(h->mu.begin(), h->mu.end(), p.gamma);   // M = gamma I (eq. PDHG)
     std::vector<double> hh((size_t)NH * N);
     const double scale = 1.0 / (p.alpha * (double)N * (double)N);
@@ -645,6 +659,7 @@ ncs_status init_state(ncs_handle* h, const void* x0_dev, int32_t dual_from_x0) {
     NCS_HIP(hipMemsetAsync(h->u, 0, h->mp * e, h->stream));
     NCS_HIP(hipMemsetAsync(h->pj, 0, h->mp * e, h->stream));
     NCS_HIP(hipMemsetAsync(h->v, 0, 2 * h->n * e, h->stream));
+    if (h->tpos) NCS_HIP(hipMemsetAsync(h->tpos, 0, h->n * e, h->stream));
     if (x0_dev) {
         NCS_HIP(hipMemcpyAsync(h->x, x0_dev, h->n * e, hipMemcpyDeviceToDevice, h->stream));
         NCS_HIP(launch_pad_image<T>(c, dctx<T>(h), c.x, h->stream));
@@ -873,6 +888,17 @@ ncs_status ncs_get_v(ncs_handle* h, void* v_out_dev) {
     return NCS_OK;
 }
 
+ncs_status ncs_get_t(ncs_handle* h, void* t_out_dev) {
+    ncs_status s = check_handle(h);
+    if (s) return s;
+    if (!t_out_dev || !h->tpos) {
+        set_err(!t_out_dev ? "ncs_get_t: null output" : "ncs_get_t: the handle has no positivity constraint");
+        return NCS_ERR_INVALID_ARG;
+    }
+    NCS_HIP(hipMemcpyAsync(t_out_dev, h->tpos, h->n * h->esz, hipMemcpyDeviceToDevice, h->stream));
+    return NCS_OK;
+}
+
 namespace {
 struct StateHeader {
     uint64_t magic;
@@ -888,7 +914,7 @@ ncs_status ncs_get_state(ncs_handle* h, void* host_buf, size_t* bytes) {
         return NCS_ERR_INVALID_ARG;
     }
     const size_t e = h->esz;
-    const size_t need = sizeof(StateHeader) + (h->n + 2 * h->n + 2 * h->mp) * e;
+    const size_t need = sizeof(StateHeader) + (h->n + 2 * h->n + 2 * h->mp + (h->tpos ? h->n : 0)) * e;
     if (!host_buf) {
         *bytes = need;
         return NCS_OK;
@@ -910,6 +936,10 @@ ncs_status ncs_get_state(ncs_handle* h, void* host_buf, size_t* bytes) {
     NCS_HIP(hipMemcpy(o, h->u, h->mp * e, hipMemcpyDeviceToHost));
     o += h->mp * e;
     NCS_HIP(hipMemcpy(o, h->pj, h->mp * e, hipMemcpyDeviceToHost));
+    if (h->tpos) {
+        o += h->mp * e;
+        NCS_HIP(hipMemcpy(o, h->tpos, h->n * e, hipMemcpyDeviceToHost));
+    }
     *bytes = need;
     return NCS_OK;
 }
@@ -918,7 +948,7 @@ ncs_status ncs_set_state(ncs_handle* h, const void* host_buf, size_t bytes) {
     ncs_status s = check_handle(h);
     if (s) return s;
     const size_t e = h->esz;
-    const size_t need = sizeof(StateHeader) + (h->n + 2 * h->n + 2 * h->mp) * e;
+    const size_t need = sizeof(StateHeader) + (h->n + 2 * h->n + 2 * h->mp + (h->tpos ? h->n : 0)) * e;
     if (!host_buf || bytes != need) {
         set_err("ncs_set_state: blob of %zu bytes, expected %zu", bytes, need);
         return NCS_ERR_INVALID_ARG;
@@ -939,6 +969,10 @@ ncs_status ncs_set_state(ncs_handle* h, const void* host_buf, size_t bytes) {
     NCS_HIP(hipMemcpy(h->u, i, h->mp * e, hipMemcpyHostToDevice));
     i += h->mp * e;
     NCS_HIP(hipMemcpy(h->pj, i, h->mp * e, hipMemcpyHostToDevice));
+    if (h->tpos) {
+        i += h->mp * e;
+        NCS_HIP(hipMemcpy(h->tpos, i, h->n * e, hipMemcpyHostToDevice));
+    }
     NCS_HIP(launch_control(h->ctl, 2, hd.iter, std::nan(""), h->stream));
     NCS_HIP(hipStreamSynchronize(h->stream));
     h->iter_host = hd.iter;

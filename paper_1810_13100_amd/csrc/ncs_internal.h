@@ -90,6 +90,7 @@ struct DevCtx {
     NCS_G T* cg_y;
     NCS_G double* cg_part;
     NCS_G double* cg_s;
+    NCS_G T* tpos;     // N*N positivity dual t (nullptr without the constraint x >= 0)
     T alpha, beta, s_tv, inv1pa;
     T dual_ramp;                     // TV-dual ramp width of the warm start (<= 0: sign)
     double lambda;

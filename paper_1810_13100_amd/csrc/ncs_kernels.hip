@@ -308,7 +308,9 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevC
     if (col > 0) dtv -= vh[pix - 1];
     if (row < N - 1) dtv += vv[pix];
     if (row > 0) dtv -= vv[pix - N];
-    c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
+    T wv = fma(c.alpha, bp, c.beta * dtv);
+    if (c.tpos) wv = fma(c.alpha, c.tpos[pix], wv);   // the rows I of x >= 0 (remark in Section 4.2)
+    c.w[pix] = wv;
 }
 
 // Quad: a 16 x 16 pixel tile per workgroup of 16 waves; each lane takes a
@@ -414,7 +416,9 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_quad(const De
     if (col > 0) dtv -= vh[pix - 1];
     if (row < N - 1) dtv += vv[pix];
     if (row > 0) dtv -= vv[pix - N];
-    c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
+    T wv = fma(c.alpha, bp, c.beta * dtv);
+    if (c.tpos) wv = fma(c.alpha, c.tpos[pix], wv);   // the rows I of x >= 0 (remark in Section 4.2)
+    c.w[pix] = wv;
 }
 
 // Hat weights clamped to [0, 1] (the clamp folds into the multiply-add).
@@ -557,7 +561,9 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
     if (col > 0) dtv -= vh[pix - 1];
     if (row < N - 1) dtv += vv[pix];
     if (row > 0) dtv -= vv[pix - N];
-    c.w[pix] = fma(c.alpha, bp, c.beta * dtv);
+    T wv = fma(c.alpha, bp, c.beta * dtv);
+    if (c.tpos) wv = fma(c.alpha, c.tpos[pix], wv);   // the rows I of x >= 0 (remark in Section 4.2)
+    c.w[pix] = wv;
 }
 
 // ---------------------------------------------------------------------------
@@ -997,6 +1003,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
         c.x[ra + n] = na;
         c.x[rb + n] = nb;
         const T ba = fma(T(2), na, -xa), bb = fma(T(2), nb, -xb);
+        if (c.tpos) {   // t+ = min(t + alpha xbar, 0): the conjugate prox of the indicator of x >= 0
+            c.tpos[ra + n] = fmin(fma(c.alpha, ba, c.tpos[ra + n]), T(0));
+            c.tpos[rb + n] = fmin(fma(c.alpha, bb, c.tpos[rb + n]), T(0));
+        }
         c.xbar[(size_t)(2 * pr) * c.P + n + 2] = ba;
         c.xbar[(size_t)(2 * pr + 1) * c.P + n + 2] = bb;
         *reinterpret_cast<Pair<T>*>(c.xbarT + (size_t)n * c.P + 2 * pr + 2) = Pair<T>{ba, bb};

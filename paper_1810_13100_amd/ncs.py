@@ -45,7 +45,7 @@ _STATUS_NAMES = {
 
 EXPORTED = [
     "ncs_setup", "ncs_set_init", "ncs_set_x", "ncs_iterate", "ncs_solve", "ncs_get_objectives",
-    "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_v", "ncs_get_state", "ncs_set_state",
+    "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_v", "ncs_get_t", "ncs_get_state", "ncs_set_state",
     "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_prefilter", "ncs_fbp", "ncs_get_eigenvalues",
     "ncs_time_phases", "ncs_get_info", "ncs_destroy", "ncs_last_error",
     "ncs_batch_setup", "ncs_batch_set_init", "ncs_batch_solve", "ncs_batch_slice", "ncs_batch_destroy",
@@ -72,7 +72,7 @@ class _Params(ctypes.Structure):
         ("check_every", ctypes.c_int32), ("diverge_checks", ctypes.c_int32),
         ("projector", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
         ("dual_ramp", ctypes.c_double), ("backprojector", ctypes.c_int32), ("method", ctypes.c_int32),
-        ("cg_iters", ctypes.c_int32), ("cg_precondition", ctypes.c_int32),
+        ("cg_iters", ctypes.c_int32), ("cg_precondition", ctypes.c_int32), ("positivity", ctypes.c_int32),
     ]
 
 
@@ -107,6 +107,7 @@ def load_library() -> ctypes.CDLL:
         "ncs_get_x": ([vp, vp], i32),
         "ncs_get_u": ([vp, vp], i32),
         "ncs_get_v": ([vp, vp], i32),
+        "ncs_get_t": ([vp, vp], i32),
         "ncs_get_state": ([vp, vp, psz], i32),
         "ncs_set_state": ([vp, vp, ctypes.c_size_t], i32),
         "ncs_forward": ([vp, vp, vp], i32),
@@ -177,6 +178,7 @@ class Params:
     method: int = 0           # METHOD_NCS, METHOD_PDHG (M = gamma I) or METHOD_ADMM_CG
     cg_iters: int = 0         # ADMM-CG: CG steps per linear solve (0: 10)
     cg_precondition: int = 1  # ADMM-CG: precondition CG with alpha M^+
+    positivity: int = 0       # 1: constrain x >= 0 (a third dual block t; NCS and PDHG)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -203,7 +205,7 @@ class Solver:
         p = _Params(params.alpha, params.beta, params.gamma, params.lam, params.c_r, params.mu_dc,
                     params.data_term, params.tv_term, params.check_every, params.diverge_checks,
                     params.projector, params.graph_chunk, params.dual_ramp, params.backprojector, params.method,
-                    params.cg_iters, params.cg_precondition)
+                    params.cg_iters, params.cg_precondition, params.positivity)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.ncs_setup(ctypes.byref(g), ctypes.byref(p),
@@ -280,6 +282,12 @@ class Solver:
     def v(self) -> torch.Tensor:
         out = torch.empty(2 * self.geom.n, dtype=self.dtype, device=self.device)
         _check(self.lib.ncs_get_v(self.h, out.data_ptr()))
+        return out
+
+    def t(self) -> torch.Tensor:
+        """The positivity dual t (params.positivity = 1 only)."""
+        out = torch.empty(self.geom.n, dtype=self.dtype, device=self.device)
+        _check(self.lib.ncs_get_t(self.h, out.data_ptr()))
         return out
 
     def get_state(self) -> bytes:
@@ -398,7 +406,7 @@ class Batch:
         G = (_Geometry * n)(*[_Geometry(g.n_side, g.n_angles, g.n_bins) for g in geoms])
         P = (_Params * n)(*[_Params(p.alpha, p.beta, p.gamma, p.lam, p.c_r, p.mu_dc, p.data_term, p.tv_term,
                                     p.check_every, p.diverge_checks, p.projector, p.graph_chunk, p.dual_ramp,
-                                    p.backprojector, p.method, p.cg_iters, p.cg_precondition)
+                                    p.backprojector, p.method, p.cg_iters, p.cg_precondition, p.positivity)
                               for p in params])
         B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
         BG = None
