@@ -174,6 +174,14 @@ __device__ inline T* stage_twiddles(const DevCtx<T>& c, T* lds_after_data) {
     return lds_after_data;
 }
 
+// The slice's stop flag through the vector-memory path (a relaxed atomic
+// load): the wait for it is the wait for the data loads issued after it, so
+// the two latencies overlap instead of adding up.
+template <class T>
+__device__ inline int stop_flag(const DevCtx<T>& c) {
+    return __hip_atomic_load(&c.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Objective of a slice after an iteration: the partial sums of the projection
 // launch added in a fixed order (double) by the first 256 threads of the
 // calling workgroup, the history entry and the stop test.  Every thread of
@@ -850,7 +858,10 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
                                                  T* __restrict__ out) {
     int local;
     const DevCtx<T>& c = slot_ctx(ctxs, map, local);
-    if (MODE == PMODE_ITER && c.ctl->stop) return;
+    // the stop flag is read at the start, with the angle's coefficients, and
+    // tested before the first global write (a stopped slice computes the ray
+    // sums and discards them)
+    const int stop = MODE == PMODE_ITER ? c.ctl->stop : 0;
     __shared__ T red[2 * kWaves * kRays];
     __shared__ double shd[kWaves];
     const int lane = threadIdx.x & 63;
@@ -858,6 +869,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     const T* img = MODE == PMODE_ITER ? c.xbar : c.xsc;
     const T* imgT = MODE == PMODE_ITER ? c.xbarT : c.xscT;
     if (MODE == PMODE_ITER && local >= c.nb_proj) {
+        if (c.ctl->stop) return;   // its own read: the TV workgroups write v at once
         const double tv = block_sum256(tv_tile(c, local - c.nb_proj), shd);
         if (threadIdx.x == 0) c.part_tv[local - c.nb_proj] = tv;
         return;
@@ -871,7 +883,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     if (VARIANT == 3) {
         ray_sum_pair(c, img, imgT, A, axis, d0, lane, wave, red);
         __syncthreads();
-        if (wave != 0) return;
+        if (wave != 0 || stop) return;   // a stopped slice writes nothing
         T sum = red[lane];
 #pragma unroll
         for (int r = 1; r < 2 * kWaves; ++r) sum += red[r * kRays + lane];
@@ -891,7 +903,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     }
     red[wave * kRays + lane] = acc;
     __syncthreads();
-    if (wave != 0) return;
+    if (wave != 0 || stop) return;   // a stopped slice writes nothing
     const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
     const double dterm = wave_sum(project_epilogue<T, MODE>(c, a, d, q, out));
     if (MODE == PMODE_ITER && lane == 0) c.part_data[local] = dterm;
@@ -901,19 +913,21 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
 // Circulant solve: 2D DFT as row transforms (two real rows packed in one
 // complex transform), column transforms with the multiplier, inverse rows.
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, bool ITER>
 __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const DevCtx<T>* __restrict__ ctxs,
                                                               const Slot* __restrict__ map,
-                                                              const T* __restrict__ src_plain, int iter) {
+                                                              const T* __restrict__ src_plain) {
     int pr;
     const DevCtx<T>& c = slot_ctx(ctxs, map, pr);
-    if (iter && c.ctl->stop) return;
+    // the stop flag is read while the rows load (its latency overlaps theirs);
+    // nothing global is written before it is tested
+    const int stop = ITER ? stop_flag(c) : 0;
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
     const T* tw = stage_twiddles(c, im + c.N);
     const int N = c.N, logN = c.log2N;
-    const T* src = iter ? c.w : src_plain;
+    const T* src = ITER ? c.w : src_plain;
     const T* ra = src + (size_t)(2 * pr) * N;
     const T* rb = ra + N;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
@@ -921,6 +935,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const DevCtx<T>* _
         re[i] = ra[n];
         im[i] = rb[n];
     }
+    if (stop) return;   // uniform: the whole workgroup returns before its first barrier
     fft_dit(re, im, tw, N, logN, false, threadIdx.x, blockDim.x);
     for (int k = threadIdx.x; k <= (N >> 1); k += blockDim.x) {
         const int m = (N - k) & (N - 1);
@@ -933,12 +948,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const DevCtx<T>* _
     }
 }
 
-template <class T>
+template <class T, bool ITER>
 __global__ __launch_bounds__(kFftThreads) void k_fft_cols(const DevCtx<T>* __restrict__ ctxs,
-                                                          const Slot* __restrict__ map, T scale, int iter) {
+                                                          const Slot* __restrict__ map, T scale) {
     int k;
     const DevCtx<T>& c = slot_ctx(ctxs, map, k);
-    if (iter && c.ctl->stop) return;
+    const int stop = ITER ? stop_flag(c) : 0;   // read with the column; tested before any global write
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
@@ -950,6 +965,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(const DevCtx<T>* __res
         re[i] = colp[2 * n];
         im[i] = colp[2 * n + 1];
     }
+    if (stop) return;   // uniform: the whole workgroup returns before its first barrier
     fft_dit(re, im, tw, N, logN, false, threadIdx.x, blockDim.x);
     const T* hk = c.hh + (size_t)k * N;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
@@ -970,7 +986,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
                                                               const Slot* __restrict__ map, T* __restrict__ out) {
     int pr;
     const DevCtx<T>& c = slot_ctx(ctxs, map, pr);
-    if (ITER && c.ctl->stop) return;
+    const int stop = ITER ? stop_flag(c) : 0;   // read with the spectrum; tested before any global write
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
@@ -988,8 +1004,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
         re[k] = ar - bi;      // Z = Ya + i Yb
         im[k] = ai + br;
     }
-    fft_dif(re, im, tw, N, logN, true, threadIdx.x, blockDim.x);
     const size_t ra = (size_t)(2 * pr) * N, rb = ra + N;
+    // the iterate's values of this thread's first column are read before the
+    // transform, so that their latency overlaps it
+    T xa0 = T(0), xb0 = T(0);
+    if (ITER && (int)threadIdx.x < N) {
+        xa0 = c.x[ra + threadIdx.x];
+        xb0 = c.x[rb + threadIdx.x];
+    }
+    if (stop) return;   // uniform: the whole workgroup returns before its first barrier
+    fft_dif(re, im, tw, N, logN, true, threadIdx.x, blockDim.x);
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
         const int i = bitrev(n, logN);
         const T da = re[i], db = im[i];
@@ -998,7 +1022,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
             out[rb + n] = db;
             continue;
         }
-        const T xa = c.x[ra + n], xb = c.x[rb + n];
+        const bool first = n == (int)threadIdx.x;
+        const T xa = first ? xa0 : c.x[ra + n], xb = first ? xb0 : c.x[rb + n];
         const T na = xa - da, nb = xb - db;
         c.x[ra + n] = na;
         c.x[rb + n] = nb;
@@ -1441,12 +1466,12 @@ hipError_t launch_iteration_phase(const IterLaunch<T>& L, int phase, hipStream_t
         case 0:
             return launch_bp_iter<T>(L, 0, st);
         case 1:
-            hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(L.rows.blocks), dim3(kFftThreads), sm, st, L.ctxs,
-                               L.rows.map, (const T*)nullptr, 1);
+            hipLaunchKernelGGL((k_fft_rows_fwd<T, true>), dim3(L.rows.blocks), dim3(kFftThreads), sm, st, L.ctxs,
+                               L.rows.map, (const T*)nullptr);
             break;
         case 2:
-            hipLaunchKernelGGL((k_fft_cols<T>), dim3(L.cols.blocks), dim3(kFftThreads), sm, st, L.ctxs, L.cols.map,
-                               T(1), 1);
+            hipLaunchKernelGGL((k_fft_cols<T, true>), dim3(L.cols.blocks), dim3(kFftThreads), sm, st, L.ctxs,
+                               L.cols.map, T(1));
             break;
         case 3:
             hipLaunchKernelGGL((k_fft_rows_inv<T, true>), dim3(L.rows.blocks), dim3(kFftThreads), sm, st, L.ctxs,
@@ -1483,9 +1508,10 @@ hipError_t launch_admm_iterations(const IterLaunch<T>& L, const DevCtx<T>& hc, i
     const T a2 = hc.alpha * hc.alpha;   // the column pass scales h/(alpha N^2): alpha^2 gives alpha M^+
     const size_t sm = fft_lds<T>(hc.N);
     auto precondition = [&]() {
-        hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr,
-                           (const T*)hc.cg_r, 0);
-        hipLaunchKernelGGL((k_fft_cols<T>), dim3(hc.N / 2 + 1), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, a2, 0);
+        hipLaunchKernelGGL((k_fft_rows_fwd<T, false>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc,
+                           (const Slot*)nullptr, (const T*)hc.cg_r);
+        hipLaunchKernelGGL((k_fft_cols<T, false>), dim3(hc.N / 2 + 1), dim3(kFftThreads), sm, st, dc,
+                           (const Slot*)nullptr, a2);
         hipLaunchKernelGGL((k_fft_rows_inv<T, false>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc,
                            (const Slot*)nullptr, (T*)hc.cg_z);
     };
@@ -1551,8 +1577,10 @@ template <class T>
 hipError_t launch_apply_minv(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* w, T* out, T scale,
                              hipStream_t st) {
     const size_t sm = fft_lds<T>(hc.N);
-    hipLaunchKernelGGL((k_fft_rows_fwd<T>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, w, 0);
-    hipLaunchKernelGGL((k_fft_cols<T>), dim3(hc.N / 2 + 1), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, scale, 0);
+    hipLaunchKernelGGL((k_fft_rows_fwd<T, false>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr,
+                       w);
+    hipLaunchKernelGGL((k_fft_cols<T, false>), dim3(hc.N / 2 + 1), dim3(kFftThreads), sm, st, dc,
+                       (const Slot*)nullptr, scale);
     hipLaunchKernelGGL((k_fft_rows_inv<T, false>), dim3(hc.N / 2), dim3(kFftThreads), sm, st, dc, (const Slot*)nullptr, out);
     return hipGetLastError();
 }
