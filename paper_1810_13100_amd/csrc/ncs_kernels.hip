@@ -166,13 +166,9 @@ __device__ void fft_dif(T* re, T* im, const T* __restrict__ tw, int N, int logN,
     __syncthreads();
 }
 
-// The N/2 complex twiddles copied to LDS (after the data area), so that no
-// butterfly stage waits on a global load.
-template <class T>
-__device__ inline T* stage_twiddles(const DevCtx<T>& c, T* lds_after_data) {
-    for (int i = threadIdx.x; i < c.N; i += blockDim.x) lds_after_data[i] = c.tw[i];
-    return lds_after_data;
-}
+// The N/2 complex twiddles are copied to LDS (after the data area) in the
+// same loop that loads a pass's data, so that the two loads are in flight
+// together and no butterfly stage waits on a global load.
 
 // The slice's stop flag through the vector-memory path (a relaxed atomic
 // load): the wait for it is the wait for the data loads issued after it, so
@@ -501,6 +497,20 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
     const int PU = c.PU, NA = c.NA, NS = c.NS;
     const T c0 = (T)(tx * kBpTile), r0 = (T)(ty * kBpTile), span = (T)(kBpTile - 1);
     const AngleT<T>* ang = c.ang;
+    // the epilogue's reads (D^T v and the positivity dual of one pixel per
+    // thread of the first 256) are issued now, so the staging hides them
+    const int pcol = tx * kBpTile + (threadIdx.x & (kBpTile - 1)), prow = ty * kBpTile + (threadIdx.x & 255) / kBpTile;
+    const size_t ppix = (size_t)prow * N + pcol;
+    T dtv = T(0), tp = T(0);
+    if (ITER && threadIdx.x < kBpTile * kBpTile) {
+        const T* vh = c.v;
+        const T* vv = c.v + (size_t)N * N;
+        if (pcol < N - 1) dtv += vh[ppix];
+        if (pcol > 0) dtv -= vh[ppix - 1];
+        if (prow < N - 1) dtv += vv[ppix];
+        if (prow > 0) dtv -= vv[ppix - N];
+        if (c.tpos) tp = c.tpos[ppix];
+    }
     T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
     for (int a0 = 0; a0 < NA; a0 += CH) {
         const int nch = min(CH, NA - a0);
@@ -555,23 +565,14 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
     T bp = red[p];
 #pragma unroll
     for (int w = 1; w < kBpQuadWaves; ++w) bp += red[w * (kBpTile * kBpTile) + p];
-    const int col = tx * kBpTile + (p & (kBpTile - 1)), row = ty * kBpTile + p / kBpTile;
-    const size_t pix = (size_t)row * N + col;
     if (!ITER) {
-        out[pix] = bp;
+        out[ppix] = bp;
         return;
     }
-    // D^T v with D of Section 2 (rows [1, -1]) on each axis, padded planes.
-    const T* vh = c.v;
-    const T* vv = c.v + (size_t)N * N;
-    T dtv = T(0);
-    if (col < N - 1) dtv += vh[pix];
-    if (col > 0) dtv -= vh[pix - 1];
-    if (row < N - 1) dtv += vv[pix];
-    if (row > 0) dtv -= vv[pix - N];
+    // D^T v with D of Section 2 (rows [1, -1]) on each axis (read above)
     T wv = fma(c.alpha, bp, c.beta * dtv);
-    if (c.tpos) wv = fma(c.alpha, c.tpos[pix], wv);   // the rows I of x >= 0 (remark in Section 4.2)
-    c.w[pix] = wv;
+    if (c.tpos) wv = fma(c.alpha, tp, wv);   // the rows I of x >= 0 (remark in Section 4.2)
+    c.w[ppix] = wv;
 }
 
 // ---------------------------------------------------------------------------
@@ -925,15 +926,18 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const DevCtx<T>* _
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
-    const T* tw = stage_twiddles(c, im + c.N);
+    T* twl = im + c.N;
+    const T* tw = twl;
     const int N = c.N, logN = c.log2N;
     const T* src = ITER ? c.w : src_plain;
     const T* ra = src + (size_t)(2 * pr) * N;
     const T* rb = ra + N;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const T t = c.tw[n], va = ra[n], vb = rb[n];
         const int i = bitrev(n, logN);
-        re[i] = ra[n];
-        im[i] = rb[n];
+        twl[n] = t;
+        re[i] = va;
+        im[i] = vb;
     }
     if (stop) return;   // uniform: the whole workgroup returns before its first barrier
     fft_dit(re, im, tw, N, logN, false, threadIdx.x, blockDim.x);
@@ -957,19 +961,25 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(const DevCtx<T>* __res
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
-    const T* tw = stage_twiddles(c, im + c.N);
+    T* twl = im + c.N;
+    const T* tw = twl;
     const int N = c.N, logN = c.log2N;
     T* colp = c.spec + 2 * (size_t)k * N;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const T t = c.tw[n], vr = colp[2 * n], vi = colp[2 * n + 1];
         const int i = bitrev(n, logN);
-        re[i] = colp[2 * n];
-        im[i] = colp[2 * n + 1];
+        twl[n] = t;
+        re[i] = vr;
+        im[i] = vi;
     }
+    // the multiplier of this thread's first entry is read now, so that the
+    // forward transform hides its latency
+    const T* hk = c.hh + (size_t)k * N;
+    const T h0 = (int)threadIdx.x < N ? hk[threadIdx.x] : T(0);
     if (stop) return;   // uniform: the whole workgroup returns before its first barrier
     fft_dit(re, im, tw, N, logN, false, threadIdx.x, blockDim.x);
-    const T* hk = c.hh + (size_t)k * N;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        const T hv = hk[j] * scale;
+        const T hv = (j == (int)threadIdx.x ? h0 : hk[j]) * scale;
         re[j] *= hv;
         im[j] *= hv;
     }
@@ -990,13 +1000,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + c.N;
-    const T* tw = stage_twiddles(c, im + c.N);
+    T* twl = im + c.N;
+    const T* tw = twl;
     const int N = c.N, logN = c.log2N;
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const int kk = k <= (N >> 1) ? k : N - k;
         const T* s = c.spec + 2 * ((size_t)kk * N + 2 * pr);
+        const T t = c.tw[k];
         const T ar = s[0], br = s[2];
         T ai = s[1], bi = s[3];
+        twl[k] = t;
         if (k > (N >> 1)) {   // Hermitian extension of both real-row spectra
             ai = -ai;
             bi = -bi;
