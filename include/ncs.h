@@ -239,12 +239,14 @@ typedef struct {
 
 ncs_status ncs_get_info(ncs_handle* h, ncs_info* info);
 
-/* Per-kernel timing: run `iters` >= 1 iterations (they advance the state like
- * ncs_iterate) with a HIP event before and after every kernel on the handle's
- * stream, and return in ms_host[0..NCS_N_PHASES-1] the mean duration per
- * iteration of each phase, in the order backprojection (with D^T v), row DFT,
- * column DFT + multiplier, inverse row DFT + x-update, projection + data prox
- * + TV update, objective reduction.  Synchronises. */
+/* Per-kernel timing: one iteration, then each phase launched `iters` >= 1
+ * times back to back between two HIP events on the handle's stream; returns in
+ * ms_host[0..NCS_N_PHASES-1] the mean duration of one launch of each phase, in
+ * the order backprojection (with D^T v), row DFT, column DFT + multiplier,
+ * inverse row DFT + x-update, projection + data prox + TV update, objective
+ * reduction.  The launches change the state (x, duals, iteration count): time
+ * on a handle whose iterate is not needed afterwards, or call ncs_set_init.
+ * Synchronises. */
 #define NCS_N_PHASES 6
 ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host);
 

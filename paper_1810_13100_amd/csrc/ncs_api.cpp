@@ -1111,27 +1111,27 @@ ncs_status ncs_time_phases(ncs_handle* h, int32_t iters, double* ms_host) {
         return NCS_ERR_INVALID_ARG;
     }
     NCS_HIP(launch_control(h->ctl, 1, 0, std::nan(""), h->stream));
-    std::vector<hipEvent_t> ev(2 * NCS_N_PHASES * (size_t)iters);
-    for (auto& e : ev) NCS_HIP(hipEventCreate(&e));
+    // one full iteration first, so that every phase starts from warm state
     hipError_t le = hipSuccess;
-    for (int i = 0; i < iters && le == hipSuccess; ++i) {
-        for (int ph = 0; ph < NCS_N_PHASES && le == hipSuccess; ++ph) {
-            const size_t k = 2 * ((size_t)i * NCS_N_PHASES + ph);
-            (void)hipEventRecord(ev[k], h->stream);
-            le = launch_phase(h, ph);
-            (void)hipEventRecord(ev[k + 1], h->stream);
-        }
+    for (int ph = 0; ph < NCS_N_PHASES && le == hipSuccess; ++ph) le = launch_phase(h, ph);
+    // each phase: iters back-to-back launches between two events, so that the
+    // event overhead is spread over them (the launches of an iteration run
+    // back to back in the replayed graphs too)
+    std::vector<hipEvent_t> ev(2 * NCS_N_PHASES);
+    for (auto& e : ev) NCS_HIP(hipEventCreate(&e));
+    for (int ph = 0; ph < NCS_N_PHASES && le == hipSuccess; ++ph) {
+        (void)hipEventRecord(ev[2 * ph], h->stream);
+        for (int i = 0; i < iters && le == hipSuccess; ++i) le = launch_phase(h, ph);
+        (void)hipEventRecord(ev[2 * ph + 1], h->stream);
     }
     hipError_t se = hipStreamSynchronize(h->stream);
     for (int ph = 0; ph < NCS_N_PHASES; ++ph) ms_host[ph] = 0.0;
     if (le == hipSuccess && se == hipSuccess) {
-        for (int i = 0; i < iters; ++i)
-            for (int ph = 0; ph < NCS_N_PHASES; ++ph) {
-                const size_t k = 2 * ((size_t)i * NCS_N_PHASES + ph);
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-                ms_host[ph] += ms / iters;
-            }
+        for (int ph = 0; ph < NCS_N_PHASES; ++ph) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[2 * ph], ev[2 * ph + 1]);
+            ms_host[ph] = ms / iters;
+        }
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     NCS_HIP(le);
