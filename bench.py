@@ -367,6 +367,10 @@ def main() -> int:
     ap.add_argument("--pdhg-iters", type=int, default=100000, help="iteration budget of the PDHG comparison")
     ap.add_argument("--admm-iters", type=int, default=5000, help="iteration budget of the ADMM-CG comparison")
     ap.add_argument("--batch-iters", type=int, default=40, help="iterations of the uneven 512-slice batch (0: skip)")
+    ap.add_argument("--projector", type=int, default=0,
+                    help="forward-projector kernel of the headline solver (0: the setup timing picks it)")
+    ap.add_argument("--backprojector", type=int, default=0,
+                    help="backprojector kernel of the headline solver (0: the setup timing picks it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -379,7 +383,9 @@ def main() -> int:
     torch.cuda.set_device(dev)
     progress(f"device {torch.cuda.get_device_name(dev)}")
     geom, b = make_data(ncs, torch, dev)
-    s = ncs.Solver(geom, params(ncs), b=b, dtype=torch.float32)
+    p_head = params(ncs)
+    p_head.projector, p_head.backprojector = args.projector, args.backprojector
+    s = ncs.Solver(geom, p_head, b=b, dtype=torch.float32)
     info = s.info()
     s.set_init()
 
@@ -433,6 +439,8 @@ def main() -> int:
                    "n_side": N_SIDE, "n_angles": N_ANGLES, "n_bins": N_BINS, "alpha": ALPHA,
                    "beta": BETA_RATIO * ALPHA, "gamma": GAMMA_FRAC * ALPHA * N_ANGLES * N_SIDE / math.pi,
                    "nnz_E": info["nnz"]},
+        "kernels": {"projector": info["projector"], "backprojector": info["backprojector"],
+                    "chosen_by": "setup timing" if args.projector == 0 and args.backprojector == 0 else "flags"},
         "wall_s_timed": wall, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "pet_time_to_gap": pet, "batch": batch,
         "cpu_baseline": cpu, "host": platform.node(),
     }

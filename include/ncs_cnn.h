@@ -99,7 +99,9 @@ typedef enum {
  * weights w_dev (bfloat16 [9][c_out][c_in]) and bias_dev (float [c_out], may
  * be NULL for NCS_CONV_MASK_BF16).  (c_in, c_out) is one of (1, 32),
  * (32, 32), (32, 1).  mask_dev: bfloat16 NHWC [.., c_out] for
- * NCS_CONV_MASK_BF16; resid_dev: float [batch][h][w] for NCS_CONV_RESID_F32. */
+ * NCS_CONV_MASK_BF16; resid_dev: float [batch][h][w] for NCS_CONV_RESID_F32.
+ * in_dev, w_dev, out_dev and mask_dev must be 16-byte aligned (channels are
+ * read and written in groups of 8); NCS_ERR_INVALID_ARG otherwise. */
 ncs_status ncs_conv3x3_bf16(const void* in_dev, const void* w_dev, const float* bias_dev, const void* mask_dev,
                             const float* resid_dev, void* out_dev, int32_t batch, int32_t height, int32_t width,
                             int32_t c_in, int32_t c_out, int32_t epilogue, void* stream);
@@ -108,7 +110,8 @@ ncs_status ncs_conv3x3_bf16(const void* in_dev, const void* w_dev, const float* 
  * (bfloat16 NHWC, c_in channels) and output gradient dz_dev (bfloat16 NHWC,
  * c_out channels), grad_dev (float, 9 c_out c_in + c_out values) receives
  * dw[t][o][i] = sum_p dz[p][o] x[p + offset_t][i] and then dbias[o] =
- * sum_p dz[p][o].  Allocates and frees a partial-sum buffer; synchronises. */
+ * sum_p dz[p][o].  x_dev and dz_dev must be 16-byte aligned.  Allocates and
+ * frees a partial-sum buffer; synchronises. */
 ncs_status ncs_conv3x3_wgrad_bf16(const void* x_dev, const void* dz_dev, int32_t batch, int32_t height,
                                   int32_t width, int32_t c_in, int32_t c_out, float* grad_dev, void* stream);
 

@@ -353,6 +353,10 @@ ncs_status ncs_conv3x3_bf16(const void* in_dev, const void* w_dev, const float* 
         set_err("ncs_conv3x3_bf16: null pointer");
         return NCS_ERR_INVALID_ARG;
     }
+    if (((uintptr_t)in_dev | (uintptr_t)w_dev | (uintptr_t)out_dev | (uintptr_t)mask_dev) % 16 != 0) {
+        set_err("ncs_conv3x3_bf16: tensors must be 16-byte aligned (read in groups of 8 channels)");
+        return NCS_ERR_INVALID_ARG;
+    }
     if (batch < 1 || height < 1 || width < 1 || (int64_t)batch * height * width > (1ll << 28)) {
         set_err("ncs_conv3x3_bf16: bad shape %d x %d x %d", batch, height, width);
         return NCS_ERR_INVALID_ARG;
@@ -382,6 +386,10 @@ ncs_status ncs_conv3x3_wgrad_bf16(const void* x_dev, const void* dz_dev, int32_t
                                   int32_t width, int32_t c_in, int32_t c_out, float* grad_dev, void* stream) {
     if (!x_dev || !dz_dev || !grad_dev) {
         set_err("ncs_conv3x3_wgrad_bf16: null pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (((uintptr_t)x_dev | (uintptr_t)dz_dev) % 16 != 0) {
+        set_err("ncs_conv3x3_wgrad_bf16: x and dz must be 16-byte aligned (read in groups of 8 channels)");
         return NCS_ERR_INVALID_ARG;
     }
     if (batch < 1 || height < 1 || width < 1 || (int64_t)batch * height * width > (1ll << 28)) {

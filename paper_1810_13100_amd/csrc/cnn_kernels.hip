@@ -301,6 +301,56 @@ __global__ __launch_bounds__(256) void k_wgrad32(const uint16_t* __restrict__ x,
 
 // Weight and bias gradient of a layer with one input or one output channel
 // (288 weights): one thread per weight, sums over the staged tile.
+// Stages a side x side block of pixels (one pixel of halo when HALO) of a
+// channels-last bfloat16 tensor into LDS as floats, zero outside the image.
+// With a multiple of 8 channels each thread reads whole 16-byte groups of 8
+// channels; every load of a thread is issued before its values are stored.
+template <int CH, int SIDE, int HALO>
+__device__ inline void stage_small(const uint16_t* __restrict__ src, size_t img, const TileXY& T, int H, int W,
+                                   float* __restrict__ dst) {
+    if constexpr (CH % 8 == 0) {
+        constexpr int G = CH / 8, NG = SIDE * SIDE * G, R = (NG + 255) / 256;
+        uint4 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = threadIdx.x + r * 256;
+            const int px = e / G, g = e - px * G;
+            const int y = T.y0 - HALO + px / SIDE, xx = T.x0 - HALO + px % SIDE;
+            v[r] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < NG && y >= 0 && y < H && xx >= 0 && xx < W)
+                v[r] = *reinterpret_cast<const uint4*>(src + (img + (size_t)y * W + xx) * CH + 8 * g);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = threadIdx.x + r * 256;
+            if (e >= NG) continue;
+            float* d = dst + 8 * e;   // pixel px, channels 8 g .. 8 g + 7
+            const uint32_t w[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                d[2 * k] = bf2f(w[k]);
+                d[2 * k + 1] = bf2f(w[k] >> 16);
+            }
+        }
+    } else {
+        constexpr int NE = SIDE * SIDE * CH, R = (NE + 255) / 256;
+        float v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = threadIdx.x + r * 256;
+            const int px = e / CH, ch = e - px * CH;
+            const int y = T.y0 - HALO + px / SIDE, xx = T.x0 - HALO + px % SIDE;
+            v[r] = (e < NE && y >= 0 && y < H && xx >= 0 && xx < W) ? bf2f(src[(img + (size_t)y * W + xx) * CH + ch])
+                                                                      : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = threadIdx.x + r * 256;
+            if (e < NE) dst[e] = v[r];
+        }
+    }
+}
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad_small(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dz,
                                                      int B, int H, int W, float* __restrict__ part) {
@@ -314,17 +364,8 @@ __global__ __launch_bounds__(256) void k_wgrad_small(const uint16_t* __restrict_
         const TileXY T = tile_of(tl, H, W);
         const size_t img = (size_t)T.b * H * W;
         __syncthreads();
-        for (int e = threadIdx.x; e < kHalo * kHalo * CIN; e += 256) {
-            const int hpix = e / CIN, ch = e - hpix * CIN;
-            const int ry = hpix / kHalo, hx = hpix - ry * kHalo;
-            const int y = T.y0 - 1 + ry, xx = T.x0 - 1 + hx;
-            xs[e] = (y >= 0 && y < H && xx >= 0 && xx < W) ? bf2f(x[(img + (size_t)y * W + xx) * CIN + ch]) : 0.f;
-        }
-        for (int e = threadIdx.x; e < kTile * kTile * COUT; e += 256) {
-            const int p = e / COUT, ch = e - p * COUT;
-            const int y = T.y0 + p / kTile, xx = T.x0 + p % kTile;
-            dzs[e] = (y < H && xx < W) ? bf2f(dz[(img + (size_t)y * W + xx) * COUT + ch]) : 0.f;
-        }
+        stage_small<CIN, kHalo, 1>(x, img, T, H, W, xs);
+        stage_small<COUT, kTile, 0>(dz, img, T, H, W, dzs);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -353,13 +394,29 @@ __global__ __launch_bounds__(256) void k_wgrad_small(const uint16_t* __restrict_
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int blocks, int n,
-                                                      float* __restrict__ out) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
+// out[j] = sum over g of part[g][j], in double.  A workgroup takes 64
+// parameters; its 16 waves take the partials g = w, w + 16, ... (each wave
+// reads 64 consecutive parameters of a partial row), and the 16 wave sums are
+// added in wave order, so the result is the same on every run.
+constexpr int kReduceWaves = 16;
+
+__global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_parts(const float* __restrict__ part, int blocks,
+                                                                   int n, float* __restrict__ out) {
+    __shared__ double sh[kReduceWaves][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int g = 0; g < blocks; ++g) s += (double)part[(size_t)g * n + j];
-    out[j] = (float)s;
+    if (j < n) {
+#pragma unroll 8
+        for (int g = wave; g < blocks; g += kReduceWaves) s += (double)part[(size_t)g * n + j];
+    }
+    sh[wave][lane] = s;
+    __syncthreads();
+    if (wave != 0 || j >= n) return;
+    double t = sh[0][lane];
+#pragma unroll
+    for (int w = 1; w < kReduceWaves; ++w) t += sh[w][lane];
+    out[j] = (float)t;
 }
 
 __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, int64_t n) {
@@ -475,7 +532,7 @@ hipError_t launch_wgrad(int cin, int cout, const uint16_t* x, const uint16_t* dz
 }
 
 hipError_t launch_reduce_parts(const float* part, int blocks, int n, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for(n)), dim3(256), 0, st, part, blocks, n, out);
+    hipLaunchKernelGGL(k_reduce_parts, dim3((n + 63) / 64), dim3(kReduceWaves * 64), 0, st, part, blocks, n, out);
     return hipGetLastError();
 }
 
