@@ -29,7 +29,7 @@ import scipy.sparse as sp
 
 import ncs_inputs
 
-from . import operators, projector
+from . import fanbeam, operators, projector
 
 
 @dataclass
@@ -68,6 +68,7 @@ class Params:
     gamma: float
     c_r: float | None = None      # None: N_theta N / pi
     mu_dc: float | None = None    # None: gamma + alpha |E 1|^2 / n
+    h_e: np.ndarray | None = None  # N x N estimate of E^T E's multiplier (eq. H-fan); None: C_R / |omega|
 
 
 def resolved_c_r(prob: Problem, par: Params) -> float:
@@ -94,8 +95,12 @@ def eigenvalues(prob: Problem, par: Params, positivity: bool = False) -> np.ndar
     block), so alpha A^T A gains alpha I and so does M: every eigenvalue,
     mu_DC included, is raised by alpha.
     """
-    mu = operators.ncs_eigenvalues(prob.n_side, par.alpha, par.beta, par.gamma,
-                                   resolved_c_r(prob, par), resolved_mu_dc(prob, par))
+    if par.h_e is None:
+        mu = operators.ncs_eigenvalues(prob.n_side, par.alpha, par.beta, par.gamma,
+                                       resolved_c_r(prob, par), resolved_mu_dc(prob, par))
+    else:   # eq. (H-fan) for E^T E, eq. (circ_D) for D^T D, the DC entry as above
+        mu = par.gamma + par.alpha * par.h_e + (par.beta ** 2 / par.alpha) * operators.multiplier_diff(prob.n_side)
+        mu[0, 0] = resolved_mu_dc(prob, par)
     return mu + par.alpha if positivity else mu
 
 
@@ -109,6 +114,20 @@ def ct_problem(n_side: int, n_angles: int, n_bins: int, seed: int, lam: float,
     sigma = noise_frac * float(np.max(clean))
     b = clean + sigma * ncs_inputs.gaussian_noise(seed, clean.size)
     return Problem("ct", tv, n_side, n_angles, n_bins, lam, E,
+                   operators.diff_2d(n_side), b, np.zeros_like(b), x_true)
+
+
+def fan_problem(n_side: int, n_views: int, n_bins: int, source_radius: float, seed: int, lam: float,
+                noise_frac: float = 0.01, tv: str = "aniso", E=None) -> Problem:
+    """The CT problem of ``ct_problem`` with the fan-beam E of ``fanbeam.fan_matrix``
+    (n_angles holds the number of views)."""
+    if E is None:
+        E = fanbeam.fan_matrix(fanbeam.FanGeometry(n_side, n_views, n_bins, source_radius))
+    x_true = ncs_inputs.phantom(n_side, seed).ravel()
+    clean = E @ x_true
+    sigma = noise_frac * float(np.max(clean))
+    b = clean + sigma * ncs_inputs.gaussian_noise(seed, clean.size)
+    return Problem("ct", tv, n_side, n_views, n_bins, lam, E,
                    operators.diff_2d(n_side), b, np.zeros_like(b), x_true)
 
 
