@@ -73,10 +73,21 @@ typedef enum { NCS_DATA_QUADRATIC = 0, NCS_DATA_POISSON = 1 } ncs_data_term;
  * isotropic sum_p |(Dx)_p|_2 (per-pixel l2-ball projection). */
 typedef enum { NCS_TV_ANISO = 0, NCS_TV_ISO = 1 } ncs_tv_term;
 
+/* Beam geometry.  Parallel: N_theta angles over [0, pi), unit bins (Section
+ * 4.1).  Fan (Section 4.1.1, divergent beam): N_theta source positions
+ * S_a = R_s (cos beta_a, sin beta_a), beta_a = 2 pi a / N_theta, over a full
+ * turn; N_s bins on an equi-angular detector whose fan just covers the circle
+ * of radius N / sqrt(2) around the image (ray d leaves S_a at angle
+ * beta_a + pi + (d - (N_s-1)/2) dgamma, dgamma = 2 asin(N / (sqrt(2) R_s)) /
+ * (N_s - 1)); Joseph interpolation along each ray's own stepping axis. */
+typedef enum { NCS_BEAM_PARALLEL = 0, NCS_BEAM_FAN = 1 } ncs_beam;
+
 typedef struct {
     int32_t n_side;    /* N: image is N x N */
-    int32_t n_angles;  /* N_theta */
+    int32_t n_angles;  /* N_theta: parallel angles, or fan source positions */
     int32_t n_bins;    /* N_s */
+    int32_t beam;      /* ncs_beam */
+    double source_radius; /* fan: R_s in pixels, > 1.01 N / sqrt(2); ignored for parallel */
 } ncs_geometry;
 
 /* The splitting: NCS with the circulant M of Section 4.1.1; PDHG (eq. PDHG,
@@ -124,6 +135,11 @@ typedef struct {
                               is raised by alpha (for PDHG, gamma must cover the extra rows).
                               The reported objective leaves out the indicator.  Not with
                               ADMM-CG. */
+    int32_t probes;        /* > 0: E^T E's multiplier estimated by eq. H-fan from this many
+                              probes (Rademacher images from SplitMix64 seeded by the probe
+                              index; least-squares average of (F E^T E v)_i / (F v)_i) instead
+                              of alpha C_R / |omega|; 0: the analytic multiplier for parallel
+                              beams and 16 probes for fan beams */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -91,6 +92,13 @@ struct ncs_handle {
     double* cg_part = nullptr;  // dot-product partials
     double* cg_s = nullptr;     // CG scalars
     void* tpos = nullptr;       // positivity dual t (params.positivity only)
+    // fan beam: per-ray and per-view tables (typed), the fan angles and the
+    // half-width in bins of the rays that can touch a pixel
+    void* rays = nullptr;
+    void* views = nullptr;
+    double gamma0 = 0.0, dgamma = 0.0;
+    int fan_w = 0;
+    std::vector<double> fan_tab;   // per ray: k0, k2, kappa, axis (double)
 
     const void* b = nullptr;    // caller-owned
     const void* bg = nullptr;   // caller-owned
@@ -175,6 +183,12 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
         c.cg_s = h->cg_s;
     }
     c.tpos = static_cast<T*>(h->tpos);
+    c.rays = static_cast<const RayT<T>*>(h->rays);
+    c.views = static_cast<const ViewT<T>*>(h->views);
+    c.gamma0 = (T)h->gamma0;
+    c.dgamma = (T)h->dgamma;
+    c.beam = h->g.beam;
+    c.fan_w = h->fan_w;
     c.alpha = (T)h->p.alpha;
     c.beta = (T)h->p.beta;
     c.s_tv = (T)(h->p.lambda * h->p.alpha / h->p.beta);
@@ -242,6 +256,169 @@ int64_t count_nnz(const ncs_geometry& g, const std::vector<double>& tab) {
         }
     }
     return taps;
+}
+
+// ---- fan beam ----------------------------------------------------------------
+// Per ray (a*N_s + d) the stepping axis and the affine coordinate of the
+// other axis along it (Joseph), from the source position and direction in
+// double: rows are stepped when |u_y| >= |u_x| - 1e-12.  Per view the source
+// and the direction of the central ray.  w bins on either side of a pixel's
+// bin hold every ray that passes within one pixel of its centre.
+void build_fan_tables(ncs_handle* h, std::vector<double>& views) {
+    const ncs_geometry& g = h->g;
+    const int N = g.n_side, NA = g.n_angles, NS = g.n_bins;
+    const double half = 0.5 * (N - 1), rs = g.source_radius, r_fov = N / std::sqrt(2.0);
+    h->dgamma = 2.0 * std::asin(r_fov / rs) / (NS - 1);
+    h->gamma0 = -0.5 * (NS - 1) * h->dgamma;
+    h->fan_w = (int)std::ceil(std::asin(1.0 / (rs - r_fov)) / h->dgamma + 0.5) + 1;
+    h->fan_tab.assign(4 * (size_t)NA * NS, 0.0);
+    views.assign(4 * (size_t)NA, 0.0);
+    for (int a = 0; a < NA; ++a) {
+        const double beta = 2.0 * kPi * a / NA;
+        const double sx = rs * std::cos(beta), sy = rs * std::sin(beta), thc = beta + kPi;
+        views[4 * (size_t)a] = sx;
+        views[4 * (size_t)a + 1] = sy;
+        views[4 * (size_t)a + 2] = thc;
+        for (int d = 0; d < NS; ++d) {
+            const double th = thc + (d - 0.5 * (NS - 1)) * h->dgamma;
+            const double ux = std::cos(th), uy = std::sin(th);
+            double* t = &h->fan_tab[4 * ((size_t)a * NS + d)];
+            if (std::fabs(uy) >= std::fabs(ux) - 1e-12) {   // rows: column coordinate at row r
+                const double k2 = ux / uy;
+                t[0] = sx - (half + sy) * k2 + half;
+                t[1] = k2;
+                t[2] = 1.0 / std::fabs(uy);
+                t[3] = 0.0;
+            } else {                                         // columns: row coordinate at column c
+                const double k2 = uy / ux;
+                t[0] = sy - (half + sx) * k2 + half;
+                t[1] = k2;
+                t[2] = 1.0 / std::fabs(ux);
+                t[3] = 1.0;
+            }
+        }
+    }
+}
+
+template <class T>
+ncs_status upload_fan(ncs_handle* h, const std::vector<double>& views) {
+    const size_t m = h->fan_tab.size() / 4, na = views.size() / 4;
+    std::vector<RayT<T>> r(m);
+    for (size_t i = 0; i < m; ++i)
+        r[i] = RayT<T>{(T)h->fan_tab[4 * i], (T)h->fan_tab[4 * i + 1], (T)h->fan_tab[4 * i + 2],
+                       (int32_t)h->fan_tab[4 * i + 3]};
+    std::vector<ViewT<T>> v(na);
+    for (size_t i = 0; i < na; ++i) v[i] = ViewT<T>{(T)views[4 * i], (T)views[4 * i + 1], (T)views[4 * i + 2], T(0)};
+    NCS_HIP(hipMemcpy(h->rays, r.data(), m * sizeof(RayT<T>), hipMemcpyHostToDevice));
+    NCS_HIP(hipMemcpy(h->views, v.data(), na * sizeof(ViewT<T>), hipMemcpyHostToDevice));
+    return NCS_OK;
+}
+
+int64_t count_nnz_fan(const ncs_handle* h) {
+    const int N = h->g.n_side;
+    int64_t taps = 0;
+    for (size_t i = 0; i < h->fan_tab.size() / 4; ++i) {
+        const double k0 = h->fan_tab[4 * i], k2 = h->fan_tab[4 * i + 1];
+        for (int st = 0; st < N; ++st) {
+            const double xi = st * k2 + k0;
+            if (xi <= -1.0 || xi >= (double)N) continue;
+            const double fl = std::floor(xi);
+            const double f = xi - fl;
+            const int c0 = (int)fl;
+            if (c0 >= 0) ++taps;
+            if (c0 + 1 <= N - 1 && f != 0.0) ++taps;
+        }
+    }
+    return taps;
+}
+
+// ---- eq. H-fan: the multiplier of E^T E estimated from probes --------------
+// Probe k: n values +-1, entry 64 j + b = bit b of the j-th output of
+// SplitMix64 (Steele, Lea and Flood) started from state k.
+void rademacher_probe(uint64_t index, size_t n, std::vector<double>& v) {
+    v.assign(n, 0.0);
+    uint64_t x = index;
+    for (size_t j = 0; 64 * j < n; ++j) {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        for (int b = 0; b < 64 && 64 * j + b < n; ++b) v[64 * j + b] = ((z >> b) & 1u) ? 1.0 : -1.0;
+    }
+}
+
+// In-place radix-2 DFT with the forward sign, sum_t a_t exp(-2 pi i f t / n).
+void dft_pow2(std::complex<double>* a, int n) {
+    for (int i = 1, j = 0; i < n; ++i) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        const double ang = -2.0 * kPi / len;
+        for (int i = 0; i < n; i += len)
+            for (int k = 0; k < len / 2; ++k) {
+                const std::complex<double> w(std::cos(ang * k), std::sin(ang * k));
+                const std::complex<double> u = a[i + k], t = w * a[i + k + len / 2];
+                a[i + k] = u + t;
+                a[i + k + len / 2] = u - t;
+            }
+    }
+}
+
+// 2D DFT of an N x N real image (row-major), the numpy fft2 convention.
+void dft2_real(const std::vector<double>& img, int N, std::vector<std::complex<double>>& out) {
+    out.assign((size_t)N * N, 0.0);
+    for (size_t i = 0; i < out.size(); ++i) out[i] = img[i];
+    for (int r = 0; r < N; ++r) dft_pow2(&out[(size_t)r * N], N);
+    std::vector<std::complex<double>> col(N);
+    for (int c = 0; c < N; ++c) {
+        for (int r = 0; r < N; ++r) col[r] = out[(size_t)r * N + c];
+        dft_pow2(col.data(), N);
+        for (int r = 0; r < N; ++r) out[(size_t)r * N + c] = col[r];
+    }
+}
+
+// he = Re( sum_v conj(F v) F(E^T E v) / sum_v |F v|^2 ) over the probes, with
+// E^T E v from the handle's own projector and backprojector.
+template <class T>
+ncs_status estimate_normal_multiplier(ncs_handle* h, int probes, std::vector<double>& he) {
+    const int N = h->g.n_side;
+    const size_t n = h->n, m = h->m;
+    T *v = nullptr, *y = nullptr, *z = nullptr;
+    ncs_status s;
+    if ((s = dev_alloc(h, reinterpret_cast<void**>(&v), n * sizeof(T))) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&y), m * sizeof(T))) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&z), n * sizeof(T))))
+        return s;
+    const DevCtx<T> c = make_ctx<T>(h);
+    std::vector<double> vd, zd(n);
+    std::vector<T> vt(n), zt(n);
+    std::vector<std::complex<double>> fv, fz, num(n, 0.0);
+    std::vector<double> den(n, 0.0);
+    for (int k = 0; k < probes; ++k) {
+        rademacher_probe((uint64_t)k, n, vd);
+        for (size_t i = 0; i < n; ++i) vt[i] = (T)vd[i];
+        NCS_HIP(hipMemcpyAsync(v, vt.data(), n * sizeof(T), hipMemcpyHostToDevice, h->stream));
+        NCS_HIP(launch_pad_image<T>(c, dctx<T>(h), v, h->stream));
+        NCS_HIP(launch_project_plain<T>(c, dctx<T>(h), h->projector, y, h->stream));
+        NCS_HIP(launch_pad_sinogram<T>(c, dctx<T>(h), y, c.ysc, h->stream));
+        NCS_HIP(launch_backproject_plain<T>(c, dctx<T>(h), h->backprojector, c.ysc, z, h->stream));
+        NCS_HIP(hipMemcpyAsync(zt.data(), z, n * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+        NCS_HIP(hipStreamSynchronize(h->stream));
+        for (size_t i = 0; i < n; ++i) zd[i] = (double)zt[i];
+        dft2_real(vd, N, fv);
+        dft2_real(zd, N, fz);
+        for (size_t i = 0; i < n; ++i) {
+            num[i] += std::conj(fv[i]) * fz[i];
+            den[i] += std::norm(fv[i]);
+        }
+    }
+    he.assign(n, 0.0);
+    for (size_t i = 0; i < n; ++i) he[i] = den[i] > 0.0 ? std::real(num[i] / den[i]) : 0.0;
+    return NCS_OK;
 }
 
 template <class T>
@@ -417,6 +594,18 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("dtype must be NCS_F32 or NCS_F64");
         return NCS_ERR_INVALID_ARG;
     }
+    if (g.beam != NCS_BEAM_PARALLEL && g.beam != NCS_BEAM_FAN) {
+        set_err("beam must be NCS_BEAM_PARALLEL (0) or NCS_BEAM_FAN (1)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (g.beam == NCS_BEAM_FAN && !(std::isfinite(g.source_radius) && g.source_radius > 1.01 * g.n_side / std::sqrt(2.0))) {
+        set_err("a fan beam needs a finite source_radius > 1.01 n_side / sqrt(2)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.probes < 0 || p.probes > 4096) {
+        set_err("probes must be in [0, 4096]");
+        return NCS_ERR_INVALID_ARG;
+    }
     if (!(p.alpha > 0.0) || !(p.beta > 0.0) || !(p.gamma >= 0.0) || !(p.lambda >= 0.0) ||
         !std::isfinite(p.alpha) || !std::isfinite(p.beta) || !std::isfinite(p.gamma) ||
         !std::isfinite(p.lambda) || !std::isfinite(p.c_r) || !std::isfinite(p.mu_dc) || !std::isfinite(p.dual_ramp)) {
@@ -460,6 +649,14 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("projector must be 0 (auto), 1 (LDS), 2 (direct) or 3 (ray pairs)");
         return NCS_ERR_INVALID_ARG;
     }
+    if (g.beam == NCS_BEAM_FAN && (p.projector != 0 || p.backprojector != 0)) {
+        set_err("a fan beam has one projector pair; leave projector and backprojector at 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (g.beam == NCS_BEAM_FAN && p.method == NCS_METHOD_ADMM_CG) {
+        set_err("fan beams run NCS or PDHG, not ADMM-CG");
+        return NCS_ERR_INVALID_ARG;
+    }
     return NCS_OK;
 }
 
@@ -476,6 +673,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
     if (p.method == NCS_METHOD_ADMM_CG && h->graph_chunk > 2) h->graph_chunk = 2;   // ~15 launches per CG step
     h->projector = p.projector == 0 ? 2 : p.projector;
     h->backprojector = p.backprojector == 0 ? 2 : p.backprojector;
+    if (g.beam == NCS_BEAM_FAN) h->projector = h->backprojector = 4;   // the fan pair
     h->dtype = dtype;
     h->esz = dtype == NCS_F64 ? 8 : 4;
     h->stream = stream;
@@ -554,6 +752,16 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
          (s = dev_alloc(h, reinterpret_cast<void**>(&h->cg_s), 4 * sizeof(double)))))
         return fail(s);
     if (p.positivity && (s = dev_alloc(h, &h->tpos, h->n * e))) return fail(s);
+    if (g.beam == NCS_BEAM_FAN) {
+        std::vector<double> views;
+        build_fan_tables(h, views);
+        const size_t ray_bytes = dtype == NCS_F64 ? sizeof(RayT<double>) : sizeof(RayT<float>);
+        const size_t view_bytes = dtype == NCS_F64 ? sizeof(ViewT<double>) : sizeof(ViewT<float>);
+        if ((s = dev_alloc(h, &h->rays, (size_t)NA * NS * ray_bytes)) ||
+            (s = dev_alloc(h, &h->views, (size_t)NA * view_bytes)) ||
+            (s = dtype == NCS_F64 ? upload_fan<double>(h, views) : upload_fan<float>(h, views)))
+            return fail(s);
+    }
     if (ext_ctl) {
         h->ctl = ext_ctl;
     } else if ((s = dev_alloc(h, reinterpret_cast<void**>(&h->ctl), sizeof(Control)))) {
@@ -594,9 +802,16 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         h->mu_dc = p.gamma + p.alpha * h->norm_e1_sq / (double)h->n;
     }
 
-    // ---- multiplier (Section 4.1.1: eq. circ_R, eq. circ_D, DC entry) -----
+    // ---- multiplier (Section 4.1.1: eq. circ_R or eq. H-fan, eq. circ_D, DC entry)
     h->mu.assign(h->n, 0.0);
     const double bta = p.beta * p.beta / p.alpha;
+    const int probes = p.probes > 0 ? p.probes : (g.beam == NCS_BEAM_FAN ? kFanProbes : 0);
+    std::vector<double> he;   // eq. H-fan estimate of E^T E's multiplier (when probes > 0)
+    if (probes > 0) {
+        s = dtype == NCS_F64 ? estimate_normal_multiplier<double>(h, probes, he)
+                             : estimate_normal_multiplier<float>(h, probes, he);
+        if (s) return fail(s);
+    }
     for (int j = 0; j < N; ++j) {
         const double jj = std::min(j, N - j);
         const double sj = std::sin(kPi * j / N);
@@ -605,7 +820,10 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
             const double sk = std::sin(kPi * k / N);
             const double rad2 = jj * jj + kk * kk;
             double mu = p.gamma + bta * 4.0 * (sj * sj + sk * sk);
-            if (rad2 > 0.0) mu += p.alpha * h->c_r / std::sqrt(rad2);
+            if (probes > 0)
+                mu += p.alpha * he[(size_t)j * N + k];
+            else if (rad2 > 0.0)
+                mu += p.alpha * h->c_r / std::sqrt(rad2);
             h->mu[(size_t)j * N + k] = mu;
         }
     }
@@ -640,11 +858,11 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         set_err("ncs_setup: stream synchronisation failed");
         return fail(NCS_ERR_HIP);
     }
-    if (autotune && p.projector == 0) {
+    if (autotune && p.projector == 0 && g.beam == NCS_BEAM_PARALLEL) {
         s = dtype == NCS_F64 ? autotune_projector<double>(h) : autotune_projector<float>(h);
         if (s) return fail(s);
     }
-    if (autotune && p.backprojector == 0) {
+    if (autotune && p.backprojector == 0 && g.beam == NCS_BEAM_PARALLEL) {
         s = dtype == NCS_F64 ? autotune_backprojector<double>(h) : autotune_backprojector<float>(h);
         if (s) return fail(s);
     }
@@ -1145,7 +1363,7 @@ ncs_status ncs_get_info(ncs_handle* h, ncs_info* info) {
         set_err("ncs_get_info: null pointer");
         return NCS_ERR_INVALID_ARG;
     }
-    if (h->nnz < 0) h->nnz = count_nnz(h->g, h->tab);
+    if (h->nnz < 0) h->nnz = h->g.beam == NCS_BEAM_FAN ? count_nnz_fan(h) : count_nnz(h->g, h->tab);
     info->nnz = h->nnz;
     info->c_r = h->c_r;
     info->mu_dc = h->mu_dc;
@@ -1324,6 +1542,10 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
         }
         if (params[i].method == NCS_METHOD_ADMM_CG) {
             set_err("ncs_batch_setup: slice %d: batches run NCS or PDHG, not ADMM-CG", i);
+            return NCS_ERR_INVALID_ARG;
+        }
+        if (geoms[i].beam != NCS_BEAM_PARALLEL) {
+            set_err("ncs_batch_setup: slice %d: batches run parallel-beam slices", i);
             return NCS_ERR_INVALID_ARG;
         }
     }

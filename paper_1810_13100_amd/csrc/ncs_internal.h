@@ -34,6 +34,22 @@ struct AngleT {
     T omk;                 // 1 - kappa
 };
 
+// Fan beam: one ray of the equi-angular fan.  Along its stepping axis
+// (axis 0: image rows, axis 1: columns) the ray crosses step s at the
+// coordinate k0 + k2 s of the other axis; kappa is its length per step.
+template <class T>
+struct RayT {
+    T k0, k2, kappa;
+    int32_t axis;
+};
+
+// Fan beam: one source position (its coordinates and the direction of its
+// central ray), used by the backprojector to find the rays near a pixel.
+template <class T>
+struct ViewT {
+    T sx, sy, theta_c, pad;
+};
+
 // Device control block of one slice.
 struct Control {
     int32_t stop;        // 1: iteration kernels of this slice return immediately
@@ -91,6 +107,12 @@ struct DevCtx {
     NCS_G double* cg_part;
     NCS_G double* cg_s;
     NCS_G T* tpos;     // N*N positivity dual t (nullptr without the constraint x >= 0)
+    // fan beam only (beam == 1): ray and view tables, the first ray's fan angle,
+    // the fan step, and the half-width in bins of the rays that can touch a pixel
+    const NCS_G RayT<T>* rays;
+    const NCS_G ViewT<T>* views;
+    T gamma0, dgamma;
+    int beam, fan_w;
     T alpha, beta, s_tv, inv1pa;
     T dual_ramp;                     // TV-dual ramp width of the warm start (<= 0: sign)
     double lambda;
@@ -122,6 +144,7 @@ struct IterLaunch {
 };
 
 constexpr int kNumBackprojectors = 3;
+constexpr int kFanProbes = 16;   // default probes of eq. H-fan for fan beams
 
 constexpr int kNumPhases = 6;   // backprojection, row DFT, column DFT, inverse row DFT + x-update,
                                 // projection + data prox + TV update, objective

@@ -317,6 +317,88 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevC
     c.w[pix] = wv;
 }
 
+// Fan beam: the direct kernel's layout (8 x 8 pixel tile, 8 waves over the
+// source positions).  A ray touches a pixel only if it passes within one pixel
+// of the pixel's centre, i.e. within asin(1 / |S - p|) of the centre's fan
+// angle; fan_w bins on either side of the centre's bin cover that for every
+// pixel of the image.  Each candidate ray's taps at this pixel are recomputed
+// exactly as the projector computes them (its coordinate at the pixel's step
+// along the ray's own axis), so this is the transpose of the fan projector.
+template <class T, bool ITER>
+__global__ __launch_bounds__(kBpWaves * 64) void k_backproject_fan(const DevCtx<T>* __restrict__ ctxs,
+                                                                   const Slot* __restrict__ map,
+                                                                   const T* __restrict__ ysrc_plain,
+                                                                   T* __restrict__ out, int fin_prev) {
+    int local;
+    const DevCtx<T>& c = slot_ctx(ctxs, map, local);
+    __shared__ T red[kBpWaves * 64];
+    if (ITER) {
+        __shared__ int stop_sh;
+        __shared__ double fin_sh[8];
+        if (threadIdx.x == 0) stop_sh = c.ctl->stop;   // one read per workgroup: the flag may change below
+        __syncthreads();
+        if (stop_sh) return;
+        if (fin_prev && local == 0) finalize_slice(c, fin_sh);   // objective of the previous iteration
+    }
+    const T* ysrc = ITER ? c.u : ysrc_plain;
+    const int N = c.N;
+    const int tiles_x = N / kBpTileD;
+    const int tx = local % tiles_x, ty = local / tiles_x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = tx * kBpTileD + (lane & 7);
+    const int row = ty * kBpTileD + (lane >> 3);
+    const T half = T(0.5) * (T)(N - 1);
+    const T px = (T)col - half, py = (T)row - half;
+    const T fc = (T)col, fr = (T)row, cmax = (T)N;
+    const int NS = c.NS, PU = c.PU, NA = c.NA, W = c.fan_w;
+    const T inv_dg = T(1) / c.dgamma;
+    const T two_pi = T(6.283185307179586476925286766559);
+    T acc = T(0);
+    for (int a = wave; a < NA; a += kBpWaves) {
+        const ViewT<T> V = c.views[a];
+        // fan angle of the pixel centre from the source, relative to the central ray
+        T g = atan2(py - V.sy, px - V.sx) - V.theta_c;
+        g -= two_pi * rint(g / two_pi);
+        const int dc = (int)floor((g - c.gamma0) * inv_dg + T(0.5));
+        const int d_lo = max(dc - W, 0), d_hi = min(dc + W, NS - 1);
+        const RayT<T>* rr = c.rays + (size_t)a * NS;
+        const T* yrow = ysrc + (size_t)a * PU + 1;
+        for (int d = d_lo; d <= d_hi; ++d) {
+            const RayT<T> R = rr[d];
+            const T st = R.axis == 0 ? fr : fc;   // the ray's step at this pixel
+            const T tp = R.axis == 0 ? fc : fr;   // the pixel's place along the interpolated axis
+            const T xi = fma(st, R.k2, R.k0);
+            const T fl = med3(floor(xi), T(-2), cmax);
+            const T f = xi - fl;
+            const T w = tp == fl ? T(1) - f : (tp == fl + T(1) ? f : T(0));
+            acc = fma(R.kappa * w, yrow[d], acc);
+        }
+    }
+    red[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    T bp = red[lane];
+#pragma unroll
+    for (int w = 1; w < kBpWaves; ++w) bp += red[w * 64 + lane];
+    const size_t pix = (size_t)row * N + col;
+    if (!ITER) {
+        out[pix] = bp;
+        return;
+    }
+    // D^T v with D of Section 2 (rows [1, -1]) on each axis, padded planes.
+    const T* vh = c.v;
+    const T* vv = c.v + (size_t)N * N;
+    T dtv = T(0);
+    if (col < N - 1) dtv += vh[pix];
+    if (col > 0) dtv -= vh[pix - 1];
+    if (row < N - 1) dtv += vv[pix];
+    if (row > 0) dtv -= vv[pix - N];
+    T wv = fma(c.alpha, bp, c.beta * dtv);
+    if (c.tpos) wv = fma(c.alpha, c.tpos[pix], wv);   // the rows I of x >= 0 (remark in Section 4.2)
+    c.w[pix] = wv;
+}
+
 // Quad: a 16 x 16 pixel tile per workgroup of 16 waves; each lane takes a
 // 2 x 2 pixel block and each wave every 16th angle.  The detector coordinates
 // of a 2 x 2 block span |q1| + |q2| <= sqrt(2) < 2 bins, so the eight taps of
@@ -810,6 +892,42 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
     return acc;
 }
 
+// Fan beam: the lane's ray summed over this wave's quarter of the steps.  Each
+// ray steps along its own axis (from the table), so lanes of one wave may read
+// the row-major or the transposed copy; each lane keeps to the steps where its
+// coordinate lies in [-2, N+1] (two zero columns each side absorb the taps of
+// the steps next to those).  The arithmetic of a tap is the direct method's.
+template <class T>
+__device__ inline T ray_sum_fan(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
+                                const RayT<T>& R, bool valid, int wave) {
+    const int N = c.N, P = c.P;
+    const T* src = R.axis == 0 ? img : imgT;
+    const int SW = N / kWaves;
+    int s_begin = wave * SW, s_end = s_begin + SW;
+    const T lo_x = T(-2), hi_x = T(N + 1);
+    if (!valid) {
+        s_end = s_begin;
+    } else if (R.k2 > T(0)) {
+        s_begin = max(s_begin, sat_int(floor((lo_x - R.k0) / R.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((hi_x - R.k0) / R.k2)) + 2);
+    } else if (R.k2 < T(0)) {
+        s_begin = max(s_begin, sat_int(floor((hi_x - R.k0) / R.k2)) - 1);
+        s_end = min(s_end, sat_int(ceil((lo_x - R.k0) / R.k2)) + 2);
+    } else if (R.k0 < lo_x || R.k0 > hi_x) {
+        s_end = s_begin;
+    }
+    const T cmax = (T)N;
+    T acc = T(0);
+    for (int s = s_begin; s < s_end; ++s) {
+        const T xi = fma((T)s, R.k2, R.k0);
+        const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
+        const T f = xi - fl;
+        const Pair<T> v = load_pair(src + (size_t)s * P + (unsigned)((int)fl + 2));
+        acc += fma(f, v.b - v.a, v.a);
+    }
+    return acc;
+}
+
 // TV dual update of one 256-pixel tile and the TV term of x+ (ITER only).
 template <class T>
 __device__ inline double tv_tile(const DevCtx<T>& c, int tile) {
@@ -881,6 +999,17 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     const int d = d0 + lane;
     const AngleT<T> A = c.ang[a];
     const int axis = c.axis[a];
+    if (VARIANT == 4) {   // fan beam: per-ray coefficients and axis
+        const bool valid = d < c.NS;
+        const RayT<T> R = c.rays[(size_t)a * c.NS + (valid ? d : c.NS - 1)];
+        red[wave * kRays + lane] = ray_sum_fan(c, img, imgT, R, valid, wave);
+        __syncthreads();
+        if (wave != 0 || stop) return;   // a stopped slice writes nothing
+        const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * R.kappa;
+        const double dterm = wave_sum(project_epilogue<T, MODE>(c, a, d, q, out));
+        if (MODE == PMODE_ITER && lane == 0) c.part_data[local] = dterm;
+        return;
+    }
     if (VARIANT == 3) {
         ray_sum_pair(c, img, imgT, A, axis, d0, lane, wave, red);
         __syncthreads();
@@ -1433,7 +1562,9 @@ inline size_t fft_lds(int N) { return 3 * (size_t)N * sizeof(T); }   // re, im, 
 template <class T, int MODE>
 hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, int projector, T* out,
                           hipStream_t st) {
-    if (projector == 1)
+    if (projector == 4)
+        hipLaunchKernelGGL((k_project<T, MODE, 4>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
+    else if (projector == 1)
         hipLaunchKernelGGL((k_project<T, MODE, 1>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
     else if (projector == 3)
         hipLaunchKernelGGL((k_project<T, MODE, 3>), dim3(blocks), dim3(256), 0, st, ctxs, map, out);
@@ -1449,7 +1580,7 @@ int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
 int cg_blocks(int N) { return (int)blocks_for((size_t)N * N); }
 
 int bp_blocks(int N, int variant) {
-    const int t = variant == 2 ? kBpTileD : kBpTile;
+    const int t = (variant == 2 || variant == 4) ? kBpTileD : kBpTile;
     return (N / t) * (N / t);
 }
 
@@ -1460,7 +1591,10 @@ hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target,
 
 template <class T>
 hipError_t launch_bp_iter(const IterLaunch<T>& L, int fin_prev, hipStream_t st) {
-    if (L.backprojector == 3)
+    if (L.backprojector == 4)
+        hipLaunchKernelGGL((k_backproject_fan<T, true>), dim3(L.bp.blocks), dim3(kBpWaves * 64), 0, st, L.ctxs,
+                           L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
+    else if (L.backprojector == 3)
         hipLaunchKernelGGL((k_backproject_quad<T, true>), dim3(L.bp.blocks), dim3(kBpQuadWaves * 64), 0, st, L.ctxs,
                            L.bp.map, (const T*)nullptr, (T*)nullptr, fin_prev);
     else if (L.backprojector == 1)
@@ -1563,7 +1697,10 @@ hipError_t launch_admm_iterations(const IterLaunch<T>& L, const DevCtx<T>& hc, i
 template <class T>
 hipError_t launch_backproject_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int variant, const T* y_padded,
                                     T* out, hipStream_t st) {
-    if (variant == 3)
+    if (variant == 4)
+        hipLaunchKernelGGL((k_backproject_fan<T, false>), dim3(bp_blocks(hc.N, 4)), dim3(kBpWaves * 64), 0, st, dc,
+                           (const Slot*)nullptr, y_padded, out, 0);
+    else if (variant == 3)
         hipLaunchKernelGGL((k_backproject_quad<T, false>), dim3(bp_blocks(hc.N, 3)), dim3(kBpQuadWaves * 64), 0, st,
                            dc, (const Slot*)nullptr, y_padded, out, 0);
     else if (variant == 1)

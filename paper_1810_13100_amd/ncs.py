@@ -35,6 +35,8 @@ DATA_QUADRATIC = 0
 DATA_POISSON = 1
 TV_ANISO = 0
 TV_ISO = 1
+BEAM_PARALLEL = 0
+BEAM_FAN = 1
 
 _STATUS_NAMES = {
     NCS_OK: "NCS_OK", NCS_NOT_CONVERGED: "NCS_NOT_CONVERGED",
@@ -61,7 +63,8 @@ class NcsError(RuntimeError):
 
 
 class _Geometry(ctypes.Structure):
-    _fields_ = [("n_side", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32)]
+    _fields_ = [("n_side", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("beam", ctypes.c_int32), ("source_radius", ctypes.c_double)]
 
 
 class _Params(ctypes.Structure):
@@ -73,6 +76,7 @@ class _Params(ctypes.Structure):
         ("projector", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
         ("dual_ramp", ctypes.c_double), ("backprojector", ctypes.c_int32), ("method", ctypes.c_int32),
         ("cg_iters", ctypes.c_int32), ("cg_precondition", ctypes.c_int32), ("positivity", ctypes.c_int32),
+        ("probes", ctypes.c_int32),
     ]
 
 
@@ -146,8 +150,13 @@ def _check(status: int, allow=(NCS_OK,)) -> int:
 @dataclass
 class Geometry:
     n_side: int
-    n_angles: int
+    n_angles: int             # parallel angles over [0, pi), or fan source positions over a full turn
     n_bins: int
+    beam: int = BEAM_PARALLEL
+    source_radius: float = 0.0  # fan: source distance from the image centre, in pixels
+
+    def _c(self) -> "_Geometry":
+        return _Geometry(self.n_side, self.n_angles, self.n_bins, self.beam, self.source_radius)
 
     @property
     def n(self) -> int:
@@ -179,6 +188,8 @@ class Params:
     cg_iters: int = 0         # ADMM-CG: CG steps per linear solve (0: 10)
     cg_precondition: int = 1  # ADMM-CG: precondition CG with alpha M^+
     positivity: int = 0       # 1: constrain x >= 0 (a third dual block t; NCS and PDHG)
+    probes: int = 0           # > 0: E^T E's multiplier from this many probes (eq. H-fan); 0: analytic
+                              # (parallel) or 16 probes (fan)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -201,11 +212,11 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._b = self._sino(b, "b") if b is not None else None
         self._bg = self._sino(bg, "bg") if bg is not None else None
-        g = _Geometry(geom.n_side, geom.n_angles, geom.n_bins)
+        g = geom._c()
         p = _Params(params.alpha, params.beta, params.gamma, params.lam, params.c_r, params.mu_dc,
                     params.data_term, params.tv_term, params.check_every, params.diverge_checks,
                     params.projector, params.graph_chunk, params.dual_ramp, params.backprojector, params.method,
-                    params.cg_iters, params.cg_precondition, params.positivity)
+                    params.cg_iters, params.cg_precondition, params.positivity, params.probes)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.ncs_setup(ctypes.byref(g), ctypes.byref(p),
@@ -403,10 +414,11 @@ class Batch:
                 raise ValueError("each b must be a contiguous tensor of n_angles*n_bins elements on the device")
         self._b = list(bs)
         self._bg = list(bgs) if bgs is not None else None
-        G = (_Geometry * n)(*[_Geometry(g.n_side, g.n_angles, g.n_bins) for g in geoms])
+        G = (_Geometry * n)(*[g._c() for g in geoms])
         P = (_Params * n)(*[_Params(p.alpha, p.beta, p.gamma, p.lam, p.c_r, p.mu_dc, p.data_term, p.tv_term,
                                     p.check_every, p.diverge_checks, p.projector, p.graph_chunk, p.dual_ramp,
-                                    p.backprojector, p.method, p.cg_iters, p.cg_precondition, p.positivity)
+                                    p.backprojector, p.method, p.cg_iters, p.cg_precondition, p.positivity,
+                                    p.probes)
                               for p in params])
         B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
         BG = None
