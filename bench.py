@@ -279,6 +279,64 @@ def pet_time_to_gap(ncs, torch, dev, fstar_iters: int) -> dict:
                            "note": "x >= 0 as a third block of A; objective without the indicator"}}
 
 
+def fan_time_to_gap(ncs, torch, dev, fstar_iters: int) -> dict:
+    """The fan-beam workload: 256^2, 90 source positions over a full turn x 368
+    equi-angular bins, source at 512 pixels from the centre, random-ellipse
+    phantom (seed 0), 1% Gaussian noise, anisotropic TV lambda 0.005.  E^T E's
+    multiplier is the 16-probe estimate of eq. H-fan.  NCS and PDHG from zero
+    to f <= f* (1 + 1e-4), f* the smallest objective of a long double-precision
+    NCS run."""
+    import ncs_inputs
+    n, nv, nb, rs, lam, alpha = 256, 90, 368, 512.0, 0.005, 1e-3
+    geom = ncs.Geometry(n, nv, nb, beam=ncs.BEAM_FAN, source_radius=rs)
+    gamma = alpha * nv * n / (2.0 * math.pi)     # 0.3 of this diverged with the probe estimate
+    p = ncs.Params(alpha, BETA_RATIO * alpha, gamma, lam)
+    op = ncs.Solver(geom, p)
+    x = torch.tensor(ncs_inputs.phantom(n, 0).ravel(), dtype=torch.float32, device=dev)
+    clean = op.forward(x)
+    eps = torch.tensor(ncs_inputs.gaussian_noise(0, geom.m), dtype=torch.float32, device=dev)
+    b = (clean + 0.01 * float(clean.max()) * eps).contiguous()
+    v = torch.randn(geom.n, generator=torch.Generator(device="cpu").manual_seed(3)).to(dev)
+    lam_e = 0.0
+    for _ in range(60):
+        w = op.adjoint(op.forward(v / torch.linalg.norm(v)))
+        lam_e = float(torch.linalg.norm(w))
+        v = w
+    op.close()
+    progress(f"fan beam f*: {fstar_iters} double-precision iterations")
+    s64 = ncs.Solver(geom, p, b=b.double(), dtype=torch.float64)
+    s64.set_init()
+    fstar = np.inf
+    done = 0
+    while done < fstar_iters:
+        k = min(5000, fstar_iters - done)
+        obj = s64.iterate(k, record=True)
+        fstar = min(fstar, float(obj.min()))
+        done += k
+    s64.close()
+    out = {"workload": "256^2 fan beam, 90 views x 368 bins, source radius 512, anisotropic TV lambda 0.005, seed 0",
+           "params": f"alpha {alpha}, beta 3 alpha, gamma = alpha N_v N / (2 pi) = {gamma:.4g}, 16 probes (eq. H-fan)",
+           "f_star": fstar, "f_star_source": f"min f over {fstar_iters} FP64 NCS iterations"}
+    gamma_p = 1.05 * alpha * (lam_e + (BETA_RATIO ** 2) * 8.0)
+    for name, pp, budget in (("ncs", p, 60000),
+                             ("pdhg", ncs.Params(alpha, BETA_RATIO * alpha, gamma_p, lam, method=ncs.METHOD_PDHG),
+                              200000)):
+        s = ncs.Solver(geom, pp, b=b)
+        s.set_init()
+        s.iterate(1)
+        s.set_init()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, f = s.solve(budget, fstar * (1.0 + GAP))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        out[name] = {"seconds": dt, "iterations": it, "reached": st == ncs.NCS_OK, "it_per_s": it / dt}
+        progress(f"fan beam {name}: {it} iterations, {dt:.3f} s, reached {st == ncs.NCS_OK}")
+    out["pdhg"]["gamma_p"] = gamma_p
+    return out
+
+
 def batch_throughput(ncs, torch, dev, iters: int) -> dict:
     """The uneven batch: 205 slices of 128^2, 205 of 256^2 and 102 of 512^2
     (angles round(1.4 side), bins side + side/64), shuffled; every slice has its
@@ -427,6 +485,7 @@ def main() -> int:
         gap = time_to_gap(ncs, torch, dev, geom, args)
 
     pet = None if args.no_gap else pet_time_to_gap(ncs, torch, dev, 20000)
+    fan = None if args.no_gap else fan_time_to_gap(ncs, torch, dev, 30000)
     batch = batch_throughput(ncs, torch, dev, args.batch_iters) if args.batch_iters > 0 else None
     cpu = cpu_baseline(args.cpu_iters) if args.cpu_iters > 0 else None
     s.close()
@@ -441,7 +500,8 @@ def main() -> int:
                    "nnz_E": info["nnz"]},
         "kernels": {"projector": info["projector"], "backprojector": info["backprojector"],
                     "chosen_by": "setup timing" if args.projector == 0 and args.backprojector == 0 else "flags"},
-        "wall_s_timed": wall, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "pet_time_to_gap": pet, "batch": batch,
+        "wall_s_timed": wall, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "pet_time_to_gap": pet, "fan_time_to_gap": fan,
+        "batch": batch,
         "cpu_baseline": cpu, "host": platform.node(),
     }
     print(json.dumps(out), flush=True)
