@@ -41,7 +41,7 @@ namespace {
 #define NCS_UNROLL_BPQ 2
 #endif
 #ifndef NCS_UNROLL_PROJ
-#define NCS_UNROLL_PROJ 4
+#define NCS_UNROLL_PROJ 8
 #endif
 #ifndef NCS_UNROLL_PAIR
 #define NCS_UNROLL_PAIR 4
