@@ -12,6 +12,12 @@ Recipe (same for every consumer):
   (2r+1)/N - 1 (rows); K ~ U{5..10} ellipses; semi-axes a, b ~ U[0.05, 0.45];
   centre at radius rho ~ U[0, 1 - max(a, b)] and angle psi ~ U[0, 2 pi);
   rotation phi ~ U[0, pi); intensity ~ U[0, 1]; overlaps add.
+* volume phantom on [-1, 1]^3 sampled at voxel centres (2c+1)/N - 1,
+  (2r+1)/N - 1, (2z+1)/N_z - 1; K ~ U{5..10} ellipsoids; in-plane semi-axes
+  a, b ~ U[0.05, 0.45], axial semi-axis c ~ U[0.1, 0.6]; centre at radius
+  rho ~ U[0, 1 - max(a, b)], angle psi ~ U[0, 2 pi), height z0 ~ U[-0.5, 0.5];
+  rotation phi ~ U[0, pi) about the z axis; intensity ~ U[0, 1]; overlaps
+  add; RNG ``default_rng([seed, 5])``.
 * phantom RNG ``numpy.random.default_rng(seed)``; Gaussian noise RNG
   ``default_rng([seed, 1])``; Poisson count RNG ``default_rng([seed, 2])``.
 * the uneven 512-slice batch: 205 slices of 128^2, 205 of 256^2, 102 of 512^2,
@@ -32,6 +38,8 @@ import numpy as np
 __all__ = [
     "ellipse_params",
     "phantom",
+    "ellipsoid_params",
+    "phantom3d",
     "gaussian_noise",
     "poisson_counts",
     "batch_sides",
@@ -76,6 +84,38 @@ def phantom(n_side: int, seed: int) -> np.ndarray:
         v = (-dx * sp + dy * cp) / b
         img += inten * (u * u + v * v <= 1.0)
     return img
+
+
+def ellipsoid_params(seed: int) -> np.ndarray:
+    """Return a (K, 8) array of ellipsoids: a, b, c, x0, y0, z0, phi, intensity."""
+    rng = np.random.default_rng([seed, 5])
+    k = int(rng.integers(5, 11))
+    a = rng.uniform(0.05, 0.45, k)
+    b = rng.uniform(0.05, 0.45, k)
+    c = rng.uniform(0.1, 0.6, k)
+    rho = rng.uniform(0.0, 1.0, k) * (1.0 - np.maximum(a, b))
+    psi = rng.uniform(0.0, 2.0 * np.pi, k)
+    z0 = rng.uniform(-0.5, 0.5, k)
+    phi = rng.uniform(0.0, np.pi, k)
+    inten = rng.uniform(0.0, 1.0, k)
+    return np.stack([a, b, c, rho * np.cos(psi), rho * np.sin(psi), z0, phi, inten], axis=1)
+
+
+def phantom3d(n_side: int, n_slices: int, seed: int) -> np.ndarray:
+    """Random-ellipsoid volume phantom, float64 array of shape
+    (n_slices, n_side, n_side): index [z, r, c], r along y, c along x."""
+    t = (2.0 * np.arange(n_side) + 1.0) / n_side - 1.0
+    tz = (2.0 * np.arange(n_slices) + 1.0) / n_slices - 1.0
+    zz, yy, xx = np.meshgrid(tz, t, t, indexing="ij")
+    vol = np.zeros((n_slices, n_side, n_side))
+    for a, b, c, x0, y0, z0, phi, inten in ellipsoid_params(seed):
+        dx, dy, dz = xx - x0, yy - y0, zz - z0
+        cp, sp = np.cos(phi), np.sin(phi)
+        u = (dx * cp + dy * sp) / a
+        v = (-dx * sp + dy * cp) / b
+        w = dz / c
+        vol += inten * (u * u + v * v + w * w <= 1.0)
+    return vol
 
 
 def gaussian_noise(seed: int, m: int) -> np.ndarray:

@@ -24,6 +24,10 @@ Near-Circulant Linear Systems: Applications to Total Variation CT and PET"):
   (eq. PDHG), ADMM in the reduced form (eq. ADMM) and in the classic form of
   the appendix.
 * ``problems``   -- assembling seeded synthetic problems.
+* ``fanbeam``    -- the fan-beam projector and the probe estimate of
+  eq. (H-fan) (Section 4.1.1).
+* ``conebeam``   -- the cone-beam projector on volumes, 3D differences, the 3D
+  multiplier and the NCS iteration on volumes (Section 4.1.1).
 
 Parity status of each function is stated in its docstring; every function is
 pinned by a ``-m "not gpu"`` test against closed forms, special cases,
