@@ -93,16 +93,25 @@ class ConeGeometry:
         return self.n_views * self.n_rows * self.n_bins
 
 
-def cone_matrix(g: ConeGeometry) -> sp.csr_matrix:
-    """The (N_v N_r N_s) x (N_z N^2) Joseph cone-beam matrix E, CSR, float64."""
+def cone_matrix(g: ConeGeometry, views=None) -> sp.csr_matrix:
+    """The (N_v N_r N_s) x (N_z N^2) Joseph cone-beam matrix E, CSR, float64.
+    With ``views`` (a list of view indices) only the rows of those views are
+    built, in the given order: the block of E for those views."""
     n, nz = g.n_side, g.n_slices
     half, half_z = (n - 1) / 2.0, (nz - 1) / 2.0
     sx, sy, ux, uy, rows = fanbeam.rays(g.fan)
     coord = np.arange(n) - half
     step = np.arange(n)
+    keep = np.ones(rows.size, dtype=bool)
+    slot = np.arange(g.n_views)
+    if views is not None:
+        views = np.asarray(views, dtype=np.int64)
+        keep = np.isin(np.arange(rows.size) // g.n_bins, views)
+        slot = np.full(g.n_views, -1)
+        slot[views] = np.arange(views.size)
     ri, ci, vi = [], [], []
     for stepping_rows in (True, False):
-        sel = np.nonzero(rows == stepping_rows)[0]       # fan rays a N_s + d
+        sel = np.nonzero((rows == stepping_rows) & keep)[0]       # fan rays a N_s + d
         if sel.size == 0:
             continue
         if stepping_rows:
@@ -116,7 +125,7 @@ def cone_matrix(g: ConeGeometry) -> sp.csr_matrix:
         c0 = np.floor(xi)
         f = xi - c0
         c0 = c0.astype(np.int64)
-        a_idx, d_idx = sel // g.n_bins, sel % g.n_bins
+        a_idx, d_idx = slot[sel // g.n_bins], sel % g.n_bins
         stp = np.broadcast_to(step[None, :], xi.shape)
         for rho, zr in enumerate(g.slopes):
             zeta = s * zr + half_z
@@ -135,8 +144,9 @@ def cone_matrix(g: ConeGeometry) -> sp.csr_matrix:
                     ri.append(ray[ok])
                     ci.append((zt * n * n + inplane)[ok])
                     vi.append((wt * scale)[ok])
+    n_rays = g.m if views is None else views.size * g.n_rows * g.n_bins
     return sp.csr_matrix((np.concatenate(vi), (np.concatenate(ri), np.concatenate(ci))),
-                         shape=(g.m, g.n))
+                         shape=(n_rays, g.n))
 
 
 def diff_3d(n: int, nz: int) -> sp.csr_matrix:

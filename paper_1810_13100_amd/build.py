@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libncs.so")
 
-SOURCES = ["ncs_kernels.hip", "ncs_api.cpp", "cnn_kernels.hip", "cnn_api.cpp"]
+SOURCES = ["ncs_kernels.hip", "ncs_api.cpp", "cnn_kernels.hip", "cnn_api.cpp", "cone.hip"]
 
 # Packed FP32 instructions are disabled for device code: the compiler must not
 # emit v_pk_{add,mul,fma}_f32 on this target.

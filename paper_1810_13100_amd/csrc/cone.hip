@@ -1,0 +1,1125 @@
+// Cone-beam NCS on volumes for gfx950 (Section 4.1.1, eq. H-fan, eq. NCS in
+// the CT form of Section 4.1): kernels and the host side of the C ABI in
+// ncs_cone.h.
+//
+// One iteration is eight launches on the handle's stream:
+//   1. k_cone_backproject<ITER>: w = alpha E^T u + beta D^T v, voxel-driven
+//      (each voxel gathers the rays whose Joseph taps include it);
+//   2-6. the 3D DFT of w as five line passes over an interleaved complex
+//      volume (x forward from the real w, y forward, z forward x (1/mu) z
+//      inverse, y inverse, x inverse with the update x+ = x - Re(.)/(n alpha),
+//      xbar = 2 x+ - x written into zero-padded copies for the projector);
+//      PDHG replaces them by one elementwise update (M = gamma I);
+//   7. k_cone_project<ITER>: E xbar ray by ray (one lane per ray), the data
+//      dual u+, E x+ = (E xbar + E x)/2 and the data term of f(x+);
+//   8. k_cone_tv: the TV dual v+ and the TV term of f(x+); then one
+//      workgroup adds the partial sums in a fixed order (k_cone_objective).
+// Reductions are in double; every sum has a fixed order, so runs repeat bit
+// for bit.
+#include "ncs_cone.h"
+#include "ncs_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr int kWaves = 4;          // projector: waves per workgroup (split the steps)
+constexpr int kBpWaves = 8;        // backprojector: waves per 8 x 8 voxel tile (split the views)
+constexpr int kFftLds = 32768;     // bytes of LDS per DFT workgroup
+constexpr int kHist = 65536;       // objective ring (doubles)
+constexpr double kPi = 3.14159265358979323846;
+
+template <class T>
+struct ConeRay {   // in-plane part of the rays (a, ., d): coordinates as linear functions of the step
+    T k0, k2;      // interpolated in-plane coordinate xi = k0 + step k2
+    T s0, s2;      // in-plane distance from the source s = s0 + step s2
+    T kxy;         // in-plane length per plane, 1/|u_y| or 1/|u_x|
+    int axis;      // 0: steps through rows, 1: through columns
+};
+
+template <class T>
+struct ConeView {
+    T sx, sy, thc, pad;
+};
+
+template <class T>
+struct ConeCtx {
+    int N, NZ, NV, NS, NR, P;   // P = N + 4: padded row
+    int W, WR;                  // half-windows of bins and detector rows in the gather
+    int n_part_data, n_part_tv;
+    T half, half_z, gamma0, inv_dgamma, inv_dzeta, cr;
+    T alpha, beta, s_tv, inv_na;   // inv_na = 1 / (n alpha)
+    double lambda;
+    const ConeRay<T>* rays;
+    const ConeView<T>* views;
+    const T* zeta;   // row slopes
+    const T* kz;     // sqrt(1 + zeta^2)
+    const T* b;
+    const T* h;      // 1 / mu
+    const T* tw_n;   // cos, -sin of 2 pi k / N
+    const T* tw_z;   // cos, -sin of 2 pi k / N_z
+    T *x, *xbar, *xbarT, *u, *p, *v, *w, *spec;
+    double *part_data, *part_tv, *obj;
+};
+
+template <class T>
+__device__ inline T clampT(T v, T lo, T hi) { return fmin(fmax(v, lo), hi); }
+template <>
+__device__ inline float clampT<float>(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Padded layout of the projector's input: (N_z + 4) slices of N rows of P
+// elements; voxel (z, r, c) at ((z + 2) N + r) P + c + 2; the pads stay zero.
+__device__ inline size_t pad_index(int z, int r, int c, int N, int P) {
+    return ((size_t)(z + 2) * N + r) * P + (c + 2);
+}
+
+// ---------------------------------------------------------------------------
+// Projector: lane = detector column d of one (view a, row rho); the 4 waves of
+// a workgroup split the N steps.  Two zero columns and two zero slices on
+// every side absorb taps off the volume, so no step needs a bounds test.
+// ---------------------------------------------------------------------------
+template <class T, bool ITER>
+__global__ __launch_bounds__(256) void k_cone_project(ConeCtx<T> c, const T* __restrict__ img,
+                                                      const T* __restrict__ imgT, T* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int d = blockIdx.x * 64 + lane;
+    const int rho = blockIdx.y, a = blockIdx.z;
+    const bool valid = d < c.NS;
+    const ConeRay<T> R = c.rays[(size_t)a * c.NS + (valid ? d : c.NS - 1)];
+    const T zr = c.zeta[rho];
+    const T* src = R.axis == 0 ? img : imgT;
+    const int N = c.N, P = c.P;
+    const size_t slice = (size_t)N * P;
+    const int SW = N / kWaves;
+    int s_begin = wave * SW, s_end = s_begin + SW;
+    // steps whose in-plane coordinate lies in [-2, N+1]; the others read pads only
+    const T lo_x = T(-2), hi_x = T(N + 1);
+    if (!valid) {
+        s_end = s_begin;
+    } else if (R.k2 > T(0)) {
+        s_begin = max(s_begin, (int)fmax(floor((lo_x - R.k0) / R.k2), T(-1e9)) - 1);
+        s_end = min(s_end, (int)fmin(ceil((hi_x - R.k0) / R.k2), T(1e9)) + 2);
+    } else if (R.k2 < T(0)) {
+        s_begin = max(s_begin, (int)fmax(floor((hi_x - R.k0) / R.k2), T(-1e9)) - 1);
+        s_end = min(s_end, (int)fmin(ceil((lo_x - R.k0) / R.k2), T(1e9)) + 2);
+    } else if (R.k0 < lo_x || R.k0 > hi_x) {
+        s_end = s_begin;
+    }
+    const T cmax = (T)N, zmax = (T)c.NZ;
+    T acc = T(0);
+#pragma unroll 4
+    for (int s = s_begin; s < s_end; ++s) {
+        const T xi = fma((T)s, R.k2, R.k0);
+        const T fl = clampT(floor(xi), T(-2), cmax);
+        const T f = xi - fl;
+        const T sd = fma((T)s, R.s2, R.s0);
+        const T ze = fma(sd, zr, c.half_z);
+        const T zl = clampT(floor(ze), T(-2), zmax);
+        const T g = ze - zl;
+        const T* p0 = src + ((size_t)((int)zl + 2) * N + s) * P + ((int)fl + 2);
+        const T a00 = p0[0], a01 = p0[1], a10 = p0[slice], a11 = p0[slice + 1];
+        const T lo = fma(f, a01 - a00, a00);
+        const T hi = fma(f, a11 - a10, a10);
+        acc += fma(g, hi - lo, lo);
+    }
+    __shared__ T red[kWaves * 64];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    const T q = ((red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane])) * (R.kxy * c.kz[rho]);
+    const size_t i = ((size_t)a * c.NR + rho) * c.NS + d;
+    if (!ITER) {
+        if (valid) out[i] = q;
+        return;
+    }
+    double dterm = 0.0;
+    if (valid) {
+        const T bb = c.b[i];
+        const T un = (c.u[i] + c.alpha * (q - bb)) / (T(1) + c.alpha);
+        const T pn = T(0.5) * (q + c.p[i]);   // E x+ = (E xbar + E x) / 2
+        c.u[i] = un;
+        c.p[i] = pn;
+        const double r = (double)pn - (double)bb;
+        dterm = 0.5 * r * r;
+    }
+    dterm = wave_sum_d(dterm);
+    if (lane == 0) c.part_data[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = dterm;
+}
+
+// ---------------------------------------------------------------------------
+// Backprojector: an 8 x 8 voxel tile of one slice per workgroup, the 8 waves
+// split the views.  For each view the voxel finds the fan bins within W of its
+// own fan angle and recomputes each ray's in-plane taps at its plane exactly as
+// the projector does; for a ray that touches it, the detector rows within WR
+// of its slope are tested the same way along z.  E^T is thus the adjoint of
+// the projector's matrix, term by term.
+// ---------------------------------------------------------------------------
+template <class T, bool ITER>
+__global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c, const T* __restrict__ ysrc,
+                                                                     T* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int N = c.N, NS = c.NS, NR = c.NR;
+    const int tiles_x = N / 8;
+    const int z = blockIdx.y;
+    const int col = (blockIdx.x % tiles_x) * 8 + (lane & 7);
+    const int row = (blockIdx.x / tiles_x) * 8 + (lane >> 3);
+    const T px = (T)col - c.half, py = (T)row - c.half;
+    const T fc = (T)col, fr = (T)row, fz = (T)z, cmax = (T)N, zmax = (T)c.NZ;
+    const T rz = fz - c.half_z;
+    const T two_pi = T(6.283185307179586476925286766559);
+    T acc = T(0);
+    for (int a = wave; a < c.NV; a += kBpWaves) {
+        const ConeView<T> V = c.views[a];
+        T gang = atan2(py - V.sy, px - V.sx) - V.thc;
+        gang -= two_pi * rint(gang / two_pi);
+        const int dc = (int)floor((gang - c.gamma0) * c.inv_dgamma + T(0.5));
+        const int d_lo = max(dc - c.W, 0), d_hi = min(dc + c.W, NS - 1);
+        const ConeRay<T>* rr = c.rays + (size_t)a * NS;
+        const T* ya = ysrc + (size_t)a * NR * NS;
+        for (int d = d_lo; d <= d_hi; ++d) {
+            const ConeRay<T> R = rr[d];
+            const T st = R.axis == 0 ? fr : fc;   // the ray's step at this voxel
+            const T tp = R.axis == 0 ? fc : fr;   // the voxel's place along the interpolated axis
+            const T xi = fma(st, R.k2, R.k0);
+            const T fl = clampT(floor(xi), T(-2), cmax);
+            const T f = xi - fl;
+            const T wxy = tp == fl ? T(1) - f : (tp == fl + T(1) ? f : T(0));
+            if (wxy == T(0)) continue;
+            const T sd = fma(st, R.s2, R.s0);
+            const int rc = (int)rint(rz / sd * c.inv_dzeta + c.cr);
+            const int r_lo = max(rc - c.WR, 0), r_hi = min(rc + c.WR, NR - 1);
+            T accd = T(0);
+            for (int rho = r_lo; rho <= r_hi; ++rho) {
+                const T ze = fma(sd, c.zeta[rho], c.half_z);
+                const T zl = clampT(floor(ze), T(-2), zmax);
+                const T g = ze - zl;
+                const T wz = fz == zl ? T(1) - g : (fz == zl + T(1) ? g : T(0));
+                accd = fma(wz * c.kz[rho], ya[(size_t)rho * NS + d], accd);
+            }
+            acc = fma(wxy * R.kxy, accd, acc);
+        }
+    }
+    __shared__ T red[kBpWaves * 64];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    T bp = red[lane];
+#pragma unroll
+    for (int k = 1; k < kBpWaves; ++k) bp += red[k * 64 + lane];
+    const size_t n2 = (size_t)N * N;
+    const size_t i = (size_t)z * n2 + (size_t)row * N + col;
+    if (!ITER) {
+        out[i] = bp;
+        return;
+    }
+    // D^T v with the differences of Section 2 (rows [1, -1], last row zero) on each axis
+    const size_t n = n2 * c.NZ;
+    const T* vx = c.v;
+    const T* vy = c.v + n;
+    const T* vz = c.v + 2 * n;
+    T dtv = T(0);
+    if (col < N - 1) dtv += vx[i];
+    if (col > 0) dtv -= vx[i - 1];
+    if (row < N - 1) dtv += vy[i];
+    if (row > 0) dtv -= vy[i - N];
+    if (z < c.NZ - 1) dtv += vz[i];
+    if (z > 0) dtv -= vz[i - n2];
+    c.w[i] = fma(c.alpha, bp, c.beta * dtv);
+}
+
+// ---------------------------------------------------------------------------
+// 3D DFT: line passes over the interleaved complex volume.  Line (A, B) of a
+// pass has its L elements at (A L + l) B + b; a workgroup holds TB lines in
+// LDS (element-major, l TB + j): adjacent b for strided passes (coalesced
+// loads across lines), adjacent rows for the x pass (B = 1, contiguous).
+// Radix-2: decimation in time from bit-reversed order for forward
+// transforms, decimation in frequency to bit-reversed order for inverse ones.
+// ---------------------------------------------------------------------------
+enum { FFT_FWD = 0, FFT_INV = 1, FFT_FWD_MUL_INV = 2 };
+enum { OUT_COMPLEX = 0, OUT_REAL = 1, OUT_UPDATE = 2 };
+
+__device__ inline int bitrev_n(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
+
+template <class T>
+__device__ void lds_dit(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, T sign) {
+    const int nb = (TB * L) >> 1;
+    for (int ls = 0; ls < logL; ++ls) {
+        const int half = 1 << ls;
+        const int tstride = L >> (ls + 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+            const int j = t % TB, bf = t / TB;
+            const int k = bf & (half - 1);
+            const int i0 = ((bf >> ls) << (ls + 1)) + k, i1 = i0 + half;
+            const T wr = tw[2 * k * tstride], wi = sign * tw[2 * k * tstride + 1];
+            const int p0 = i0 * TB + j, p1 = i1 * TB + j;
+            const T br = re[p1] * wr - im[p1] * wi, bi = re[p1] * wi + im[p1] * wr;
+            const T ar = re[p0], ai = im[p0];
+            re[p0] = ar + br;
+            im[p0] = ai + bi;
+            re[p1] = ar - br;
+            im[p1] = ai - bi;
+        }
+    }
+    __syncthreads();
+}
+
+template <class T>
+__device__ void lds_dif(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, T sign) {
+    const int nb = (TB * L) >> 1;
+    for (int ls = logL - 1; ls >= 0; --ls) {
+        const int half = 1 << ls;
+        const int tstride = L >> (ls + 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+            const int j = t % TB, bf = t / TB;
+            const int k = bf & (half - 1);
+            const int i0 = ((bf >> ls) << (ls + 1)) + k, i1 = i0 + half;
+            const T wr = tw[2 * k * tstride], wi = sign * tw[2 * k * tstride + 1];
+            const int p0 = i0 * TB + j, p1 = i1 * TB + j;
+            const T ar = re[p0], ai = im[p0], br = re[p1], bi = im[p1];
+            re[p0] = ar + br;
+            im[p0] = ai + bi;
+            const T dr = ar - br, di = ai - bi;
+            re[p1] = dr * wr - di * wi;
+            im[p1] = dr * wi + di * wr;
+        }
+    }
+    __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int out_mode, int L, int logL, int B,
+                                                  int TB, const T* __restrict__ tw, const T* __restrict__ real_in,
+                                                  T* __restrict__ zc, T* __restrict__ real_out) {
+    extern __shared__ unsigned char smem_raw[];
+    T* re = reinterpret_cast<T*>(smem_raw);
+    T* im = re + TB * L;
+    const int tot = TB * L;
+    const bool bitrev_in = mode != FFT_INV;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        int j, l;
+        if (B == 1) { l = t & (L - 1); j = t >> logL; }
+        else { j = t % TB; l = t / TB; }
+        const size_t gid = (size_t)blockIdx.x * TB + j;
+        const size_t e = (gid / B) * (size_t)L * B + gid % B + (size_t)l * B;
+        const int pos = (bitrev_in ? bitrev_n(l, logL) : l) * TB + j;
+        if (real_in) {
+            re[pos] = real_in[e];
+            im[pos] = T(0);
+        } else {
+            re[pos] = zc[2 * e];
+            im[pos] = zc[2 * e + 1];
+        }
+    }
+    if (mode == FFT_FWD || mode == FFT_FWD_MUL_INV) lds_dit(re, im, tw, L, logL, TB, T(1));
+    if (mode == FFT_FWD_MUL_INV) {
+        for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+            const int j = t % TB, l = t / TB;
+            const size_t gid = (size_t)blockIdx.x * TB + j;
+            const size_t e = (gid / B) * (size_t)L * B + gid % B + (size_t)l * B;
+            const T hv = c.h[e];
+            re[l * TB + j] *= hv;
+            im[l * TB + j] *= hv;
+        }
+    }
+    if (mode == FFT_INV || mode == FFT_FWD_MUL_INV) lds_dif(re, im, tw, L, logL, TB, T(-1));
+    const bool bitrev_out = mode != FFT_FWD;
+    const int N = c.N, P = c.P;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        int j, l;
+        if (B == 1) { l = t & (L - 1); j = t >> logL; }
+        else { j = t % TB; l = t / TB; }
+        const size_t gid = (size_t)blockIdx.x * TB + j;
+        const size_t e = (gid / B) * (size_t)L * B + gid % B + (size_t)l * B;
+        const int pos = (bitrev_out ? bitrev_n(l, logL) : l) * TB + j;
+        if (out_mode == OUT_COMPLEX) {
+            zc[2 * e] = re[pos];
+            zc[2 * e + 1] = im[pos];
+        } else if (out_mode == OUT_REAL) {
+            real_out[e] = re[pos] * c.inv_na;   // here inv_na holds 1/n
+        } else {
+            // x pass (B = 1): e = (z N + r) N + col with the row gid = z N + r
+            const int col = l, r = (int)(gid % N), z = (int)(gid / N);
+            const T xo = c.x[e];
+            const T xn = xo - re[pos] * c.inv_na;
+            const T xb = T(2) * xn - xo;
+            c.x[e] = xn;
+            c.xbar[pad_index(z, r, col, N, P)] = xb;
+            c.xbarT[pad_index(z, col, r, N, P)] = xb;
+        }
+    }
+}
+
+// x+ = x - w / (alpha gamma) (PDHG: M = gamma I), xbar into the padded copies
+template <class T>
+__global__ __launch_bounds__(256) void k_cone_update_direct(ConeCtx<T> c, T scale) {
+    const size_t n = (size_t)c.N * c.N * c.NZ;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int N = c.N, col = (int)(i % N), r = (int)((i / N) % N), z = (int)(i / ((size_t)N * N));
+    const T xo = c.x[i];
+    const T xn = xo - c.w[i] * scale;
+    const T xb = T(2) * xn - xo;
+    c.x[i] = xn;
+    c.xbar[pad_index(z, r, col, N, c.P)] = xb;
+    c.xbarT[pad_index(z, col, r, N, c.P)] = xb;
+}
+
+// a plain volume into padded copies (projector input)
+template <class T>
+__global__ __launch_bounds__(256) void k_cone_pad(ConeCtx<T> c, const T* __restrict__ img, T* __restrict__ pad,
+                                                  T* __restrict__ padT) {
+    const size_t n = (size_t)c.N * c.N * c.NZ;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int N = c.N, col = (int)(i % N), r = (int)((i / N) % N), z = (int)(i / ((size_t)N * N));
+    const T v = img[i];
+    pad[pad_index(z, r, col, N, c.P)] = v;
+    padT[pad_index(z, col, r, N, c.P)] = v;
+}
+
+// TV dual v+ = clamp(v + beta D xbar, -s, s) and the TV term |D x+|_1
+template <class T>
+__global__ __launch_bounds__(256) void k_cone_tv(ConeCtx<T> c) {
+    const int N = c.N, NZ = c.NZ, P = c.P;
+    const size_t n2 = (size_t)N * N, n = n2 * NZ;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double tv = 0.0;
+    if (i < n) {
+        const int col = (int)(i % N), r = (int)((i / N) % N), z = (int)(i / n2);
+        const size_t pi = pad_index(z, r, col, N, P);
+        const T xb = c.xbar[pi];
+        const T gx = col < N - 1 ? xb - c.xbar[pi + 1] : T(0);
+        const T gy = r < N - 1 ? xb - c.xbar[pi + P] : T(0);
+        const T gz = z < NZ - 1 ? xb - c.xbar[pi + (size_t)N * P] : T(0);
+        T* vx = c.v;
+        T* vy = c.v + n;
+        T* vz = c.v + 2 * n;
+        vx[i] = clampT(fma(c.beta, gx, vx[i]), -c.s_tv, c.s_tv);
+        vy[i] = clampT(fma(c.beta, gy, vy[i]), -c.s_tv, c.s_tv);
+        vz[i] = clampT(fma(c.beta, gz, vz[i]), -c.s_tv, c.s_tv);
+        const T xv = c.x[i];
+        if (col < N - 1) tv += fabs((double)xv - (double)c.x[i + 1]);
+        if (r < N - 1) tv += fabs((double)xv - (double)c.x[i + N]);
+        if (z < NZ - 1) tv += fabs((double)xv - (double)c.x[i + n2]);
+    }
+    __shared__ double sh[4];
+    tv = wave_sum_d(tv);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = tv;
+    __syncthreads();
+    if (threadIdx.x == 0) c.part_tv[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// f(x+) from the partial sums, in a fixed order
+template <class T>
+__global__ __launch_bounds__(256) void k_cone_objective(ConeCtx<T> c, int slot) {
+    double d = 0.0, t = 0.0;
+    for (int k = threadIdx.x; k < c.n_part_data; k += 256) d += c.part_data[k];
+    for (int k = threadIdx.x; k < c.n_part_tv; k += 256) t += c.part_tv[k];
+    __shared__ double sd[4], st[4];
+    d = wave_sum_d(d);
+    t = wave_sum_d(t);
+    if ((threadIdx.x & 63) == 0) {
+        sd[threadIdx.x >> 6] = d;
+        st[threadIdx.x >> 6] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        c.obj[slot] = ((sd[0] + sd[1]) + (sd[2] + sd[3])) + c.lambda * ((st[0] + st[1]) + (st[2] + st[3]));
+}
+
+// num += Re(conj(F v) F z), den += |F v|^2 (the probe average of eq. H-fan)
+template <class T>
+__global__ __launch_bounds__(256) void k_cone_probe_acc(const T* __restrict__ fv, const T* __restrict__ fz,
+                                                        double* __restrict__ num, double* __restrict__ den, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double vr = fv[2 * i], vi = fv[2 * i + 1], zr = fz[2 * i], zi = fz[2 * i + 1];
+    num[i] += vr * zr + vi * zi;
+    den[i] += vr * vr + vi * vi;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void set_err(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ncs::set_error_message(buf);
+}
+
+#define CONE_HIP(expr)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            set_err("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__);     \
+            return NCS_ERR_HIP;                                                                     \
+        }                                                                                           \
+    } while (0)
+
+#define CONE_TRY(expr)                   \
+    do {                                 \
+        ncs_status s_ = (expr);          \
+        if (s_ != NCS_OK) return s_;     \
+    } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int log2i(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+struct ncs_cone {
+    ncs_cone_geometry g{};
+    ncs_cone_params p{};
+    int dtype = NCS_F32;
+    size_t tsize = 4;
+    hipStream_t stream = nullptr;
+    size_t n = 0, m = 0, npad = 0;
+    int W = 0, WR = 0;
+    double dgamma = 0, gamma0 = 0, dzeta = 0, norm_e1_sq = 0, mu_dc = 0;
+    std::vector<double> mu;
+    const void* b = nullptr;
+    int iter = 0;
+    int nbx = 0;   // projector workgroups along the detector columns
+    // device memory
+    std::vector<void*> allocs;
+    void *rays = nullptr, *views = nullptr, *zeta = nullptr, *kz = nullptr, *h = nullptr;
+    void *tw_n = nullptr, *tw_z = nullptr;
+    void *x = nullptr, *xbar = nullptr, *xbarT = nullptr, *xsc = nullptr, *xscT = nullptr;
+    void *u = nullptr, *pp = nullptr, *v = nullptr, *w = nullptr, *spec = nullptr, *ysc = nullptr;
+    double *part_data = nullptr, *part_tv = nullptr, *obj = nullptr;
+};
+
+namespace {
+
+ncs_status dalloc(ncs_cone* H, void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) {
+        set_err("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return NCS_ERR_OOM;
+    }
+    H->allocs.push_back(*ptr);
+    e = hipMemsetAsync(*ptr, 0, std::max<size_t>(bytes, 256), H->stream);
+    if (e != hipSuccess) {
+        set_err("hipMemsetAsync failed: %s", hipGetErrorString(e));
+        return NCS_ERR_HIP;
+    }
+    return NCS_OK;
+}
+
+template <class T>
+ConeCtx<T> make_ctx(const ncs_cone* H) {
+    ConeCtx<T> c{};
+    const ncs_cone_geometry& g = H->g;
+    c.N = g.n_side;
+    c.NZ = g.n_slices;
+    c.NV = g.n_views;
+    c.NS = g.n_bins;
+    c.NR = g.n_rows;
+    c.P = g.n_side + 4;
+    c.W = H->W;
+    c.WR = H->WR;
+    c.n_part_data = g.n_views * g.n_rows * H->nbx;
+    c.n_part_tv = (int)((H->n + 255) / 256);
+    c.half = (T)(0.5 * (g.n_side - 1));
+    c.half_z = (T)(0.5 * (g.n_slices - 1));
+    c.gamma0 = (T)H->gamma0;
+    c.inv_dgamma = (T)(1.0 / H->dgamma);
+    c.inv_dzeta = (T)(1.0 / H->dzeta);
+    c.cr = (T)(0.5 * (g.n_rows - 1));
+    c.alpha = (T)H->p.alpha;
+    c.beta = (T)H->p.beta;
+    c.s_tv = (T)(H->p.lambda * H->p.alpha / H->p.beta);
+    c.inv_na = (T)(1.0 / ((double)H->n * H->p.alpha));
+    c.lambda = H->p.lambda;
+    c.rays = static_cast<const ConeRay<T>*>(H->rays);
+    c.views = static_cast<const ConeView<T>*>(H->views);
+    c.zeta = static_cast<const T*>(H->zeta);
+    c.kz = static_cast<const T*>(H->kz);
+    c.b = static_cast<const T*>(H->b);
+    c.h = static_cast<const T*>(H->h);
+    c.tw_n = static_cast<const T*>(H->tw_n);
+    c.tw_z = static_cast<const T*>(H->tw_z);
+    c.x = static_cast<T*>(H->x);
+    c.xbar = static_cast<T*>(H->xbar);
+    c.xbarT = static_cast<T*>(H->xbarT);
+    c.u = static_cast<T*>(H->u);
+    c.p = static_cast<T*>(H->pp);
+    c.v = static_cast<T*>(H->v);
+    c.w = static_cast<T*>(H->w);
+    c.spec = static_cast<T*>(H->spec);
+    c.part_data = H->part_data;
+    c.part_tv = H->part_tv;
+    c.obj = H->obj;
+    return c;
+}
+
+template <class T>
+hipError_t launch_pad(const ncs_cone* H, const ConeCtx<T>& c, const void* img, void* pad, void* padT) {
+    const unsigned blocks = (unsigned)((H->n + 255) / 256);
+    hipLaunchKernelGGL((k_cone_pad<T>), dim3(blocks), dim3(256), 0, H->stream, c, static_cast<const T*>(img),
+                       static_cast<T*>(pad), static_cast<T*>(padT));
+    return hipGetLastError();
+}
+
+template <class T, bool ITER>
+hipError_t launch_project(const ncs_cone* H, const ConeCtx<T>& c, const void* img, const void* imgT, void* out) {
+    hipLaunchKernelGGL((k_cone_project<T, ITER>), dim3(H->nbx, H->g.n_rows, H->g.n_views), dim3(256), 0, H->stream,
+                       c, static_cast<const T*>(img), static_cast<const T*>(imgT), static_cast<T*>(out));
+    return hipGetLastError();
+}
+
+template <class T, bool ITER>
+hipError_t launch_backproject(const ncs_cone* H, const ConeCtx<T>& c, const void* y, void* out) {
+    const int N = H->g.n_side;
+    hipLaunchKernelGGL((k_cone_backproject<T, ITER>), dim3((N / 8) * (N / 8), H->g.n_slices), dim3(kBpWaves * 64), 0,
+                       H->stream, c, static_cast<const T*>(y), static_cast<T*>(out));
+    return hipGetLastError();
+}
+
+// One line pass of the 3D DFT along the axis with L elements at stride B.
+template <class T>
+hipError_t launch_fft(const ncs_cone* H, const ConeCtx<T>& c, int mode, int out_mode, int L, int B, const void* tw,
+                      const void* real_in, void* zc, void* real_out) {
+    const size_t lines = H->n / L;
+    const int cap = (int)(kFftLds / (2 * sizeof(T)) / L);
+    int TB;
+    if (B == 1) TB = (int)std::min<size_t>(cap, lines);
+    else TB = std::min(std::min(B, cap), 64);
+    const unsigned blocks = (unsigned)(lines / TB);
+    const size_t lds = 2 * sizeof(T) * (size_t)TB * L;
+    hipLaunchKernelGGL((k_cone_fft<T>), dim3(blocks), dim3(256), lds, H->stream, c, mode, out_mode, L, log2i(L), B, TB,
+                       static_cast<const T*>(tw), static_cast<const T*>(real_in), static_cast<T*>(zc),
+                       static_cast<T*>(real_out));
+    return hipGetLastError();
+}
+
+// The forward 3D DFT of a real volume into zc.
+template <class T>
+hipError_t launch_fft3_forward(const ncs_cone* H, const ConeCtx<T>& c, const void* real_in, void* zc) {
+    const int N = H->g.n_side, NZ = H->g.n_slices;
+    hipError_t e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, 1, H->tw_n, real_in, zc, nullptr)) != hipSuccess) return e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, N, H->tw_n, nullptr, zc, nullptr)) != hipSuccess) return e;
+    return launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, NZ, N * N, H->tw_z, nullptr, zc, nullptr);
+}
+
+// w (real) -> F^-1 diag(h) F w: forward x and y passes, z forward x h inverse,
+// inverse y, inverse x into real_out (scaled by 1/n) or into the NCS update.
+template <class T>
+hipError_t launch_minv(const ncs_cone* H, const ConeCtx<T>& c, const void* w, int out_mode, void* real_out) {
+    const int N = H->g.n_side, NZ = H->g.n_slices;
+    hipError_t e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, 1, H->tw_n, w, H->spec, nullptr)) != hipSuccess) return e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, N, H->tw_n, nullptr, H->spec, nullptr)) != hipSuccess) return e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD_MUL_INV, OUT_COMPLEX, NZ, N * N, H->tw_z, nullptr, H->spec, nullptr)) != hipSuccess)
+        return e;
+    if ((e = launch_fft<T>(H, c, FFT_INV, OUT_COMPLEX, N, N, H->tw_n, nullptr, H->spec, nullptr)) != hipSuccess) return e;
+    return launch_fft<T>(H, c, FFT_INV, out_mode, N, 1, H->tw_n, nullptr, H->spec, real_out);
+}
+
+template <class T>
+hipError_t launch_update(const ncs_cone* H, const ConeCtx<T>& c) {
+    if (H->p.method == NCS_METHOD_PDHG) {
+        const unsigned blocks = (unsigned)((H->n + 255) / 256);
+        hipLaunchKernelGGL((k_cone_update_direct<T>), dim3(blocks), dim3(256), 0, H->stream, c,
+                           (T)(1.0 / (H->p.alpha * H->p.gamma)));
+        return hipGetLastError();
+    }
+    return launch_minv<T>(H, c, H->w, OUT_UPDATE, nullptr);
+}
+
+template <class T>
+hipError_t launch_tv(const ncs_cone* H, const ConeCtx<T>& c) {
+    hipLaunchKernelGGL((k_cone_tv<T>), dim3((unsigned)((H->n + 255) / 256)), dim3(256), 0, H->stream, c);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_objective(const ncs_cone* H, const ConeCtx<T>& c, int slot) {
+    hipLaunchKernelGGL((k_cone_objective<T>), dim3(1), dim3(256), 0, H->stream, c, slot);
+    return hipGetLastError();
+}
+
+template <class T>
+ncs_status run_iterations(ncs_cone* H, int k) {
+    const ConeCtx<T> c = make_ctx<T>(H);
+    for (int it = 0; it < k; ++it) {
+        CONE_HIP((launch_backproject<T, true>(H, c, H->u, nullptr)));
+        CONE_HIP(launch_update<T>(H, c));
+        CONE_HIP((launch_project<T, true>(H, c, H->xbar, H->xbarT, nullptr)));
+        CONE_HIP(launch_tv<T>(H, c));
+        CONE_HIP(launch_objective<T>(H, c, (H->iter + it) & (kHist - 1)));
+    }
+    return NCS_OK;
+}
+
+// y = E x for a plain volume x (device), through the scratch padded copies
+template <class T>
+ncs_status forward_plain(ncs_cone* H, const void* x, void* y) {
+    const ConeCtx<T> c = make_ctx<T>(H);
+    CONE_HIP(launch_pad<T>(H, c, x, H->xsc, H->xscT));
+    CONE_HIP((launch_project<T, false>(H, c, H->xsc, H->xscT, y)));
+    return NCS_OK;
+}
+
+void build_tables(ncs_cone* H, std::vector<double>& rays, std::vector<double>& views, std::vector<double>& zeta) {
+    const ncs_cone_geometry& g = H->g;
+    const int N = g.n_side, NV = g.n_views, NS = g.n_bins, NR = g.n_rows;
+    const double half = 0.5 * (N - 1), rs = g.source_radius, r_fov = N / std::sqrt(2.0);
+    H->dgamma = 2.0 * std::asin(r_fov / rs) / (NS - 1);
+    H->gamma0 = -0.5 * (NS - 1) * H->dgamma;
+    H->W = (int)std::ceil(std::asin(1.0 / (rs - r_fov)) / H->dgamma + 0.5) + 1;
+    const double z_max = 0.5 * g.n_slices / (rs - r_fov);
+    H->dzeta = 2.0 * z_max / (NR - 1);
+    H->WR = (int)std::ceil(1.0 / ((rs - r_fov - 1.0) * H->dzeta) + 0.5) + 1;
+    rays.assign(6 * (size_t)NV * NS, 0.0);
+    views.assign(4 * (size_t)NV, 0.0);
+    zeta.assign(NR, 0.0);
+    for (int r = 0; r < NR; ++r) zeta[r] = (r - 0.5 * (NR - 1)) * H->dzeta;
+    for (int a = 0; a < NV; ++a) {
+        const double beta = 2.0 * kPi * a / NV;
+        const double sx = rs * std::cos(beta), sy = rs * std::sin(beta), thc = beta + kPi;
+        views[4 * (size_t)a] = sx;
+        views[4 * (size_t)a + 1] = sy;
+        views[4 * (size_t)a + 2] = thc;
+        for (int d = 0; d < NS; ++d) {
+            const double th = thc + (d - 0.5 * (NS - 1)) * H->dgamma;
+            const double ux = std::cos(th), uy = std::sin(th);
+            double* t = &rays[6 * ((size_t)a * NS + d)];
+            if (std::fabs(uy) >= std::fabs(ux) - 1e-12) {   // rows: column coordinate and distance at row r
+                const double k2 = ux / uy;
+                t[0] = sx - (half + sy) * k2 + half;
+                t[1] = k2;
+                t[2] = (-half - sy) / uy;
+                t[3] = 1.0 / uy;
+                t[4] = 1.0 / std::fabs(uy);
+                t[5] = 0.0;
+            } else {                                         // columns: row coordinate and distance at column c
+                const double k2 = uy / ux;
+                t[0] = sy - (half + sx) * k2 + half;
+                t[1] = k2;
+                t[2] = (-half - sx) / ux;
+                t[3] = 1.0 / ux;
+                t[4] = 1.0 / std::fabs(ux);
+                t[5] = 1.0;
+            }
+        }
+    }
+}
+
+// Probe k: n values +-1, entry 64 j + b = bit b of the j-th output of
+// SplitMix64 (Steele, Lea and Flood) started from state k.
+void probe_values(uint64_t index, size_t n, std::vector<double>& v) {
+    v.assign(n, 0.0);
+    uint64_t x = index;
+    for (size_t j = 0; 64 * j < n; ++j) {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        for (int b = 0; b < 64 && 64 * j + b < n; ++b) v[64 * j + b] = ((z >> b) & 1u) ? 1.0 : -1.0;
+    }
+}
+
+template <class T>
+ncs_status upload(ncs_cone* H, void* dst, const std::vector<double>& src) {
+    std::vector<T> tmp(src.begin(), src.end());
+    CONE_HIP(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, H->stream));
+    CONE_HIP(hipStreamSynchronize(H->stream));
+    return NCS_OK;
+}
+
+template <class T>
+ncs_status setup_typed(ncs_cone* H) {
+    const ncs_cone_geometry& g = H->g;
+    const int N = g.n_side, NZ = g.n_slices;
+    H->n = (size_t)N * N * NZ;
+    H->m = (size_t)g.n_views * g.n_rows * g.n_bins;
+    H->npad = (size_t)(NZ + 4) * N * (N + 4);
+    H->nbx = (g.n_bins + 63) / 64;
+    std::vector<double> rays, views, zeta;
+    build_tables(H, rays, views, zeta);
+    // device tables
+    std::vector<ConeRay<T>> rt((size_t)g.n_views * g.n_bins);
+    for (size_t i = 0; i < rt.size(); ++i) {
+        const double* t = &rays[6 * i];
+        rt[i] = ConeRay<T>{(T)t[0], (T)t[1], (T)t[2], (T)t[3], (T)t[4], (int)t[5]};
+    }
+    std::vector<ConeView<T>> vt(g.n_views);
+    for (int a = 0; a < g.n_views; ++a)
+        vt[a] = ConeView<T>{(T)views[4 * a], (T)views[4 * a + 1], (T)views[4 * a + 2], T(0)};
+    std::vector<double> kz(zeta.size());
+    for (size_t r = 0; r < zeta.size(); ++r) kz[r] = std::sqrt(1.0 + zeta[r] * zeta[r]);
+    auto twiddles = [](int L) {
+        std::vector<double> t(L, 0.0);
+        for (int k = 0; k < L / 2; ++k) {
+            t[2 * k] = std::cos(2.0 * kPi * k / L);
+            t[2 * k + 1] = -std::sin(2.0 * kPi * k / L);
+        }
+        return t;
+    };
+    const size_t ts = sizeof(T);
+    CONE_TRY(dalloc(H, &H->rays, rt.size() * sizeof(ConeRay<T>)));
+    CONE_TRY(dalloc(H, &H->views, vt.size() * sizeof(ConeView<T>)));
+    CONE_TRY(dalloc(H, &H->zeta, zeta.size() * ts));
+    CONE_TRY(dalloc(H, &H->kz, kz.size() * ts));
+    CONE_TRY(dalloc(H, &H->tw_n, (size_t)N * ts));
+    CONE_TRY(dalloc(H, &H->tw_z, (size_t)NZ * ts));
+    CONE_TRY(dalloc(H, &H->h, H->n * ts));
+    CONE_TRY(dalloc(H, &H->x, H->n * ts));
+    CONE_TRY(dalloc(H, &H->xbar, H->npad * ts));
+    CONE_TRY(dalloc(H, &H->xbarT, H->npad * ts));
+    CONE_TRY(dalloc(H, &H->xsc, H->npad * ts));
+    CONE_TRY(dalloc(H, &H->xscT, H->npad * ts));
+    CONE_TRY(dalloc(H, &H->u, H->m * ts));
+    CONE_TRY(dalloc(H, &H->pp, H->m * ts));
+    CONE_TRY(dalloc(H, &H->ysc, H->m * ts));
+    CONE_TRY(dalloc(H, &H->v, 3 * H->n * ts));
+    CONE_TRY(dalloc(H, &H->w, H->n * ts));
+    CONE_TRY(dalloc(H, &H->spec, 2 * H->n * ts));
+    CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->part_data), (size_t)g.n_views * g.n_rows * H->nbx * sizeof(double)));
+    CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->part_tv), ((H->n + 255) / 256) * sizeof(double)));
+    CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->obj), kHist * sizeof(double)));
+    CONE_HIP(hipMemcpyAsync(H->rays, rt.data(), rt.size() * sizeof(ConeRay<T>), hipMemcpyHostToDevice, H->stream));
+    CONE_HIP(hipMemcpyAsync(H->views, vt.data(), vt.size() * sizeof(ConeView<T>), hipMemcpyHostToDevice, H->stream));
+    CONE_TRY(upload<T>(H, H->zeta, zeta));
+    CONE_TRY(upload<T>(H, H->kz, kz));
+    CONE_TRY(upload<T>(H, H->tw_n, twiddles(N)));
+    CONE_TRY(upload<T>(H, H->tw_z, twiddles(NZ)));
+    ConeCtx<T> c = make_ctx<T>(H);
+    // |E 1|^2 (the DC eigenvalue)
+    {
+        std::vector<double> ones(H->n, 1.0);
+        CONE_TRY(upload<T>(H, H->w, ones));
+        CONE_TRY(forward_plain<T>(H, H->w, H->ysc));
+        std::vector<T> y(H->m);
+        CONE_HIP(hipMemcpyAsync(y.data(), H->ysc, H->m * ts, hipMemcpyDeviceToHost, H->stream));
+        CONE_HIP(hipStreamSynchronize(H->stream));
+        double s = 0.0;
+        for (size_t i = 0; i < H->m; ++i) s += (double)y[i] * (double)y[i];
+        H->norm_e1_sq = s;
+    }
+    const ncs_cone_params& p = H->p;
+    H->mu_dc = p.mu_dc > 0.0 ? p.mu_dc : p.gamma + p.alpha * H->norm_e1_sq / (double)H->n;
+    H->mu.assign(H->n, p.gamma);
+    if (p.method == NCS_METHOD_NCS) {
+        // eq. H-fan with the 3D DFT: num and den accumulated in double on the device
+        const int probes = p.probes > 0 ? p.probes : 16;
+        double *num = nullptr, *den = nullptr;
+        void* spec2 = nullptr;
+        CONE_TRY(dalloc(H, reinterpret_cast<void**>(&num), H->n * sizeof(double)));
+        CONE_TRY(dalloc(H, reinterpret_cast<void**>(&den), H->n * sizeof(double)));
+        CONE_TRY(dalloc(H, &spec2, 2 * H->n * ts));
+        std::vector<double> pv;
+        for (int k = 0; k < probes; ++k) {
+            probe_values((uint64_t)k, H->n, pv);
+            CONE_TRY(upload<T>(H, H->w, pv));
+            CONE_TRY(forward_plain<T>(H, H->w, H->ysc));
+            CONE_HIP((launch_backproject<T, false>(H, c, H->ysc, H->x)));
+            CONE_HIP(launch_fft3_forward<T>(H, c, H->w, H->spec));
+            CONE_HIP(launch_fft3_forward<T>(H, c, H->x, spec2));
+            hipLaunchKernelGGL((k_cone_probe_acc<T>), dim3((unsigned)((H->n + 255) / 256)), dim3(256), 0, H->stream,
+                               static_cast<const T*>(H->spec), static_cast<const T*>(spec2), num, den, H->n);
+            CONE_HIP(hipGetLastError());
+        }
+        std::vector<double> hn(H->n), hd(H->n);
+        CONE_HIP(hipMemcpyAsync(hn.data(), num, H->n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+        CONE_HIP(hipMemcpyAsync(hd.data(), den, H->n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+        CONE_HIP(hipStreamSynchronize(H->stream));
+        std::vector<double> s2(N), s2z(NZ);
+        for (int k = 0; k < N; ++k) s2[k] = std::pow(std::sin(k * kPi / N), 2);
+        for (int l = 0; l < NZ; ++l) s2z[l] = std::pow(std::sin(l * kPi / NZ), 2);
+        const double ratio = p.beta * p.beta / p.alpha;
+        for (int l = 0; l < NZ; ++l)
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < N; ++k) {
+                    const size_t i = ((size_t)l * N + j) * N + k;
+                    const double he = hd[i] > 0.0 ? hn[i] / hd[i] : 0.0;
+                    H->mu[i] = p.gamma + p.alpha * he + ratio * 4.0 * (s2z[l] + s2[j] + s2[k]);
+                }
+        H->mu[0] = H->mu_dc;
+        // the temporaries are the last three allocations
+        for (int r = 0; r < 3; ++r) {
+            CONE_HIP(hipFree(H->allocs.back()));
+            H->allocs.pop_back();
+        }
+        CONE_HIP(hipMemsetAsync(H->x, 0, H->n * ts, H->stream));
+    }
+    std::vector<double> hv(H->n);
+    for (size_t i = 0; i < H->n; ++i) hv[i] = H->mu[i] != 0.0 ? 1.0 / H->mu[i] : 0.0;
+    CONE_TRY(upload<T>(H, H->h, hv));
+    CONE_HIP(hipMemsetAsync(H->w, 0, H->n * ts, H->stream));
+    CONE_HIP(hipStreamSynchronize(H->stream));
+    return NCS_OK;
+}
+
+ncs_status check_handle(const ncs_cone* H) {
+    if (!H) {
+        set_err("null handle");
+        return NCS_ERR_INVALID_ARG;
+    }
+    return NCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ncs_status ncs_cone_setup(const ncs_cone_geometry* geom, const ncs_cone_params* params, int32_t dtype,
+                          const void* b_dev, void* stream, ncs_cone** out) {
+    if (!geom || !params || !out) {
+        set_err("null argument");
+        return NCS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    const ncs_cone_geometry& g = *geom;
+    const ncs_cone_params& p = *params;
+    if (!is_pow2(g.n_side) || g.n_side < 16 || g.n_side > 512) {
+        set_err("n_side must be a power of two in [16, 512] (got %d)", g.n_side);
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!is_pow2(g.n_slices) || g.n_slices < 4 || g.n_slices > 256) {
+        set_err("n_slices must be a power of two in [4, 256] (got %d)", g.n_slices);
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (g.n_views < 1 || g.n_bins < 2 || g.n_rows < 2 || g.reserved != 0) {
+        set_err("need n_views >= 1, n_bins >= 2, n_rows >= 2 and reserved = 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!(std::isfinite(g.source_radius) && g.source_radius >= g.n_side / std::sqrt(2.0) + 4.0)) {
+        set_err("source_radius must be finite and >= n_side / sqrt(2) + 4");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (dtype != NCS_F32 && dtype != NCS_F64) {
+        set_err("dtype must be NCS_F32 or NCS_F64");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!(p.alpha > 0.0 && p.beta > 0.0 && p.gamma >= 0.0 && p.lambda >= 0.0) || !std::isfinite(p.alpha) ||
+        !std::isfinite(p.beta) || !std::isfinite(p.gamma) || !std::isfinite(p.lambda)) {
+        set_err("need alpha > 0, beta > 0, gamma >= 0, lambda >= 0 (finite)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.method != NCS_METHOD_NCS && p.method != NCS_METHOD_PDHG) {
+        set_err("cone beams run NCS_METHOD_NCS or NCS_METHOD_PDHG");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.method == NCS_METHOD_PDHG && !(p.gamma > 0.0)) {
+        set_err("PDHG needs gamma > 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (p.probes < 0 || p.probes > 4096) {
+        set_err("probes must be in [0, 4096]");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const double n = (double)g.n_side * g.n_side * g.n_slices;
+    const double m = (double)g.n_views * g.n_rows * g.n_bins;
+    if (m > 2.0e9 || n > 2.0e9) {
+        set_err("volume or sinogram too large");
+        return NCS_ERR_INVALID_ARG;
+    }
+    ncs_cone* H = new (std::nothrow) ncs_cone();
+    if (!H) {
+        set_err("out of host memory");
+        return NCS_ERR_OOM;
+    }
+    H->g = g;
+    H->p = p;
+    H->dtype = dtype;
+    H->tsize = dtype == NCS_F64 ? 8 : 4;
+    H->stream = static_cast<hipStream_t>(stream);
+    H->b = b_dev;
+    const ncs_status s = dtype == NCS_F64 ? setup_typed<double>(H) : setup_typed<float>(H);
+    if (s != NCS_OK) {
+        ncs_cone_destroy(H);
+        return s;
+    }
+    *out = H;
+    return NCS_OK;
+}
+
+void ncs_cone_destroy(ncs_cone* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : h->allocs) (void)hipFree(p);
+    delete h;
+}
+
+ncs_status ncs_cone_set_init(ncs_cone* h, const void* x0_dev) {
+    CONE_TRY(check_handle(h));
+    const size_t ts = h->tsize;
+    if (x0_dev) CONE_HIP(hipMemcpyAsync(h->x, x0_dev, h->n * ts, hipMemcpyDeviceToDevice, h->stream));
+    else CONE_HIP(hipMemsetAsync(h->x, 0, h->n * ts, h->stream));
+    CONE_HIP(hipMemsetAsync(h->u, 0, h->m * ts, h->stream));
+    CONE_HIP(hipMemsetAsync(h->v, 0, 3 * h->n * ts, h->stream));
+    // p = E x0
+    if (x0_dev) {
+        CONE_TRY(h->dtype == NCS_F64 ? forward_plain<double>(h, h->x, h->pp) : forward_plain<float>(h, h->x, h->pp));
+    } else {
+        CONE_HIP(hipMemsetAsync(h->pp, 0, h->m * ts, h->stream));
+    }
+    h->iter = 0;
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_iterate(ncs_cone* h, int32_t k, double* obj_host) {
+    CONE_TRY(check_handle(h));
+    if (k < 0 || (obj_host && k > kHist)) {
+        set_err("k must be in [0, %d] when objectives are returned", kHist);
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!h->b) {
+        set_err("this handle has no data b");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const int first = h->iter;
+    CONE_TRY(h->dtype == NCS_F64 ? run_iterations<double>(h, k) : run_iterations<float>(h, k));
+    h->iter += k;
+    if (!obj_host || k == 0) return NCS_OK;
+    CONE_HIP(hipStreamSynchronize(h->stream));
+    int done = 0;
+    while (done < k) {
+        const int slot = (first + done) & (kHist - 1);
+        const int cnt = std::min(k - done, kHist - slot);
+        CONE_HIP(hipMemcpy(obj_host + done, h->obj + slot, cnt * sizeof(double), hipMemcpyDeviceToHost));
+        done += cnt;
+    }
+    for (int i = 0; i < k; ++i)
+        if (std::isnan(obj_host[i])) {
+            set_err("the objective became NaN at iteration %d", first + i + 1);
+            return NCS_ERR_NONFINITE;
+        }
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_get_x(ncs_cone* h, void* x_out_dev) {
+    CONE_TRY(check_handle(h));
+    if (!x_out_dev) { set_err("null output"); return NCS_ERR_INVALID_ARG; }
+    CONE_HIP(hipMemcpyAsync(x_out_dev, h->x, h->n * h->tsize, hipMemcpyDeviceToDevice, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_get_u(ncs_cone* h, void* u_out_dev) {
+    CONE_TRY(check_handle(h));
+    if (!u_out_dev) { set_err("null output"); return NCS_ERR_INVALID_ARG; }
+    CONE_HIP(hipMemcpyAsync(u_out_dev, h->u, h->m * h->tsize, hipMemcpyDeviceToDevice, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_get_v(ncs_cone* h, void* v_out_dev) {
+    CONE_TRY(check_handle(h));
+    if (!v_out_dev) { set_err("null output"); return NCS_ERR_INVALID_ARG; }
+    CONE_HIP(hipMemcpyAsync(v_out_dev, h->v, 3 * h->n * h->tsize, hipMemcpyDeviceToDevice, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_forward(ncs_cone* h, const void* x_dev, void* y_dev) {
+    CONE_TRY(check_handle(h));
+    if (!x_dev || !y_dev) { set_err("null argument"); return NCS_ERR_INVALID_ARG; }
+    return h->dtype == NCS_F64 ? forward_plain<double>(h, x_dev, y_dev) : forward_plain<float>(h, x_dev, y_dev);
+}
+
+ncs_status ncs_cone_adjoint(ncs_cone* h, const void* y_dev, void* x_dev) {
+    CONE_TRY(check_handle(h));
+    if (!x_dev || !y_dev) { set_err("null argument"); return NCS_ERR_INVALID_ARG; }
+    if (h->dtype == NCS_F64) CONE_HIP((launch_backproject<double, false>(h, make_ctx<double>(h), y_dev, x_dev)));
+    else CONE_HIP((launch_backproject<float, false>(h, make_ctx<float>(h), y_dev, x_dev)));
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_apply_minv(ncs_cone* h, const void* w_dev, void* out_dev) {
+    CONE_TRY(check_handle(h));
+    if (!w_dev || !out_dev) { set_err("null argument"); return NCS_ERR_INVALID_ARG; }
+    if (h->dtype == NCS_F64) {
+        ConeCtx<double> c = make_ctx<double>(h);
+        c.inv_na = 1.0 / (double)h->n;
+        CONE_HIP(launch_minv<double>(h, c, w_dev, OUT_REAL, out_dev));
+    } else {
+        ConeCtx<float> c = make_ctx<float>(h);
+        c.inv_na = (float)(1.0 / (double)h->n);
+        CONE_HIP(launch_minv<float>(h, c, w_dev, OUT_REAL, out_dev));
+    }
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_get_eigenvalues(ncs_cone* h, double* mu_host) {
+    CONE_TRY(check_handle(h));
+    if (!mu_host) { set_err("null output"); return NCS_ERR_INVALID_ARG; }
+    std::memcpy(mu_host, h->mu.data(), h->n * sizeof(double));
+    return NCS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <class T>
+ncs_status time_phases_typed(ncs_cone* H, int iters, double* ms) {
+    const ConeCtx<T> c = make_ctx<T>(H);
+    hipEvent_t e0, e1;
+    CONE_HIP(hipEventCreate(&e0));
+    CONE_HIP(hipEventCreate(&e1));
+    for (int ph = 0; ph < 5; ++ph) {
+        auto launch = [&]() -> hipError_t {
+            switch (ph) {
+                case 0: return launch_backproject<T, true>(H, c, H->u, nullptr);
+                case 1: return launch_update<T>(H, c);
+                case 2: return launch_project<T, true>(H, c, H->xbar, H->xbarT, nullptr);
+                case 3: return launch_tv<T>(H, c);
+                default: return launch_objective<T>(H, c, 0);
+            }
+        };
+        CONE_HIP(launch());   // warm
+        CONE_HIP(hipEventRecord(e0, H->stream));
+        for (int i = 0; i < iters; ++i) CONE_HIP(launch());
+        CONE_HIP(hipEventRecord(e1, H->stream));
+        CONE_HIP(hipEventSynchronize(e1));
+        float t = 0.0f;
+        CONE_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms[ph] = (double)t / iters;
+    }
+    CONE_HIP(hipEventDestroy(e0));
+    CONE_HIP(hipEventDestroy(e1));
+    return NCS_OK;
+}
+
+}  // namespace
+
+extern "C" ncs_status ncs_cone_time_phases(ncs_cone* h, int32_t iters, double* ms_host) {
+    CONE_TRY(check_handle(h));
+    if (iters < 1 || !ms_host) {
+        set_err("need iters >= 1 and an output array of 5 doubles");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!h->b) {
+        set_err("this handle has no data b");
+        return NCS_ERR_INVALID_ARG;
+    }
+    return h->dtype == NCS_F64 ? time_phases_typed<double>(h, iters, ms_host) : time_phases_typed<float>(h, iters, ms_host);
+}

@@ -23,7 +23,8 @@ def declared_functions():
 def test_header_declares_the_api():
     names = declared_functions()
     for n in ("ncs_setup", "ncs_iterate", "ncs_solve", "ncs_destroy", "ncs_last_error", "ncs_prefilter",
-              "ncs_cnn_create", "ncs_cnn_forward", "ncs_cnn_train_step", "ncs_conv3x3_bf16"):
+              "ncs_cnn_create", "ncs_cnn_forward", "ncs_cnn_train_step", "ncs_conv3x3_bf16",
+              "ncs_cone_setup", "ncs_cone_iterate", "ncs_cone_adjoint"):
         assert n in names
 
 
@@ -33,8 +34,8 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    from paper_1810_13100_amd import cnn, ncs
-    assert sorted(ncs.EXPORTED + cnn.EXPORTED) == declared_functions()
+    from paper_1810_13100_amd import cnn, cone, ncs
+    assert sorted(ncs.EXPORTED + cnn.EXPORTED + cone.EXPORTED) == declared_functions()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libncs.so not built")
@@ -56,3 +57,9 @@ def test_null_arguments_are_rejected_without_gpu_work():
     assert b"null" in lib.ncs_last_error()
     lib.ncs_iterate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
     assert lib.ncs_iterate(None, 1, None) == -1
+    lib.ncs_cone_setup.restype = ctypes.c_int32
+    assert lib.ncs_cone_setup(None, None, 0, None, None, None) == -1
+    assert b"null" in lib.ncs_last_error()
+    lib.ncs_cone_iterate.restype = ctypes.c_int32
+    lib.ncs_cone_iterate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+    assert lib.ncs_cone_iterate(None, 1, None) == -1

@@ -106,6 +106,13 @@ def test_chord_lengths_of_the_unit_volume(E32):
     assert inside.sum() > 3000 and np.all(err[inside] <= 0.5 * kappa[inside])
 
 
+def test_view_subset_is_the_block_of_those_views(E32):
+    sub = conebeam.cone_matrix(G, views=[17, 3])
+    blk = G.n_rows * G.n_bins
+    want = sp.vstack([E32[17 * blk:18 * blk], E32[3 * blk:4 * blk]]).tocsr()
+    assert sub.shape == want.shape and abs(sub - want).max() == 0.0
+
+
 def test_quarter_turn_shifts_the_views(E32):
     vol = np.random.default_rng(2).standard_normal((16, 32, 32))
     y = (E32 @ vol.ravel()).reshape(24, 11, 48)
