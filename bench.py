@@ -41,6 +41,8 @@ HBM_PEAK_GBS = 8000.0
 COPY_MIB = 256          # plain device copy used to calibrate the HBM byte counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1810_13100_amd", "csrc", "ncs_kernels.hip")
+CONE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cone_traffic.json")
+CONE_SOURCE = os.path.join(ROOT, "paper_1810_13100_amd", "csrc", "cone.hip")
 
 
 def progress(msg: str) -> None:
@@ -67,14 +69,14 @@ def make_data(ncs, torch, dev):
     return geom, b
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, traffic_file: str = TRAFFIC_FILE, source: str = KERNEL_SOURCE):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when the kernel source changed since the counters were taken."""
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file) as f:
             rec = json.load(f)
-        with open(KERNEL_SOURCE, "rb") as f:
+        with open(source, "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
@@ -337,6 +339,130 @@ def fan_time_to_gap(ncs, torch, dev, fstar_iters: int) -> dict:
     return out
 
 
+def cone_data(cone, ncs, torch, dev, geom, seed: int = 0):
+    """b = E x_true + 1% Gaussian noise for the random-ellipsoid volume of `seed`."""
+    import ncs_inputs
+    op = cone.ConeSolver(geom, cone.ConeParams(1e-3, 3e-3, 1.0, 0.0, method=ncs.METHOD_PDHG))
+    x = torch.tensor(ncs_inputs.phantom3d(geom.n_side, geom.n_slices, seed).ravel(), dtype=torch.float32,
+                     device=dev)
+    clean = op.forward(x)
+    eps = torch.tensor(ncs_inputs.gaussian_noise(seed, geom.m), dtype=torch.float32, device=dev)
+    b = (clean + 0.01 * float(clean.max()) * eps).contiguous()
+    # lambda_max(E^T E) by power iteration (the PDHG step)
+    v = torch.randn(geom.n, generator=torch.Generator(device="cpu").manual_seed(3)).to(dev)
+    lam_e = 0.0
+    for _ in range(60):
+        w = op.adjoint(op.forward(v / torch.linalg.norm(v)))
+        lam_e = float(torch.linalg.norm(w))
+        v = w
+    torch.cuda.synchronize()
+    op.close()
+    return b, lam_e
+
+
+def cone_legs(ncs, torch, dev, steps: int, fstar_iters: int) -> dict:
+    """Cone-beam CT on volumes (ncs_cone.h).
+
+    Throughput: 256^2 x 64 voxels, 72 source positions over a full turn, a
+    cylindrical detector of 64 rows x 368 equi-angular columns, source at 512
+    voxels; `steps` timed FP32 NCS iterations and the per-phase times.
+
+    Time to gap: 128^2 x 32 voxels, 48 views x 32 rows x 184 columns, source at
+    256; NCS and PDHG (FP32) from zero to f <= f* (1 + 1e-4), f* the smallest
+    objective of long FP64 NCS and PDHG runs of the same library.  The solvers
+    are checked every 10 iterations (the time includes at most 9 iterations
+    past the target).  Both use alpha = 3e-3, beta = 3 alpha, lambda = 0.005;
+    NCS gamma = 3.2 alpha N_v N / (2 pi) (smaller factors break M >= alpha A^T A
+    with the probe-estimated multiplier), PDHG gamma_P = 1.05 alpha
+    (lambda_max(E^T E) + 9 x 12)."""
+    from paper_1810_13100_amd import cone
+    lam, alpha = 0.005, 3e-3
+    out = {}
+    geom = cone.ConeGeometry(256, 64, 72, 368, 64, 512.0)
+    gamma = 3.2 * cone.default_gamma(geom, alpha)
+    progress("cone beam 256^2 x 64: data and setup")
+    b, _ = cone_data(cone, ncs, torch, dev, geom)
+    t0 = time.perf_counter()
+    s = cone.ConeSolver(geom, cone.ConeParams(alpha, 3 * alpha, gamma, lam), b=b)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    s.set_init()
+    s.iterate(5)
+    torch.cuda.synchronize()
+    progress(f"cone beam: timing {steps} iterations")
+    t0 = time.perf_counter()
+    s.iterate(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = s.info()
+    phases = s.time_phases(10)
+    s.close()
+    dom = max(phases, key=phases.get)
+    flops = 2.0 * info["nnz"]
+    roof = {"kernel": dom, "ms_per_launch": phases[dom]}
+    if dom in ("backproject", "project_dataprox"):
+        ach = flops / (phases[dom] * 1e-3) / 1e12
+        roof.update({"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic(dom, CONE_TRAFFIC_FILE, CONE_SOURCE),
+                     "work_per_launch": f"2 x nnz(E) = {flops:.4g} flop"})
+    out["throughput"] = {
+        "workload": "256^2 x 64 cone beam, 72 views x 64 rows x 368 columns, source radius 512, "
+                    "anisotropic 3D TV lambda 0.005, random-ellipsoid volume seed 0, 1% Gaussian noise",
+        "dtype": "f32", "iterations": steps, "seconds": dt, "it_per_s": steps / dt, "ms_per_iteration": 1e3 * dt / steps,
+        "setup_s": setup_s, "nnz_E": info["nnz"], "phases_ms": phases, "roofline": roof,
+        "windows": {"bins": info["bin_window"], "rows": info["row_window"]}}
+    progress(f"cone beam: {steps / dt:.1f} it/s, phases {phases}")
+    if fstar_iters <= 0:
+        return out
+
+    geom = cone.ConeGeometry(128, 32, 48, 184, 32, 256.0)
+    gamma = 3.2 * cone.default_gamma(geom, alpha)
+    b, lam_e = cone_data(cone, ncs, torch, dev, geom)
+    gamma_p = 1.05 * alpha * (lam_e + 9.0 * 12.0)
+    p_ncs = cone.ConeParams(alpha, 3 * alpha, gamma, lam)
+    p_pdhg = cone.ConeParams(alpha, 3 * alpha, gamma_p, lam, method=ncs.METHOD_PDHG)
+    progress(f"cone beam f*: {fstar_iters} FP64 NCS and PDHG iterations at 128^2 x 32")
+    fstar = np.inf
+    for pp in (p_ncs, p_pdhg):
+        s64 = cone.ConeSolver(geom, pp, b=b.double(), dtype=torch.float64)
+        s64.set_init()
+        done = 0
+        while done < fstar_iters:
+            k = min(2000, fstar_iters - done)
+            fstar = min(fstar, float(np.nanmin(s64.iterate(k, record=True))))
+            done += k
+        s64.close()
+    gap = {"workload": "128^2 x 32 cone beam, 48 views x 32 rows x 184 columns, source radius 256, "
+                       "anisotropic 3D TV lambda 0.005, seed 0, 1% noise",
+           "params": f"alpha {alpha}, beta 3 alpha, NCS gamma 3.2 alpha N_v N / (2 pi) = {gamma:.4g}, "
+                     f"PDHG gamma_P = {gamma_p:.4g}, 16 probes (eq. H-fan, 3D DFT)",
+           "f_star": fstar, "f_star_source": f"min f over {fstar_iters} FP64 NCS and {fstar_iters} FP64 PDHG iterations"}
+    target = fstar * (1.0 + GAP)
+    for name, pp, budget in (("ncs", p_ncs, 40000), ("pdhg", p_pdhg, 80000)):
+        s = cone.ConeSolver(geom, pp, b=b)
+        s.set_init()
+        s.iterate(2)
+        s.set_init()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, hit = 0, None
+        while done < budget and hit is None:
+            obj = s.iterate(10, record=True)
+            below = np.nonzero(obj <= target)[0]
+            if below.size:
+                hit = done + int(below[0]) + 1
+            done += 10
+        dt = time.perf_counter() - t0
+        s.close()
+        gap[name] = {"seconds": dt, "iterations": hit if hit is not None else done, "reached": hit is not None,
+                     "it_per_s": done / dt}
+        progress(f"cone beam {name}: {gap[name]['iterations']} iterations, {dt:.3f} s, reached {hit is not None}")
+    gap["pdhg"]["gamma_p"] = gamma_p
+    out["time_to_gap"] = gap
+    return out
+
+
 def batch_throughput(ncs, torch, dev, iters: int) -> dict:
     """The uneven batch: 205 slices of 128^2, 205 of 256^2 and 102 of 512^2
     (angles round(1.4 side), bins side + side/64), shuffled; every slice has its
@@ -429,6 +555,8 @@ def main() -> int:
                     help="forward-projector kernel of the headline solver (0: the setup timing picks it)")
     ap.add_argument("--backprojector", type=int, default=0,
                     help="backprojector kernel of the headline solver (0: the setup timing picks it)")
+    ap.add_argument("--cone-steps", type=int, default=50, help="timed cone-beam iterations (0: skip the cone legs)")
+    ap.add_argument("--cone-fstar-iters", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -487,6 +615,9 @@ def main() -> int:
     pet = None if args.no_gap else pet_time_to_gap(ncs, torch, dev, 20000)
     fan = None if args.no_gap else fan_time_to_gap(ncs, torch, dev, 30000)
     batch = batch_throughput(ncs, torch, dev, args.batch_iters) if args.batch_iters > 0 else None
+    cone_out = None
+    if args.cone_steps > 0:
+        cone_out = cone_legs(ncs, torch, dev, args.cone_steps, 0 if args.no_gap else args.cone_fstar_iters)
     cpu = cpu_baseline(args.cpu_iters) if args.cpu_iters > 0 else None
     s.close()
     out = {
@@ -501,7 +632,7 @@ def main() -> int:
         "kernels": {"projector": info["projector"], "backprojector": info["backprojector"],
                     "chosen_by": "setup timing" if args.projector == 0 and args.backprojector == 0 else "flags"},
         "wall_s_timed": wall, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "pet_time_to_gap": pet, "fan_time_to_gap": fan,
-        "batch": batch,
+        "batch": batch, "cone": cone_out,
         "cpu_baseline": cpu, "host": platform.node(),
     }
     print(json.dumps(out), flush=True)

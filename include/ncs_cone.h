@@ -109,6 +109,18 @@ ncs_status ncs_cone_apply_minv(ncs_cone* h, const void* w_dev, void* out_dev);
 /* The eigenvalues mu of M (N_z N^2 doubles, numpy fftn order [l, j, k]). */
 ncs_status ncs_cone_get_eigenvalues(ncs_cone* h, double* mu_host);
 
+typedef struct {
+    int64_t nnz;           /* nonzeros of E (taps of nonzero weight inside the volume) */
+    double norm_e1_sq;     /* |E 1|^2 */
+    double mu_dc;          /* the DC eigenvalue used */
+    int32_t bin_window;    /* W: fan bins tested per voxel and view on each side */
+    int32_t row_window;    /* W_r: detector rows tested per touching bin on each side */
+} ncs_cone_info;
+
+/* Sizes and setup values of the handle.  nnz is counted on the host in double
+ * precision the first time it is asked for (a pass over every ray and step). */
+ncs_status ncs_cone_get_info(ncs_cone* h, ncs_cone_info* info);
+
 /* Milliseconds per launch of each phase of the iteration, from HIP events
  * around iters back-to-back launches of that phase on the handle's stream:
  * ms_host[0] backprojection (w), [1] the five DFT passes with the update,

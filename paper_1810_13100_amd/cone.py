@@ -17,7 +17,7 @@ from .ncs import METHOD_NCS, NCS_F32, NCS_F64, _check, load_library
 EXPORTED = [
     "ncs_cone_setup", "ncs_cone_set_init", "ncs_cone_iterate", "ncs_cone_get_x", "ncs_cone_get_u",
     "ncs_cone_get_v", "ncs_cone_forward", "ncs_cone_adjoint", "ncs_cone_apply_minv",
-    "ncs_cone_get_eigenvalues", "ncs_cone_time_phases", "ncs_cone_destroy",
+    "ncs_cone_get_eigenvalues", "ncs_cone_get_info", "ncs_cone_time_phases", "ncs_cone_destroy",
 ]
 PHASES = ["backproject", "dft_update", "project_dataprox", "tv_dual", "objective_reduce"]
 
@@ -32,6 +32,11 @@ class _ConeParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("mu_dc", ctypes.c_double), ("method", ctypes.c_int32),
                 ("probes", ctypes.c_int32)]
+
+
+class _ConeInfo(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int64), ("norm_e1_sq", ctypes.c_double), ("mu_dc", ctypes.c_double),
+                ("bin_window", ctypes.c_int32), ("row_window", ctypes.c_int32)]
 
 
 _bound = False
@@ -55,6 +60,7 @@ def _lib() -> ctypes.CDLL:
         "ncs_cone_adjoint": ([vp, vp, vp], i32),
         "ncs_cone_apply_minv": ([vp, vp, vp], i32),
         "ncs_cone_get_eigenvalues": ([vp, pdbl], i32),
+        "ncs_cone_get_info": ([vp, ctypes.POINTER(_ConeInfo)], i32),
         "ncs_cone_time_phases": ([vp, i32, pdbl], i32),
         "ncs_cone_destroy": ([vp], None),
     }
@@ -177,6 +183,11 @@ class ConeSolver:
         mu = np.empty(g.n, dtype=np.float64)
         _check(self.lib.ncs_cone_get_eigenvalues(self.h, mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return mu.reshape(g.n_slices, g.n_side, g.n_side)
+
+    def info(self) -> dict:
+        inf = _ConeInfo()
+        _check(self.lib.ncs_cone_get_info(self.h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _ConeInfo._fields_}
 
     def time_phases(self, iters: int = 20) -> dict:
         ms = np.zeros(5, dtype=np.float64)

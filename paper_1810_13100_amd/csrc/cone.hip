@@ -505,6 +505,7 @@ struct ncs_cone {
     const void* b = nullptr;
     int iter = 0;
     int nbx = 0;   // projector workgroups along the detector columns
+    long long nnz = -1;   // counted on first request
     // device memory
     std::vector<void*> allocs;
     void *rays = nullptr, *views = nullptr, *zeta = nullptr, *kz = nullptr, *h = nullptr;
@@ -880,6 +881,36 @@ ncs_status setup_typed(ncs_cone* H) {
     return NCS_OK;
 }
 
+// Nonzeros of E: per ray and step, the in-plane taps inside the image with
+// nonzero weight times the slice taps inside the volume with nonzero weight.
+long long count_nnz(const ncs_cone* H) {
+    std::vector<double> rays, views, zeta;
+    ncs_cone tmp = *H;
+    build_tables(&tmp, rays, views, zeta);
+    const ncs_cone_geometry& g = H->g;
+    const int N = g.n_side, NZ = g.n_slices;
+    const double hz = 0.5 * (NZ - 1);
+    long long total = 0;
+    for (size_t r = 0; r < rays.size() / 6; ++r) {
+        const double* t = &rays[6 * r];
+        for (int s = 0; s < N; ++s) {
+            const double xi = s * t[1] + t[0];
+            const double fl = std::floor(xi), f = xi - fl;
+            const int c0 = (int)fl;
+            const int cxy = (c0 >= 0 && c0 < N && f != 1.0) + (c0 + 1 >= 0 && c0 + 1 < N && f != 0.0);
+            if (cxy == 0) continue;
+            const double sd = s * t[3] + t[2];
+            for (int rho = 0; rho < g.n_rows; ++rho) {
+                const double ze = sd * zeta[rho] + hz;
+                const double zl = std::floor(ze), gz = ze - zl;
+                const int z0 = (int)zl;
+                total += cxy * ((z0 >= 0 && z0 < NZ && gz != 1.0) + (z0 + 1 >= 0 && z0 + 1 < NZ && gz != 0.0));
+            }
+        }
+    }
+    return total;
+}
+
 ncs_status check_handle(const ncs_cone* H) {
     if (!H) {
         set_err("null handle");
@@ -1065,6 +1096,18 @@ ncs_status ncs_cone_apply_minv(ncs_cone* h, const void* w_dev, void* out_dev) {
         c.inv_na = (float)(1.0 / (double)h->n);
         CONE_HIP(launch_minv<float>(h, c, w_dev, OUT_REAL, out_dev));
     }
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_get_info(ncs_cone* h, ncs_cone_info* info) {
+    CONE_TRY(check_handle(h));
+    if (!info) { set_err("null output"); return NCS_ERR_INVALID_ARG; }
+    if (h->nnz < 0) h->nnz = count_nnz(h);
+    info->nnz = h->nnz;
+    info->norm_e1_sq = h->norm_e1_sq;
+    info->mu_dc = h->mu_dc;
+    info->bin_window = h->W;
+    info->row_window = h->WR;
     return NCS_OK;
 }
 

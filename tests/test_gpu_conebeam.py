@@ -58,8 +58,10 @@ def test_cone_operators_match_oracle(key, prec):
     y = np.random.default_rng(2).standard_normal(E.shape[0])
     back = s.adjoint(torch.tensor(y, dtype=DT[prec], device=DEV)).double().cpu().numpy()
     e2 = rel_l2(back, E.T @ y)
+    nnz = s.info()["nnz"]
     s.close()
-    log(f"  forward rel-L2 {e1:.2e}, adjoint rel-L2 {e2:.2e}")
+    log(f"  forward rel-L2 {e1:.2e}, adjoint rel-L2 {e2:.2e}, nnz {nnz} (oracle {E.nnz})")
+    assert nnz == pytest.approx(E.nnz, rel=1e-4)
     assert e1 <= (1e-11 if prec == "f64" else 1e-5)
     assert e2 <= (1e-11 if prec == "f64" else 1e-4)
 
