@@ -411,7 +411,7 @@ def cone_legs(ncs, torch, dev, steps: int, fstar_iters: int) -> dict:
                     "anisotropic 3D TV lambda 0.005, random-ellipsoid volume seed 0, 1% Gaussian noise",
         "dtype": "f32", "iterations": steps, "seconds": dt, "it_per_s": steps / dt, "ms_per_iteration": 1e3 * dt / steps,
         "setup_s": setup_s, "nnz_E": info["nnz"], "phases_ms": phases, "roofline": roof,
-        "windows": {"bins": info["bin_window"], "rows": info["row_window"]}}
+        "bin_window": info["bin_window"]}
     progress(f"cone beam: {steps / dt:.1f} it/s, phases {phases}")
     if fstar_iters <= 0:
         return out

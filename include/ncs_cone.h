@@ -114,7 +114,6 @@ typedef struct {
     double norm_e1_sq;     /* |E 1|^2 */
     double mu_dc;          /* the DC eigenvalue used */
     int32_t bin_window;    /* W: fan bins tested per voxel and view on each side */
-    int32_t row_window;    /* W_r: detector rows tested per touching bin on each side */
 } ncs_cone_info;
 
 /* Sizes and setup values of the handle.  nnz is counted on the host in double

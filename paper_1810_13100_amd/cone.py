@@ -36,7 +36,7 @@ class _ConeParams(ctypes.Structure):
 
 class _ConeInfo(ctypes.Structure):
     _fields_ = [("nnz", ctypes.c_int64), ("norm_e1_sq", ctypes.c_double), ("mu_dc", ctypes.c_double),
-                ("bin_window", ctypes.c_int32), ("row_window", ctypes.c_int32)]
+                ("bin_window", ctypes.c_int32)]
 
 
 _bound = False

@@ -4,7 +4,8 @@
 //
 // One iteration is eight launches on the handle's stream:
 //   1. k_cone_backproject<ITER>: w = alpha E^T u + beta D^T v, voxel-driven
-//      (each voxel gathers the rays whose Joseph taps include it);
+//      (each run of voxels along z gathers the rays whose Joseph taps
+//      include them);
 //   2-6. the 3D DFT of w as five line passes over an interleaved complex
 //      volume (x forward from the real w, y forward, z forward x (1/mu) z
 //      inverse, y inverse, x inverse with the update x+ = x - Re(.)/(n alpha),
@@ -53,7 +54,7 @@ struct ConeView {
 template <class T>
 struct ConeCtx {
     int N, NZ, NV, NS, NR, P;   // P = N + 4: padded row
-    int W, WR;                  // half-windows of bins and detector rows in the gather
+    int W;                      // half-window of fan bins in the gather
     int n_part_data, n_part_tv;
     T half, half_z, gamma0, inv_dgamma, inv_dzeta, cr;
     T alpha, beta, s_tv, inv_na;   // inv_na = 1 / (n alpha)
@@ -162,28 +163,33 @@ __global__ __launch_bounds__(256) void k_cone_project(ConeCtx<T> c, const T* __r
 }
 
 // ---------------------------------------------------------------------------
-// Backprojector: an 8 x 8 voxel tile of one slice per workgroup, the 8 waves
-// split the views.  For each view the voxel finds the fan bins within W of its
-// own fan angle and recomputes each ray's in-plane taps at its plane exactly as
-// the projector does; for a ray that touches it, the detector rows within WR
-// of its slope are tested the same way along z.  E^T is thus the adjoint of
-// the projector's matrix, term by term.
+// Backprojector: an 8 x 8 voxel tile per workgroup, each lane a run of ZR
+// voxels along z of one (row, column); the 8 waves split the views.  For each
+// view the lane finds the fan bins within W of its own fan angle and
+// recomputes each ray's in-plane coordinate at its plane exactly as the
+// projector does (once for the run); for a ray that reaches it, the detector
+// rows whose slice coordinate falls within one slice of the run are summed
+// into the run.  Joseph's weights are the tents max(0, 1 - |coordinate -
+// voxel index|) in each interpolated axis, so E^T is the adjoint of the
+// projector's matrix, term by term.
 // ---------------------------------------------------------------------------
-template <class T, bool ITER>
+template <class T, bool ITER, int ZR>
 __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c, const T* __restrict__ ysrc,
                                                                      T* __restrict__ out) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int N = c.N, NS = c.NS, NR = c.NR;
     const int tiles_x = N / 8;
-    const int z = blockIdx.y;
-    const int col = (blockIdx.x % tiles_x) * 8 + (lane & 7);
-    const int row = (blockIdx.x / tiles_x) * 8 + (lane >> 3);
+    const int z0 = blockIdx.y * ZR;
+    const int tx = (blockIdx.x % tiles_x) * 8, ty = (blockIdx.x / tiles_x) * 8;
+    const int col = tx + (lane & 7), row = ty + (lane >> 3);
     const T px = (T)col - c.half, py = (T)row - c.half;
-    const T fc = (T)col, fr = (T)row, fz = (T)z, cmax = (T)N, zmax = (T)c.NZ;
-    const T rz = fz - c.half_z;
+    const T fc = (T)col, fr = (T)row;
+    const T zlo = T(z0 - 1) - c.half_z, zhi = T(z0 + ZR) - c.half_z;
     const T two_pi = T(6.283185307179586476925286766559);
-    T acc = T(0);
+    T acc[ZR];
+#pragma unroll
+    for (int k = 0; k < ZR; ++k) acc[k] = T(0);
     for (int a = wave; a < c.NV; a += kBpWaves) {
         const ConeView<T> V = c.views[a];
         T gang = atan2(py - V.sy, px - V.sx) - V.thc;
@@ -194,53 +200,55 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
         const T* ya = ysrc + (size_t)a * NR * NS;
         for (int d = d_lo; d <= d_hi; ++d) {
             const ConeRay<T> R = rr[d];
-            const T st = R.axis == 0 ? fr : fc;   // the ray's step at this voxel
-            const T tp = R.axis == 0 ? fc : fr;   // the voxel's place along the interpolated axis
+            const T st = R.axis == 0 ? fr : fc;   // the ray's step at this column of voxels
+            const T tp = R.axis == 0 ? fc : fr;   // the voxels' place along the interpolated axis
             const T xi = fma(st, R.k2, R.k0);
-            const T fl = clampT(floor(xi), T(-2), cmax);
-            const T f = xi - fl;
-            const T wxy = tp == fl ? T(1) - f : (tp == fl + T(1) ? f : T(0));
+            const T wxy = fmax(T(0), T(1) - fabs(xi - tp));
             if (wxy == T(0)) continue;
             const T sd = fma(st, R.s2, R.s0);
-            const int rc = (int)rint(rz / sd * c.inv_dzeta + c.cr);
-            const int r_lo = max(rc - c.WR, 0), r_hi = min(rc + c.WR, NR - 1);
-            T accd = T(0);
+            // rows with slice coordinate hz + sd (rho - cr) dz in (z0 - 1, z0 + ZR), one row of margin
+            const T inv = c.inv_dzeta / sd;
+            const int r_lo = max((int)floor(fma(zlo, inv, c.cr)) - 1, 0);
+            const int r_hi = min((int)ceil(fma(zhi, inv, c.cr)) + 1, NR - 1);
+            const T coef = wxy * R.kxy;
             for (int rho = r_lo; rho <= r_hi; ++rho) {
-                const T ze = fma(sd, c.zeta[rho], c.half_z);
-                const T zl = clampT(floor(ze), T(-2), zmax);
-                const T g = ze - zl;
-                const T wz = fz == zl ? T(1) - g : (fz == zl + T(1) ? g : T(0));
-                accd = fma(wz * c.kz[rho], ya[(size_t)rho * NS + d], accd);
+                const T ze = fma(sd, c.zeta[rho], c.half_z) - T(z0);
+                const T yv = ya[(size_t)rho * NS + d] * (coef * c.kz[rho]);
+#pragma unroll
+                for (int k = 0; k < ZR; ++k) acc[k] = fma(yv, fmax(T(0), T(1) - fabs(ze - T(k))), acc[k]);
             }
-            acc = fma(wxy * R.kxy, accd, acc);
         }
     }
-    __shared__ T red[kBpWaves * 64];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (wave != 0) return;
-    T bp = red[lane];
+    __shared__ T red[kBpWaves * ZR * 64];
 #pragma unroll
-    for (int k = 1; k < kBpWaves; ++k) bp += red[k * 64 + lane];
+    for (int k = 0; k < ZR; ++k) red[(wave * ZR + k) * 64 + lane] = acc[k];
+    __syncthreads();
     const size_t n2 = (size_t)N * N;
-    const size_t i = (size_t)z * n2 + (size_t)row * N + col;
-    if (!ITER) {
-        out[i] = bp;
-        return;
-    }
-    // D^T v with the differences of Section 2 (rows [1, -1], last row zero) on each axis
     const size_t n = n2 * c.NZ;
-    const T* vx = c.v;
-    const T* vy = c.v + n;
-    const T* vz = c.v + 2 * n;
-    T dtv = T(0);
-    if (col < N - 1) dtv += vx[i];
-    if (col > 0) dtv -= vx[i - 1];
-    if (row < N - 1) dtv += vy[i];
-    if (row > 0) dtv -= vy[i - N];
-    if (z < c.NZ - 1) dtv += vz[i];
-    if (z > 0) dtv -= vz[i - n2];
-    c.w[i] = fma(c.alpha, bp, c.beta * dtv);
+    for (int o = threadIdx.x; o < 64 * ZR; o += kBpWaves * 64) {
+        const int l = o & 63, k = o >> 6;
+        T bp = red[k * 64 + l];
+#pragma unroll
+        for (int w = 1; w < kBpWaves; ++w) bp += red[(w * ZR + k) * 64 + l];
+        const int cc = tx + (l & 7), rw = ty + (l >> 3), z = z0 + k;
+        const size_t i = (size_t)z * n2 + (size_t)rw * N + cc;
+        if (!ITER) {
+            out[i] = bp;
+            continue;
+        }
+        // D^T v with the differences of Section 2 (rows [1, -1], last row zero) on each axis
+        const T* vx = c.v;
+        const T* vy = c.v + n;
+        const T* vz = c.v + 2 * n;
+        T dtv = T(0);
+        if (cc < N - 1) dtv += vx[i];
+        if (cc > 0) dtv -= vx[i - 1];
+        if (rw < N - 1) dtv += vy[i];
+        if (rw > 0) dtv -= vy[i - N];
+        if (z < c.NZ - 1) dtv += vz[i];
+        if (z > 0) dtv -= vz[i - n2];
+        c.w[i] = fma(c.alpha, bp, c.beta * dtv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -499,7 +507,7 @@ struct ncs_cone {
     size_t tsize = 4;
     hipStream_t stream = nullptr;
     size_t n = 0, m = 0, npad = 0;
-    int W = 0, WR = 0;
+    int W = 0;
     double dgamma = 0, gamma0 = 0, dzeta = 0, norm_e1_sq = 0, mu_dc = 0;
     std::vector<double> mu;
     const void* b = nullptr;
@@ -544,7 +552,6 @@ ConeCtx<T> make_ctx(const ncs_cone* H) {
     c.NR = g.n_rows;
     c.P = g.n_side + 4;
     c.W = H->W;
-    c.WR = H->WR;
     c.n_part_data = g.n_views * g.n_rows * H->nbx;
     c.n_part_tv = (int)((H->n + 255) / 256);
     c.half = (T)(0.5 * (g.n_side - 1));
@@ -597,9 +604,13 @@ hipError_t launch_project(const ncs_cone* H, const ConeCtx<T>& c, const void* im
 
 template <class T, bool ITER>
 hipError_t launch_backproject(const ncs_cone* H, const ConeCtx<T>& c, const void* y, void* out) {
-    const int N = H->g.n_side;
-    hipLaunchKernelGGL((k_cone_backproject<T, ITER>), dim3((N / 8) * (N / 8), H->g.n_slices), dim3(kBpWaves * 64), 0,
-                       H->stream, c, static_cast<const T*>(y), static_cast<T*>(out));
+    const int N = H->g.n_side, NZ = H->g.n_slices;
+    if (NZ >= 8)
+        hipLaunchKernelGGL((k_cone_backproject<T, ITER, 8>), dim3((N / 8) * (N / 8), NZ / 8), dim3(kBpWaves * 64), 0,
+                           H->stream, c, static_cast<const T*>(y), static_cast<T*>(out));
+    else
+        hipLaunchKernelGGL((k_cone_backproject<T, ITER, 4>), dim3((N / 8) * (N / 8), NZ / 4), dim3(kBpWaves * 64), 0,
+                           H->stream, c, static_cast<const T*>(y), static_cast<T*>(out));
     return hipGetLastError();
 }
 
@@ -698,7 +709,6 @@ void build_tables(ncs_cone* H, std::vector<double>& rays, std::vector<double>& v
     H->W = (int)std::ceil(std::asin(1.0 / (rs - r_fov)) / H->dgamma + 0.5) + 1;
     const double z_max = 0.5 * g.n_slices / (rs - r_fov);
     H->dzeta = 2.0 * z_max / (NR - 1);
-    H->WR = (int)std::ceil(1.0 / ((rs - r_fov - 1.0) * H->dzeta) + 0.5) + 1;
     rays.assign(6 * (size_t)NV * NS, 0.0);
     views.assign(4 * (size_t)NV, 0.0);
     zeta.assign(NR, 0.0);
@@ -1107,7 +1117,6 @@ ncs_status ncs_cone_get_info(ncs_cone* h, ncs_cone_info* info) {
     info->norm_e1_sq = h->norm_e1_sq;
     info->mu_dc = h->mu_dc;
     info->bin_window = h->W;
-    info->row_window = h->WR;
     return NCS_OK;
 }
 
