@@ -618,11 +618,14 @@ hipError_t launch_backproject(const ncs_cone* H, const ConeCtx<T>& c, const void
 template <class T>
 hipError_t launch_fft(const ncs_cone* H, const ConeCtx<T>& c, int mode, int out_mode, int L, int B, const void* tw,
                       const void* real_in, void* zc, void* real_out) {
+    // lines per workgroup: enough workgroups to fill the chip (about 2048),
+    // at least 16 adjacent lines in strided passes (128-byte segments)
     const size_t lines = H->n / L;
     const int cap = (int)(kFftLds / (2 * sizeof(T)) / L);
-    int TB;
-    if (B == 1) TB = (int)std::min<size_t>(cap, lines);
-    else TB = std::min(std::min(B, cap), 64);
+    int TB = 1;
+    while ((size_t)TB * 2 <= lines / 2048 && TB * 2 <= cap) TB *= 2;
+    if (B > 1) TB = std::min(std::max(TB, std::min(16, cap)), B);
+    TB = (int)std::min<size_t>(TB, lines);
     const unsigned blocks = (unsigned)(lines / TB);
     const size_t lds = 2 * sizeof(T) * (size_t)TB * L;
     hipLaunchKernelGGL((k_cone_fft<T>), dim3(blocks), dim3(256), lds, H->stream, c, mode, out_mode, L, log2i(L), B, TB,
