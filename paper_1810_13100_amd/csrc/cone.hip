@@ -82,6 +82,12 @@ __device__ inline double wave_sum_d(double v) {
     return v;
 }
 
+// Two consecutive elements read with one load (element alignment only).
+template <class T>
+struct alignas(sizeof(T)) Pair2 {
+    T a, b;
+};
+
 // Padded layout of the projector's input: (N_z + 4) slices of N rows of P
 // elements; voxel (z, r, c) at ((z + 2) N + r) P + c + 2; the pads stay zero.
 __device__ inline size_t pad_index(int z, int r, int c, int N, int P) {
@@ -133,9 +139,10 @@ __global__ __launch_bounds__(256) void k_cone_project(ConeCtx<T> c, const T* __r
         const T zl = clampT(floor(ze), T(-2), zmax);
         const T g = ze - zl;
         const T* p0 = src + ((size_t)((int)zl + 2) * N + s) * P + ((int)fl + 2);
-        const T a00 = p0[0], a01 = p0[1], a10 = p0[slice], a11 = p0[slice + 1];
-        const T lo = fma(f, a01 - a00, a00);
-        const T hi = fma(f, a11 - a10, a10);
+        const Pair2<T> v0 = *reinterpret_cast<const Pair2<T>*>(p0);
+        const Pair2<T> v1 = *reinterpret_cast<const Pair2<T>*>(p0 + slice);
+        const T lo = fma(f, v0.b - v0.a, v0.a);
+        const T hi = fma(f, v1.b - v1.a, v1.a);
         acc += fma(g, hi - lo, lo);
     }
     __shared__ T red[kWaves * 64];
