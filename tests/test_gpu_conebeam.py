@@ -28,7 +28,8 @@ DEV = torch.device("cuda", 0)
 DT = {"f32": torch.float32, "f64": torch.float64}
 CONE = {"c32": (32, 16, 24, 48, 11, 60.0),                           # 32^2 x 16, 24 views x 11 rows x 48 bins
         "ragged": (16, 8, 7, 19, 4, 30.0),                           # odd views, even rows, 19 bins
-        "wide": (64, 32, 30, 96, 16, 64 / math.sqrt(2.0) + 6.0)}     # two bin blocks, slopes up to 2.7
+        "wide": (64, 32, 30, 96, 16, 64 / math.sqrt(2.0) + 6.0),     # two bin blocks, slopes up to 2.7
+        "flat": (16, 4, 9, 21, 5, 16 / math.sqrt(2.0) + 4.0)}        # N_z = 4 (runs of 4 voxels), smallest R_s
 BENCH = (256, 64, 72, 368, 64, 512.0)
 
 
@@ -45,7 +46,7 @@ def _params(**kw):
     return cone.ConeParams(0.01, 0.03, 1.0, 0.01, **kw)
 
 
-@pytest.mark.parametrize("key", ["c32", "ragged", "wide"])
+@pytest.mark.parametrize("key", ["c32", "ragged", "wide", "flat"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_cone_operators_match_oracle(key, prec):
     n, nz = CONE[key][0], CONE[key][1]
@@ -229,3 +230,25 @@ def test_cone_rejects_bad_arguments():
         s.iterate(1)
     assert e.value.status == ncs.NCS_ERR_INVALID_ARG
     s.close()
+
+
+def test_cone_flat_volume_trajectory_matches_oracle():
+    # N_z = 4: the z pass of the DFT has 4 points and the adjoint runs of 4
+    # voxels; the source sits at the smallest radius allowed
+    g = conebeam.ConeGeometry(*CONE["flat"])
+    prob = conebeam.cone_problem(g, 2, 0.01, E=cone_E("flat"))
+    a, be = 0.01, 0.03
+    gam = 3.2 * a * g.n_views * g.n_side / (2.0 * np.pi)
+    h_e = conebeam.probe_multiplier_3d(lambda v: prob.Et @ (prob.E @ v), g.shape, 16)
+    h = 1.0 / conebeam.eigenvalues3d(prob, a, be, gam, h_e)
+    x_ref, _, v_ref, obj_ref = conebeam.ncs3d(prob, a, be, h, 40)
+    s = cone.ConeSolver(geometry("flat"), cone.ConeParams(a, be, gam, prob.lam),
+                        b=torch.tensor(prob.b, device=DEV), dtype=torch.float64)
+    s.set_init()
+    obj = s.iterate(40, record=True)
+    x, v = s.x().cpu().numpy(), s.v().cpu().numpy()
+    s.close()
+    ex, ev = rel_l2(x, x_ref), rel_l2(v, v_ref)
+    ef = float(np.max(np.abs(obj - obj_ref) / np.abs(obj_ref)))
+    log(f"cone flat volume ncs f64: rel-L2 x {ex:.2e}, v {ev:.2e}, max rel f {ef:.2e}")
+    assert max(ex, ev, ef) <= 1e-10
