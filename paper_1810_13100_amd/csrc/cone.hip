@@ -34,6 +34,7 @@ namespace {
 
 constexpr int kWaves = 4;          // projector: waves per workgroup (split the steps)
 constexpr int kBpWaves = 8;        // backprojector: waves per 8 x 8 voxel tile (split the views)
+constexpr int kHits = 4;           // backprojector: rays collected per lane before their rows are summed
 constexpr int kFftLds = 32768;     // bytes of LDS per DFT workgroup
 constexpr int kHist = 65536;       // objective ring (doubles)
 constexpr double kPi = 3.14159265358979323846;
@@ -183,8 +184,17 @@ __global__ __launch_bounds__(256) void k_cone_project(ConeCtx<T> c, const T* __r
 template <class T, bool ITER, int ZR>
 __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c, const T* __restrict__ ysrc,
                                                                      T* __restrict__ out) {
+    // LDS: per wave and lane up to kHits rays that reach the lane's voxels
+    // (bin, weight, in-plane distance); after the view loop, the per-wave sums.
+    constexpr int kHitBytes = kBpWaves * kHits * 64 * (4 + 2 * (int)sizeof(T));
+    constexpr int kRedBytes = kBpWaves * ZR * 64 * (int)sizeof(T);
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kHitBytes > kRedBytes ? kHitBytes : kRedBytes];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    T* hit_c = reinterpret_cast<T*>(smem) + (size_t)wave * kHits * 64;
+    T* hit_s = reinterpret_cast<T*>(smem) + (size_t)(kBpWaves + wave) * kHits * 64;
+    int* hit_d = reinterpret_cast<int*>(reinterpret_cast<T*>(smem) + (size_t)2 * kBpWaves * kHits * 64) +
+                 wave * kHits * 64;
     const int N = c.N, NS = c.NS, NR = c.NR;
     const int tiles_x = N / 8;
     const int z0 = blockIdx.y * ZR;
@@ -202,31 +212,48 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
         T gang = atan2(py - V.sy, px - V.sx) - V.thc;
         gang -= two_pi * rint(gang / two_pi);
         const int dc = (int)floor((gang - c.gamma0) * c.inv_dgamma + T(0.5));
-        const int d_lo = max(dc - c.W, 0), d_hi = min(dc + c.W, NS - 1);
+        int d = max(dc - c.W, 0);
+        const int d_hi = min(dc + c.W, NS - 1);
         const ConeRay<T>* rr = c.rays + (size_t)a * NS;
         const T* ya = ysrc + (size_t)a * NR * NS;
-        for (int d = d_lo; d <= d_hi; ++d) {
-            const ConeRay<T> R = rr[d];
-            const T st = R.axis == 0 ? fr : fc;   // the ray's step at this column of voxels
-            const T tp = R.axis == 0 ? fc : fr;   // the voxels' place along the interpolated axis
-            const T xi = fma(st, R.k2, R.k0);
-            const T wxy = fmax(T(0), T(1) - fabs(xi - tp));
-            if (wxy == T(0)) continue;
-            const T sd = fma(st, R.s2, R.s0);
-            // rows with slice coordinate hz + sd (rho - cr) dz in (z0 - 1, z0 + ZR), one row of margin
-            const T inv = c.inv_dzeta / sd;
-            const int r_lo = max((int)floor(fma(zlo, inv, c.cr)) - 1, 0);
-            const int r_hi = min((int)ceil(fma(zhi, inv, c.cr)) + 1, NR - 1);
-            const T coef = wxy * R.kxy;
-            for (int rho = r_lo; rho <= r_hi; ++rho) {
-                const T ze = fma(sd, c.zeta[rho], c.half_z) - T(z0);
-                const T yv = ya[(size_t)rho * NS + d] * (coef * c.kz[rho]);
+        // Lanes reach different candidate bins, so each first collects the rays
+        // that reach it (up to kHits at a time) and then all lanes sum their
+        // j-th ray together: the row loop runs once per hit, not per candidate.
+        while (__any(d <= d_hi)) {
+            int nh = 0;
+            for (; d <= d_hi && nh < kHits; ++d) {
+                const ConeRay<T> R = rr[d];
+                const T st = R.axis == 0 ? fr : fc;   // the ray's step at this column of voxels
+                const T tp = R.axis == 0 ? fc : fr;   // the voxels' place along the interpolated axis
+                const T xi = fma(st, R.k2, R.k0);
+                const T wxy = fmax(T(0), T(1) - fabs(xi - tp));
+                if (wxy > T(0)) {
+                    hit_d[nh * 64 + lane] = d;
+                    hit_c[nh * 64 + lane] = wxy * R.kxy;
+                    hit_s[nh * 64 + lane] = fma(st, R.s2, R.s0);
+                    ++nh;
+                }
+            }
+            for (int j = 0; __any(j < nh); ++j) {
+                if (j >= nh) continue;
+                const int dj = hit_d[j * 64 + lane];
+                const T coef = hit_c[j * 64 + lane];
+                const T sd = hit_s[j * 64 + lane];
+                // rows with slice coordinate hz + sd (rho - cr) dz in (z0 - 1, z0 + ZR), one row of margin
+                const T inv = c.inv_dzeta / sd;
+                const int r_lo = max((int)floor(fma(zlo, inv, c.cr)) - 1, 0);
+                const int r_hi = min((int)ceil(fma(zhi, inv, c.cr)) + 1, NR - 1);
+                for (int rho = r_lo; rho <= r_hi; ++rho) {
+                    const T ze = fma(sd, c.zeta[rho], c.half_z) - T(z0);
+                    const T yv = ya[(size_t)rho * NS + dj] * (coef * c.kz[rho]);
 #pragma unroll
-                for (int k = 0; k < ZR; ++k) acc[k] = fma(yv, fmax(T(0), T(1) - fabs(ze - T(k))), acc[k]);
+                    for (int k = 0; k < ZR; ++k) acc[k] = fma(yv, fmax(T(0), T(1) - fabs(ze - T(k))), acc[k]);
+                }
             }
         }
     }
-    __shared__ T red[kBpWaves * ZR * 64];
+    __syncthreads();   // the hit lists are dead; the LDS now holds the per-wave sums
+    T* red = reinterpret_cast<T*>(smem);
 #pragma unroll
     for (int k = 0; k < ZR; ++k) red[(wave * ZR + k) * 64 + lane] = acc[k];
     __syncthreads();
