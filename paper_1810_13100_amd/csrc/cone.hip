@@ -209,11 +209,16 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
     for (int k = 0; k < ZR; ++k) acc[k] = T(0);
     for (int a = wave; a < c.NV; a += kBpWaves) {
         const ConeView<T> V = c.views[a];
-        T gang = atan2(py - V.sy, px - V.sx) - V.thc;
+        const T dx = px - V.sx, dy = py - V.sy;
+        T gang = atan2(dy, dx) - V.thc;
         gang -= two_pi * rint(gang / two_pi);
         const int dc = (int)floor((gang - c.gamma0) * c.inv_dgamma + T(0.5));
-        int d = max(dc - c.W, 0);
-        const int d_hi = min(dc + c.W, NS - 1);
+        // A ray that reaches the voxels passes within one voxel of their centre
+        // line, so its fan angle is within asin(1/dist) of theirs, dist >= 4:
+        // asin(x) <= 1.02 x for x <= 1/4, and one bin of slack for rounding.
+        const int wv = min((int)ceil(T(1.02) * c.inv_dgamma / sqrt(fma(dx, dx, dy * dy)) + T(0.5)) + 1, c.W);
+        int d = max(dc - wv, 0);
+        const int d_hi = min(dc + wv, NS - 1);
         const ConeRay<T>* rr = c.rays + (size_t)a * NS;
         const T* ya = ysrc + (size_t)a * NR * NS;
         // Lanes reach different candidate bins, so each first collects the rays
