@@ -112,55 +112,123 @@ __device__ inline float med3<float>(float v, float lo, float hi) { return __buil
 template <>
 __device__ inline double med3<double>(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
 
+// One radix-2 butterfly of each kind on values in registers: decimation in
+// time (x0, x1) <- (x0 + w x1, x0 - w x1); in frequency (x0, x1) <- (x0 + x1,
+// (x0 - x1) w).
+template <class T>
+__device__ inline void bfly_dit(T& ar, T& ai, T& br, T& bi, T wr, T wi) {
+    const T tr = wr * br - wi * bi;
+    const T tim = wr * bi + wi * br;
+    br = ar - tr;
+    bi = ai - tim;
+    ar = ar + tr;
+    ai = ai + tim;
+}
+
+template <class T>
+__device__ inline void bfly_dif(T& ar, T& ai, T& br, T& bi, T wr, T wi) {
+    const T dr = ar - br, di = ai - bi;
+    ar = ar + br;
+    ai = ai + bi;
+    br = wr * dr - wi * di;
+    bi = wr * di + wi * dr;
+}
+
 // Radix-2 decimation-in-time transform in LDS: input in bit-reversed order,
 // output in natural order.  tw[2k], tw[2k+1] = cos, -sin of 2 pi k / N.
+// Stages ls and ls + 1 close over the quads (i0, i0 + h, i0 + 2h, i0 + 3h),
+// h = 2^ls, so each thread takes a quad through both stages in registers:
+// one LDS round trip and one barrier per two stages, the same arithmetic.
 template <class T>
 __device__ void fft_dit(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
                         int tid, int nthr) {
-    for (int ls = 0; ls < logN; ++ls) {
-        const int half = 1 << ls;
+    const T sg = inverse ? T(-1) : T(1);
+    int ls = 0;
+    for (; ls + 1 < logN; ls += 2) {
+        const int h = 1 << ls;
+        __syncthreads();
+        for (int q = tid; q < (N >> 2); q += nthr) {
+            const int pos = q & (h - 1);
+            const int i0 = ((q >> ls) << (ls + 2)) + pos;
+            const int t1 = pos << (logN - ls - 1);
+            const int t2 = pos << (logN - ls - 2), t3 = (pos + h) << (logN - ls - 2);
+            T r0 = re[i0], m0 = im[i0], r1 = re[i0 + h], m1 = im[i0 + h];
+            T r2 = re[i0 + 2 * h], m2 = im[i0 + 2 * h], r3 = re[i0 + 3 * h], m3 = im[i0 + 3 * h];
+            const T w1r = tw[2 * t1], w1i = sg * tw[2 * t1 + 1];
+            bfly_dit(r0, m0, r1, m1, w1r, w1i);
+            bfly_dit(r2, m2, r3, m3, w1r, w1i);
+            bfly_dit(r0, m0, r2, m2, tw[2 * t2], sg * tw[2 * t2 + 1]);
+            bfly_dit(r1, m1, r3, m3, tw[2 * t3], sg * tw[2 * t3 + 1]);
+            re[i0] = r0;
+            im[i0] = m0;
+            re[i0 + h] = r1;
+            im[i0 + h] = m1;
+            re[i0 + 2 * h] = r2;
+            im[i0 + 2 * h] = m2;
+            re[i0 + 3 * h] = r3;
+            im[i0 + 3 * h] = m3;
+        }
+    }
+    if (ls < logN) {   // odd stage count: the last stage alone
+        const int h = 1 << ls;
         __syncthreads();
         for (int bi = tid; bi < (N >> 1); bi += nthr) {
-            const int pos = bi & (half - 1);
+            const int pos = bi & (h - 1);
             const int i0 = ((bi >> ls) << (ls + 1)) + pos;
-            const int i1 = i0 + half;
             const int ti = pos << (logN - ls - 1);
-            const T wr = tw[2 * ti];
-            const T wi = inverse ? -tw[2 * ti + 1] : tw[2 * ti + 1];
-            const T xr = re[i1], xi = im[i1];
-            const T tr = wr * xr - wi * xi;
-            const T tim = wr * xi + wi * xr;
-            const T ar = re[i0], ai = im[i0];
-            re[i0] = ar + tr;
-            im[i0] = ai + tim;
-            re[i1] = ar - tr;
-            im[i1] = ai - tim;
+            T r0 = re[i0], m0 = im[i0], r1 = re[i0 + h], m1 = im[i0 + h];
+            bfly_dit(r0, m0, r1, m1, tw[2 * ti], sg * tw[2 * ti + 1]);
+            re[i0] = r0;
+            im[i0] = m0;
+            re[i0 + h] = r1;
+            im[i0 + h] = m1;
         }
     }
     __syncthreads();
 }
 
 // Radix-2 decimation-in-frequency transform in LDS: input natural, output in
-// bit-reversed order.
+// bit-reversed order; stages ls and ls - 1 are taken together on quads.
 template <class T>
 __device__ void fft_dif(T* re, T* im, const T* __restrict__ tw, int N, int logN, bool inverse,
                         int tid, int nthr) {
-    for (int ls = logN - 1; ls >= 0; --ls) {
-        const int half = 1 << ls;
+    const T sg = inverse ? T(-1) : T(1);
+    int ls = logN - 1;
+    for (; ls >= 1; ls -= 2) {
+        const int H = 1 << ls, h = H >> 1;
+        __syncthreads();
+        for (int q = tid; q < (N >> 2); q += nthr) {
+            const int pos = q & (h - 1);
+            const int i0 = ((q >> (ls - 1)) << (ls + 1)) + pos;
+            const int t1 = pos << (logN - ls - 1), t2 = (pos + h) << (logN - ls - 1);
+            const int t3 = pos << (logN - ls);
+            T r0 = re[i0], m0 = im[i0], r1 = re[i0 + h], m1 = im[i0 + h];
+            T r2 = re[i0 + H], m2 = im[i0 + H], r3 = re[i0 + H + h], m3 = im[i0 + H + h];
+            bfly_dif(r0, m0, r2, m2, tw[2 * t1], sg * tw[2 * t1 + 1]);
+            bfly_dif(r1, m1, r3, m3, tw[2 * t2], sg * tw[2 * t2 + 1]);
+            const T w3r = tw[2 * t3], w3i = sg * tw[2 * t3 + 1];
+            bfly_dif(r0, m0, r1, m1, w3r, w3i);
+            bfly_dif(r2, m2, r3, m3, w3r, w3i);
+            re[i0] = r0;
+            im[i0] = m0;
+            re[i0 + h] = r1;
+            im[i0 + h] = m1;
+            re[i0 + H] = r2;
+            im[i0 + H] = m2;
+            re[i0 + H + h] = r3;
+            im[i0 + H + h] = m3;
+        }
+    }
+    if (ls == 0) {   // odd stage count: the last stage alone
         __syncthreads();
         for (int bi = tid; bi < (N >> 1); bi += nthr) {
-            const int pos = bi & (half - 1);
-            const int i0 = ((bi >> ls) << (ls + 1)) + pos;
-            const int i1 = i0 + half;
-            const int ti = pos << (logN - ls - 1);
-            const T wr = tw[2 * ti];
-            const T wi = inverse ? -tw[2 * ti + 1] : tw[2 * ti + 1];
-            const T ar = re[i0], ai = im[i0], br = re[i1], bim = im[i1];
-            re[i0] = ar + br;
-            im[i0] = ai + bim;
-            const T dr = ar - br, di = ai - bim;
-            re[i1] = wr * dr - wi * di;
-            im[i1] = wr * di + wi * dr;
+            const int i0 = bi << 1;
+            T r0 = re[i0], m0 = im[i0], r1 = re[i0 + 1], m1 = im[i0 + 1];
+            bfly_dif(r0, m0, r1, m1, tw[0], sg * tw[1]);
+            re[i0] = r0;
+            im[i0] = m0;
+            re[i0 + 1] = r1;
+            im[i0 + 1] = m1;
         }
     }
     __syncthreads();
