@@ -296,7 +296,8 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
 // LDS (element-major, l TB + j): adjacent b for strided passes (coalesced
 // loads across lines), adjacent rows for the x pass (B = 1, contiguous).
 // Radix-2: decimation in time from bit-reversed order for forward
-// transforms, decimation in frequency to bit-reversed order for inverse ones.
+// transforms, decimation in frequency to bit-reversed order for inverse ones,
+// two stages per LDS round trip.
 // ---------------------------------------------------------------------------
 enum { FFT_FWD = 0, FFT_INV = 1, FFT_FWD_MUL_INV = 2 };
 enum { OUT_COMPLEX = 0, OUT_REAL = 1, OUT_UPDATE = 2 };
@@ -304,24 +305,61 @@ enum { OUT_COMPLEX = 0, OUT_REAL = 1, OUT_UPDATE = 2 };
 __device__ inline int bitrev_n(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
 
 template <class T>
+__device__ inline void bfly_dit(T& ar, T& ai, T& br, T& bi, T wr, T wi) {
+    const T tr = br * wr - bi * wi, ti = br * wi + bi * wr;
+    br = ar - tr;
+    bi = ai - ti;
+    ar = ar + tr;
+    ai = ai + ti;
+}
+
+template <class T>
+__device__ inline void bfly_dif(T& ar, T& ai, T& br, T& bi, T wr, T wi) {
+    const T dr = ar - br, di = ai - bi;
+    ar = ar + br;
+    ai = ai + bi;
+    br = dr * wr - di * wi;
+    bi = dr * wi + di * wr;
+}
+
+// Stages ls and ls + 1 close over the quads (i0, i0 + h, i0 + 2h, i0 + 3h),
+// h = 2^ls: each thread takes a quad of one line through both stages in
+// registers (one LDS round trip and barrier per two stages); an odd last
+// stage runs alone.
+template <class T>
 __device__ void lds_dit(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, T sign) {
-    const int nb = (TB * L) >> 1;
-    for (int ls = 0; ls < logL; ++ls) {
-        const int half = 1 << ls;
-        const int tstride = L >> (ls + 1);
+    int ls = 0;
+    for (; ls + 1 < logL; ls += 2) {
+        const int h = 1 << ls;
         __syncthreads();
-        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+        for (int t = threadIdx.x; t < (TB * L) >> 2; t += blockDim.x) {
+            const int j = t % TB, q = t / TB;
+            const int pos = q & (h - 1);
+            const int i0 = ((q >> ls) << (ls + 2)) + pos;
+            const int t1 = pos * (L >> (ls + 1)), t2 = pos * (L >> (ls + 2)), t3 = (pos + h) * (L >> (ls + 2));
+            const int p0 = i0 * TB + j, p1 = (i0 + h) * TB + j, p2 = (i0 + 2 * h) * TB + j, p3 = (i0 + 3 * h) * TB + j;
+            T r0 = re[p0], m0 = im[p0], r1 = re[p1], m1 = im[p1], r2 = re[p2], m2 = im[p2], r3 = re[p3], m3 = im[p3];
+            const T w1r = tw[2 * t1], w1i = sign * tw[2 * t1 + 1];
+            bfly_dit(r0, m0, r1, m1, w1r, w1i);
+            bfly_dit(r2, m2, r3, m3, w1r, w1i);
+            bfly_dit(r0, m0, r2, m2, tw[2 * t2], sign * tw[2 * t2 + 1]);
+            bfly_dit(r1, m1, r3, m3, tw[2 * t3], sign * tw[2 * t3 + 1]);
+            re[p0] = r0; im[p0] = m0; re[p1] = r1; im[p1] = m1;
+            re[p2] = r2; im[p2] = m2; re[p3] = r3; im[p3] = m3;
+        }
+    }
+    if (ls < logL) {
+        const int h = 1 << ls;
+        __syncthreads();
+        for (int t = threadIdx.x; t < (TB * L) >> 1; t += blockDim.x) {
             const int j = t % TB, bf = t / TB;
-            const int k = bf & (half - 1);
-            const int i0 = ((bf >> ls) << (ls + 1)) + k, i1 = i0 + half;
-            const T wr = tw[2 * k * tstride], wi = sign * tw[2 * k * tstride + 1];
-            const int p0 = i0 * TB + j, p1 = i1 * TB + j;
-            const T br = re[p1] * wr - im[p1] * wi, bi = re[p1] * wi + im[p1] * wr;
-            const T ar = re[p0], ai = im[p0];
-            re[p0] = ar + br;
-            im[p0] = ai + bi;
-            re[p1] = ar - br;
-            im[p1] = ai - bi;
+            const int k = bf & (h - 1);
+            const int i0 = ((bf >> ls) << (ls + 1)) + k;
+            const int ti = k * (L >> (ls + 1));
+            const int p0 = i0 * TB + j, p1 = (i0 + h) * TB + j;
+            T r0 = re[p0], m0 = im[p0], r1 = re[p1], m1 = im[p1];
+            bfly_dit(r0, m0, r1, m1, tw[2 * ti], sign * tw[2 * ti + 1]);
+            re[p0] = r0; im[p0] = m0; re[p1] = r1; im[p1] = m1;
         }
     }
     __syncthreads();
@@ -329,23 +367,34 @@ __device__ void lds_dit(T* re, T* im, const T* __restrict__ tw, int L, int logL,
 
 template <class T>
 __device__ void lds_dif(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, T sign) {
-    const int nb = (TB * L) >> 1;
-    for (int ls = logL - 1; ls >= 0; --ls) {
-        const int half = 1 << ls;
-        const int tstride = L >> (ls + 1);
+    int ls = logL - 1;
+    for (; ls >= 1; ls -= 2) {   // stages ls and ls - 1 on quads (i0, i0 + h, i0 + H, i0 + H + h)
+        const int H = 1 << ls, h = H >> 1;
         __syncthreads();
-        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+        for (int t = threadIdx.x; t < (TB * L) >> 2; t += blockDim.x) {
+            const int j = t % TB, q = t / TB;
+            const int pos = q & (h - 1);
+            const int i0 = ((q >> (ls - 1)) << (ls + 1)) + pos;
+            const int t1 = pos * (L >> (ls + 1)), t2 = (pos + h) * (L >> (ls + 1)), t3 = pos * (L >> ls);
+            const int p0 = i0 * TB + j, p1 = (i0 + h) * TB + j, p2 = (i0 + H) * TB + j, p3 = (i0 + H + h) * TB + j;
+            T r0 = re[p0], m0 = im[p0], r1 = re[p1], m1 = im[p1], r2 = re[p2], m2 = im[p2], r3 = re[p3], m3 = im[p3];
+            bfly_dif(r0, m0, r2, m2, tw[2 * t1], sign * tw[2 * t1 + 1]);
+            bfly_dif(r1, m1, r3, m3, tw[2 * t2], sign * tw[2 * t2 + 1]);
+            const T w3r = tw[2 * t3], w3i = sign * tw[2 * t3 + 1];
+            bfly_dif(r0, m0, r1, m1, w3r, w3i);
+            bfly_dif(r2, m2, r3, m3, w3r, w3i);
+            re[p0] = r0; im[p0] = m0; re[p1] = r1; im[p1] = m1;
+            re[p2] = r2; im[p2] = m2; re[p3] = r3; im[p3] = m3;
+        }
+    }
+    if (ls == 0) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < (TB * L) >> 1; t += blockDim.x) {
             const int j = t % TB, bf = t / TB;
-            const int k = bf & (half - 1);
-            const int i0 = ((bf >> ls) << (ls + 1)) + k, i1 = i0 + half;
-            const T wr = tw[2 * k * tstride], wi = sign * tw[2 * k * tstride + 1];
-            const int p0 = i0 * TB + j, p1 = i1 * TB + j;
-            const T ar = re[p0], ai = im[p0], br = re[p1], bi = im[p1];
-            re[p0] = ar + br;
-            im[p0] = ai + bi;
-            const T dr = ar - br, di = ai - bi;
-            re[p1] = dr * wr - di * wi;
-            im[p1] = dr * wi + di * wr;
+            const int p0 = (2 * bf) * TB + j, p1 = (2 * bf + 1) * TB + j;
+            T r0 = re[p0], m0 = im[p0], r1 = re[p1], m1 = im[p1];
+            bfly_dif(r0, m0, r1, m1, tw[0], sign * tw[1]);
+            re[p0] = r0; im[p0] = m0; re[p1] = r1; im[p1] = m1;
         }
     }
     __syncthreads();
