@@ -252,3 +252,30 @@ def test_cone_flat_volume_trajectory_matches_oracle():
     ef = float(np.max(np.abs(obj - obj_ref) / np.abs(obj_ref)))
     log(f"cone flat volume ncs f64: rel-L2 x {ex:.2e}, v {ev:.2e}, max rel f {ef:.2e}")
     assert max(ex, ev, ef) <= 1e-10
+
+
+def test_cone_probe_count_mu_dc_and_info():
+    # 4 probes instead of 16, a given DC eigenvalue, and the setup facts
+    prob = _problem()
+    a, be, gam = 0.01, 0.03, _gamma()
+    h4 = conebeam.probe_multiplier_3d(lambda v: prob.Et @ (prob.E @ v), prob.geom.shape, 4)
+    ref = conebeam.eigenvalues3d(prob, a, be, gam, h4, mu_dc=7.5)
+    s = cone.ConeSolver(geometry("c32"), cone.ConeParams(a, be, gam, 0.01, mu_dc=7.5, probes=4), dtype=torch.float64)
+    mu = s.eigenvalues()
+    info = s.info()
+    s.close()
+    assert float(np.max(np.abs(mu - ref) / np.abs(ref))) <= 1e-9
+    assert mu[0, 0, 0] == 7.5 and info["mu_dc"] == 7.5
+    e1 = prob.E @ np.ones(prob.n)
+    assert info["norm_e1_sq"] == pytest.approx(float(e1 @ e1), rel=1e-12)
+    assert info["bin_window"] >= 1
+
+
+def test_cone_time_phases():
+    prob = _problem()
+    s = cone.ConeSolver(geometry("c32"), cone.ConeParams(0.01, 0.03, _gamma(), prob.lam),
+                        b=torch.tensor(prob.b, dtype=torch.float32, device=DEV))
+    s.set_init()
+    ph = s.time_phases(3)
+    s.close()
+    assert list(ph) == cone.PHASES and all(v > 0 and np.isfinite(v) for v in ph.values())
