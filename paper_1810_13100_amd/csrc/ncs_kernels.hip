@@ -811,8 +811,11 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
         const T xi = fma((T)s, A.k2, base);
         const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
         const T f = xi - fl;
-        const unsigned off = (unsigned)((int)fl + 2);
-        const Pair<T> v = load_pair(src + (size_t)s * P + off);
+        // the row address is the same for the whole wave (scalar registers);
+        // each lane adds a 32-bit byte offset
+        const char* row = reinterpret_cast<const char*>(src + (size_t)s * P);
+        const unsigned boff = (unsigned)((int)fl + 2) * (unsigned)sizeof(T);
+        const Pair<T> v = *reinterpret_cast<const Pair<T>*>(row + boff);
         acc += fma(f, v.b - v.a, v.a);
     }
     return acc;
