@@ -139,9 +139,11 @@ __global__ __launch_bounds__(256) void k_cone_project(ConeCtx<T> c, const T* __r
         const T ze = fma(sd, zr, c.half_z);
         const T zl = clampT(floor(ze), T(-2), zmax);
         const T g = ze - zl;
-        const T* p0 = src + ((size_t)((int)zl + 2) * N + s) * P + ((int)fl + 2);
+        // a 32-bit byte offset from the volume's base (the padded volume is far below 4 GiB)
+        const unsigned e0 = ((unsigned)((int)zl + 2) * (unsigned)N + (unsigned)s) * (unsigned)P + (unsigned)((int)fl + 2);
+        const char* p0 = reinterpret_cast<const char*>(src) + e0 * (unsigned)sizeof(T);
         const Pair2<T> v0 = *reinterpret_cast<const Pair2<T>*>(p0);
-        const Pair2<T> v1 = *reinterpret_cast<const Pair2<T>*>(p0 + slice);
+        const Pair2<T> v1 = *reinterpret_cast<const Pair2<T>*>(p0 + slice * sizeof(T));
         const T lo = fma(f, v0.b - v0.a, v0.a);
         const T hi = fma(f, v1.b - v1.a, v1.a);
         acc += fma(g, hi - lo, lo);

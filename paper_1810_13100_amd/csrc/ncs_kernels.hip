@@ -993,7 +993,8 @@ __device__ inline T ray_sum_fan(const DevCtx<T>& c, const T* __restrict__ img, c
         const T xi = fma((T)s, R.k2, R.k0);
         const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
         const T f = xi - fl;
-        const Pair<T> v = load_pair(src + (size_t)s * P + (unsigned)((int)fl + 2));
+        const char* row = reinterpret_cast<const char*>(src + (size_t)s * P);   // the same for the wave
+        const Pair<T> v = *reinterpret_cast<const Pair<T>*>(row + (unsigned)((int)fl + 2) * (unsigned)sizeof(T));
         acc += fma(f, v.b - v.a, v.a);
     }
     return acc;
