@@ -544,7 +544,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-iters", type=int, default=200, help="oracle iterations of the CPU baseline (0: skip)")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap measurement")
     ap.add_argument("--fstar-iters", type=int, default=12000)
     ap.add_argument("--gap-seeds", type=int, default=8, help="evaluation slices of the time-to-gap measurement")
