@@ -283,8 +283,11 @@ void ncs_destroy(ncs_handle* h);
 typedef struct ncs_batch ncs_batch;
 
 /* geoms, params, b_dev: arrays of n_slices (b_dev entries non-NULL); bg_dev:
- * NULL or an array of n_slices (entries may be NULL).  The projector is
- * params[0].projector, or (0) the faster variant on the largest slice. */
+ * NULL or an array of n_slices (entries may be NULL).  The slices are all
+ * parallel-beam or all fan-beam (each fan slice estimates its own multiplier
+ * from probes); methods NCS or PDHG.  For parallel beams the projector is
+ * params[0].projector, or (0) the faster variant on the largest slice; fan
+ * beams have one projector pair. */
 ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const ncs_params* params,
                            int32_t dtype, const void* const* b_dev, const void* const* bg_dev,
                            void* stream, ncs_batch** out);

@@ -1544,11 +1544,12 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
             set_err("ncs_batch_setup: slice %d: batches run NCS or PDHG, not ADMM-CG", i);
             return NCS_ERR_INVALID_ARG;
         }
-        if (geoms[i].beam != NCS_BEAM_PARALLEL) {
-            set_err("ncs_batch_setup: slice %d: batches run parallel-beam slices", i);
+        if (geoms[i].beam != geoms[0].beam) {
+            set_err("ncs_batch_setup: slice %d: the slices of a batch are all parallel-beam or all fan-beam", i);
             return NCS_ERR_INVALID_ARG;
         }
     }
+    const bool fan = geoms[0].beam == NCS_BEAM_FAN;   // fan slices have one projector pair
     ncs_batch* B = new ncs_batch();
     B->n = n_slices;
     B->dtype = dtype;
@@ -1585,7 +1586,7 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
             if ((pass == 0) != (i == largest)) continue;
             ncs_params p = params[i];
             p.graph_chunk = -1;
-            if (pass == 1) {
+            if (pass == 1 && !fan) {
                 p.projector = B->projector;
                 p.backprojector = B->backprojector;
             }
@@ -1622,7 +1623,7 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
     ncs_status s = dtype == NCS_F64 ? batch_upload_ctxs<double>(B) : batch_upload_ctxs<float>(B);
     if (s) return fail(s);
     if ((s = build_maps(B))) return fail(s);
-    const bool tune_p = params[0].projector == 0, tune_b = params[0].backprojector == 0;
+    const bool tune_p = !fan && params[0].projector == 0, tune_b = !fan && params[0].backprojector == 0;
     if (tune_p || tune_b) {
         s = dtype == NCS_F64 ? autotune_batch<double>(B, tune_p, tune_b) : autotune_batch<float>(B, tune_p, tune_b);
         if (s) return fail(s);

@@ -148,6 +148,33 @@ def test_fan_restrictions():
         ncs.Solver(ncs.Geometry(64, 60, 128, beam=ncs.BEAM_FAN, source_radius=40.0),
                    ncs.Params(0.01, 0.03, 1.0, 0.01), b=b)
     assert e.value.status == ncs.NCS_ERR_INVALID_ARG
-    with pytest.raises(ncs.NcsError) as e:
-        ncs.Batch([geometry("c64")], [ncs.Params(0.01, 0.03, 1.0, 0.01)], [b])
+    with pytest.raises(ncs.NcsError) as e:   # a batch mixing fan and parallel slices
+        p = ncs.Params(0.01, 0.03, 1.0, 0.01)
+        ncs.Batch([geometry("c64"), ncs.Geometry(64, 90, 92)], [p, p], [b, torch.zeros(90 * 92, device=DEV)])
     assert e.value.status == ncs.NCS_ERR_INVALID_ARG
+
+
+def test_fan_slices_in_a_batch():
+    # two fan geometries of different sizes share every launch; each slice
+    # follows its own oracle trajectory
+    K = 100
+    cases = []
+    for key, seed in (("c64", 0), ("ragged", 1)):
+        n, nv, nb, rs = FAN[key]
+        prob = problems.fan_problem(n, nv, nb, rs, seed, 0.01, E=fan_E(key))
+        par0 = fan_params(n, nv)
+        h_e = fanbeam.probe_multiplier(lambda v, p=prob: p.Et @ (p.E @ v), n, 16)
+        par = problems.Params(par0.alpha, par0.beta, par0.gamma, h_e=h_e)
+        cases.append((key, prob, par, solvers.ncs(prob, par, K, record=False).x))
+    geoms = [geometry(k) for k, _, _, _ in cases]
+    params = [ncs.Params(par.alpha, par.beta, par.gamma, prob.lam) for _, prob, par, _ in cases]
+    bs = [torch.tensor(prob.b, dtype=torch.float32, device=DEV) for _, prob, _, _ in cases]
+    bat = ncs.Batch(geoms, params, bs)
+    bat.set_init()
+    bat.solve(K)
+    errs = [rel_l2(bat.slice(i).x().double().cpu().numpy(), cases[i][3]) for i in range(len(cases))]
+    info = bat.slice(0).info()
+    bat.close()
+    log(f"fan batch: rel-L2 x {errs}")
+    assert info["projector"] == 4 and info["backprojector"] == 4
+    assert max(errs) <= 1e-4
