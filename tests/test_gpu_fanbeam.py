@@ -178,3 +178,31 @@ def test_fan_slices_in_a_batch():
     log(f"fan batch: rel-L2 x {errs}")
     assert info["projector"] == 4 and info["backprojector"] == 4
     assert max(errs) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fan_with_positivity_matches_oracle(prec):
+    # the constraint x >= 0 (remark in Section 4.2) on a fan-beam problem: the
+    # estimated multiplier raised by alpha, t = min(t + alpha xbar, 0)
+    K = 100
+    prob = _fan_problem()
+    par0 = fan_params(64, 60)
+    h_e = fanbeam.probe_multiplier(lambda v: prob.Et @ (prob.E @ v), 64, 16)
+    par = problems.Params(par0.alpha, par0.beta, par0.gamma, h_e=h_e)
+    ref = solvers.ncs(prob, par, K, positivity=True)
+    free = solvers.ncs(prob, par, K, record=False)
+    p = ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, positivity=1)
+    s = ncs.Solver(geometry("c64"), p, b=torch.tensor(prob.b, dtype=DT[prec], device=DEV), dtype=DT[prec])
+    s.set_init()
+    obj = s.iterate(K, record=True)
+    x = s.x().double().cpu().numpy()
+    t = s.t().double().cpu().numpy()
+    s.close()
+    assert free.x.min() < 0 and ref.t.min() < 0   # the constraint is active
+    ex, et = rel_l2(x, ref.x), rel_l2(t, ref.t)
+    ef = float(np.max(np.abs(obj - ref.obj) / np.abs(ref.obj)))
+    log(f"fan with x >= 0, {prec}: rel-L2 x {ex:.2e}, t {et:.2e}, max rel f {ef:.2e}")
+    if prec == "f64":
+        assert max(ex, et, ef) <= 1e-10
+    else:
+        assert ex <= 1e-4 and et <= 1e-4 and ef <= 1e-4
