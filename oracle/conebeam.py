@@ -44,7 +44,10 @@ a flip along z mirrors the rows); ``diff_3d`` and ``multiplier_diff_3d`` by
 the Kronecker form of D^T D and the periodic 7-point stencil;
 ``probe_multiplier_3d`` by exact recovery of a circulant operator; ``ncs3d``
 by PDHG in its stacked form (a constant multiplier) and by the common limit
-of NCS and PDHG.
+of NCS and PDHG; its positivity form by the stacked form of eq. (NCS) on
+A' = [E; (beta/alpha) D; I] with the conjugate prox of the indicator from the
+Moreau identity, and by a constrained limit that is nonnegative and lower
+than every nonnegative point of the unconstrained run.
 """
 from __future__ import annotations
 
@@ -223,19 +226,21 @@ def objective3d(prob: ConeProblem, x: np.ndarray) -> float:
 
 
 def eigenvalues3d(prob: ConeProblem, alpha: float, beta: float, gamma: float, h_e: np.ndarray,
-                  mu_dc: float | None = None) -> np.ndarray:
-    """mu = gamma + alpha h_E + (beta^2/alpha) H_D3, DC entry gamma + alpha |E 1|^2 / n."""
+                  mu_dc: float | None = None, positivity: bool = False) -> np.ndarray:
+    """mu = gamma + alpha h_E + (beta^2/alpha) H_D3, DC entry gamma + alpha |E 1|^2 / n;
+    with ``positivity`` (the rows I of x >= 0 in A, remark in Section 4.2) every
+    eigenvalue is raised by alpha."""
     g = prob.geom
     mu = gamma + alpha * h_e + (beta * beta / alpha) * multiplier_diff_3d(g.n_side, g.n_slices)
     if mu_dc is None:
         e1 = prob.E @ np.ones(prob.n)
         mu_dc = gamma + alpha * float(e1 @ e1) / prob.n
     mu[0, 0, 0] = mu_dc
-    return mu
+    return mu + alpha if positivity else mu
 
 
 def ncs3d(prob: ConeProblem, alpha: float, beta: float, h: np.ndarray, iters: int, x0=None,
-          record: bool = True):
+          record: bool = True, positivity: bool = False, with_t: bool = False):
     """The CT form of eq. (NCS) on a volume (Section 4.1):
 
         x+ = x - (1/alpha) F^-1 diag(h) F (alpha E^T u + beta D^T v)
@@ -243,20 +248,30 @@ def ncs3d(prob: ConeProblem, alpha: float, beta: float, h: np.ndarray, iters: in
         v+ = Pi_[-s,s](v + beta D(2x+ - x)),  s = lambda alpha / beta
 
     with F the 3D DFT and h = 1/mu (a constant h = 1/gamma_P gives eq. PDHG).
-    Returns x, u, v and the objective after each iteration."""
+    With ``positivity`` the constraint x >= 0 is a third block of A (rows I,
+    the remark in Section 4.2) with its own dual t: alpha t joins the
+    backprojection and t+ = min(t + alpha (2x+ - x), 0) (h must then invert
+    the eigenvalues raised by alpha, ``eigenvalues3d(..., positivity=True)``).
+    Returns x, u, v and the objective after each iteration (and t with
+    ``with_t``)."""
     shape = prob.geom.shape
     s = prob.lam * alpha / beta
     x = np.zeros(prob.n) if x0 is None else np.array(x0, dtype=np.float64)
     u = np.zeros(prob.m)
     v = np.zeros(3 * prob.n)
+    t = np.zeros(prob.n)
     obj = np.full(iters, np.nan)
     for k in range(iters):
         w = alpha * (prob.Et @ u) + beta * (prob.Dt @ v)
+        if positivity:
+            w = w + alpha * t
         x_new = x - np.real(np.fft.ifftn(h * np.fft.fftn(w.reshape(shape)))).ravel() / alpha
         xbar = 2.0 * x_new - x
         u = prox.conj_quadratic(u + alpha * (prob.E @ xbar) - alpha * prob.b, alpha)
         v = prox.box(v + beta * (prob.D @ xbar), s)
+        if positivity:
+            t = prox.nonpositive(t + alpha * xbar)
         x = x_new
         if record:
             obj[k] = objective3d(prob, x)
-    return x, u, v, obj
+    return (x, u, v, obj, t) if with_t else (x, u, v, obj)

@@ -208,3 +208,52 @@ def test_ncs_and_pdhg_reach_the_common_limit():
     # the sparse matrix has the expected shape and touches every voxel
     assert prob.E.shape == (g.m, g.n) and np.all(np.asarray(abs(prob.E).sum(axis=0)).ravel() > 0)
     assert isinstance(prob.E, sp.csr_matrix)
+
+
+def test_positivity_form_is_the_stacked_iteration_with_the_identity_block():
+    # eq. (NCS) on A' = [E; (beta/alpha) D; I] with M^+ = F^-1 diag(h') F, the
+    # prox of alpha g* from the Moreau identity (primal proxes: quadratic,
+    # soft threshold, max(., 0) for the indicator of x >= 0)
+    prob = _tiny()
+    g = prob.geom
+    a, be = 0.05, 0.15
+    s_tv = prob.lam * a / be
+    h_e = conebeam.probe_multiplier_3d(lambda v: prob.Et @ (prob.E @ v), g.shape, 4)
+    mu = conebeam.eigenvalues3d(prob, a, be, 2.0, h_e, positivity=True)
+    h = 1.0 / mu
+    x_n, u_n, v_n, _, t_n = conebeam.ncs3d(prob, a, be, h, 20, record=False, positivity=True, with_t=True)
+    m, n = prob.m, prob.n
+    ratio = be / a
+    x, y = np.zeros(n), np.zeros(m + 4 * n)
+    for _ in range(20):
+        aty = prob.Et @ y[:m] + ratio * (prob.Dt @ y[m:m + 3 * n]) + y[m + 3 * n:]
+        x_new = x - np.real(np.fft.ifftn(h * np.fft.fftn(aty.reshape(g.shape)))).ravel()
+        xb = 2 * x_new - x
+        w = y + a * (np.concatenate([prob.E @ xb - prob.b, ratio * (prob.D @ xb), xb]))
+        y = np.concatenate([prox.moreau_conj(prox.prox_quadratic, w[:m], a),
+                            prox.moreau_conj(lambda z, t: prox.soft_threshold(z, t * s_tv), w[m:m + 3 * n], a),
+                            prox.moreau_conj(lambda z, t: np.maximum(z, 0.0), w[m + 3 * n:], a)])
+        x = x_new
+    np.testing.assert_allclose(x_n, x, rtol=0, atol=1e-12 * np.abs(x).max())
+    np.testing.assert_allclose(np.concatenate([u_n, v_n, t_n]), y, rtol=0, atol=1e-12 * np.abs(y).max())
+    assert np.all(t_n <= 0)
+
+
+def test_positivity_limit_is_nonnegative_and_optimal():
+    # with x >= 0 the iteration converges to a nonnegative point whose objective
+    # is no higher than that of the clipped unconstrained minimiser
+    prob = _tiny()
+    g = prob.geom
+    a, be = 0.05, 0.1
+    h_e = conebeam.probe_multiplier_3d(lambda v: prob.Et @ (prob.E @ v), g.shape, 8)
+    ata = (prob.Et @ prob.E).toarray() + (be / a) ** 2 * (prob.Dt @ prob.D).toarray() + np.eye(prob.n)
+    gp = 1.05 * a * np.linalg.eigvalsh(ata)[-1]
+    x_c, _, _, _, t_c = conebeam.ncs3d(prob, a, be, np.full(g.shape, 1.0 / gp), 20000, record=False,
+                                       positivity=True, with_t=True)
+    x_f, _, _, _ = conebeam.ncs3d(prob, a, be, np.full(g.shape, 1.0 / (1.05 * a * np.linalg.eigvalsh(ata - np.eye(prob.n))[-1])),
+                                  20000, record=False)
+    assert x_f.min() < -1e-3 * x_f.max()                 # the constraint matters
+    assert x_c.min() >= -1e-7 * x_c.max()
+    f_c = conebeam.objective3d(prob, x_c)
+    assert f_c <= conebeam.objective3d(prob, np.maximum(x_f, 0.0)) + 1e-9 * abs(f_c)
+    assert np.abs(t_c * x_c).max() <= 1e-6 * np.abs(t_c).max() * x_c.max()   # complementarity
