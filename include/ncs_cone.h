@@ -77,6 +77,11 @@ typedef struct {
     int32_t method;        /* NCS_METHOD_NCS or NCS_METHOD_PDHG */
     int32_t probes;        /* probes of eq. (H-fan), 0: 16; Rademacher images from SplitMix64
                               seeded by the probe index, bit j of output k giving voxel 64 k + j */
+    int32_t positivity;    /* 1: constrain x >= 0 (the remark in Section 4.2): A gains the rows I
+                              with the indicator of x >= 0, a dual t with t+ = min(t + alpha xbar, 0),
+                              alpha t in the backprojection and every eigenvalue of M raised by alpha
+                              (NCS; PDHG keeps M = gamma I) */
+    int32_t reserved;      /* must be 0 */
 } ncs_cone_params;
 
 typedef struct ncs_cone ncs_cone;
@@ -88,7 +93,7 @@ typedef struct ncs_cone ncs_cone;
 ncs_status ncs_cone_setup(const ncs_cone_geometry* geom, const ncs_cone_params* params, int32_t dtype,
                           const void* b_dev, void* stream, ncs_cone** out);
 
-/* x = x0_dev (NULL: zeros), u = v = 0, iteration counter 0. */
+/* x = x0_dev (NULL: zeros), u = v = 0 (and t = 0), iteration counter 0. */
 ncs_status ncs_cone_set_init(ncs_cone* h, const void* x0_dev);
 
 /* Run k >= 0 iterations; obj_host (length k, may be NULL) receives f(x^{k+1})
@@ -96,10 +101,12 @@ ncs_status ncs_cone_set_init(ncs_cone* h, const void* x0_dev);
 ncs_status ncs_cone_iterate(ncs_cone* h, int32_t k, double* obj_host);
 
 /* Copies of the state: x (N_z N^2), u (N_v N_r N_s), v (3 N_z N^2: the x-,
- * y- and z-difference volumes, each (z N + r) N + c). */
+ * y- and z-difference volumes, each (z N + r) N + c), t (N_z N^2, the
+ * positivity dual; NCS_ERR_INVALID_ARG without params.positivity). */
 ncs_status ncs_cone_get_x(ncs_cone* h, void* x_out_dev);
 ncs_status ncs_cone_get_u(ncs_cone* h, void* u_out_dev);
 ncs_status ncs_cone_get_v(ncs_cone* h, void* v_out_dev);
+ncs_status ncs_cone_get_t(ncs_cone* h, void* t_out_dev);
 
 /* Operators: y = E x, x = E^T y, out = F^-1 diag(1/mu) F w (real volume). */
 ncs_status ncs_cone_forward(ncs_cone* h, const void* x_dev, void* y_dev);

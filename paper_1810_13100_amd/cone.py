@@ -16,7 +16,7 @@ from .ncs import METHOD_NCS, NCS_F32, NCS_F64, _check, load_library
 
 EXPORTED = [
     "ncs_cone_setup", "ncs_cone_set_init", "ncs_cone_iterate", "ncs_cone_get_x", "ncs_cone_get_u",
-    "ncs_cone_get_v", "ncs_cone_forward", "ncs_cone_adjoint", "ncs_cone_apply_minv",
+    "ncs_cone_get_v", "ncs_cone_get_t", "ncs_cone_forward", "ncs_cone_adjoint", "ncs_cone_apply_minv",
     "ncs_cone_get_eigenvalues", "ncs_cone_get_info", "ncs_cone_time_phases", "ncs_cone_destroy",
 ]
 PHASES = ["backproject", "dft_update", "project_dataprox", "tv_dual", "objective_reduce"]
@@ -31,7 +31,7 @@ class _ConeGeometry(ctypes.Structure):
 class _ConeParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("mu_dc", ctypes.c_double), ("method", ctypes.c_int32),
-                ("probes", ctypes.c_int32)]
+                ("probes", ctypes.c_int32), ("positivity", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _ConeInfo(ctypes.Structure):
@@ -56,6 +56,7 @@ def _lib() -> ctypes.CDLL:
         "ncs_cone_get_x": ([vp, vp], i32),
         "ncs_cone_get_u": ([vp, vp], i32),
         "ncs_cone_get_v": ([vp, vp], i32),
+        "ncs_cone_get_t": ([vp, vp], i32),
         "ncs_cone_forward": ([vp, vp, vp], i32),
         "ncs_cone_adjoint": ([vp, vp, vp], i32),
         "ncs_cone_apply_minv": ([vp, vp, vp], i32),
@@ -103,6 +104,7 @@ class ConeParams:
     mu_dc: float = 0.0        # <= 0: gamma + alpha |E 1|^2 / n
     method: int = METHOD_NCS  # METHOD_NCS or METHOD_PDHG
     probes: int = 0           # probes of eq. (H-fan); 0: 16
+    positivity: int = 0       # 1: constrain x >= 0 (a dual t)
 
 
 class ConeSolver:
@@ -120,7 +122,7 @@ class ConeSolver:
         self._b = self._dev(b, geom.m, "b") if b is not None else None
         g = geom._c()
         p = _ConeParams(params.alpha, params.beta, params.gamma, params.lam, params.mu_dc, params.method,
-                        params.probes)
+                        params.probes, params.positivity, 0)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.ncs_cone_setup(ctypes.byref(g), ctypes.byref(p), NCS_F64 if dtype == torch.float64 else NCS_F32,
@@ -162,6 +164,10 @@ class ConeSolver:
 
     def v(self) -> torch.Tensor:
         return self._get(self.lib.ncs_cone_get_v, 3 * self.geom.n)
+
+    def t(self) -> torch.Tensor:
+        """The positivity dual t (params.positivity = 1 only)."""
+        return self._get(self.lib.ncs_cone_get_t, self.geom.n)
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty(self.geom.m, dtype=self.dtype, device=self.device)

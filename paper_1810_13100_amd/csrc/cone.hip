@@ -69,6 +69,7 @@ struct ConeCtx {
     const T* tw_n;   // cos, -sin of 2 pi k / N
     const T* tw_z;   // cos, -sin of 2 pi k / N_z
     T *x, *xbar, *xbarT, *u, *p, *v, *w, *spec;
+    T* tpos;         // positivity dual t (NULL without the constraint)
     double *part_data, *part_tv, *obj;
 };
 
@@ -288,7 +289,9 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
         if (rw > 0) dtv -= vy[i - N];
         if (z < c.NZ - 1) dtv += vz[i];
         if (z > 0) dtv -= vz[i - n2];
-        c.w[i] = fma(c.alpha, bp, c.beta * dtv);
+        T wv = fma(c.alpha, bp, c.beta * dtv);
+        if (c.tpos) wv = fma(c.alpha, c.tpos[i], wv);   // the rows I of x >= 0 (remark in Section 4.2)
+        c.w[i] = wv;
     }
 }
 
@@ -459,6 +462,7 @@ __global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int ou
             const T xn = xo - re[pos] * c.inv_na;
             const T xb = T(2) * xn - xo;
             c.x[e] = xn;
+            if (c.tpos) c.tpos[e] = fmin(fma(c.alpha, xb, c.tpos[e]), T(0));   // t+ = min(t + alpha xbar, 0)
             c.xbar[pad_index(z, r, col, N, P)] = xb;
             c.xbarT[pad_index(z, col, r, N, P)] = xb;
         }
@@ -476,6 +480,7 @@ __global__ __launch_bounds__(256) void k_cone_update_direct(ConeCtx<T> c, T scal
     const T xn = xo - c.w[i] * scale;
     const T xb = T(2) * xn - xo;
     c.x[i] = xn;
+    if (c.tpos) c.tpos[i] = fmin(fma(c.alpha, xb, c.tpos[i]), T(0));   // t+ = min(t + alpha xbar, 0)
     c.xbar[pad_index(z, r, col, N, c.P)] = xb;
     c.xbarT[pad_index(z, col, r, N, c.P)] = xb;
 }
@@ -610,6 +615,7 @@ struct ncs_cone {
     void *tw_n = nullptr, *tw_z = nullptr;
     void *x = nullptr, *xbar = nullptr, *xbarT = nullptr, *xsc = nullptr, *xscT = nullptr;
     void *u = nullptr, *pp = nullptr, *v = nullptr, *w = nullptr, *spec = nullptr, *ysc = nullptr;
+    void* tpos = nullptr;   // positivity dual (params.positivity only)
     double *part_data = nullptr, *part_tv = nullptr, *obj = nullptr;
 };
 
@@ -671,6 +677,7 @@ ConeCtx<T> make_ctx(const ncs_cone* H) {
     c.v = static_cast<T*>(H->v);
     c.w = static_cast<T*>(H->w);
     c.spec = static_cast<T*>(H->spec);
+    c.tpos = static_cast<T*>(H->tpos);
     c.part_data = H->part_data;
     c.part_tv = H->part_tv;
     c.obj = H->obj;
@@ -909,6 +916,7 @@ ncs_status setup_typed(ncs_cone* H) {
     CONE_TRY(dalloc(H, &H->v, 3 * H->n * ts));
     CONE_TRY(dalloc(H, &H->w, H->n * ts));
     CONE_TRY(dalloc(H, &H->spec, 2 * H->n * ts));
+    if (H->p.positivity) CONE_TRY(dalloc(H, &H->tpos, H->n * ts));
     CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->part_data), (size_t)g.n_views * g.n_rows * H->nbx * sizeof(double)));
     CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->part_tv), ((H->n + 255) / 256) * sizeof(double)));
     CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->obj), kHist * sizeof(double)));
@@ -970,6 +978,9 @@ ncs_status setup_typed(ncs_cone* H) {
                     H->mu[i] = p.gamma + p.alpha * he + ratio * 4.0 * (s2z[l] + s2[j] + s2[k]);
                 }
         H->mu[0] = H->mu_dc;
+        // x >= 0 (remark in Section 4.2): A gains the rows I, so alpha A^T A and M gain alpha I
+        if (p.positivity)
+            for (double& m : H->mu) m += p.alpha;
         // the temporaries are the last three allocations
         for (int r = 0; r < 3; ++r) {
             CONE_HIP(hipFree(H->allocs.back()));
@@ -1069,6 +1080,10 @@ ncs_status ncs_cone_setup(const ncs_cone_geometry* geom, const ncs_cone_params* 
         set_err("PDHG needs gamma > 0");
         return NCS_ERR_INVALID_ARG;
     }
+    if ((p.positivity != 0 && p.positivity != 1) || p.reserved != 0) {
+        set_err("positivity must be 0 or 1 and reserved 0");
+        return NCS_ERR_INVALID_ARG;
+    }
     if (p.probes < 0 || p.probes > 4096) {
         set_err("probes must be in [0, 4096]");
         return NCS_ERR_INVALID_ARG;
@@ -1113,6 +1128,7 @@ ncs_status ncs_cone_set_init(ncs_cone* h, const void* x0_dev) {
     else CONE_HIP(hipMemsetAsync(h->x, 0, h->n * ts, h->stream));
     CONE_HIP(hipMemsetAsync(h->u, 0, h->m * ts, h->stream));
     CONE_HIP(hipMemsetAsync(h->v, 0, 3 * h->n * ts, h->stream));
+    if (h->tpos) CONE_HIP(hipMemsetAsync(h->tpos, 0, h->n * ts, h->stream));
     // p = E x0
     if (x0_dev) {
         CONE_TRY(h->dtype == NCS_F64 ? forward_plain<double>(h, h->x, h->pp) : forward_plain<float>(h, h->x, h->pp));
@@ -1171,6 +1187,16 @@ ncs_status ncs_cone_get_v(ncs_cone* h, void* v_out_dev) {
     CONE_TRY(check_handle(h));
     if (!v_out_dev) { set_err("null output"); return NCS_ERR_INVALID_ARG; }
     CONE_HIP(hipMemcpyAsync(v_out_dev, h->v, 3 * h->n * h->tsize, hipMemcpyDeviceToDevice, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_get_t(ncs_cone* h, void* t_out_dev) {
+    CONE_TRY(check_handle(h));
+    if (!t_out_dev || !h->tpos) {
+        set_err(!t_out_dev ? "null output" : "ncs_cone_get_t: the handle has no positivity constraint");
+        return NCS_ERR_INVALID_ARG;
+    }
+    CONE_HIP(hipMemcpyAsync(t_out_dev, h->tpos, h->n * h->tsize, hipMemcpyDeviceToDevice, h->stream));
     return NCS_OK;
 }
 

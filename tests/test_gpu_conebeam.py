@@ -279,3 +279,36 @@ def test_cone_time_phases():
     ph = s.time_phases(3)
     s.close()
     assert list(ph) == cone.PHASES and all(v > 0 and np.isfinite(v) for v in ph.values())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cone_positivity_matches_oracle(prec):
+    # x >= 0 as a third block of A (remark in Section 4.2) on a volume
+    K = 60
+    prob = _problem()
+    a, be, gam = 0.01, 0.03, _gamma()
+    h = 1.0 / conebeam.eigenvalues3d(prob, a, be, gam, _h_e(), positivity=True)
+    x_ref, _, _, obj_ref, t_ref = conebeam.ncs3d(prob, a, be, h, K, positivity=True, with_t=True)
+    x_free = _ref("ncs", K)[0]
+    s = cone.ConeSolver(geometry("c32"), cone.ConeParams(a, be, gam, prob.lam, positivity=1),
+                        b=torch.tensor(prob.b, dtype=DT[prec], device=DEV), dtype=DT[prec])
+    s.set_init()
+    obj = s.iterate(K, record=True)
+    x, t = s.x().double().cpu().numpy(), s.t().double().cpu().numpy()
+    s.close()
+    assert x_free.min() < 0 and t_ref.min() < 0   # the constraint is active
+    ex, et = rel_l2(x, x_ref), rel_l2(t, t_ref)
+    ef = float(np.max(np.abs(obj - obj_ref) / np.abs(obj_ref)))
+    log(f"cone with x >= 0, {prec}: rel-L2 x {ex:.2e}, t {et:.2e}, max rel f {ef:.2e}")
+    if prec == "f64":
+        assert max(ex, et, ef) <= 1e-10
+    else:
+        assert ex <= 1e-4 and et <= 1e-4 and ef <= 1e-4
+    assert t.max() <= 0.0
+
+
+def test_cone_t_needs_positivity():
+    s = cone.ConeSolver(geometry("c32"), _params(method=ncs.METHOD_PDHG))
+    with pytest.raises(ncs.NcsError):
+        s.t()
+    s.close()
