@@ -108,6 +108,13 @@ ncs_status ncs_cone_get_u(ncs_cone* h, void* u_out_dev);
 ncs_status ncs_cone_get_v(ncs_cone* h, void* v_out_dev);
 ncs_status ncs_cone_get_t(ncs_cone* h, void* t_out_dev);
 
+/* Checkpoint: the full state (x, u, v, E x, t, iteration count) as an opaque
+ * host blob; with host_buf NULL, *bytes receives the size needed.  A handle
+ * with the same geometry, parameters and precision resumes from it bit for
+ * bit. */
+ncs_status ncs_cone_get_state(ncs_cone* h, void* host_buf, size_t* bytes);
+ncs_status ncs_cone_set_state(ncs_cone* h, const void* host_buf, size_t bytes);
+
 /* Operators: y = E x, x = E^T y, out = F^-1 diag(1/mu) F w (real volume). */
 ncs_status ncs_cone_forward(ncs_cone* h, const void* x_dev, void* y_dev);
 ncs_status ncs_cone_adjoint(ncs_cone* h, const void* y_dev, void* x_dev);

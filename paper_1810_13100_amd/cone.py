@@ -18,6 +18,7 @@ EXPORTED = [
     "ncs_cone_setup", "ncs_cone_set_init", "ncs_cone_iterate", "ncs_cone_get_x", "ncs_cone_get_u",
     "ncs_cone_get_v", "ncs_cone_get_t", "ncs_cone_forward", "ncs_cone_adjoint", "ncs_cone_apply_minv",
     "ncs_cone_get_eigenvalues", "ncs_cone_get_info", "ncs_cone_time_phases", "ncs_cone_destroy",
+    "ncs_cone_get_state", "ncs_cone_set_state",
 ]
 PHASES = ["backproject", "dft_update", "project_dataprox", "tv_dual", "objective_reduce"]
 
@@ -64,6 +65,8 @@ def _lib() -> ctypes.CDLL:
         "ncs_cone_get_info": ([vp, ctypes.POINTER(_ConeInfo)], i32),
         "ncs_cone_time_phases": ([vp, i32, pdbl], i32),
         "ncs_cone_destroy": ([vp], None),
+        "ncs_cone_get_state": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "ncs_cone_set_state": ([vp, vp, ctypes.c_size_t], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -168,6 +171,17 @@ class ConeSolver:
     def t(self) -> torch.Tensor:
         """The positivity dual t (params.positivity = 1 only)."""
         return self._get(self.lib.ncs_cone_get_t, self.geom.n)
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(self.lib.ncs_cone_get_state(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self.lib.ncs_cone_get_state(self.h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def set_state(self, blob: bytes) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self.lib.ncs_cone_set_state(self.h, buf, len(blob)))
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty(self.geom.m, dtype=self.dtype, device=self.device)

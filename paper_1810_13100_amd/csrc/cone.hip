@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 namespace {
@@ -1026,6 +1027,13 @@ long long count_nnz(const ncs_cone* H) {
     return total;
 }
 
+constexpr uint64_t kConeStateMagic = 0x454e4f4353434e31ull;   // blob tag
+
+struct ConeStateHeader {
+    uint64_t magic;
+    int32_t dtype, n_side, n_slices, n_views, n_bins, n_rows, iter, positivity, pad;
+};
+
 ncs_status check_handle(const ncs_cone* H) {
     if (!H) {
         set_err("null handle");
@@ -1197,6 +1205,56 @@ ncs_status ncs_cone_get_t(ncs_cone* h, void* t_out_dev) {
         return NCS_ERR_INVALID_ARG;
     }
     CONE_HIP(hipMemcpyAsync(t_out_dev, h->tpos, h->n * h->tsize, hipMemcpyDeviceToDevice, h->stream));
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_get_state(ncs_cone* h, void* host_buf, size_t* bytes) {
+    CONE_TRY(check_handle(h));
+    if (!bytes) { set_err("null size"); return NCS_ERR_INVALID_ARG; }
+    const size_t ts = h->tsize, n = h->n, m = h->m;
+    const size_t need = sizeof(ConeStateHeader) + ts * (n + 2 * m + 3 * n + (h->tpos ? n : 0));
+    if (!host_buf) { *bytes = need; return NCS_OK; }
+    if (*bytes < need) { set_err("buffer of %zu bytes, need %zu", *bytes, need); return NCS_ERR_INVALID_ARG; }
+    ConeStateHeader hd{kConeStateMagic, h->dtype, h->g.n_side, h->g.n_slices, h->g.n_views, h->g.n_bins,
+                       h->g.n_rows, h->iter, h->tpos ? 1 : 0, 0};
+    unsigned char* o = static_cast<unsigned char*>(host_buf);
+    std::memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    const std::pair<const void*, size_t> parts[] = {{h->x, n}, {h->u, m}, {h->pp, m}, {h->v, 3 * n}, {h->tpos, n}};
+    for (const auto& pt : parts) {
+        if (!pt.first) continue;
+        CONE_HIP(hipMemcpyAsync(o, pt.first, pt.second * ts, hipMemcpyDeviceToHost, h->stream));
+        o += pt.second * ts;
+    }
+    CONE_HIP(hipStreamSynchronize(h->stream));
+    *bytes = need;
+    return NCS_OK;
+}
+
+ncs_status ncs_cone_set_state(ncs_cone* h, const void* host_buf, size_t bytes) {
+    CONE_TRY(check_handle(h));
+    ConeStateHeader hd{};
+    if (!host_buf || bytes < sizeof(hd)) { set_err("no state blob"); return NCS_ERR_INVALID_ARG; }
+    std::memcpy(&hd, host_buf, sizeof(hd));
+    const size_t ts = h->tsize, n = h->n, m = h->m;
+    const size_t need = sizeof(hd) + ts * (n + 2 * m + 3 * n + (h->tpos ? n : 0));
+    if (hd.magic != kConeStateMagic || hd.dtype != h->dtype || hd.n_side != h->g.n_side ||
+        hd.n_slices != h->g.n_slices || hd.n_views != h->g.n_views || hd.n_bins != h->g.n_bins ||
+        hd.n_rows != h->g.n_rows || hd.positivity != (h->tpos ? 1 : 0) || bytes != need) {
+        set_err("the state blob does not match this handle");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const unsigned char* in = static_cast<const unsigned char*>(host_buf) + sizeof(hd);
+    void* parts_dst[] = {h->x, h->u, h->pp, h->v, h->tpos};
+    const size_t parts_n[] = {n, m, m, 3 * n, n};
+    for (int i = 0; i < 5; ++i) {
+        if (!parts_dst[i]) continue;
+        CONE_HIP(hipMemcpyAsync(parts_dst[i], in, parts_n[i] * ts, hipMemcpyHostToDevice, h->stream));
+        in += parts_n[i] * ts;
+    }
+    // x-bar = x is not needed: every iteration writes x-bar before reading it
+    CONE_HIP(hipStreamSynchronize(h->stream));
+    h->iter = hd.iter;
     return NCS_OK;
 }
 

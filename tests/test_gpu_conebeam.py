@@ -312,3 +312,26 @@ def test_cone_t_needs_positivity():
     with pytest.raises(ncs.NcsError):
         s.t()
     s.close()
+
+
+@pytest.mark.parametrize("positivity", [0, 1])
+def test_cone_checkpoint_resumes_bit_for_bit(positivity):
+    prob = _problem()
+    b = torch.tensor(prob.b, dtype=torch.float32, device=DEV)
+    p = cone.ConeParams(0.01, 0.03, _gamma(), prob.lam, positivity=positivity)
+    a = cone.ConeSolver(geometry("c32"), p, b=b)
+    a.set_init()
+    a.iterate(20)
+    blob = a.get_state()
+    obj_a = a.iterate(20, record=True)
+    c = cone.ConeSolver(geometry("c32"), p, b=b)
+    c.set_state(blob)
+    obj_c = c.iterate(20, record=True)
+    assert torch.equal(c.x().cpu(), a.x().cpu()) and np.array_equal(obj_a, obj_c)
+    if positivity:
+        assert torch.equal(c.t().cpu(), a.t().cpu())
+    d = cone.ConeSolver(geometry("c32"), cone.ConeParams(0.01, 0.03, _gamma(), prob.lam, positivity=1 - positivity), b=b)
+    with pytest.raises(ncs.NcsError):
+        d.set_state(blob)
+    for s in (a, c, d):
+        s.close()
