@@ -1001,7 +1001,8 @@ ncs_status setup_typed(ncs_cone* H) {
 // nonzero weight times the slice taps inside the volume with nonzero weight.
 long long count_nnz(const ncs_cone* H) {
     std::vector<double> rays, views, zeta;
-    ncs_cone tmp = *H;
+    ncs_cone tmp;   // the tables need the geometry only
+    tmp.g = H->g;
     build_tables(&tmp, rays, views, zeta);
     const ncs_cone_geometry& g = H->g;
     const int N = g.n_side, NZ = g.n_slices;
