@@ -38,7 +38,8 @@
  *    of the four voxels around its (column or row, slice) coordinates, times
  *    sqrt(1 + z_rho^2) / |u_y| (or / |u_x|).  E^T is the exact adjoint of that
  *    matrix, evaluated voxel by voxel.
- *  - N_v >= 1, N_s >= 2, N_r >= 2, R_s >= N/sqrt 2 + 4.
+ *  - 1 <= N_v <= 65535, N_s >= 2, 2 <= N_r <= 65535, N_r N_s <= 2^24,
+ *    R_s >= N/sqrt 2 + 4.
  *
  * Conventions (as in ncs.h): a handle is NCS_F32 or NCS_F64 and every device
  * buffer holds that type; *_dev pointers are device pointers owned by the

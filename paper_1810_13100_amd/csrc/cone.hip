@@ -35,7 +35,8 @@ namespace {
 
 constexpr int kWaves = 4;          // projector: waves per workgroup (split the steps)
 constexpr int kBpWaves = 8;        // backprojector: waves per 8 x 8 voxel tile (split the views)
-constexpr int kHits = 4;           // backprojector: rays collected per lane before their rows are summed
+constexpr int kHits = 2;           // backprojector: rays collected per lane before their rows are summed
+constexpr int kBpRunMax = 16;      // backprojector: longest run of voxels along z per lane
 constexpr int kFftLds = 32768;     // bytes of LDS per DFT workgroup
 constexpr int kHist = 65536;       // objective ring (doubles)
 constexpr double kPi = 3.14159265358979323846;
@@ -46,6 +47,16 @@ struct ConeRay {   // in-plane part of the rays (a, ., d): coordinates as linear
     T s0, s2;      // in-plane distance from the source s = s0 + step s2
     T kxy;         // in-plane length per plane, 1/|u_y| or 1/|u_x|
     int axis;      // 0: steps through rows, 1: through columns
+};
+
+// What the adjoint needs of a ray to find the voxels it reaches: the
+// in-plane coordinate k0 + step k2, the length per plane kxy and the axis.
+// At a voxel's plane the in-plane distance from the source is the offset
+// from the source along the stepping axis times kxy.
+template <class T>
+struct alignas(4 * sizeof(T)) ConeRayHead {
+    T k0, k2, kxy;
+    int axis;
 };
 
 template <class T>
@@ -62,6 +73,7 @@ struct ConeCtx {
     T alpha, beta, s_tv, inv_na;   // inv_na = 1 / (n alpha)
     double lambda;
     const ConeRay<T>* rays;
+    const ConeRayHead<T>* heads;
     const ConeView<T>* views;
     const T* zeta;   // row slopes
     const T* kz;     // sqrt(1 + zeta^2)
@@ -176,29 +188,62 @@ __global__ __launch_bounds__(256) void k_cone_project(ConeCtx<T> c, const T* __r
 
 // ---------------------------------------------------------------------------
 // Backprojector: an 8 x 8 voxel tile per workgroup, each lane a run of ZR
-// voxels along z of one (row, column); the 8 waves split the views.  For each
-// view the lane finds the fan bins within W of its own fan angle and
-// recomputes each ray's in-plane coordinate at its plane exactly as the
-// projector does (once for the run); for a ray that reaches it, the detector
-// rows whose slice coordinate falls within one slice of the run are summed
-// into the run.  Joseph's weights are the tents max(0, 1 - |coordinate -
-// voxel index|) in each interpolated axis, so E^T is the adjoint of the
-// projector's matrix, term by term.
+// voxels along z of one (row, column) (ZR = min(N_z, 16), halved while the
+// workgroup's LDS would exceed the device's limit); the 8 waves split the
+// views.  For each view the lane finds the fan bins within W of its own fan
+// angle and recomputes each ray's in-plane coordinate at its plane from the
+// projector's k0 and k2 (once for the run); for a ray that reaches it, the
+// detector rows whose slice coordinate falls within one slice of the run
+// are summed into the run.  Joseph's weights are the tents max(0, 1 -
+// |coordinate - voxel index|) in each interpolated axis, so E^T is the
+// adjoint of the projector's matrix, term by term.  Along z a row's slice
+// coordinate ze lies between voxels floor(ze) and floor(ze) + 1 of the run,
+// the only two with nonzero tents, (1 - f) and f for f = ze - floor(ze): the
+// row adds those two terms to the lane's accumulators in LDS (slots padded by
+// two voxels on each side, which take the terms of voxels outside the run).
+// Each lane owns its slots, so a plain read-modify-write suffices (LDS float
+// atomics measured several times slower) and every sum keeps the row order.
 // ---------------------------------------------------------------------------
-template <class T, bool ITER, int ZR>
+template <class T>
+struct alignas(2 * sizeof(T)) ZetaKz {   // a detector row's slope and sqrt(1 + slope^2)
+    T z, k;
+};
+
+// Rows up to this count keep their (slope, sqrt(1 + slope^2)) pairs in LDS.
+constexpr int kBpTableRows = 2048;
+constexpr int kRowBatch = 4;   // detector rows whose loads the adjoint issues together
+
+// Reciprocal and reciprocal square root where only a conservative bound is
+// needed (row ranges and bin windows carry a margin of a whole row or bin):
+// the hardware approximations in FP32, exact operations in FP64.
+template <class T>
+__device__ inline T rcp_bound(T v) { return T(1) / v; }
+template <>
+__device__ inline float rcp_bound<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <class T>
+__device__ inline T rsqrt_bound(T v) { return T(1) / sqrt(v); }
+template <>
+__device__ inline float rsqrt_bound<float>(float v) { return __builtin_amdgcn_rsqf(v); }
+
+template <class T, bool ITER, int ZR, bool TAB>
 __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c, const T* __restrict__ ysrc,
                                                                      T* __restrict__ out) {
     // LDS: per wave and lane up to kHits rays that reach the lane's voxels
-    // (bin, weight, in-plane distance); after the view loop, the per-wave sums.
+    // (bin, weight, in-plane distance) and the run's accumulators (slot j:
+    // voxel j - 2); with TAB, the rows' (slope, sqrt(1 + slope^2)) after them.
+    constexpr int kSlots = ZR + 4;
     constexpr int kHitBytes = kBpWaves * kHits * 64 * (4 + 2 * (int)sizeof(T));
-    constexpr int kRedBytes = kBpWaves * ZR * 64 * (int)sizeof(T);
-    __shared__ __attribute__((aligned(16))) unsigned char smem[kHitBytes > kRedBytes ? kHitBytes : kRedBytes];
+    constexpr int kAccBytes = kBpWaves * kSlots * 64 * (int)sizeof(T);
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     T* hit_c = reinterpret_cast<T*>(smem) + (size_t)wave * kHits * 64;
     T* hit_s = reinterpret_cast<T*>(smem) + (size_t)(kBpWaves + wave) * kHits * 64;
     int* hit_d = reinterpret_cast<int*>(reinterpret_cast<T*>(smem) + (size_t)2 * kBpWaves * kHits * 64) +
                  wave * kHits * 64;
+    T* const accs = reinterpret_cast<T*>(smem + kHitBytes);
+    T* const acc_l = accs + (size_t)wave * kSlots * 64 + lane;   // slot j at acc_l[j * 64]
+    ZetaKz<T>* const zk = reinterpret_cast<ZetaKz<T>*>(smem + kHitBytes + kAccBytes);
     const int N = c.N, NS = c.NS, NR = c.NR;
     const int tiles_x = N / 8;
     const int z0 = blockIdx.y * ZR;
@@ -208,9 +253,12 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
     const T fc = (T)col, fr = (T)row;
     const T zlo = T(z0 - 1) - c.half_z, zhi = T(z0 + ZR) - c.half_z;
     const T two_pi = T(6.283185307179586476925286766559);
-    T acc[ZR];
 #pragma unroll
-    for (int k = 0; k < ZR; ++k) acc[k] = T(0);
+    for (int j = 0; j < kSlots; ++j) acc_l[j * 64] = T(0);
+    if (TAB) {
+        for (int r = threadIdx.x; r < NR; r += kBpWaves * 64) zk[r] = ZetaKz<T>{c.zeta[r], c.kz[r]};
+        __syncthreads();
+    }
     for (int a = wave; a < c.NV; a += kBpWaves) {
         const ConeView<T> V = c.views[a];
         const T dx = px - V.sx, dy = py - V.sy;
@@ -220,10 +268,10 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
         // A ray that reaches the voxels passes within one voxel of their centre
         // line, so its fan angle is within asin(1/dist) of theirs, dist >= 4:
         // asin(x) <= 1.02 x for x <= 1/4, and one bin of slack for rounding.
-        const int wv = min((int)ceil(T(1.02) * c.inv_dgamma / sqrt(fma(dx, dx, dy * dy)) + T(0.5)) + 1, c.W);
+        const int wv = min((int)ceil(T(1.02) * c.inv_dgamma * rsqrt_bound(fma(dx, dx, dy * dy)) + T(0.5)) + 1, c.W);
         int d = max(dc - wv, 0);
         const int d_hi = min(dc + wv, NS - 1);
-        const ConeRay<T>* rr = c.rays + (size_t)a * NS;
+        const ConeRayHead<T>* rr = c.heads + (size_t)a * NS;
         const T* ya = ysrc + (size_t)a * NR * NS;
         // Lanes reach different candidate bins, so each first collects the rays
         // that reach it (up to kHits at a time) and then all lanes sum their
@@ -231,7 +279,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
         while (__any(d <= d_hi)) {
             int nh = 0;
             for (; d <= d_hi && nh < kHits; ++d) {
-                const ConeRay<T> R = rr[d];
+                const ConeRayHead<T> R = rr[d];
                 const T st = R.axis == 0 ? fr : fc;   // the ray's step at this column of voxels
                 const T tp = R.axis == 0 ? fc : fr;   // the voxels' place along the interpolated axis
                 const T xi = fma(st, R.k2, R.k0);
@@ -239,7 +287,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
                 if (wxy > T(0)) {
                     hit_d[nh * 64 + lane] = d;
                     hit_c[nh * 64 + lane] = wxy * R.kxy;
-                    hit_s[nh * 64 + lane] = fma(st, R.s2, R.s0);
+                    hit_s[nh * 64 + lane] = fabs(R.axis == 0 ? dy : dx) * R.kxy;   // in-plane distance
                     ++nh;
                 }
             }
@@ -248,31 +296,53 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
                 const int dj = hit_d[j * 64 + lane];
                 const T coef = hit_c[j * 64 + lane];
                 const T sd = hit_s[j * 64 + lane];
-                // rows with slice coordinate hz + sd (rho - cr) dz in (z0 - 1, z0 + ZR), one row of margin
-                const T inv = c.inv_dzeta / sd;
-                const int r_lo = max((int)floor(fma(zlo, inv, c.cr)) - 1, 0);
-                const int r_hi = min((int)ceil(fma(zhi, inv, c.cr)) + 1, NR - 1);
-                for (int rho = r_lo; rho <= r_hi; ++rho) {
-                    const T ze = fma(sd, c.zeta[rho], c.half_z) - T(z0);
-                    const T yv = ya[(size_t)rho * NS + dj] * (coef * c.kz[rho]);
+                // rows with slice coordinate hz + sd (rho - cr) dz in (z0 - 1, z0 + ZR): those
+                // strictly between the two roots, and one row beyond each for rounding
+                const T inv = c.inv_dzeta * rcp_bound(sd);
+                const int r_lo = max((int)floor(fma(zlo, inv, c.cr)), 0);
+                const int r_hi = min((int)ceil(fma(zhi, inv, c.cr)), NR - 1);
+                const T* yr = ya + dj + (size_t)r_lo * NS;   // row rho of bin dj
+                // rows in groups of kRowBatch: their loads are issued before
+                // the group's LDS updates, so they are in flight together
+                for (int rho = r_lo; rho <= r_hi; rho += kRowBatch, yr += (size_t)kRowBatch * NS) {
+                    T yk[kRowBatch];
+                    ZetaKz<T> tk[kRowBatch];
+                    const unsigned left = (unsigned)(r_hi - rho);   // rows past rho still in range
 #pragma unroll
-                    for (int k = 0; k < ZR; ++k) acc[k] = fma(yv, fmax(T(0), T(1) - fabs(ze - T(k))), acc[k]);
+                    for (int k = 0; k < kRowBatch; ++k) {
+                        const unsigned dk = min((unsigned)k, left);  // the last row stands in for rows past r_hi
+                        yk[k] = yr[__umul24(dk, (unsigned)NS)];     // N_s < 2^24
+                        tk[k] = TAB ? zk[rho + dk] : ZetaKz<T>{c.zeta[rho + dk], c.kz[rho + dk]};
+                    }
+                    // an empty statement that takes each value keeps the compiler
+                    // from moving the loads into the guarded steps below
+#pragma unroll
+                    for (int k = 0; k < kRowBatch; ++k) asm volatile("" : "+v"(yk[k]));
+#pragma unroll
+                    for (int k = 0; k < kRowBatch; ++k) {
+                        if (rho + k > r_hi) break;
+                        // the projector's slice coordinate, less z0 (exact in the run's range)
+                        const T ze = fma(sd, tk[k].z, c.half_z) - T(z0);
+                        const T yv = yk[k] * (coef * tk[k].k);
+                        const T fl = clampT(floor(ze), T(-2), T(ZR));
+                        const T f = ze - fl;
+                        T* const ap = acc_l + ((int)fl + 2) * 64;
+                        const T a0 = ap[0], a1 = ap[64];
+                        ap[0] = a0 + yv * (T(1) - f);
+                        ap[64] = a1 + yv * f;
+                    }
                 }
             }
         }
     }
-    __syncthreads();   // the hit lists are dead; the LDS now holds the per-wave sums
-    T* red = reinterpret_cast<T*>(smem);
-#pragma unroll
-    for (int k = 0; k < ZR; ++k) red[(wave * ZR + k) * 64 + lane] = acc[k];
-    __syncthreads();
+    __syncthreads();   // every wave's accumulators are complete
     const size_t n2 = (size_t)N * N;
     const size_t n = n2 * c.NZ;
     for (int o = threadIdx.x; o < 64 * ZR; o += kBpWaves * 64) {
         const int l = o & 63, k = o >> 6;
-        T bp = red[k * 64 + l];
+        T bp = accs[(k + 2) * 64 + l];
 #pragma unroll
-        for (int w = 1; w < kBpWaves; ++w) bp += red[(w * ZR + k) * 64 + l];
+        for (int w = 1; w < kBpWaves; ++w) bp += accs[(w * kSlots + k + 2) * 64 + l];
         const int cc = tx + (l & 7), rw = ty + (l >> 3), z = z0 + k;
         const size_t i = (size_t)z * n2 + (size_t)rw * N + cc;
         if (!ITER) {
@@ -609,10 +679,11 @@ struct ncs_cone {
     const void* b = nullptr;
     int iter = 0;
     int nbx = 0;   // projector workgroups along the detector columns
+    int bp_run = 4;   // adjoint: voxels per lane along z (chosen at setup)
     long long nnz = -1;   // counted on first request
     // device memory
     std::vector<void*> allocs;
-    void *rays = nullptr, *views = nullptr, *zeta = nullptr, *kz = nullptr, *h = nullptr;
+    void *rays = nullptr, *heads = nullptr, *views = nullptr, *zeta = nullptr, *kz = nullptr, *h = nullptr;
     void *tw_n = nullptr, *tw_z = nullptr;
     void *x = nullptr, *xbar = nullptr, *xbarT = nullptr, *xsc = nullptr, *xscT = nullptr;
     void *u = nullptr, *pp = nullptr, *v = nullptr, *w = nullptr, *spec = nullptr, *ysc = nullptr;
@@ -663,6 +734,7 @@ ConeCtx<T> make_ctx(const ncs_cone* H) {
     c.inv_na = (T)(1.0 / ((double)H->n * H->p.alpha));
     c.lambda = H->p.lambda;
     c.rays = static_cast<const ConeRay<T>*>(H->rays);
+    c.heads = static_cast<const ConeRayHead<T>*>(H->heads);
     c.views = static_cast<const ConeView<T>*>(H->views);
     c.zeta = static_cast<const T*>(H->zeta);
     c.kz = static_cast<const T*>(H->kz);
@@ -700,15 +772,46 @@ hipError_t launch_project(const ncs_cone* H, const ConeCtx<T>& c, const void* im
     return hipGetLastError();
 }
 
+// Bytes of LDS per adjoint workgroup: hit lists, accumulators and, with the
+// row table, N_r (slope, sqrt(1 + slope^2)) pairs.
+template <class T>
+size_t bp_lds_bytes(int zr, bool tab, int n_rows) {
+    return (size_t)kBpWaves * kHits * 64 * (4 + 2 * sizeof(T)) + (size_t)kBpWaves * (zr + 4) * 64 * sizeof(T) +
+           (tab ? (size_t)n_rows * sizeof(ZetaKz<T>) : 0);
+}
+
+template <class T, bool ITER, int ZR, bool TAB>
+void launch_backproject_zr(const ncs_cone* H, const ConeCtx<T>& c, const void* y, void* out) {
+    const int N = H->g.n_side, NZ = H->g.n_slices;
+    hipLaunchKernelGGL((k_cone_backproject<T, ITER, ZR, TAB>), dim3((N / 8) * (N / 8), NZ / ZR),
+                       dim3(kBpWaves * 64), bp_lds_bytes<T>(ZR, TAB, H->g.n_rows), H->stream, c,
+                       static_cast<const T*>(y), static_cast<T*>(out));
+}
+
+template <class T, int ZR, bool TAB>
+hipError_t allow_bp_lds(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cone_backproject<T, false, ZR, TAB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cone_backproject<T, true, ZR, TAB>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <class T, bool ITER>
 hipError_t launch_backproject(const ncs_cone* H, const ConeCtx<T>& c, const void* y, void* out) {
-    const int N = H->g.n_side, NZ = H->g.n_slices;
-    if (NZ >= 8)
-        hipLaunchKernelGGL((k_cone_backproject<T, ITER, 8>), dim3((N / 8) * (N / 8), NZ / 8), dim3(kBpWaves * 64), 0,
-                           H->stream, c, static_cast<const T*>(y), static_cast<T*>(out));
-    else
-        hipLaunchKernelGGL((k_cone_backproject<T, ITER, 4>), dim3((N / 8) * (N / 8), NZ / 4), dim3(kBpWaves * 64), 0,
-                           H->stream, c, static_cast<const T*>(y), static_cast<T*>(out));
+    // runs of H->bp_run voxels, a power of two in [4, N_z]
+    const bool tab = H->g.n_rows <= kBpTableRows;
+    const int zr = H->bp_run;
+    if (zr == 16) {
+        if (tab) launch_backproject_zr<T, ITER, 16, true>(H, c, y, out);
+        else launch_backproject_zr<T, ITER, 16, false>(H, c, y, out);
+    } else if (zr == 8) {
+        if (tab) launch_backproject_zr<T, ITER, 8, true>(H, c, y, out);
+        else launch_backproject_zr<T, ITER, 8, false>(H, c, y, out);
+    } else {
+        if (tab) launch_backproject_zr<T, ITER, 4, true>(H, c, y, out);
+        else launch_backproject_zr<T, ITER, 4, false>(H, c, y, out);
+    }
     return hipGetLastError();
 }
 
@@ -869,9 +972,34 @@ ncs_status upload(ncs_cone* H, void* dst, const std::vector<double>& src) {
     return NCS_OK;
 }
 
+// The adjoint's LDS depends on N_r: check it against the device's limit per
+// workgroup and allow it for the two instantiations this geometry launches.
+template <class T>
+ncs_status prepare_backproject(ncs_cone* H) {
+    const bool tab = H->g.n_rows <= kBpTableRows;
+    int dev = 0, limit = 0;
+    CONE_HIP(hipGetDevice(&dev));
+    CONE_HIP(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // the longest run (up to N_z and kBpRunMax) whose accumulators fit
+    int zr = std::min(H->g.n_slices, kBpRunMax);
+    while (zr > 4 && bp_lds_bytes<T>(zr, tab, H->g.n_rows) > (size_t)limit) zr /= 2;
+    H->bp_run = zr;
+    const size_t bytes = bp_lds_bytes<T>(zr, tab, H->g.n_rows);
+    if (bytes > (size_t)limit) {
+        set_err("the adjoint needs %zu bytes of LDS per workgroup; the device allows %d", bytes, limit);
+        return NCS_ERR_INVALID_ARG;
+    }
+    const hipError_t e = zr == 16 ? (tab ? allow_bp_lds<T, 16, true>(bytes) : allow_bp_lds<T, 16, false>(bytes))
+                         : zr == 8 ? (tab ? allow_bp_lds<T, 8, true>(bytes) : allow_bp_lds<T, 8, false>(bytes))
+                                   : (tab ? allow_bp_lds<T, 4, true>(bytes) : allow_bp_lds<T, 4, false>(bytes));
+    CONE_HIP(e);
+    return NCS_OK;
+}
+
 template <class T>
 ncs_status setup_typed(ncs_cone* H) {
     const ncs_cone_geometry& g = H->g;
+    CONE_TRY(prepare_backproject<T>(H));
     const int N = g.n_side, NZ = g.n_slices;
     H->n = (size_t)N * N * NZ;
     H->m = (size_t)g.n_views * g.n_rows * g.n_bins;
@@ -885,6 +1013,8 @@ ncs_status setup_typed(ncs_cone* H) {
         const double* t = &rays[6 * i];
         rt[i] = ConeRay<T>{(T)t[0], (T)t[1], (T)t[2], (T)t[3], (T)t[4], (int)t[5]};
     }
+    std::vector<ConeRayHead<T>> ht(rt.size());
+    for (size_t i = 0; i < rt.size(); ++i) ht[i] = ConeRayHead<T>{rt[i].k0, rt[i].k2, rt[i].kxy, rt[i].axis};
     std::vector<ConeView<T>> vt(g.n_views);
     for (int a = 0; a < g.n_views; ++a)
         vt[a] = ConeView<T>{(T)views[4 * a], (T)views[4 * a + 1], (T)views[4 * a + 2], T(0)};
@@ -900,6 +1030,7 @@ ncs_status setup_typed(ncs_cone* H) {
     };
     const size_t ts = sizeof(T);
     CONE_TRY(dalloc(H, &H->rays, rt.size() * sizeof(ConeRay<T>)));
+    CONE_TRY(dalloc(H, &H->heads, ht.size() * sizeof(ConeRayHead<T>)));
     CONE_TRY(dalloc(H, &H->views, vt.size() * sizeof(ConeView<T>)));
     CONE_TRY(dalloc(H, &H->zeta, zeta.size() * ts));
     CONE_TRY(dalloc(H, &H->kz, kz.size() * ts));
@@ -922,6 +1053,8 @@ ncs_status setup_typed(ncs_cone* H) {
     CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->part_tv), ((H->n + 255) / 256) * sizeof(double)));
     CONE_TRY(dalloc(H, reinterpret_cast<void**>(&H->obj), kHist * sizeof(double)));
     CONE_HIP(hipMemcpyAsync(H->rays, rt.data(), rt.size() * sizeof(ConeRay<T>), hipMemcpyHostToDevice, H->stream));
+    CONE_HIP(hipMemcpyAsync(H->heads, ht.data(), ht.size() * sizeof(ConeRayHead<T>), hipMemcpyHostToDevice,
+                            H->stream));
     CONE_HIP(hipMemcpyAsync(H->views, vt.data(), vt.size() * sizeof(ConeView<T>), hipMemcpyHostToDevice, H->stream));
     CONE_TRY(upload<T>(H, H->zeta, zeta));
     CONE_TRY(upload<T>(H, H->kz, kz));
@@ -1066,6 +1199,10 @@ ncs_status ncs_cone_setup(const ncs_cone_geometry* geom, const ncs_cone_params* 
     }
     if (g.n_views < 1 || g.n_bins < 2 || g.n_rows < 2 || g.reserved != 0) {
         set_err("need n_views >= 1, n_bins >= 2, n_rows >= 2 and reserved = 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (g.n_views > 65535 || g.n_rows > 65535 || (int64_t)g.n_rows * g.n_bins > (int64_t)1 << 24) {
+        set_err("need n_views <= 65535, n_rows <= 65535 and n_rows * n_bins <= 2^24");
         return NCS_ERR_INVALID_ARG;
     }
     if (!(std::isfinite(g.source_radius) && g.source_radius >= g.n_side / std::sqrt(2.0) + 4.0)) {

@@ -29,7 +29,14 @@ DT = {"f32": torch.float32, "f64": torch.float64}
 CONE = {"c32": (32, 16, 24, 48, 11, 60.0),                           # 32^2 x 16, 24 views x 11 rows x 48 bins
         "ragged": (16, 8, 7, 19, 4, 30.0),                           # odd views, even rows, 19 bins
         "wide": (64, 32, 30, 96, 16, 64 / math.sqrt(2.0) + 6.0),     # two bin blocks, slopes up to 2.7
-        "flat": (16, 4, 9, 21, 5, 16 / math.sqrt(2.0) + 4.0)}        # N_z = 4 (runs of 4 voxels), smallest R_s
+        "flat": (16, 4, 9, 21, 5, 16 / math.sqrt(2.0) + 4.0),        # N_z = 4 (runs of 4 voxels), smallest R_s
+        # tall detectors: the adjoint keeps up to 2048 rows' slopes in LDS and
+        # reads them from global memory beyond that
+        "rows2048": (16, 8, 2, 20, 2048, 24.0),
+        "rows2056": (16, 8, 2, 20, 2056, 24.0),
+        "rows2056z4": (16, 4, 2, 20, 2056, 24.0),
+        "rows2056z16": (16, 16, 2, 20, 2056, 24.0),
+        "rows2056z32": (16, 32, 2, 20, 2056, 24.0)}
 BENCH = (256, 64, 72, 368, 64, 512.0)
 
 
@@ -46,7 +53,8 @@ def _params(**kw):
     return cone.ConeParams(0.01, 0.03, 1.0, 0.01, **kw)
 
 
-@pytest.mark.parametrize("key", ["c32", "ragged", "wide", "flat"])
+@pytest.mark.parametrize("key", ["c32", "ragged", "wide", "flat", "rows2048", "rows2056", "rows2056z4", "rows2056z16",
+                                 "rows2056z32"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_cone_operators_match_oracle(key, prec):
     n, nz = CONE[key][0], CONE[key][1]
@@ -218,7 +226,9 @@ def test_cone_benchmark_size_sampled_views():
 def test_cone_rejects_bad_arguments():
     bad = [cone.ConeGeometry(32, 16, 24, 48, 11, 25.0),   # source inside the margin
            cone.ConeGeometry(32, 12, 24, 48, 11, 60.0),   # N_z not a power of two
-           cone.ConeGeometry(32, 16, 24, 48, 1, 60.0)]    # one detector row
+           cone.ConeGeometry(32, 16, 24, 48, 1, 60.0),    # one detector row
+           cone.ConeGeometry(32, 16, 24, 4097, 4096, 60.0),   # N_r N_s above 2^24
+           cone.ConeGeometry(32, 16, 65536, 48, 11, 60.0)]    # N_v above 65535
     for g in bad:
         with pytest.raises(ncs.NcsError) as e:
             cone.ConeSolver(g, _params())
