@@ -403,13 +403,13 @@ __device__ inline void bfly_dif(T& ar, T& ai, T& br, T& bi, T wr, T wi) {
 // registers (one LDS round trip and barrier per two stages); an odd last
 // stage runs alone.
 template <class T>
-__device__ void lds_dit(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, T sign) {
+__device__ void lds_dit(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, int logTB, T sign) {
     int ls = 0;
     for (; ls + 1 < logL; ls += 2) {
         const int h = 1 << ls;
         __syncthreads();
         for (int t = threadIdx.x; t < (TB * L) >> 2; t += blockDim.x) {
-            const int j = t % TB, q = t / TB;
+            const int j = t & (TB - 1), q = t >> logTB;
             const int pos = q & (h - 1);
             const int i0 = ((q >> ls) << (ls + 2)) + pos;
             const int t1 = pos * (L >> (ls + 1)), t2 = pos * (L >> (ls + 2)), t3 = (pos + h) * (L >> (ls + 2));
@@ -428,7 +428,7 @@ __device__ void lds_dit(T* re, T* im, const T* __restrict__ tw, int L, int logL,
         const int h = 1 << ls;
         __syncthreads();
         for (int t = threadIdx.x; t < (TB * L) >> 1; t += blockDim.x) {
-            const int j = t % TB, bf = t / TB;
+            const int j = t & (TB - 1), bf = t >> logTB;
             const int k = bf & (h - 1);
             const int i0 = ((bf >> ls) << (ls + 1)) + k;
             const int ti = k * (L >> (ls + 1));
@@ -442,13 +442,13 @@ __device__ void lds_dit(T* re, T* im, const T* __restrict__ tw, int L, int logL,
 }
 
 template <class T>
-__device__ void lds_dif(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, T sign) {
+__device__ void lds_dif(T* re, T* im, const T* __restrict__ tw, int L, int logL, int TB, int logTB, T sign) {
     int ls = logL - 1;
     for (; ls >= 1; ls -= 2) {   // stages ls and ls - 1 on quads (i0, i0 + h, i0 + H, i0 + H + h)
         const int H = 1 << ls, h = H >> 1;
         __syncthreads();
         for (int t = threadIdx.x; t < (TB * L) >> 2; t += blockDim.x) {
-            const int j = t % TB, q = t / TB;
+            const int j = t & (TB - 1), q = t >> logTB;
             const int pos = q & (h - 1);
             const int i0 = ((q >> (ls - 1)) << (ls + 1)) + pos;
             const int t1 = pos * (L >> (ls + 1)), t2 = (pos + h) * (L >> (ls + 1)), t3 = pos * (L >> ls);
@@ -466,7 +466,7 @@ __device__ void lds_dif(T* re, T* im, const T* __restrict__ tw, int L, int logL,
     if (ls == 0) {
         __syncthreads();
         for (int t = threadIdx.x; t < (TB * L) >> 1; t += blockDim.x) {
-            const int j = t % TB, bf = t / TB;
+            const int j = t & (TB - 1), bf = t >> logTB;
             const int p0 = (2 * bf) * TB + j, p1 = (2 * bf + 1) * TB + j;
             T r0 = re[p0], m0 = im[p0], r1 = re[p1], m1 = im[p1];
             bfly_dif(r0, m0, r1, m1, tw[0], sign * tw[1]);
@@ -478,19 +478,36 @@ __device__ void lds_dif(T* re, T* im, const T* __restrict__ tw, int L, int logL,
 
 template <class T>
 __global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int out_mode, int L, int logL, int B,
-                                                  int TB, const T* __restrict__ tw, const T* __restrict__ real_in,
-                                                  T* __restrict__ zc, T* __restrict__ real_out) {
+                                                  int TB, int logTB, const T* __restrict__ tw,
+                                                  const T* __restrict__ real_in, T* __restrict__ zc,
+                                                  T* __restrict__ real_out) {
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + TB * L;
     const int tot = TB * L;
     const bool bitrev_in = mode != FFT_INV;
+    // Element l of line j: contiguous lines (B = 1) at line L + l; in strided
+    // passes a thread keeps one j (TB divides the block size), so the line's
+    // base (line / B) L B + line % B is computed once.
+    const unsigned jt = threadIdx.x & (TB - 1);
+    size_t sbase = 0;
+    if (B > 1) {
+        const size_t line = (size_t)blockIdx.x * TB + jt;
+        sbase = (line / (size_t)B) * (size_t)L * B + line % (size_t)B;
+    }
+    auto elem = [&](int t, int& j, int& l) -> size_t {
+        if (B == 1) {
+            l = t & (L - 1);
+            j = t >> logL;
+            return ((size_t)blockIdx.x * TB + j) * (size_t)L + l;
+        }
+        j = (int)jt;
+        l = t >> logTB;
+        return sbase + (size_t)l * B;
+    };
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
         int j, l;
-        if (B == 1) { l = t & (L - 1); j = t >> logL; }
-        else { j = t % TB; l = t / TB; }
-        const size_t gid = (size_t)blockIdx.x * TB + j;
-        const size_t e = (gid / B) * (size_t)L * B + gid % B + (size_t)l * B;
+        const size_t e = elem(t, j, l);
         const int pos = (bitrev_in ? bitrev_n(l, logL) : l) * TB + j;
         if (real_in) {
             re[pos] = real_in[e];
@@ -500,26 +517,23 @@ __global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int ou
             im[pos] = zc[2 * e + 1];
         }
     }
-    if (mode == FFT_FWD || mode == FFT_FWD_MUL_INV) lds_dit(re, im, tw, L, logL, TB, T(1));
-    if (mode == FFT_FWD_MUL_INV) {
+    if (mode == FFT_FWD || mode == FFT_FWD_MUL_INV) lds_dit(re, im, tw, L, logL, TB, logTB, T(1));
+    if (mode == FFT_FWD_MUL_INV) {   // a strided pass (the z lines)
         for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-            const int j = t % TB, l = t / TB;
-            const size_t gid = (size_t)blockIdx.x * TB + j;
-            const size_t e = (gid / B) * (size_t)L * B + gid % B + (size_t)l * B;
+            int j, l;
+            const size_t e = elem(t, j, l);
             const T hv = c.h[e];
             re[l * TB + j] *= hv;
             im[l * TB + j] *= hv;
         }
     }
-    if (mode == FFT_INV || mode == FFT_FWD_MUL_INV) lds_dif(re, im, tw, L, logL, TB, T(-1));
+    if (mode == FFT_INV || mode == FFT_FWD_MUL_INV) lds_dif(re, im, tw, L, logL, TB, logTB, T(-1));
     const bool bitrev_out = mode != FFT_FWD;
     const int N = c.N, P = c.P;
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
         int j, l;
-        if (B == 1) { l = t & (L - 1); j = t >> logL; }
-        else { j = t % TB; l = t / TB; }
+        const size_t e = elem(t, j, l);
         const size_t gid = (size_t)blockIdx.x * TB + j;
-        const size_t e = (gid / B) * (size_t)L * B + gid % B + (size_t)l * B;
         const int pos = (bitrev_out ? bitrev_n(l, logL) : l) * TB + j;
         if (out_mode == OUT_COMPLEX) {
             zc[2 * e] = re[pos];
@@ -527,8 +541,8 @@ __global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int ou
         } else if (out_mode == OUT_REAL) {
             real_out[e] = re[pos] * c.inv_na;   // here inv_na holds 1/n
         } else {
-            // x pass (B = 1): e = (z N + r) N + col with the row gid = z N + r
-            const int col = l, r = (int)(gid % N), z = (int)(gid / N);
+            // x pass (B = 1, L = N): e = (z N + r) N + col with the row gid = z N + r
+            const int col = l, r = (int)(gid & (size_t)(N - 1)), z = (int)(gid >> logL);
             const T xo = c.x[e];
             const T xn = xo - re[pos] * c.inv_na;
             const T xb = T(2) * xn - xo;
@@ -828,10 +842,11 @@ hipError_t launch_fft(const ncs_cone* H, const ConeCtx<T>& c, int mode, int out_
     while ((size_t)TB * 2 <= lines / 2048 && TB * 2 <= cap) TB *= 2;
     if (B > 1) TB = std::min(std::max(TB, std::min(8, cap)), B);
     TB = (int)std::min<size_t>(TB, lines);
+    TB = std::min(TB, 256);   // a power of two dividing the block size
     const unsigned blocks = (unsigned)(lines / TB);
     const size_t lds = 2 * sizeof(T) * (size_t)TB * L;
     hipLaunchKernelGGL((k_cone_fft<T>), dim3(blocks), dim3(256), lds, H->stream, c, mode, out_mode, L, log2i(L), B, TB,
-                       static_cast<const T*>(tw), static_cast<const T*>(real_in), static_cast<T*>(zc),
+                       log2i(TB), static_cast<const T*>(tw), static_cast<const T*>(real_in), static_cast<T*>(zc),
                        static_cast<T*>(real_out));
     return hipGetLastError();
 }
