@@ -79,6 +79,7 @@ struct ConeCtx {
     const T* kz;     // sqrt(1 + zeta^2)
     const T* b;
     const T* h;      // 1 / mu
+    const T* hh;     // 1 / mu on the half spectrum (k <= N/2 along x)
     const T* tw_n;   // cos, -sin of 2 pi k / N
     const T* tw_z;   // cos, -sin of 2 pi k / N_z
     T *x, *xbar, *xbarT, *u, *p, *v, *w, *spec;
@@ -367,16 +368,18 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
 }
 
 // ---------------------------------------------------------------------------
-// 3D DFT: line passes over the interleaved complex volume.  Line (A, B) of a
+// 3D DFT: line passes over an interleaved complex volume.  Line (A, B) of a
 // pass has its L elements at (A L + l) B + b; a workgroup holds TB lines in
 // LDS (element-major, l TB + j): adjacent b for strided passes (coalesced
 // loads across lines), adjacent rows for the x pass (B = 1, contiguous).
 // Radix-2: decimation in time from bit-reversed order for forward
 // transforms, decimation in frequency to bit-reversed order for inverse ones,
-// two stages per LDS round trip.
+// two stages per LDS round trip.  The circulant solve works on the half
+// spectrum of its real volume (k = 0..N/2 along x, B = N/2 + 1 for the y
+// lines); the setup's transforms of the probes use the full layout.
 // ---------------------------------------------------------------------------
 enum { FFT_FWD = 0, FFT_INV = 1, FFT_FWD_MUL_INV = 2 };
-enum { OUT_COMPLEX = 0, OUT_REAL = 1, OUT_UPDATE = 2 };
+enum { OUT_REAL = 1, OUT_UPDATE = 2 };   // the solve's result: M+ w, or the NCS update
 
 __device__ inline int bitrev_n(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
 
@@ -477,10 +480,9 @@ __device__ void lds_dif(T* re, T* im, const T* __restrict__ tw, int L, int logL,
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int out_mode, int L, int logL, int B,
-                                                  int TB, int logTB, const T* __restrict__ tw,
-                                                  const T* __restrict__ real_in, T* __restrict__ zc,
-                                                  T* __restrict__ real_out) {
+__global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int L, int logL, int B, int TB, int logTB,
+                                                  const T* __restrict__ tw, const T* __restrict__ real_in,
+                                                  T* __restrict__ zc) {
     extern __shared__ unsigned char smem_raw[];
     T* re = reinterpret_cast<T*>(smem_raw);
     T* im = re + TB * L;
@@ -522,35 +524,100 @@ __global__ __launch_bounds__(256) void k_cone_fft(ConeCtx<T> c, int mode, int ou
         for (int t = threadIdx.x; t < tot; t += blockDim.x) {
             int j, l;
             const size_t e = elem(t, j, l);
-            const T hv = c.h[e];
+            const T hv = c.hh[e];   // the multiplied pass runs on the half spectrum
             re[l * TB + j] *= hv;
             im[l * TB + j] *= hv;
         }
     }
     if (mode == FFT_INV || mode == FFT_FWD_MUL_INV) lds_dif(re, im, tw, L, logL, TB, logTB, T(-1));
     const bool bitrev_out = mode != FFT_FWD;
-    const int N = c.N, P = c.P;
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
         int j, l;
         const size_t e = elem(t, j, l);
-        const size_t gid = (size_t)blockIdx.x * TB + j;
         const int pos = (bitrev_out ? bitrev_n(l, logL) : l) * TB + j;
-        if (out_mode == OUT_COMPLEX) {
-            zc[2 * e] = re[pos];
-            zc[2 * e + 1] = im[pos];
-        } else if (out_mode == OUT_REAL) {
-            real_out[e] = re[pos] * c.inv_na;   // here inv_na holds 1/n
-        } else {
-            // x pass (B = 1, L = N): e = (z N + r) N + col with the row gid = z N + r
-            const int col = l, r = (int)(gid & (size_t)(N - 1)), z = (int)(gid >> logL);
-            const T xo = c.x[e];
-            const T xn = xo - re[pos] * c.inv_na;
-            const T xb = T(2) * xn - xo;
-            c.x[e] = xn;
-            if (c.tpos) c.tpos[e] = fmin(fma(c.alpha, xb, c.tpos[e]), T(0));   // t+ = min(t + alpha xbar, 0)
-            c.xbar[pad_index(z, r, col, N, P)] = xb;
-            c.xbarT[pad_index(z, col, r, N, P)] = xb;
+        zc[2 * e] = re[pos];
+        zc[2 * e + 1] = im[pos];
+    }
+}
+
+// Result of the circulant solve for voxel (row, col), row = z N + r:
+// OUT_REAL writes v / n (inv_na holds 1/n then); OUT_UPDATE does
+// x+ = x - v / (n alpha), xbar = 2 x+ - x into both padded copies, and the
+// positivity dual.
+template <class T>
+__device__ inline void x_result(const ConeCtx<T>& c, int out_mode, T* __restrict__ real_out, int row, int col, T v) {
+    const int N = c.N, P = c.P;
+    const size_t e = (size_t)row * N + col;
+    if (out_mode == OUT_REAL) {
+        real_out[e] = v * c.inv_na;
+        return;
+    }
+    const int r = row & (N - 1), z = row >> (31 - __builtin_clz((unsigned)N));   // N a power of two
+    const T xo = c.x[e];
+    const T xn = xo - v * c.inv_na;
+    const T xb = T(2) * xn - xo;
+    c.x[e] = xn;
+    if (c.tpos) c.tpos[e] = fmin(fma(c.alpha, xb, c.tpos[e]), T(0));   // t+ = min(t + alpha xbar, 0)
+    c.xbar[pad_index(z, r, col, N, P)] = xb;
+    c.xbarT[pad_index(z, col, r, N, P)] = xb;
+}
+
+// x passes on the half spectrum: the rows of the volume are real, so two rows
+// a, b share one complex transform of a + i b.  Forward: the transform Z of
+// the pair gives A[k] = (Z[k] + conj Z[N-k]) / 2 and B[k] = (Z[k] -
+// conj Z[N-k]) / 2i, stored for k = 0..N/2 at (row) (N/2 + 1) + k.  Inverse:
+// Z[k] = A[k] + i B[k] with A, B extended by conjugate symmetry; the inverse
+// transform's real and imaginary parts are rows a and b.  TP pairs of rows
+// per workgroup, element l of pair j at LDS l TP + j.
+template <class T>
+__global__ __launch_bounds__(256) void k_cone_fft_xpair(ConeCtx<T> c, int inverse, int out_mode, int TP, int logTP,
+                                                        const T* __restrict__ tw, const T* __restrict__ real_in,
+                                                        T* __restrict__ zh, T* __restrict__ real_out) {
+    extern __shared__ unsigned char smem_raw[];
+    const int N = c.N, logN = 31 - __builtin_clz((unsigned)c.N), H = N / 2 + 1;
+    T* re = reinterpret_cast<T*>(smem_raw);
+    T* im = re + TP * N;
+    const int row0 = blockIdx.x * TP * 2;   // first row of the workgroup's pairs
+    if (!inverse) {
+        for (int t = threadIdx.x; t < TP * N; t += blockDim.x) {
+            const int l = t & (N - 1), j = t >> logN;
+            const size_t ea = (size_t)(row0 + 2 * j) * N + l;
+            const int pos = bitrev_n(l, logN) * TP + j;
+            re[pos] = real_in[ea];
+            im[pos] = real_in[ea + N];
         }
+        lds_dit(re, im, tw, N, logN, TP, logTP, T(1));
+        for (int t = threadIdx.x; t < TP * H; t += blockDim.x) {
+            const int j = t / H, k = t - j * H;
+            const int m = (N - k) & (N - 1);
+            const T zr = re[k * TP + j], zi = im[k * TP + j], mr = re[m * TP + j], mi = im[m * TP + j];
+            T* oa = zh + 2 * ((size_t)(row0 + 2 * j) * H + k);
+            T* ob = oa + 2 * H;
+            oa[0] = (zr + mr) * T(0.5);
+            oa[1] = (zi - mi) * T(0.5);
+            ob[0] = (zi + mi) * T(0.5);
+            ob[1] = (mr - zr) * T(0.5);
+        }
+        return;
+    }
+    for (int t = threadIdx.x; t < TP * H; t += blockDim.x) {
+        const int j = t / H, k = t - j * H;
+        const T* ia = zh + 2 * ((size_t)(row0 + 2 * j) * H + k);
+        const T* ib = ia + 2 * H;
+        const T ar = ia[0], ai = ia[1], br = ib[0], bi = ib[1];
+        re[k * TP + j] = ar - bi;   // Z[k] = A[k] + i B[k]
+        im[k * TP + j] = ai + br;
+        if (k > 0 && k < N / 2) {   // Z[N-k] = conj A[k] + i conj B[k]
+            re[(N - k) * TP + j] = ar + bi;
+            im[(N - k) * TP + j] = br - ai;
+        }
+    }
+    lds_dif(re, im, tw, N, logN, TP, logTP, T(-1));
+    for (int t = threadIdx.x; t < TP * N; t += blockDim.x) {
+        const int l = t & (N - 1), j = t >> logN;
+        const int pos = bitrev_n(l, logN) * TP + j;
+        x_result(c, out_mode, real_out, row0 + 2 * j, l, re[pos]);
+        x_result(c, out_mode, real_out, row0 + 2 * j + 1, l, im[pos]);
     }
 }
 
@@ -698,6 +765,7 @@ struct ncs_cone {
     // device memory
     std::vector<void*> allocs;
     void *rays = nullptr, *heads = nullptr, *views = nullptr, *zeta = nullptr, *kz = nullptr, *h = nullptr;
+    void* hh = nullptr;   // 1 / mu on the half spectrum
     void *tw_n = nullptr, *tw_z = nullptr;
     void *x = nullptr, *xbar = nullptr, *xbarT = nullptr, *xsc = nullptr, *xscT = nullptr;
     void *u = nullptr, *pp = nullptr, *v = nullptr, *w = nullptr, *spec = nullptr, *ysc = nullptr;
@@ -754,6 +822,7 @@ ConeCtx<T> make_ctx(const ncs_cone* H) {
     c.kz = static_cast<const T*>(H->kz);
     c.b = static_cast<const T*>(H->b);
     c.h = static_cast<const T*>(H->h);
+    c.hh = static_cast<const T*>(H->hh);
     c.tw_n = static_cast<const T*>(H->tw_n);
     c.tw_z = static_cast<const T*>(H->tw_z);
     c.x = static_cast<T*>(H->x);
@@ -831,48 +900,69 @@ hipError_t launch_backproject(const ncs_cone* H, const ConeCtx<T>& c, const void
 
 // One line pass of the 3D DFT along the axis with L elements at stride B.
 template <class T>
-hipError_t launch_fft(const ncs_cone* H, const ConeCtx<T>& c, int mode, int out_mode, int L, int B, const void* tw,
-                      const void* real_in, void* zc, void* real_out) {
+hipError_t launch_fft(const ncs_cone* H, const ConeCtx<T>& c, int mode, int L, int B, size_t total, const void* tw,
+                      const void* real_in, void* zc) {
     // lines per workgroup: enough workgroups to fill the chip (about 2048),
     // at least 8 adjacent lines in strided passes (64-byte segments; 16 lines
-    // measured 3-8% slower)
-    const size_t lines = H->n / L;
+    // measured 3-8% slower); a power of two that divides both the block size
+    // and the line count (the half spectrum's y lines number N_z (N/2 + 1))
+    const size_t lines = total / L;
     const int cap = (int)(kFftLds / (2 * sizeof(T)) / L);
     int TB = 1;
     while ((size_t)TB * 2 <= lines / 2048 && TB * 2 <= cap) TB *= 2;
     if (B > 1) TB = std::min(std::max(TB, std::min(8, cap)), B);
     TB = (int)std::min<size_t>(TB, lines);
-    TB = std::min(TB, 256);   // a power of two dividing the block size
+    TB = std::min(TB, 256);
+    while (lines % TB != 0) TB >>= 1;
     const unsigned blocks = (unsigned)(lines / TB);
     const size_t lds = 2 * sizeof(T) * (size_t)TB * L;
-    hipLaunchKernelGGL((k_cone_fft<T>), dim3(blocks), dim3(256), lds, H->stream, c, mode, out_mode, L, log2i(L), B, TB,
-                       log2i(TB), static_cast<const T*>(tw), static_cast<const T*>(real_in), static_cast<T*>(zc),
-                       static_cast<T*>(real_out));
+    hipLaunchKernelGGL((k_cone_fft<T>), dim3(blocks), dim3(256), lds, H->stream, c, mode, L, log2i(L), B, TB,
+                       log2i(TB), static_cast<const T*>(tw), static_cast<const T*>(real_in), static_cast<T*>(zc));
     return hipGetLastError();
 }
 
-// The forward 3D DFT of a real volume into zc.
+// x passes of the half spectrum: pairs of real rows (forward from real_in
+// into zh) or pairs of half-spectrum rows (inverse into out_mode's result).
+template <class T>
+hipError_t launch_xpair(const ncs_cone* H, const ConeCtx<T>& c, bool inverse, int out_mode, const void* real_in,
+                        void* zh, void* real_out) {
+    const int N = H->g.n_side;
+    const size_t pairs = (size_t)H->g.n_slices * N / 2;
+    const int cap = (int)(kFftLds / (2 * sizeof(T)) / N);
+    int TP = 1;
+    while ((size_t)TP * 2 <= pairs / 2048 && TP * 2 <= cap && TP * 2 <= 256) TP *= 2;
+    const unsigned blocks = (unsigned)(pairs / TP);   // pairs and TP are powers of two
+    const size_t lds = 2 * sizeof(T) * (size_t)TP * N;
+    hipLaunchKernelGGL((k_cone_fft_xpair<T>), dim3(blocks), dim3(256), lds, H->stream, c, inverse ? 1 : 0, out_mode,
+                       TP, log2i(TP), static_cast<const T*>(H->tw_n), static_cast<const T*>(real_in),
+                       static_cast<T*>(zh), static_cast<T*>(real_out));
+    return hipGetLastError();
+}
+
+// The forward 3D DFT of a real volume into zc (full complex layout).
 template <class T>
 hipError_t launch_fft3_forward(const ncs_cone* H, const ConeCtx<T>& c, const void* real_in, void* zc) {
     const int N = H->g.n_side, NZ = H->g.n_slices;
     hipError_t e;
-    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, 1, H->tw_n, real_in, zc, nullptr)) != hipSuccess) return e;
-    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, N, H->tw_n, nullptr, zc, nullptr)) != hipSuccess) return e;
-    return launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, NZ, N * N, H->tw_z, nullptr, zc, nullptr);
+    if ((e = launch_fft<T>(H, c, FFT_FWD, N, 1, H->n, H->tw_n, real_in, zc)) != hipSuccess) return e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD, N, N, H->n, H->tw_n, nullptr, zc)) != hipSuccess) return e;
+    return launch_fft<T>(H, c, FFT_FWD, NZ, N * N, H->n, H->tw_z, nullptr, zc);
 }
 
-// w (real) -> F^-1 diag(h) F w: forward x and y passes, z forward x h inverse,
-// inverse y, inverse x into real_out (scaled by 1/n) or into the NCS update.
+// w (real) -> F^-1 diag(h) F w on the half spectrum (N_z N (N/2 + 1) complex
+// values, ((z N + r) (N/2 + 1) + k)): x forward by pairs of rows, y forward,
+// z forward x h inverse, y inverse, x inverse by pairs into real_out (scaled
+// by 1/n) or into the NCS update.
 template <class T>
 hipError_t launch_minv(const ncs_cone* H, const ConeCtx<T>& c, const void* w, int out_mode, void* real_out) {
-    const int N = H->g.n_side, NZ = H->g.n_slices;
+    const int N = H->g.n_side, NZ = H->g.n_slices, Hh = N / 2 + 1;
+    const size_t half = (size_t)NZ * N * Hh;
     hipError_t e;
-    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, 1, H->tw_n, w, H->spec, nullptr)) != hipSuccess) return e;
-    if ((e = launch_fft<T>(H, c, FFT_FWD, OUT_COMPLEX, N, N, H->tw_n, nullptr, H->spec, nullptr)) != hipSuccess) return e;
-    if ((e = launch_fft<T>(H, c, FFT_FWD_MUL_INV, OUT_COMPLEX, NZ, N * N, H->tw_z, nullptr, H->spec, nullptr)) != hipSuccess)
-        return e;
-    if ((e = launch_fft<T>(H, c, FFT_INV, OUT_COMPLEX, N, N, H->tw_n, nullptr, H->spec, nullptr)) != hipSuccess) return e;
-    return launch_fft<T>(H, c, FFT_INV, out_mode, N, 1, H->tw_n, nullptr, H->spec, real_out);
+    if ((e = launch_xpair<T>(H, c, false, out_mode, w, H->spec, nullptr)) != hipSuccess) return e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD, N, Hh, half, H->tw_n, nullptr, H->spec)) != hipSuccess) return e;
+    if ((e = launch_fft<T>(H, c, FFT_FWD_MUL_INV, NZ, N * Hh, half, H->tw_z, nullptr, H->spec)) != hipSuccess) return e;
+    if ((e = launch_fft<T>(H, c, FFT_INV, N, Hh, half, H->tw_n, nullptr, H->spec)) != hipSuccess) return e;
+    return launch_xpair<T>(H, c, true, out_mode, nullptr, H->spec, real_out);
 }
 
 template <class T>
@@ -1052,6 +1142,7 @@ ncs_status setup_typed(ncs_cone* H) {
     CONE_TRY(dalloc(H, &H->tw_n, (size_t)N * ts));
     CONE_TRY(dalloc(H, &H->tw_z, (size_t)NZ * ts));
     CONE_TRY(dalloc(H, &H->h, H->n * ts));
+    CONE_TRY(dalloc(H, &H->hh, (size_t)NZ * N * (N / 2 + 1) * ts));
     CONE_TRY(dalloc(H, &H->x, H->n * ts));
     CONE_TRY(dalloc(H, &H->xbar, H->npad * ts));
     CONE_TRY(dalloc(H, &H->xbarT, H->npad * ts));
@@ -1140,6 +1231,13 @@ ncs_status setup_typed(ncs_cone* H) {
     std::vector<double> hv(H->n);
     for (size_t i = 0; i < H->n; ++i) hv[i] = H->mu[i] != 0.0 ? 1.0 / H->mu[i] : 0.0;
     CONE_TRY(upload<T>(H, H->h, hv));
+    {   // the half spectrum's copy: k = 0..N/2 of every (z, r) line
+        const int Hh = N / 2 + 1;
+        std::vector<double> hhv((size_t)NZ * N * Hh);
+        for (size_t row = 0; row < (size_t)NZ * N; ++row)
+            for (int k = 0; k < Hh; ++k) hhv[row * Hh + k] = hv[row * N + k];
+        CONE_TRY(upload<T>(H, H->hh, hhv));
+    }
     CONE_HIP(hipMemsetAsync(H->w, 0, H->n * ts, H->stream));
     CONE_HIP(hipStreamSynchronize(H->stream));
     return NCS_OK;
