@@ -268,8 +268,10 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
         const int dc = (int)floor((gang - c.gamma0) * c.inv_dgamma + T(0.5));
         // A ray that reaches the voxels passes within one voxel of their centre
         // line, so its fan angle is within asin(1/dist) of theirs, dist >= 4:
-        // asin(x) <= 1.02 x for x <= 1/4, and one bin of slack for rounding.
-        const int wv = min((int)ceil(T(1.02) * c.inv_dgamma * rsqrt_bound(fma(dx, dx, dy * dy)) + T(0.5)) + 1, c.W);
+        // asin(x) <= 1.02 x for x <= 1/4.  dc is the nearest bin to their fan
+        // angle (half a bin), and 0.01 bin covers the rounding of both (about
+        // 1e-4 bin in FP32).
+        const int wv = min((int)ceil(T(1.02) * c.inv_dgamma * rsqrt_bound(fma(dx, dx, dy * dy)) + T(0.51)), c.W);
         int d = max(dc - wv, 0);
         const int d_hi = min(dc + wv, NS - 1);
         const ConeRayHead<T>* rr = c.heads + (size_t)a * NS;
