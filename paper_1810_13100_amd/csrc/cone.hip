@@ -197,7 +197,9 @@ __global__ __launch_bounds__(256) void k_cone_project(ConeCtx<T> c, const T* __r
 // detector rows whose slice coordinate falls within one slice of the run
 // are summed into the run.  Joseph's weights are the tents max(0, 1 -
 // |coordinate - voxel index|) in each interpolated axis, so E^T is the
-// adjoint of the projector's matrix, term by term.  Along z a row's slice
+// adjoint of the projector's matrix term by term, up to the rounding of the
+// slice coordinate (the projector forms the in-plane distance from its step,
+// the adjoint from the voxels' offset to the source).  Along z a row's slice
 // coordinate ze lies between voxels floor(ze) and floor(ze) + 1 of the run,
 // the only two with nonzero tents, (1 - f) and f for f = ze - floor(ze): the
 // row adds those two terms to the lane's accumulators in LDS (slots padded by
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_cone_backproject(ConeCtx<T> c
 #pragma unroll
                     for (int k = 0; k < kRowBatch; ++k) {
                         if (rho + k > r_hi) break;
-                        // the projector's slice coordinate, less z0 (exact in the run's range)
+                        // the ray's slice coordinate at the voxels' plane, less z0
                         const T ze = fma(sd, tk[k].z, c.half_z) - T(z0);
                         const T yv = yk[k] * (coef * tk[k].k);
                         const T fl = clampT(floor(ze), T(-2), T(ZR));
