@@ -63,3 +63,41 @@ def test_null_arguments_are_rejected_without_gpu_work():
     lib.ncs_cone_iterate.restype = ctypes.c_int32
     lib.ncs_cone_iterate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
     assert lib.ncs_cone_iterate(None, 1, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libncs.so not built")
+def test_cone_geometry_and_parameters_are_validated_before_gpu_work():
+    """ncs_cone_setup checks its geometry and parameters before any HIP call
+    (include/ncs_cone.h: the limits of the geometry and of the parameters)."""
+    import torch  # noqa: F401
+    from paper_1810_13100_amd import cone, ncs
+    lib = ctypes.CDLL(LIB)
+    lib.ncs_cone_setup.restype = ctypes.c_int32
+    lib.ncs_last_error.restype = ctypes.c_char_p
+    good = (32, 16, 24, 48, 11, 0, 60.0)
+    ok_params = (0.01, 0.03, 1.0, 0.01, 0.0, ncs.METHOD_NCS, 0, 0, 0)
+    cases = [
+        ((32, 16, 24, 48, 11, 0, 25.0), ok_params, b"source_radius"),     # source inside the margin
+        ((24, 16, 24, 48, 11, 0, 60.0), ok_params, b"n_side"),            # N not a power of two
+        ((32, 512, 24, 48, 11, 0, 60.0), ok_params, b"n_slices"),         # N_z above 256
+        ((32, 16, 24, 48, 1, 0, 60.0), ok_params, b"n_rows >= 2"),        # one detector row
+        ((32, 16, 65536, 48, 11, 0, 60.0), ok_params, b"65535"),          # N_v above 65535
+        ((32, 16, 24, 4097, 4096, 0, 60.0), ok_params, b"2^24"),          # N_r N_s above 2^24
+        ((32, 16, 24, 48, 11, 1, 60.0), ok_params, b"reserved"),          # reserved field set
+        (good, (0.0,) + ok_params[1:], b"alpha > 0"),                     # alpha = 0
+        (good, ok_params[:5] + (ncs.METHOD_ADMM_CG,) + ok_params[6:], b"NCS_METHOD"),
+        (good, ok_params[:7] + (2, 0), b"positivity"),                    # positivity not 0 or 1
+    ]
+    for geo, par, msg in cases:
+        g = cone._ConeGeometry(*geo)
+        p = cone._ConeParams(*par)
+        h = ctypes.c_void_p()
+        st = lib.ncs_cone_setup(ctypes.byref(g), ctypes.byref(p), ncs.NCS_F32, None, None, ctypes.byref(h))
+        assert st == ncs.NCS_ERR_INVALID_ARG, (geo, par)
+        assert h.value is None
+        assert msg in lib.ncs_last_error(), (geo, par, lib.ncs_last_error())
+    g = cone._ConeGeometry(*good)
+    p = cone._ConeParams(*ok_params)
+    h = ctypes.c_void_p()
+    assert lib.ncs_cone_setup(ctypes.byref(g), ctypes.byref(p), 7, None, None, ctypes.byref(h)) == -1   # dtype
+    assert b"dtype" in lib.ncs_last_error()
