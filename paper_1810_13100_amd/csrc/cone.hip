@@ -1099,9 +1099,13 @@ ncs_status prepare_backproject(ncs_cone* H) {
         set_err("the adjoint needs %zu bytes of LDS per workgroup; the device allows %d", bytes, limit);
         return NCS_ERR_INVALID_ARG;
     }
-    const hipError_t e = zr == 16 ? (tab ? allow_bp_lds<T, 16, true>(bytes) : allow_bp_lds<T, 16, false>(bytes))
-                         : zr == 8 ? (tab ? allow_bp_lds<T, 8, true>(bytes) : allow_bp_lds<T, 8, false>(bytes))
-                                   : (tab ? allow_bp_lds<T, 4, true>(bytes) : allow_bp_lds<T, 4, false>(bytes));
+    // the attribute belongs to the kernel, shared by every handle in the
+    // process: allow the device's whole limit, so that a later handle with a
+    // smaller table does not lower it under an earlier one's launches
+    const size_t lim = (size_t)limit;
+    const hipError_t e = zr == 16 ? (tab ? allow_bp_lds<T, 16, true>(lim) : allow_bp_lds<T, 16, false>(lim))
+                         : zr == 8 ? (tab ? allow_bp_lds<T, 8, true>(lim) : allow_bp_lds<T, 8, false>(lim))
+                                   : (tab ? allow_bp_lds<T, 4, true>(lim) : allow_bp_lds<T, 4, false>(lim));
     CONE_HIP(e);
     return NCS_OK;
 }

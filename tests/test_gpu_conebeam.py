@@ -75,6 +75,26 @@ def test_cone_operators_match_oracle(key, prec):
     assert e2 <= (1e-11 if prec == "f64" else 1e-4)
 
 
+def test_cone_handles_with_different_row_tables_coexist():
+    """Two live handles whose adjoints launch the same kernel with different LDS
+    (2048 and 4 detector rows in the table): the later setup leaves the earlier
+    handle's launches valid."""
+    log("cone handles: 2048-row table, then 4-row table, both live")
+    big = cone.ConeSolver(geometry("rows2048"), _params(method=ncs.METHOD_PDHG), dtype=torch.float64)
+    small = cone.ConeSolver(geometry("ragged"), _params(method=ncs.METHOD_PDHG), dtype=torch.float64)
+    rng = np.random.default_rng(4)
+    y_big = rng.standard_normal(big.geom.m)
+    y_small = rng.standard_normal(small.geom.m)
+    back_big = big.adjoint(torch.tensor(y_big, dtype=torch.float64, device=DEV)).cpu().numpy()
+    back_small = small.adjoint(torch.tensor(y_small, dtype=torch.float64, device=DEV)).cpu().numpy()
+    big.close()
+    small.close()
+    e_big = rel_l2(back_big, cone_E("rows2048").T @ y_big)
+    e_small = rel_l2(back_small, cone_E("ragged").T @ y_small)
+    log(f"  adjoint rel-L2 {e_big:.2e} (2048 rows), {e_small:.2e} (4 rows)")
+    assert e_big <= 1e-11 and e_small <= 1e-11
+
+
 def test_cone_pair_is_adjoint():
     g = geometry("c32")
     s = cone.ConeSolver(g, _params(method=ncs.METHOD_PDHG), dtype=torch.float64)
