@@ -36,8 +36,9 @@
  *  - Joseph's method: the ray steps through the rows (|u_y| >= |u_x| - 1e-12)
  *    or columns of every slice; at each plane it takes the bilinear weights
  *    of the four voxels around its (column or row, slice) coordinates, times
- *    sqrt(1 + z_rho^2) / |u_y| (or / |u_x|).  E^T is the exact adjoint of that
- *    matrix, evaluated voxel by voxel.
+ *    sqrt(1 + z_rho^2) / |u_y| (or / |u_x|).  E^T is the adjoint of that
+ *    matrix, evaluated voxel by voxel: the same taps and weights, up to the
+ *    rounding of each tap's slice coordinate.
  *  - 1 <= N_v <= 65535, N_s >= 2, 2 <= N_r <= 65535, N_r N_s <= 2^24,
  *    R_s >= N/sqrt 2 + 4.
  *
