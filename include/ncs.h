@@ -113,8 +113,11 @@ typedef struct {
     int32_t projector; /* forward-projector kernel: 0 = time all at setup and keep the
                           fastest, 1 = LDS-staged row windows, 2 = direct coalesced loads,
                           3 = two adjacent rays per lane, one 16-byte load per step */
-    int32_t graph_chunk; /* iterations per replayed HIP graph; 0 selects 25, < 0 disables
-                            graphs (every kernel launched directly) */
+    int32_t graph_chunk; /* largest number of iterations per replayed HIP graph; 0 selects 32,
+                            < 0 disables graphs (every kernel launched directly).  One graph
+                            per power of two up to it is captured at the first iteration
+                            request, so every count k is replayed (largest chunk repeated,
+                            then the binary digits of the remainder). */
     double dual_ramp;    /* ncs_set_init with dual_from_x0: width tau of the ramp of the TV
                             dual, v = s clamp(D x0 / tau, -1, 1) (anisotropic) or
                             s (D x0)_p / max(|(D x0)_p|, tau) (isotropic); <= 0 gives the
@@ -127,7 +130,10 @@ typedef struct {
     int32_t method;        /* ncs_method: NCS (M circulant), PDHG (M = gamma I; needs
                               gamma > alpha lambda_max(A^T A) to converge) or ADMM-CG */
     int32_t cg_iters;      /* ADMM-CG: CG steps per linear solve; 0 selects 10 */
-    int32_t cg_precondition; /* ADMM-CG: 1 = precondition CG with alpha M^+, 0 = plain CG */
+    int32_t cg_precondition; /* ADMM-CG: 1 = precondition CG with alpha M^+, 0 = plain CG
+                                (double precision only: NCS_F32 gives NCS_ERR_INVALID_ARG,
+                                since plain CG amplifies single-precision rounding by about
+                                the condition number of A^T A) */
     int32_t positivity;    /* 1: constrain x >= 0 (remark in Section 4.2): A gains the rows I with
                               the indicator of the nonnegative orthant in g, a dual t (N*N,
                               zero at ncs_set_init) updated as t = min(t + alpha xbar, 0), the
@@ -139,7 +145,10 @@ typedef struct {
                               probes (Rademacher images from SplitMix64 seeded by the probe
                               index; least-squares average of (F E^T E v)_i / (F v)_i) instead
                               of alpha C_R / |omega|; 0: the analytic multiplier for parallel
-                              beams and 16 probes for fan beams */
+                              beams and 16 probes for fan beams.  The products E^T E v run
+                              through the library's double-precision kernels for handles of
+                              either precision (a single-precision handle builds a temporary
+                              double-precision twin at setup), so both run the same M. */
 } ncs_params;
 
 typedef struct ncs_handle ncs_handle;

@@ -91,7 +91,9 @@ typedef struct ncs_cone ncs_cone;
 /* Create a solver.  b_dev (N_v N_r N_s values) may be NULL for a handle used
  * only for the operators.  Builds the ray tables in double precision on the
  * host, estimates h_E on the device (params.probes products E^T E v and their
- * 3D DFTs, accumulated in double), and sets x = u = v = 0. */
+ * 3D DFTs, accumulated in double, always with the double-precision kernels: a
+ * single-precision handle builds a temporary double-precision twin for it, so
+ * both precisions run the same M), and sets x = u = v = 0. */
 ncs_status ncs_cone_setup(const ncs_cone_geometry* geom, const ncs_cone_params* params, int32_t dtype,
                           const void* b_dev, void* stream, ncs_cone** out);
 

@@ -766,6 +766,7 @@ struct ncs_cone {
     int iter = 0;
     int nbx = 0;   // projector workgroups along the detector columns
     int bp_run = 4;   // adjoint: voxels per lane along z (chosen at setup)
+    bool operators_only = false;   // tables and workspace only (no multiplier)
     long long nnz = -1;   // counted on first request
     // device memory
     std::vector<void*> allocs;
@@ -1111,6 +1112,68 @@ ncs_status prepare_backproject(ncs_cone* H) {
 }
 
 template <class T>
+ncs_status setup_typed(ncs_cone* H);
+
+// num = sum_k Re(conj(F v_k) F(E^T E v_k)), den = sum_k |F v_k|^2 over the
+// probes v_k (eq. H-fan), accumulated in double on the device with this
+// handle's projector pair and 3D DFT.
+template <class T>
+ncs_status probe_estimate(ncs_cone* H, int probes, std::vector<double>& hn, std::vector<double>& hd) {
+    const ConeCtx<T> c = make_ctx<T>(H);
+    double *num = nullptr, *den = nullptr;
+    void* spec2 = nullptr;
+    CONE_TRY(dalloc(H, reinterpret_cast<void**>(&num), H->n * sizeof(double)));
+    CONE_TRY(dalloc(H, reinterpret_cast<void**>(&den), H->n * sizeof(double)));
+    CONE_TRY(dalloc(H, &spec2, 2 * H->n * H->tsize));
+    std::vector<double> pv;
+    for (int k = 0; k < probes; ++k) {
+        probe_values((uint64_t)k, H->n, pv);
+        CONE_TRY(upload<T>(H, H->w, pv));
+        CONE_TRY(forward_plain<T>(H, H->w, H->ysc));
+        CONE_HIP((launch_backproject<T, false>(H, c, H->ysc, H->x)));
+        CONE_HIP(launch_fft3_forward<T>(H, c, H->w, H->spec));
+        CONE_HIP(launch_fft3_forward<T>(H, c, H->x, spec2));
+        hipLaunchKernelGGL((k_cone_probe_acc<T>), dim3((unsigned)((H->n + 255) / 256)), dim3(256), 0, H->stream,
+                           static_cast<const T*>(H->spec), static_cast<const T*>(spec2), num, den, H->n);
+        CONE_HIP(hipGetLastError());
+    }
+    hn.resize(H->n);
+    hd.resize(H->n);
+    CONE_HIP(hipMemcpyAsync(hn.data(), num, H->n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    CONE_HIP(hipMemcpyAsync(hd.data(), den, H->n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    CONE_HIP(hipStreamSynchronize(H->stream));
+    // the temporaries are the last three allocations
+    for (int r = 0; r < 3; ++r) {
+        CONE_HIP(hipFree(H->allocs.back()));
+        H->allocs.pop_back();
+    }
+    CONE_HIP(hipMemsetAsync(H->x, 0, H->n * H->tsize, H->stream));
+    return NCS_OK;
+}
+
+// The probe estimate for a handle of either precision: a single-precision
+// handle borrows a double-precision twin (same geometry, tables and
+// workspace only), so that both precisions run the same M.
+ncs_status probe_estimate_fp64(ncs_cone* H, int probes, std::vector<double>& hn, std::vector<double>& hd) {
+    if (H->dtype == NCS_F64) return probe_estimate<double>(H, probes, hn, hd);
+    ncs_cone* twin = new (std::nothrow) ncs_cone();
+    if (!twin) {
+        set_err("out of host memory");
+        return NCS_ERR_OOM;
+    }
+    twin->g = H->g;
+    twin->p = H->p;
+    twin->dtype = NCS_F64;
+    twin->tsize = 8;
+    twin->stream = H->stream;
+    twin->operators_only = true;
+    ncs_status s = setup_typed<double>(twin);
+    if (s == NCS_OK) s = probe_estimate<double>(twin, probes, hn, hd);
+    ncs_cone_destroy(twin);
+    return s;
+}
+
+template <class T>
 ncs_status setup_typed(ncs_cone* H) {
     const ncs_cone_geometry& g = H->g;
     CONE_TRY(prepare_backproject<T>(H));
@@ -1175,7 +1238,10 @@ ncs_status setup_typed(ncs_cone* H) {
     CONE_TRY(upload<T>(H, H->kz, kz));
     CONE_TRY(upload<T>(H, H->tw_n, twiddles(N)));
     CONE_TRY(upload<T>(H, H->tw_z, twiddles(NZ)));
-    ConeCtx<T> c = make_ctx<T>(H);
+    if (H->operators_only) {   // a twin for probe_estimate_fp64
+        CONE_HIP(hipStreamSynchronize(H->stream));
+        return NCS_OK;
+    }
     // |E 1|^2 (the DC eigenvalue)
     {
         std::vector<double> ones(H->n, 1.0);
@@ -1192,29 +1258,9 @@ ncs_status setup_typed(ncs_cone* H) {
     H->mu_dc = p.mu_dc > 0.0 ? p.mu_dc : p.gamma + p.alpha * H->norm_e1_sq / (double)H->n;
     H->mu.assign(H->n, p.gamma);
     if (p.method == NCS_METHOD_NCS) {
-        // eq. H-fan with the 3D DFT: num and den accumulated in double on the device
-        const int probes = p.probes > 0 ? p.probes : 16;
-        double *num = nullptr, *den = nullptr;
-        void* spec2 = nullptr;
-        CONE_TRY(dalloc(H, reinterpret_cast<void**>(&num), H->n * sizeof(double)));
-        CONE_TRY(dalloc(H, reinterpret_cast<void**>(&den), H->n * sizeof(double)));
-        CONE_TRY(dalloc(H, &spec2, 2 * H->n * ts));
-        std::vector<double> pv;
-        for (int k = 0; k < probes; ++k) {
-            probe_values((uint64_t)k, H->n, pv);
-            CONE_TRY(upload<T>(H, H->w, pv));
-            CONE_TRY(forward_plain<T>(H, H->w, H->ysc));
-            CONE_HIP((launch_backproject<T, false>(H, c, H->ysc, H->x)));
-            CONE_HIP(launch_fft3_forward<T>(H, c, H->w, H->spec));
-            CONE_HIP(launch_fft3_forward<T>(H, c, H->x, spec2));
-            hipLaunchKernelGGL((k_cone_probe_acc<T>), dim3((unsigned)((H->n + 255) / 256)), dim3(256), 0, H->stream,
-                               static_cast<const T*>(H->spec), static_cast<const T*>(spec2), num, den, H->n);
-            CONE_HIP(hipGetLastError());
-        }
-        std::vector<double> hn(H->n), hd(H->n);
-        CONE_HIP(hipMemcpyAsync(hn.data(), num, H->n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
-        CONE_HIP(hipMemcpyAsync(hd.data(), den, H->n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
-        CONE_HIP(hipStreamSynchronize(H->stream));
+        // eq. H-fan with the 3D DFT, always through double-precision kernels
+        std::vector<double> hn, hd;
+        CONE_TRY(probe_estimate_fp64(H, p.probes > 0 ? p.probes : 16, hn, hd));
         std::vector<double> s2(N), s2z(NZ);
         for (int k = 0; k < N; ++k) s2[k] = std::pow(std::sin(k * kPi / N), 2);
         for (int l = 0; l < NZ; ++l) s2z[l] = std::pow(std::sin(l * kPi / NZ), 2);
@@ -1230,12 +1276,6 @@ ncs_status setup_typed(ncs_cone* H) {
         // x >= 0 (remark in Section 4.2): A gains the rows I, so alpha A^T A and M gain alpha I
         if (p.positivity)
             for (double& m : H->mu) m += p.alpha;
-        // the temporaries are the last three allocations
-        for (int r = 0; r < 3; ++r) {
-            CONE_HIP(hipFree(H->allocs.back()));
-            H->allocs.pop_back();
-        }
-        CONE_HIP(hipMemsetAsync(H->x, 0, H->n * ts, H->stream));
     }
     std::vector<double> hv(H->n);
     for (size_t i = 0; i < H->n; ++i) hv[i] = H->mu[i] != 0.0 ? 1.0 / H->mu[i] : 0.0;

@@ -50,6 +50,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr uint64_t kStateMagic = 0x3130303331303831ull;  // blob tag
 constexpr int kXcds = 8;                                 // XCDs of an MI355X (round-robin dispatch)
+constexpr int kGraphLevels = 8;                          // replayed chunks of 1, 2, 4, ..., 128 iterations
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -111,9 +112,10 @@ struct ncs_handle {
     double projector_ms[3] = {0.0, 0.0, 0.0};
     int backprojector = 2;
     double backprojector_ms[3] = {0.0, 0.0, 0.0};
-    int graph_chunk = 25;                 // <= 0: no graphs
+    int graph_chunk = 32;                 // largest replayed chunk; <= 0: no graphs
     hipStream_t cap_stream = nullptr;     // private stream used only for graph capture
-    hipGraphExec_t graph_exec = nullptr;  // graph_chunk iterations
+    int graph_levels = 0;                 // graphs[l] holds 2^l iterations, l < graph_levels
+    hipGraphExec_t graphs[kGraphLevels] = {};
     int iter_host = 0;                    // iteration count as last seen by the host
     std::vector<void*> allocs;
 };
@@ -463,44 +465,63 @@ hipError_t launch_phase(ncs_handle* h, int ph) {
                                : launch_iteration_phase<float>(single_launch<float>(h), ph, h->stream);
 }
 
-// Capture graph_chunk iterations once (on a private stream) and keep the
-// executable graph; replays then cost one launch per chunk.  Any capture
-// failure switches the handle to direct launches.
-void ensure_graph(ncs_handle* h) {
-    if (h->graph_exec || h->graph_chunk <= 0) return;
+// Capture one graph per power of two up to graph_chunk iterations (on a
+// private stream), all at the first iteration request, and keep the
+// executable graphs: any k is then replayed as the largest chunk repeated plus
+// the binary digits of the remainder, at most log2(graph_chunk) + k/graph_chunk
+// launches.  Any capture failure switches the handle to direct launches.
+void drop_graphs(ncs_handle* h) {
+    for (int l = 0; l < h->graph_levels; ++l)
+        if (h->graphs[l]) (void)hipGraphExecDestroy(h->graphs[l]);
+    for (auto& g : h->graphs) g = nullptr;
+    h->graph_levels = 0;
+}
+
+void ensure_graphs(ncs_handle* h) {
+    if (h->graph_levels > 0 || h->graph_chunk <= 0) return;
     if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         h->graph_chunk = 0;
         return;
     }
-    if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        h->graph_chunk = 0;
-        return;
-    }
-    const hipError_t le = launch_eager(h, h->graph_chunk, h->cap_stream);
-    hipGraph_t graph = nullptr;
-    const hipError_t ee = hipStreamEndCapture(h->cap_stream, &graph);
-    if (le != hipSuccess || ee != hipSuccess || !graph) {
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipGetLastError();
-        h->graph_chunk = 0;
-        return;
-    }
-    const hipError_t ie = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) {
-        h->graph_exec = nullptr;
-        (void)hipGetLastError();
-        h->graph_chunk = 0;
+    int levels = 0;
+    while (levels < kGraphLevels && (1 << levels) <= h->graph_chunk) ++levels;
+    for (int l = 0; l < levels; ++l) {
+        bool ok = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const hipError_t le = launch_eager(h, 1 << l, h->cap_stream);
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(h->cap_stream, &graph);
+            ok = le == hipSuccess && ee == hipSuccess && graph &&
+                 hipGraphInstantiate(&h->graphs[l], graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        if (!ok) {
+            (void)hipGetLastError();
+            h->graphs[l] = nullptr;
+            h->graph_levels = l;
+            drop_graphs(h);
+            h->graph_chunk = 0;
+            return;
+        }
+        h->graph_levels = l + 1;
     }
 }
 
 hipError_t launch_iters(ncs_handle* h, int k) {
-    if (h->graph_chunk > 0 && k >= h->graph_chunk) {
-        ensure_graph(h);
-        while (h->graph_exec && k >= h->graph_chunk) {
-            const hipError_t e = hipGraphLaunch(h->graph_exec, h->stream);
-            if (e != hipSuccess) return e;
-            k -= h->graph_chunk;
+    if (h->graph_chunk > 0 && k > 0) {
+        ensure_graphs(h);
+        if (h->graph_levels > 0) {
+            const int top = h->graph_levels - 1;
+            for (; k >= (1 << top); k -= 1 << top) {
+                const hipError_t e = hipGraphLaunch(h->graphs[top], h->stream);
+                if (e != hipSuccess) return e;
+            }
+            for (int l = top - 1; l >= 0; --l) {
+                if (!(k & (1 << l))) continue;
+                const hipError_t e = hipGraphLaunch(h->graphs[l], h->stream);
+                if (e != hipSuccess) return e;
+                k -= 1 << l;
+            }
         }
     }
     return k > 0 ? launch_eager(h, k, h->stream) : hipSuccess;
@@ -629,6 +650,13 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
         set_err("ADMM-CG needs 0 <= cg_iters <= 1000 (0 selects 10) and cg_precondition 0 or 1");
         return NCS_ERR_INVALID_ARG;
     }
+    if (p.method == NCS_METHOD_ADMM_CG && p.cg_precondition == 0 && dtype == NCS_F32) {
+        // unpreconditioned CG amplifies FP32 rounding by about the condition
+        // number of A^T A; its single-precision trajectories leave the FP64
+        // method by more than 1e-4, so only double precision runs it
+        set_err("ADMM-CG without the preconditioner runs in double precision only (NCS_F64)");
+        return NCS_ERR_INVALID_ARG;
+    }
     if (p.positivity != 0 && p.positivity != 1) {
         set_err("positivity must be 0 or 1");
         return NCS_ERR_INVALID_ARG;
@@ -664,12 +692,32 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
 // block owned by a batch; autotune = time the projector variants.
 ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype, const void* b_dev,
                        const void* bg_dev, hipStream_t stream, Control* ext_ctl, bool autotune,
-                       ncs_handle** out) {
+                       ncs_handle** out, bool operators_only = false);
+
+// eq. H-fan for a handle of either precision: the probes always go through
+// double-precision kernels, so that a single-precision handle runs the same M
+// as a double-precision one.  A single-precision handle borrows a
+// double-precision twin (same geometry, no data, no multiplier) for this.
+ncs_status estimate_multiplier_fp64(ncs_handle* h, int probes, std::vector<double>& he) {
+    if (h->dtype == NCS_F64) return estimate_normal_multiplier<double>(h, probes, he);
+    ncs_params q = h->p;
+    q.mu_dc = 1.0;   // the twin evaluates no |E 1|^2
+    ncs_handle* twin = nullptr;
+    ncs_status s = setup_slice(h->g, q, NCS_F64, nullptr, nullptr, h->stream, nullptr, false, &twin, true);
+    if (s) return s;
+    s = estimate_normal_multiplier<double>(twin, probes, he);
+    ncs_destroy(twin);
+    return s;
+}
+
+ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype, const void* b_dev,
+                       const void* bg_dev, hipStream_t stream, Control* ext_ctl, bool autotune,
+                       ncs_handle** out, bool operators_only) {
     ncs_handle* h = new ncs_handle();
     h->g = g;
     h->p = p;
     if (h->p.check_every <= 0) h->p.check_every = 50;
-    h->graph_chunk = p.graph_chunk == 0 ? 25 : (p.graph_chunk < 0 ? 0 : p.graph_chunk);
+    h->graph_chunk = p.graph_chunk == 0 ? 32 : (p.graph_chunk < 0 ? 0 : p.graph_chunk);
     if (p.method == NCS_METHOD_ADMM_CG && h->graph_chunk > 2) h->graph_chunk = 2;   // ~15 launches per CG step
     h->projector = p.projector == 0 ? 2 : p.projector;
     h->backprojector = p.backprojector == 0 ? 2 : p.backprojector;
@@ -807,11 +855,11 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
     const double bta = p.beta * p.beta / p.alpha;
     const int probes = p.probes > 0 ? p.probes : (g.beam == NCS_BEAM_FAN ? kFanProbes : 0);
     std::vector<double> he;   // eq. H-fan estimate of E^T E's multiplier (when probes > 0)
-    if (probes > 0) {
-        s = dtype == NCS_F64 ? estimate_normal_multiplier<double>(h, probes, he)
-                             : estimate_normal_multiplier<float>(h, probes, he);
-        if (s) return fail(s);
+    if (operators_only) {   // a twin for estimate_multiplier_fp64: tables and workspace only
+        *out = h;
+        return hipStreamSynchronize(stream) == hipSuccess ? NCS_OK : fail(NCS_ERR_HIP);
     }
+    if (probes > 0 && (s = estimate_multiplier_fp64(h, probes, he))) return fail(s);
     for (int j = 0; j < N; ++j) {
         const double jj = std::min(j, N - j);
         const double sj = std::sin(kPi * j / N);
@@ -914,7 +962,7 @@ void ncs_destroy(ncs_handle* h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
-    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    drop_graphs(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (void* ptr : h->allocs) (void)hipFree(ptr);
     delete h;

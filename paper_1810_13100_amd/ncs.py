@@ -180,7 +180,7 @@ class Params:
     check_every: int = 50
     diverge_checks: int = 0
     projector: int = 0        # 0: autotune at setup, 1: LDS-staged, 2: direct, 3: ray pairs
-    graph_chunk: int = 0      # 0: 25 iterations per HIP graph, < 0: no graphs
+    graph_chunk: int = 0      # 0: graphs of up to 32 iterations, < 0: no graphs
     dual_ramp: float = 0.0    # TV-dual ramp width of the warm start (0: sign)
     backprojector: int = 0    # 0: autotune at setup, 1: LDS-staged windows, 2: direct, 3: 2x2 per lane
                               # with 16-byte windows

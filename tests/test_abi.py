@@ -136,7 +136,8 @@ def test_slice_geometry_and_parameters_are_validated_before_gpu_work():
         ({}, dict(backprojector=4), b"backprojector"),
         ({}, dict(projector=4), b"projector"),
         (dict(beam=1, source_radius=128.0), dict(projector=1), b"fan beam"),
-        (dict(beam=1, source_radius=128.0), dict(method=2), b"fan beams run"),
+        (dict(beam=1, source_radius=128.0), dict(method=2, cg_precondition=1), b"fan beams run"),
+        ({}, dict(method=2, cg_precondition=0), b"double precision only"),   # FP32 plain CG
     ]
     for gk, pk, msg in cases:
         g = ncs._Geometry(**{**geo, **gk})

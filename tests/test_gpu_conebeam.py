@@ -5,9 +5,9 @@ solve, and whole NCS and PDHG trajectories (x, u, v and every objective).
 
 Gates: FP64 operators rel <= 1e-11 and adjointness to 1e-12; FP32 operators
 <= 1e-5 (phantom) and 1e-4 (random data); eigenvalues FP64 <= 1e-9, FP32
-<= 1e-4 (E^T E v and the DFT in FP32); trajectories FP64 x, u, v and f
-<= 1e-10; FP32 x <= 1e-4, f <= 1e-5 (PDHG) and 1e-4 (NCS, whose FP32 handle
-estimates the multiplier in FP32).  At the benchmark's size (256^2 x 64,
+<= 1e-6 (the probes of an FP32 handle go through the library's FP64 kernels;
+only the DC entry's |E 1|^2 comes from the FP32 projector); trajectories FP64
+x, u, v and f <= 1e-10; FP32 x <= 1e-4 and every f within 1e-5.  At the benchmark's size (256^2 x 64,
 72 views x 64 rows x 368 bins) the rays of sampled views are compared with
 the oracle's rows for those views, and the adjoint with the oracle's block
 transpose on data supported on those views."""
@@ -124,7 +124,7 @@ def _gamma():
     return 0.01 * nv * n / (2.0 * np.pi)
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-6)])
 def test_cone_eigenvalues_match_the_probe_estimate(prec, tol):
     prob = _problem()
     ref = conebeam.eigenvalues3d(prob, 0.01, 0.03, _gamma(), _h_e())
@@ -187,7 +187,7 @@ def test_cone_trajectory_matches_oracle(method, prec):
     if prec == "f64":
         assert max(ex, eu, ev, ef) <= 1e-10
     else:
-        assert ex <= 1e-4 and ef <= (1e-4 if method == "ncs" else 1e-5)
+        assert ex <= 1e-4 and ef <= 1e-5
 
 
 def test_cone_runs_repeat_bit_for_bit():
@@ -333,7 +333,7 @@ def test_cone_positivity_matches_oracle(prec):
     if prec == "f64":
         assert max(ex, et, ef) <= 1e-10
     else:
-        assert ex <= 1e-4 and et <= 1e-4 and ef <= 1e-4
+        assert ex <= 1e-4 and et <= 1e-4 and ef <= 1e-5
     assert t.max() <= 0.0
 
 

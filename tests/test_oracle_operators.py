@@ -59,7 +59,10 @@ def test_h_r_mask_closed_form():
     np.testing.assert_array_equal(hr, hr.T)
 
 
-def test_ncs_multiplier_terms_and_dc():
+def test_ncs_multiplier_layout_and_dc():
+    # index layout only (numpy FFT order, the DC slot, h = 1/mu); the weights of
+    # the terms are pinned against the operators themselves in
+    # test_mu_matches_the_probe_estimate_of_alpha_AtA
     n, a, b, g, cr, dc = 8, 0.3, 0.7, 2.0, 5.0, 11.0
     mu = operators.ncs_eigenvalues(n, a, b, g, cr, dc)
     assert mu[0, 0] == dc
@@ -68,6 +71,42 @@ def test_ncs_multiplier_terms_and_dc():
     assert mu[j, k] == pytest.approx(expect)
     h = operators.ncs_multiplier(n, a, b, g, cr, dc)
     np.testing.assert_allclose(h * mu, 1.0)
+
+
+def _ring_ratios(est, mu_minus_gamma, n):
+    """Sum of est over sum of mu - gamma on each ring round(|omega|) = 1, 2, ..."""
+    jj = np.minimum(np.arange(n), n - np.arange(n))
+    ring = np.rint(np.sqrt(jj[:, None] ** 2 + jj[None, :] ** 2)).astype(int)
+    return np.array([est[ring == r].sum() / mu_minus_gamma[ring == r].sum() for r in range(1, ring.max() + 1)])
+
+
+def test_mu_matches_the_probe_estimate_of_alpha_AtA():
+    # M - gamma I = alpha C must approximate alpha A^T A = alpha E^T E + (beta^2/alpha) D^T D
+    # (Sections 1.2 and 4.1.1: eq. circ_R for E^T E, eq. circ_D for D^T D).  The
+    # multiplier of the actual operator alpha A^T A is estimated from 32 probes
+    # (eq. H-fan) and compared with the oracle's mu - gamma ring by ring at 64^2.
+    # Joseph interpolation damps E^T E at high frequencies (ratios fall to about
+    # 0.64 there) but the low rings, where alpha C_R / |omega| dominates, agree
+    # within 10%; with beta/alpha = 30 the difference term dominates every ring
+    # and all agree within 10%.  A dropped alpha on H_R, a D weight of beta,
+    # beta^2/alpha^2 or beta^2, or an M scaled by 2 breaks one of the bands.
+    from oracle import fanbeam, problems, projector
+    n, na, ns = 64, 90, 92
+    E = projector.joseph_matrix(n, na, ns)
+    Et = E.T.tocsr()
+    D = operators.diff_2d(n)
+    Dt = D.T.tocsr()
+    z = np.zeros(E.shape[0])
+    prob = problems.Problem("ct", "aniso", n, na, ns, 0.01, E, D, z, z, np.zeros(n * n))
+    for a, b, lo_band, all_band in ((0.01, 0.03, (0.9, 1.05), (0.6, 1.05)),
+                                   (0.01, 0.3, (0.9, 1.05), (0.9, 1.05))):
+        g = 0.3 * a * operators.default_c_r(n, na)
+        mu = problems.eigenvalues(prob, problems.Params(a, b, g))
+        r2 = (b / a) ** 2
+        est = a * fanbeam.probe_multiplier(lambda v: Et @ (E @ v) + r2 * (Dt @ (D @ v)), n, 32)
+        rat = _ring_ratios(est, mu - g, n)
+        assert lo_band[0] <= rat[:8].min() and rat[:8].max() <= lo_band[1], rat[:8]
+        assert all_band[0] <= rat.min() and rat.max() <= all_band[1], rat
 
 
 def test_circulant_pseudo_inverse():
