@@ -60,6 +60,16 @@ def oracle_ncs(prob, par, iters):
     return _traj_cache[key]
 
 
+def assert_converging(obj) -> None:
+    """A trajectory compared for parity must come from a convergent run: its
+    objective ends finite, below the first value and within 5% of its minimum
+    (relative errors between two diverging runs say nothing)."""
+    obj = np.asarray(obj, dtype=np.float64)
+    fin = obj[np.isfinite(obj)]
+    assert fin.size and np.isfinite(obj[-1]), "objective not finite at the end"
+    assert obj[-1] < fin[0] and obj[-1] <= fin.min() + 0.05 * abs(fin.min()), (fin[0], fin.min(), obj[-1])
+
+
 def rel_l2(a, b) -> float:
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)

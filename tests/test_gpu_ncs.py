@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import ncs_inputs
-from gpu_common import GEOMS, ct_params, ct_problem, joseph, log, oracle_ncs, pet_problem, rel_l2
+from gpu_common import GEOMS, assert_converging, ct_params, ct_problem, joseph, log, oracle_ncs, pet_problem, rel_l2
 from oracle import problems, solvers
 from paper_1810_13100_amd import ncs
 
@@ -41,6 +41,7 @@ def pet_params(n_side, n_angles):
 
 def check_trajectory(prob, par, iters, prec, **kw):
     ref = oracle_ncs(prob, par, iters)
+    assert_converging(ref.obj)
     s = make_solver(prob, par, DT[prec], **kw)
     s.set_init()
     obj = s.iterate(iters, record=True)
