@@ -112,6 +112,8 @@ struct ncs_handle {
     double projector_ms[3] = {0.0, 0.0, 0.0};
     int backprojector = 2;
     double backprojector_ms[3] = {0.0, 0.0, 0.0};
+    int32_t* aorder = nullptr;            // angles by stepping axis (single parallel-beam slices)
+    int nar = 0;                          // row-stepping angles
     int graph_chunk = 32;                 // largest replayed chunk; <= 0: no graphs
     hipStream_t cap_stream = nullptr;     // private stream used only for graph capture
     int graph_levels = 0;                 // graphs[l] holds 2^l iterations, l < graph_levels
@@ -149,8 +151,11 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
     c.NA = h->g.n_angles;
     c.NS = h->g.n_bins;
     c.PU = h->PU;
-    c.P = h->g.n_side + 4;
+    c.P = h->g.n_side + 2 * kPadL;
     c.nb_proj = project_blocks(c.NA, c.NS);
+    c.aorder = h->aorder;
+    c.nar = h->nar;
+    c.nwg_proj = h->aorder ? project_wgs_split(c.NA, c.NS, h->nar) : c.nb_proj;
     c.nb_tv = tv_blocks(c.N);
     c.ang = static_cast<const AngleT<T>*>(h->ang);
     c.axis = h->axis;
@@ -215,7 +220,8 @@ IterLaunch<T> single_launch(const ncs_handle* h) {
     L.bp = {nullptr, bp_blocks(N, h->backprojector)};
     L.rows = {nullptr, N / 2};
     L.cols = {nullptr, N / 2 + 1};
-    L.proj = {nullptr, project_blocks(h->g.n_angles, h->g.n_bins) + tv_blocks(N)};
+    L.proj = {nullptr, (h->aorder ? project_wgs_split(h->g.n_angles, h->g.n_bins, h->nar)
+                                  : project_blocks(h->g.n_angles, h->g.n_bins)) + tv_blocks(N)};
     L.fin = {nullptr, 1};
     L.max_N = N;
     L.projector = h->projector;
@@ -776,7 +782,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
     // ---- workspace ---------------------------------------------------------
     const size_t e = h->esz;
     const int NH = N / 2 + 1;
-    const size_t padded = (size_t)N * (N + 4) * e;
+    const size_t padded = (size_t)N * (N + 2 * kPadL) * e;
     const size_t nparts = std::max<size_t>({(size_t)project_blocks(NA, NS), (h->m + 255) / 256, (size_t)1});
     const size_t ctx_bytes = dtype == NCS_F64 ? sizeof(DevCtx<double>) : sizeof(DevCtx<float>);
     ncs_status s;
@@ -809,6 +815,22 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
             (s = dev_alloc(h, &h->views, (size_t)NA * view_bytes)) ||
             (s = dtype == NCS_F64 ? upload_fan<double>(h, views) : upload_fan<float>(h, views)))
             return fail(s);
+    }
+    // a single parallel-beam slice splits its projection blocks over the XCDs
+    // by stepping axis (batches map their workgroups themselves)
+    if (!ext_ctl && g.beam == NCS_BEAM_PARALLEL) {
+        std::vector<int32_t> order;
+        order.reserve(NA);
+        for (int a = 0; a < NA; ++a)
+            if (axis[a] == 0) order.push_back(a);
+        h->nar = (int)order.size();
+        for (int a = 0; a < NA; ++a)
+            if (axis[a] != 0) order.push_back(a);
+        if ((s = dev_alloc(h, reinterpret_cast<void**>(&h->aorder), (size_t)NA * sizeof(int32_t)))) return fail(s);
+        if (hipMemcpy(h->aorder, order.data(), (size_t)NA * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            set_err("ncs_setup: angle order upload failed");
+            return fail(NCS_ERR_HIP);
+        }
     }
     if (ext_ctl) {
         h->ctl = ext_ctl;

@@ -17,6 +17,13 @@
 
 namespace ncs {
 
+// Zero columns on each side of a row of the padded image copies (x bar, its
+// transpose and the scratch pair).  A 64-ray projector block spans at most
+// 63 sqrt(2) < 90 columns, and every step of its range has some ray within
+// [-2, N + 1] (two steps of margin included), so each tap of every ray of the
+// block lies in [-96, N + 95]: the direct projector reads them without a clamp.
+constexpr int kPadL = 96;
+
 // Per-angle geometry, precomputed in double on the host and stored in T.
 //   forward (ray-driven):  sampled coordinate of ray d at step s
 //                          xi(d, s) = fma(s, k2, fma(d, k1, k0))
@@ -72,8 +79,16 @@ enum { TV_ANISO = 0, TV_ISO = 1 };
 template <class T>
 struct DevCtx {
     int N, log2N, NA, NS, PU;        // PU: padded sinogram pitch = NS + 3 (entry d at a*PU + 1 + d)
-    int P;                           // padded image pitch = N + 4 (pixel c of a row at offset c + 2)
-    int nb_proj, nb_tv;              // projection and TV workgroups of this slice
+    int P;                           // padded image pitch = N + 2 kPadL (pixel c of a row at offset c + kPadL)
+    int nb_proj, nb_tv;              // (angle, 64-ray block) pairs and TV tiles of this slice
+    int nwg_proj;                    // projection workgroups of a launch (>= nb_proj with aorder)
+    // single parallel-beam slices: the angles ordered by stepping axis (row-
+    // stepping ones first, nar of them); a projection launch then sends
+    // row-stepping blocks to XCDs 0-3 and column-stepping ones to XCDs 4-7
+    // (workgroup b runs on XCD b mod 8), so each XCD's L2 holds one image copy.
+    // Null: workgroup b takes block b (batches, fan beams).
+    const NCS_G int32_t* aorder;
+    int nar;
     const NCS_G AngleT<T>* ang;
     const NCS_G int32_t* axis;
     NCS_G T* x;        // N*N current image
@@ -195,6 +210,8 @@ hipError_t launch_control(Control* ctl, int op, int iter_value, double f_target,
 void set_error_message(const char* msg);
 
 int project_blocks(int NA, int NS);
+// projection workgroups when the blocks are split by stepping axis over the XCDs
+int project_wgs_split(int NA, int NS, int nar);
 int tv_blocks(int N);
 int bp_blocks(int N, int variant);
 

@@ -37,14 +37,11 @@ namespace {
 #ifndef NCS_UNROLL_BP
 #define NCS_UNROLL_BP 4
 #endif
-#ifndef NCS_UNROLL_BPQ
-#define NCS_UNROLL_BPQ 2
-#endif
-#ifndef NCS_UNROLL_PROJ
-#define NCS_UNROLL_PROJ 8
-#endif
 #ifndef NCS_UNROLL_PAIR
 #define NCS_UNROLL_PAIR 4
+#endif
+#ifndef NCS_UNROLL_BPQ
+#define NCS_UNROLL_BPQ 2
 #endif
 
 constexpr int kRays = 64;      // rays per projector workgroup (one per lane)
@@ -776,25 +773,40 @@ __device__ inline double project_epilogue(const DevCtx<T>& c, int a, int d, T q,
     return dterm;
 }
 
-// Ray sum of lane's ray by the direct method: one lane per ray, the 4 waves
-// split the steps.  Column-stepping angles read the transposed copy so that
-// every angle walks along contiguous rows; two zero columns on each side of
-// a row absorb taps that fall off the image, so the clamped tap index needs
-// no per-step test.
+// floor(v) as an integer and v - floor(v), one instruction each in single
+// precision (v_cvt_flr_i32_f32, v_fract_f32).
 template <class T>
-__device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
-                                   const AngleT<T>& A, int axis, int d0, int d, int wave) {
-    const int N = c.N, P = c.P;
-    const T* src = axis == 0 ? img : imgT;
-    const T base = fma((T)d, A.k1, A.k0);
-    // Steps where some ray of the block has xi in [-2, N+1] (all rays of an
-    // angle share the slope k2 in s, so the block's xi at step s spans
-    // [blo, bhi] + s k2); the margin keeps the range conservative.
+__device__ inline int floor_int(T v) {
+    return (int)floor(v);
+}
+template <>
+__device__ inline int floor_int<float>(float v) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+template <class T>
+__device__ inline T frac_part(T v) {
+    return v - floor(v);
+}
+template <>
+__device__ inline float frac_part<float>(float v) {
+    return __builtin_amdgcn_fractf(v);
+}
+
+// Steps [s_begin, s_end) of part `part` of `nparts` of the steps where some ray
+// of the 64-ray block starting at d0 has its coordinate in [-2, N + 1].  All
+// rays of an angle share the slope k2 in s, so the block's coordinates at step
+// s span [blo, bhi] + s k2; one step of margin on each side keeps the range
+// conservative under rounding.
+template <class T>
+__device__ inline void block_step_range(const AngleT<T>& A, int N, int d0, int part, int nparts, int& s_begin,
+                                        int& s_end) {
     const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
     const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
     const T lo_x = T(-2), hi_x = T(N + 1);
-    const int SW = N / kWaves;
-    int s_begin = wave * SW, s_end = s_begin + SW;
+    s_begin = (part * N) / nparts;
+    s_end = ((part + 1) * N) / nparts;
     if (A.k2 > T(0)) {
         s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
         s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
@@ -804,19 +816,54 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
     } else if (bhi < lo_x || blo > hi_x) {
         s_end = s_begin;
     }
+}
+
+// Ray sum of the lane's ray by the direct method: one lane per ray, the waves
+// of the workgroup split the steps.  Column-stepping angles read the
+// transposed copy so that every angle walks along contiguous rows.  The
+// kPadL zero columns on each side of a row hold every tap of the block's rays
+// at the steps of its range, so a tap is read without a clamp: per step the
+// coordinate (one multiply-add from an anchor taken every 8 steps), its floor
+// as an integer and its fraction, one byte offset from the wave-uniform row
+// address, one 8-byte load and the linear interpolation.
+template <class T>
+__device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
+                                   const AngleT<T>& A, int axis, int d0, int d, int part, int nparts) {
+    const int P = c.P;
+    const T* src = axis == 0 ? img : imgT;
+    const T base = fma((T)d, A.k1, A.k0);
+    int s_begin, s_end;
+    block_step_range(A, c.N, d0, part, nparts, s_begin, s_end);
+    const T k2 = A.k2;
     T acc = T(0);
-    const T cmax = (T)N;
-#pragma unroll NCS_UNROLL_PROJ
-    for (int s = s_begin; s < s_end; ++s) {
-        const T xi = fma((T)s, A.k2, base);
-        const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
-        const T f = xi - fl;
-        // the row address is the same for the whole wave (scalar registers);
-        // each lane adds a 32-bit byte offset
-        const char* row = reinterpret_cast<const char*>(src + (size_t)s * P);
-        const unsigned boff = (unsigned)((int)fl + 2) * (unsigned)sizeof(T);
+    // the row address is the same for the whole wave (scalar registers); each
+    // lane adds a 32-bit byte offset (the zero margin keeps it nonnegative)
+    const char* row = reinterpret_cast<const char*>(src + (size_t)max(s_begin, 0) * P);
+    const size_t pitch = (size_t)P * sizeof(T);
+    constexpr unsigned pad_bytes = kPadL * sizeof(T);
+    constexpr int B = 8;   // steps per unrolled group (loads in flight per lane)
+    int s = s_begin;
+    for (; s + B <= s_end; s += B) {
+        const T xa = fma((T)s, k2, base);
+        Pair<T> v[B];
+        T f[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const T xi = j == 0 ? xa : fma((T)j, k2, xa);
+            f[j] = frac_part(xi);
+            const unsigned boff = (unsigned)floor_int(xi) * (unsigned)sizeof(T) + pad_bytes;
+            v[j] = *reinterpret_cast<const Pair<T>*>(row + (size_t)j * pitch + boff);
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc += fma(f[j], v[j].b - v[j].a, v[j].a);
+        row += B * pitch;
+    }
+    for (; s < s_end; ++s) {
+        const T xi = fma((T)s, k2, base);
+        const unsigned boff = (unsigned)floor_int(xi) * (unsigned)sizeof(T) + pad_bytes;
         const Pair<T> v = *reinterpret_cast<const Pair<T>*>(row + boff);
-        acc += fma(f, v.b - v.a, v.a);
+        acc += fma(frac_part(xi), v.b - v.a, v.a);
+        row += pitch;
     }
     return acc;
 }
@@ -859,7 +906,7 @@ __device__ inline void ray_sum_pair(const DevCtx<T>& c, const T* __restrict__ im
         const T l0 = med3(floor(x0), T(-2), cmax), l1 = med3(floor(x1), T(-2), cmax);   // zero columns off the image
         // the 4 elements from the smaller tap, kept inside the padded row
         const int base = min((int)fmin(l0, l1), N - 2);
-        const Four<T> v = *reinterpret_cast<const Four<T>*>(src + (size_t)s * P + base + 2);
+        const Four<T> v = *reinterpret_cast<const Four<T>*>(src + (size_t)s * P + base + kPadL);
         const T fb = (T)base;
         const int j0 = min(max((int)(l0 - fb), 0), 2), j1 = min(max((int)(l1 - fb), 0), 2);
         const T f0 = x0 - l0, f1 = x1 - l1;
@@ -892,8 +939,8 @@ __device__ inline void wave_lds_sync() {
 
 template <class T>
 __device__ inline int row_window_base(const AngleT<T>& A, int s, T blo, T cmax) {
-    // element index (column + 2) of the column left of the clamped smallest coordinate
-    const int lo = (int)med3(floor(fma((T)s, A.k2, blo)), T(-2), cmax) + 1;
+    // element index (column + kPadL) of the column left of the clamped smallest coordinate
+    const int lo = (int)med3(floor(fma((T)s, A.k2, blo)), T(-2), cmax) + kPadL - 1;
     return lo & ~3;
 }
 
@@ -953,7 +1000,7 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
             const T xi = fma((T)(s0 + i), A.k2, base);
             const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
             const T f = xi - fl;
-            int j = (int)fl + 2 - rbase[i];
+            int j = (int)fl + kPadL - rbase[i];
             j = min(max(j, 0), kRowWin - 2);
             const T* tp = stage + i * kRowWin + j;
             const T v0 = tp[0], v1 = tp[1];
@@ -994,7 +1041,7 @@ __device__ inline T ray_sum_fan(const DevCtx<T>& c, const T* __restrict__ img, c
         const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
         const T f = xi - fl;
         const char* row = reinterpret_cast<const char*>(src + (size_t)s * P);   // the same for the wave
-        const Pair<T> v = *reinterpret_cast<const Pair<T>*>(row + (unsigned)((int)fl + 2) * (unsigned)sizeof(T));
+        const Pair<T> v = *reinterpret_cast<const Pair<T>*>(row + (unsigned)((int)fl + kPadL) * (unsigned)sizeof(T));
         acc += fma(f, v.b - v.a, v.a);
     }
     return acc;
@@ -1002,15 +1049,14 @@ __device__ inline T ray_sum_fan(const DevCtx<T>& c, const T* __restrict__ img, c
 
 // TV dual update of one 256-pixel tile and the TV term of x+ (ITER only).
 template <class T>
-__device__ inline double tv_tile(const DevCtx<T>& c, int tile) {
+__device__ inline double tv_pixel(const DevCtx<T>& c, size_t pix) {
     const int N = c.N;
     const size_t NN = (size_t)N * N;
-    const size_t pix = (size_t)tile * 256 + threadIdx.x;
     if (pix >= NN) return 0.0;
     const int r = (int)(pix >> c.log2N);
     const int col = (int)(pix & (size_t)(N - 1));
     const bool hx = col < N - 1, hy = r < N - 1;
-    const T* xbp = c.xbar + (size_t)r * c.P + col + 2;
+    const T* xbp = c.xbar + (size_t)r * c.P + col + kPadL;
     const T xb = xbp[0];
     const T dh = hx ? xb - xbp[1] : T(0);
     const T dv = hy ? xb - xbp[c.P] : T(0);
@@ -1032,6 +1078,11 @@ __device__ inline double tv_tile(const DevCtx<T>& c, int tile) {
     const double th = hx ? xx - (double)c.x[pix + 1] : 0.0;
     const double tw = hy ? xx - (double)c.x[pix + N] : 0.0;
     return c.tv_term == TV_ANISO ? fabs(th) + fabs(tw) : sqrt(th * th + tw * tw);
+}
+
+template <class T>
+__device__ inline double tv_tile(const DevCtx<T>& c, int tile) {
+    return tv_pixel(c, (size_t)tile * 256 + threadIdx.x);
 }
 
 template <class T>
@@ -1059,15 +1110,27 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const T* img = MODE == PMODE_ITER ? c.xbar : c.xsc;
     const T* imgT = MODE == PMODE_ITER ? c.xbarT : c.xscT;
-    if (MODE == PMODE_ITER && local >= c.nb_proj) {
+    if (MODE == PMODE_ITER && local >= c.nwg_proj) {
         if (c.ctl->stop) return;   // its own read: the TV workgroups write v at once
-        const double tv = block_sum256(tv_tile(c, local - c.nb_proj), shd);
-        if (threadIdx.x == 0) c.part_tv[local - c.nb_proj] = tv;
+        const double tv = block_sum256(tv_tile(c, local - c.nwg_proj), shd);
+        if (threadIdx.x == 0) c.part_tv[local - c.nwg_proj] = tv;
         return;
     }
     const int nb = (c.NS + kRays - 1) / kRays;
-    const int a = local / nb;
-    const int d0 = (local - a * nb) * kRays;
+    int a, rb;
+    if (c.aorder) {   // XCDs 0-3: row-stepping blocks, XCDs 4-7: column-stepping blocks
+        const int xcd = local & 7, k = (local >> 3) * 4 + (xcd & 3);
+        const bool colsax = xcd >= 4;
+        if (k >= (colsax ? c.NA - c.nar : c.nar) * nb) return;   // an idle slot of the split grid
+        const int j = k / nb;
+        rb = k - j * nb;
+        a = c.aorder[(colsax ? c.nar : 0) + j];
+    } else {
+        a = local / nb;
+        rb = local - a * nb;
+    }
+    const int blk = a * nb + rb;   // this block's data partial
+    const int d0 = rb * kRays;
     const int d = d0 + lane;
     const AngleT<T> A = c.ang[a];
     const int axis = c.axis[a];
@@ -1079,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
         if (wave != 0 || stop) return;   // a stopped slice writes nothing
         const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * R.kappa;
         const double dterm = wave_sum(project_epilogue<T, MODE>(c, a, d, q, out));
-        if (MODE == PMODE_ITER && lane == 0) c.part_data[local] = dterm;
+        if (MODE == PMODE_ITER && lane == 0) c.part_data[blk] = dterm;
         return;
     }
     if (VARIANT == 3) {
@@ -1091,7 +1154,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
         for (int r = 1; r < 2 * kWaves; ++r) sum += red[r * kRays + lane];
         const T q = sum * A.kappa;
         const double dterm = wave_sum(project_epilogue<T, MODE>(c, a, d, q, out));
-        if (MODE == PMODE_ITER && lane == 0) c.part_data[local] = dterm;
+        if (MODE == PMODE_ITER && lane == 0) c.part_data[blk] = dterm;
         return;
     }
     T acc;
@@ -1101,14 +1164,14 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
         acc = ray_sum_lds(c, img, imgT, A, axis, d0, d, lane, wave, stage + wave * kStageRows * kRowWin,
                           rbase + wave * kStageRows);
     } else {
-        acc = ray_sum_direct(c, img, imgT, A, axis, d0, d, wave);
+        acc = ray_sum_direct(c, img, imgT, A, axis, d0, d, wave, kWaves);
     }
     red[wave * kRays + lane] = acc;
     __syncthreads();
     if (wave != 0 || stop) return;   // a stopped slice writes nothing
     const T q = ((red[lane] + red[kRays + lane]) + (red[2 * kRays + lane] + red[3 * kRays + lane])) * A.kappa;
     const double dterm = wave_sum(project_epilogue<T, MODE>(c, a, d, q, out));
-    if (MODE == PMODE_ITER && lane == 0) c.part_data[local] = dterm;
+    if (MODE == PMODE_ITER && lane == 0) c.part_data[blk] = dterm;
 }
 
 // ---------------------------------------------------------------------------
@@ -1246,9 +1309,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const DevCtx<T>* _
             c.tpos[ra + n] = fmin(fma(c.alpha, ba, c.tpos[ra + n]), T(0));
             c.tpos[rb + n] = fmin(fma(c.alpha, bb, c.tpos[rb + n]), T(0));
         }
-        c.xbar[(size_t)(2 * pr) * c.P + n + 2] = ba;
-        c.xbar[(size_t)(2 * pr + 1) * c.P + n + 2] = bb;
-        *reinterpret_cast<Pair<T>*>(c.xbarT + (size_t)n * c.P + 2 * pr + 2) = Pair<T>{ba, bb};
+        c.xbar[(size_t)(2 * pr) * c.P + n + kPadL] = ba;
+        c.xbar[(size_t)(2 * pr + 1) * c.P + n + kPadL] = bb;
+        *reinterpret_cast<Pair<T>*>(c.xbarT + (size_t)n * c.P + 2 * pr + kPadL) = Pair<T>{ba, bb};
     }
 }
 
@@ -1336,8 +1399,8 @@ __global__ __launch_bounds__(256) void k_ones_image(const DevCtx<T>* __restrict_
     if (pix >= (size_t)c.N * c.N) return;
     const int r = (int)(pix >> c.log2N);
     const int col = (int)(pix & (size_t)(c.N - 1));
-    c.xsc[(size_t)r * c.P + col + 2] = T(1);
-    c.xscT[(size_t)col * c.P + r + 2] = T(1);
+    c.xsc[(size_t)r * c.P + col + kPadL] = T(1);
+    c.xscT[(size_t)col * c.P + r + kPadL] = T(1);
 }
 
 // which: 1 = evaluation (eval_out = data + constant + lambda TV),
@@ -1400,8 +1463,8 @@ __global__ __launch_bounds__(256) void k_pad_image(const DevCtx<T>* __restrict__
     const int r = (int)(pix >> c.log2N);
     const int col = (int)(pix & (size_t)(c.N - 1));
     const T v = img[pix];
-    c.xsc[(size_t)r * c.P + col + 2] = v;
-    c.xscT[(size_t)col * c.P + r + 2] = v;
+    c.xsc[(size_t)r * c.P + col + kPadL] = v;
+    c.xscT[(size_t)col * c.P + r + kPadL] = v;
 }
 
 // Dual initialisation from x0 (fixed-point relations of the optimality
@@ -1613,8 +1676,8 @@ __global__ __launch_bounds__(256) void k_admm_update(const DevCtx<T>* __restrict
     const T xn = x - c.cg_d[pix] / c.alpha;
     c.x[pix] = xn;
     const T xb = fma(T(2), xn, -x);
-    c.xbar[(size_t)r * c.P + col + 2] = xb;
-    c.xbarT[(size_t)col * c.P + r + 2] = xb;
+    c.xbar[(size_t)r * c.P + col + kPadL] = xb;
+    c.xbarT[(size_t)col * c.P + r + kPadL] = xb;
 }
 
 __global__ void k_control(Control* ctl, int op, int iter_value, double f_target) {
@@ -1648,6 +1711,13 @@ hipError_t launch_project(const DevCtx<T>* ctxs, const Slot* map, int blocks, in
 }  // namespace
 
 int project_blocks(int NA, int NS) { return NA * ((NS + kRays - 1) / kRays); }
+
+int project_wgs_split(int NA, int NS, int nar) {
+    const int nb = (NS + kRays - 1) / kRays;
+    const int items = std::max(nar, NA - nar) * nb;
+    return 8 * ((items + 3) / 4);
+}
+
 int tv_blocks(int N) { return (int)blocks_for((size_t)N * N); }
 int cg_blocks(int N) { return (int)blocks_for((size_t)N * N); }
 
@@ -1745,9 +1815,7 @@ hipError_t launch_admm_iterations(const IterLaunch<T>& L, const DevCtx<T>& hc, i
         for (int j = 0; j < cg_iters; ++j) {
             // q = A^T A p = E^T E p + (beta/alpha)^2 D^T D p
             hipLaunchKernelGGL((k_pad_image<T>), dim3(tv_blocks(hc.N)), dim3(256), 0, st, dc, (const T*)hc.cg_p);
-            if ((e = launch_project<T, PMODE_PLAIN>(dc, nullptr, project_blocks(hc.NA, hc.NS), L.projector,
-                                                    (T*)hc.cg_y, st)) != hipSuccess)
-                return e;
+            if ((e = launch_project_plain<T>(hc, dc, L.projector, (T*)hc.cg_y, st)) != hipSuccess) return e;
             if ((e = launch_pad_sinogram<T>(hc, dc, (const T*)hc.cg_y, hc.ysc, st)) != hipSuccess) return e;
             if ((e = launch_backproject_plain<T>(hc, dc, L.backprojector, hc.ysc, hc.cg_q, st)) != hipSuccess)
                 return e;
@@ -1815,12 +1883,12 @@ hipError_t launch_pad_image(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* i
 
 template <class T>
 hipError_t launch_project_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, T* out, hipStream_t st) {
-    return launch_project<T, PMODE_PLAIN>(dc, nullptr, project_blocks(hc.NA, hc.NS), projector, out, st);
+    return launch_project<T, PMODE_PLAIN>(dc, nullptr, hc.nwg_proj, projector, out, st);
 }
 
 template <class T>
 hipError_t launch_project_setp(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, hipStream_t st) {
-    return launch_project<T, PMODE_SETP>(dc, nullptr, project_blocks(hc.NA, hc.NS), projector, (T*)nullptr, st);
+    return launch_project<T, PMODE_SETP>(dc, nullptr, hc.nwg_proj, projector, (T*)nullptr, st);
 }
 
 // f(img): project into the scratch sinogram (unpadded view), data and TV

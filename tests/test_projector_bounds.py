@@ -1,0 +1,135 @@
+"""Address bounds and grid decode of the direct projector, checked on the CPU.
+
+The direct kernel (projector 2) reads image rows without clamping the tap
+column: it relies on the kPadL = 96 zero columns on each side of a padded row
+(csrc/ncs_internal.h) to hold every tap of a 64-ray block at every step of the
+block's step range.  This test replays the
+kernels' single-precision address arithmetic (per-angle coefficients from
+double on the host rounded to float, the block step range with its float
+divisions, the anchored fused multiply-adds of the unrolled loops and the
+remainder loop) for the workload geometries and asserts that every read stays
+inside the padded row: columns -96 .. N+95.  Fused multiply-adds are replayed
+exactly: the product of a small integer and a float is exact in double, so
+one rounding of the double sum is the fused result.
+"""
+import math
+
+import numpy as np
+import pytest
+
+PAD = 96
+F32 = np.float32
+
+
+def _r32(x):
+    return np.asarray(x, dtype=np.float64).astype(F32)
+
+
+def _fma32(a, b, c):
+    """fma(a, b, c) in single precision for integer-valued a (exact product in double)."""
+    return _r32(np.asarray(a, np.float64) * np.asarray(b, np.float64) + np.asarray(c, np.float64))
+
+
+def _angles(n, na, ns):
+    """k1, k2, k0 per angle (float32), as the host computes them in double."""
+    hn, hs = 0.5 * (n - 1), 0.5 * (ns - 1)
+    out = []
+    for a in range(na):
+        th = math.pi * a / na
+        ct, st = math.cos(th), math.sin(th)
+        if 4 * a <= na or 4 * a >= 3 * na:
+            k1, k2, k0 = 1.0 / ct, -st / ct, -hs / ct + hn * st / ct + hn
+        else:
+            k1, k2, k0 = 1.0 / st, -ct / st, -hs / st + hn * ct / st + hn
+        out.append((F32(k1), F32(k2), F32(k0)))
+    return out
+
+
+def _sat(v):
+    return int(min(max(float(v), -1.0e9), 1.0e9))
+
+
+def _block_range(k1, k2, k0, n, d0, part, nparts):
+    bA, bB = _fma32(d0, k1, k0), _fma32(d0 + 63, k1, k0)
+    blo, bhi = min(bA, bB), max(bA, bB)
+    lo_x, hi_x = F32(-2), F32(n + 1)
+    sb, se = (part * n) // nparts, ((part + 1) * n) // nparts
+    if k2 > 0:
+        sb = max(sb, _sat(np.floor(F32(lo_x - bhi) / k2)) - 1)
+        se = min(se, _sat(np.ceil(F32(hi_x - blo) / k2)) + 2)
+    elif k2 < 0:
+        sb = max(sb, _sat(np.floor(F32(hi_x - blo) / k2)) - 1)
+        se = min(se, _sat(np.ceil(F32(lo_x - bhi) / k2)) + 2)
+    elif bhi < lo_x or blo > hi_x:
+        se = sb
+    return sb, se
+
+
+def _coords(base, k2, sb, se, unroll):
+    """Coordinates of each step of [sb, se) as the unrolled loop forms them
+    (rows: lanes, columns: steps)."""
+    cols = []
+    s = sb
+    while s + unroll <= se:
+        xa = _fma32(s, k2, base)
+        cols.append(xa)
+        for j in range(1, unroll):
+            cols.append(_fma32(j, k2, xa))
+        s += unroll
+    for s in range(s, se):
+        cols.append(_fma32(s, k2, base))
+    return np.stack(cols, axis=1) if cols else np.zeros((base.size, 0), F32)
+
+
+GEOMS = [(16, 7, 23), (64, 90, 92), (128, 179, 130), (128, 180, 185), (256, 358, 260), (256, 360, 367),
+         (512, 717, 520)]
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=[f"{g[0]}x{g[1]}x{g[2]}" for g in GEOMS])
+def test_direct_projector_reads_stay_in_the_padded_rows(geom):
+    n, na, ns = geom
+    nb = (ns + 63) // 64
+    angles = range(na) if n <= 256 else sorted(set(range(0, na, 5)) | {179, 180, 537, 538, na - 1})
+    tab = _angles(n, na, ns)
+    lo, hi = 0, 0
+    for a in angles:
+        k1, k2, k0 = tab[a]
+        for rb in range(nb):
+            d0 = rb * 64
+            lanes = np.arange(d0, d0 + 64)
+            # projector 2: one ray per lane, 4 waves split the steps, anchors every 8 steps
+            base = _fma32(lanes, k1, k0)
+            for part in range(4):
+                sb, se = _block_range(k1, k2, k0, n, d0, part, 4)
+                if se <= sb:
+                    continue
+                c = np.floor(_coords(base, k2, sb, se, 8).astype(np.float64))
+                lo, hi = min(lo, c.min()), max(hi, c.max() + 1)
+                assert c.min() >= -PAD and c.max() + 1 <= n + PAD - 1, (a, rb, part, c.min(), c.max())
+    # the margins are used, but with room to spare
+    assert lo >= -PAD and hi <= n + PAD - 1
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=[f"{g[0]}x{g[1]}x{g[2]}" for g in GEOMS])
+def test_axis_split_grid_covers_every_block_once(geom):
+    """The single-slice projection grid sends row-stepping blocks to XCDs 0-3
+    and column-stepping ones to XCDs 4-7 (workgroup b on XCD b mod 8): replay
+    the kernel's decode of every workgroup of the grid the host launches and
+    check that each (angle, 64-ray block) pair is taken exactly once."""
+    n, na, ns = geom
+    nb = (ns + 63) // 64
+    rows = [a for a in range(na) if 4 * a <= na or 4 * a >= 3 * na]
+    order = rows + [a for a in range(na) if a not in set(rows)]
+    nar = len(rows)
+    wgs = 8 * ((max(nar, na - nar) * nb + 3) // 4)   # project_wgs_split
+    seen = np.zeros((na, nb), dtype=int)
+    for local in range(wgs):
+        xcd, k = local & 7, (local >> 3) * 4 + (local & 3)
+        colsax = xcd >= 4
+        if k >= (na - nar if colsax else nar) * nb:
+            continue
+        j, rb = divmod(k, nb)
+        a = order[(nar if colsax else 0) + j]
+        assert (xcd >= 4) == (a not in set(rows))
+        seen[a, rb] += 1
+    assert np.all(seen == 1)
