@@ -80,6 +80,7 @@ struct ncs_handle {
     void* hh = nullptr;
     void* tw = nullptr;
     void* ang = nullptr;
+    double* ang64 = nullptr;   // k1, k2, k0, q1, q2, q0 per angle in double
     int32_t* axis = nullptr;
     void* ysc = nullptr;
     double* part_data = nullptr;
@@ -158,6 +159,7 @@ DevCtx<T> make_ctx(const ncs_handle* h) {
     c.nwg_proj = h->aorder ? project_wgs_split(c.NA, c.NS, h->nar) : c.nb_proj;
     c.nb_tv = tv_blocks(c.N);
     c.ang = static_cast<const AngleT<T>*>(h->ang);
+    c.ang64 = h->ang64;
     c.axis = h->axis;
     c.x = static_cast<T*>(h->x);
     c.xbar = static_cast<T*>(h->xbar);
@@ -793,6 +795,7 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         (s = dev_alloc(h, &h->w, h->n * e)) || (s = dev_alloc(h, &h->spec, 2 * (size_t)NH * N * e)) ||
         (s = dev_alloc(h, &h->hh, (size_t)NH * N * e)) || (s = dev_alloc(h, &h->tw, (size_t)N * e)) ||
         (s = dev_alloc(h, &h->ang, 10 * (size_t)NA * e)) ||
+        (s = dev_alloc(h, reinterpret_cast<void**>(&h->ang64), 6 * (size_t)NA * sizeof(double))) ||
         (s = dev_alloc(h, reinterpret_cast<void**>(&h->axis), (size_t)NA * sizeof(int32_t))) ||
         (s = dev_alloc(h, &h->ysc, h->mp * e)) ||
         (s = dev_alloc(h, reinterpret_cast<void**>(&h->part_data), nparts * sizeof(double))) ||
@@ -838,6 +841,12 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
         return fail(s);
     }
     if ((s = upload_typed(h, h->ang, h->tab))) return fail(s);
+    {
+        std::vector<double> t64(6 * (size_t)NA);
+        for (int a = 0; a < NA; ++a)
+            for (int k = 0; k < 6; ++k) t64[6 * (size_t)a + k] = h->tab[10 * (size_t)a + k];
+        if ((s = upload<double>(h->ang64, t64))) return fail(s);
+    }
     Control c0{};
     c0.f_target = std::nan("");
     if (hipMemcpy(h->axis, axis.data(), NA * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||

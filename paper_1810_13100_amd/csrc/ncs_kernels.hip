@@ -109,6 +109,43 @@ __device__ inline float med3<float>(float v, float lo, float hi) { return __buil
 template <>
 __device__ inline double med3<double>(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
 
+// floor(v) as an integer and v - floor(v), one instruction each in single
+// precision (v_cvt_flr_i32_f32, v_fract_f32).
+template <class T>
+__device__ inline int floor_int(T v) {
+    return (int)floor(v);
+}
+template <>
+__device__ inline int floor_int<float>(float v) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+template <class T>
+__device__ inline T frac_part(T v) {
+    return v - floor(v);
+}
+template <>
+__device__ inline float frac_part<float>(float v) {
+    return __builtin_amdgcn_fractf(v);
+}
+
+// Coordinates are formed as an integer from a double-precision anchor plus a
+// small offset in T: the coordinate at step s + j is i + t with
+// (i, t0) = (floor, fraction) of fma(s, k2, base) in double and
+// t = fma(j, k2, t0) in T.  In single precision a coordinate near 300 held
+// whole would carry about 1.5e-5 of rounding, and a trajectory of some
+// thousand iterations amplifies those tap-weight errors by about 50 in the
+// image; the split form keeps each coordinate within about 1e-6.
+struct Anchor {
+    int i;
+    double t;
+};
+__device__ inline Anchor make_anchor(double x) {
+    const double fl = floor(x);
+    return Anchor{(int)fl, x - fl};
+}
+
 // One radix-2 butterfly of each kind on values in registers: decimation in
 // time (x0, x1) <- (x0 + w x1, x0 - w x1); in frequency (x0, x1) <- (x0 + x1,
 // (x0 - x1) w).
@@ -338,20 +375,25 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject_direct(const DevC
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = tx * kBpTileD + (lane & 7);
     const int row = ty * kBpTileD + (lane >> 3);
-    const T fc = (T)col, fr = (T)row;
-    const T tmax = (T)c.NS;
+    const double oc = (double)(tx * kBpTileD), orow = (double)(ty * kBpTileD);
+    const T lcf = (T)(lane & 7), lrf = (T)(lane >> 3);
     const int PU = c.PU;
-    const int NA = c.NA;
+    const int NA = c.NA, NS = c.NS;
     const AngleT<T>* ang = c.ang;
     T acc = T(0);
 #pragma unroll NCS_UNROLL_BP
     for (int a = wave; a < NA; a += kBpWaves) {
         const AngleT<T> A = ang[a];
-        // outside the detector both taps land on the zero pads at d = -1, N_s, N_s + 1
-        const T t = med3(fma(fc, A.q1, fma(fr, A.q2, A.q0)), T(-1), tmax);
-        const T fl = floor(t);
-        const T f = t - fl;
-        const unsigned off = (unsigned)((int)fl + 1);
+        // the pixel's detector coordinate as the tile origin's (an integer and a
+        // fraction, from double precision) plus a small offset in T; outside
+        // the detector both taps land on the zero pads at d = -1, N_s, N_s + 1
+        const NCS_G double* g = c.ang64 + 6 * a;
+        const Anchor an = make_anchor(fma(oc, g[3], fma(orow, g[4], g[5])));
+        const T tr = fma(lcf, A.q1, fma(lrf, A.q2, (T)an.t));
+        const int lraw = an.i + floor_int(tr);
+        const T f = lraw < -1 ? T(0) : frac_part(tr);
+        const int fl = min(max(lraw, -1), NS);
+        const unsigned off = (unsigned)(fl + 1);
         const Pair<T> y = load_pair(ysrc + (size_t)a * PU + off);
         const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));
         const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));
@@ -505,41 +547,45 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_quad(const De
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lc = 2 * (lane & 7), lr = 2 * (lane >> 3);          // block corner within the tile
-    const T fc0 = (T)(tx * kBpTile + lc), fc1 = fc0 + T(1);
-    const T fr0 = (T)(ty * kBpTile + lr), fr1 = fr0 + T(1);
-    const T tmax = (T)c.NS;
+    const double oc = (double)(tx * kBpTile), orow = (double)(ty * kBpTile);
+    const T lc0 = (T)lc, lc1 = lc0 + T(1), lr0 = (T)lr, lr1 = lr0 + T(1);
     const int PU = c.PU, NA = c.NA, NS = c.NS;
     const AngleT<T>* ang = c.ang;
     T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
 #pragma unroll NCS_UNROLL_BPQ
     for (int a = wave; a < NA; a += kBpQuadWaves) {
         const AngleT<T> A = ang[a];
-        // the direct kernel's coordinate of each pixel; outside the detector the
-        // taps land on the zero pads at d = -1, N_s, N_s + 1
-        const T t00 = med3(fma(fc0, A.q1, fma(fr0, A.q2, A.q0)), T(-1), tmax);
-        const T t01 = med3(fma(fc1, A.q1, fma(fr0, A.q2, A.q0)), T(-1), tmax);
-        const T t10 = med3(fma(fc0, A.q1, fma(fr1, A.q2, A.q0)), T(-1), tmax);
-        const T t11 = med3(fma(fc1, A.q1, fma(fr1, A.q2, A.q0)), T(-1), tmax);
-        const T l00 = floor(t00), l01 = floor(t01), l10 = floor(t10), l11 = floor(t11);
+        // the direct kernel's coordinate of each pixel: the tile origin's (an
+        // integer and a fraction, from double precision) plus a small offset in
+        // T; outside the detector the taps land on the zero pads at
+        // d = -1, N_s, N_s + 1 (a coordinate below -1 counts as -1)
+        const NCS_G double* g = c.ang64 + 6 * a;
+        const Anchor an = make_anchor(fma(oc, g[3], fma(orow, g[4], g[5])));
+        const T t0 = (T)an.t;
+        const T t00 = fma(lc0, A.q1, fma(lr0, A.q2, t0)), t01 = fma(lc1, A.q1, fma(lr0, A.q2, t0));
+        const T t10 = fma(lc0, A.q1, fma(lr1, A.q2, t0)), t11 = fma(lc1, A.q1, fma(lr1, A.q2, t0));
+        const int r00 = an.i + floor_int(t00), r01 = an.i + floor_int(t01);
+        const int r10 = an.i + floor_int(t10), r11 = an.i + floor_int(t11);
+        const int l00 = min(max(r00, -1), NS), l01 = min(max(r01, -1), NS);
+        const int l10 = min(max(r10, -1), NS), l11 = min(max(r11, -1), NS);
         // window start: the smallest bin, kept <= N_s - 2 so that the 4 bins stay
         // inside the padded row (bins -1 .. N_s + 1)
-        const int base = min((int)fmin(fmin(l00, l01), fmin(l10, l11)), NS - 2);
+        const int base = min(min(min(l00, l01), min(l10, l11)), NS - 2);
         const Four<T> y = *reinterpret_cast<const Four<T>*>(ysrc + (size_t)a * PU + 1 + base);
-        const T fb = (T)base;
-#define NCS_BP_TAP(acc, t, l)                                                              \
+#define NCS_BP_TAP(acc, t, l, r)                                                           \
         {                                                                                  \
-            const T f = t - l;                                                             \
-            const int j = min(max((int)(l - fb), 0), 2);                                   \
+            const T f = r < -1 ? T(0) : frac_part(t);                                      \
+            const int j = min(max(l - base, 0), 2);                                        \
             const T y0 = pick(j, y.a, y.b, y.c), y1 = pick(j, y.b, y.c, y.d);              \
             const T w0 = fmax(T(0), fma(-A.kappa2, f, A.kappa));                           \
             const T w1 = fmax(T(0), fma(A.kappa2, f, A.kd));                               \
             acc = fma(w0, y0, acc);                                                        \
             acc = fma(w1, y1, acc);                                                        \
         }
-        NCS_BP_TAP(a00, t00, l00)
-        NCS_BP_TAP(a01, t01, l01)
-        NCS_BP_TAP(a10, t10, l10)
-        NCS_BP_TAP(a11, t11, l11)
+        NCS_BP_TAP(a00, t00, l00, r00)
+        NCS_BP_TAP(a01, t01, l01, r01)
+        NCS_BP_TAP(a10, t10, l10, r10)
+        NCS_BP_TAP(a11, t11, l11, r11)
 #undef NCS_BP_TAP
     }
     T* rw = red + wave * (kBpTile * kBpTile);
@@ -631,6 +677,7 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
     constexpr int NT = kBpQuadWaves * 64;
     __shared__ T win[CH * kBpWin];
     __shared__ int wbase[CH];
+    __shared__ T tref[CH];
     __shared__ T red[kBpQuadWaves * kBpTile * kBpTile];
     const T* ysrc = ITER ? c.u : ysrc_plain;
     const int N = c.N;
@@ -639,10 +686,9 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lc = 2 * (lane & 7), lr = 2 * (lane >> 3);          // block corner within the tile
-    const T fc0 = (T)(tx * kBpTile + lc), fc1 = fc0 + T(1);
-    const T fr0 = (T)(ty * kBpTile + lr), fr1 = fr0 + T(1);
+    const T lc0 = (T)lc, lc1 = lc0 + T(1), lr0 = (T)lr, lr1 = lr0 + T(1);
     const int PU = c.PU, NA = c.NA, NS = c.NS;
-    const T c0 = (T)(tx * kBpTile), r0 = (T)(ty * kBpTile), span = (T)(kBpTile - 1);
+    const double c0 = (double)(tx * kBpTile), r0 = (double)(ty * kBpTile), span = (double)(kBpTile - 1);
     const AngleT<T>* ang = c.ang;
     // the epilogue's reads (D^T v and the positivity dual of one pixel per
     // thread of the first 256) are issued now, so the staging hides them
@@ -664,10 +710,15 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
         __syncthreads();   // the previous chunk has been consumed
         // window of angle a: bins wbase .. wbase + kBpWin - 1 from one below the
         // floor of the smallest (unclamped) coordinate of the tile
+        // (and the tile origin's coordinate relative to the window, in double
+        // then T: a small number, so each pixel's coordinate stays within ~1e-6)
         for (int k = threadIdx.x; k < nch; k += NT) {
-            const AngleT<T> A = ang[a0 + k];
-            const T tmin = fma(c0, A.q1, fma(r0, A.q2, A.q0)) + span * (fmin(A.q1, T(0)) + fmin(A.q2, T(0)));
-            wbase[k] = (int)floor(tmin) - 1;
+            const NCS_G double* g = c.ang64 + 6 * (a0 + k);
+            const double q1 = g[3], q2 = g[4];
+            const double torg = fma(c0, q1, fma(r0, q2, g[5]));
+            const int wb = (int)floor(torg + span * (fmin(q1, 0.0) + fmin(q2, 0.0))) - 1;
+            wbase[k] = wb;
+            tref[k] = (T)(torg - (double)wb);
         }
         __syncthreads();
         {
@@ -691,14 +742,15 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
         __syncthreads();
         for (int k = wave; k < nch; k += kBpQuadWaves) {
             const AngleT<T> A = ang[a0 + k];
-            // angle k's window starts at bin wbase[k] (a wave-uniform offset, so
+            // coordinates relative to angle k's window (a wave-uniform offset, so
             // that each pixel's address is one shift-and-add)
-            const int woffb = __builtin_amdgcn_readfirstlane((k * kBpWin - wbase[k]) * (int)sizeof(T));
-            const T q0r0 = fma(fr0, A.q2, A.q0), q0r1 = fma(fr1, A.q2, A.q0);
-            bp_window_tap(a00, fma(fc0, A.q1, q0r0), win, woffb, A);
-            bp_window_tap(a01, fma(fc1, A.q1, q0r0), win, woffb, A);
-            bp_window_tap(a10, fma(fc0, A.q1, q0r1), win, woffb, A);
-            bp_window_tap(a11, fma(fc1, A.q1, q0r1), win, woffb, A);
+            const int woffb = __builtin_amdgcn_readfirstlane(k * kBpWin * (int)sizeof(T));
+            const T tr = tref[k];
+            const T q0r0 = fma(lr0, A.q2, tr), q0r1 = fma(lr1, A.q2, tr);
+            bp_window_tap(a00, fma(lc0, A.q1, q0r0), win, woffb, A);
+            bp_window_tap(a01, fma(lc1, A.q1, q0r0), win, woffb, A);
+            bp_window_tap(a10, fma(lc0, A.q1, q0r1), win, woffb, A);
+            bp_window_tap(a11, fma(lc1, A.q1, q0r1), win, woffb, A);
         }
     }
     T* rw = red + wave * (kBpTile * kBpTile);
@@ -773,27 +825,6 @@ __device__ inline double project_epilogue(const DevCtx<T>& c, int a, int d, T q,
     return dterm;
 }
 
-// floor(v) as an integer and v - floor(v), one instruction each in single
-// precision (v_cvt_flr_i32_f32, v_fract_f32).
-template <class T>
-__device__ inline int floor_int(T v) {
-    return (int)floor(v);
-}
-template <>
-__device__ inline int floor_int<float>(float v) {
-    int r;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-    return r;
-}
-template <class T>
-__device__ inline T frac_part(T v) {
-    return v - floor(v);
-}
-template <>
-__device__ inline float frac_part<float>(float v) {
-    return __builtin_amdgcn_fractf(v);
-}
-
 // Steps [s_begin, s_end) of part `part` of `nparts` of the steps where some ray
 // of the 64-ray block starting at d0 has its coordinate in [-2, N + 1].  All
 // rays of an angle share the slope k2 in s, so the block's coordinates at step
@@ -823,15 +854,16 @@ __device__ inline void block_step_range(const AngleT<T>& A, int N, int d0, int p
 // transposed copy so that every angle walks along contiguous rows.  The
 // kPadL zero columns on each side of a row hold every tap of the block's rays
 // at the steps of its range, so a tap is read without a clamp: per step the
-// coordinate (one multiply-add from an anchor taken every 8 steps), its floor
-// as an integer and its fraction, one byte offset from the wave-uniform row
-// address, one 8-byte load and the linear interpolation.
+// coordinate's offset from an anchor taken every 8 steps (one multiply-add),
+// its floor as an integer and its fraction, one byte offset from the
+// wave-uniform row address, one 8-byte load and the linear interpolation.
 template <class T>
 __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
-                                   const AngleT<T>& A, int axis, int d0, int d, int part, int nparts) {
+                                   const AngleT<T>& A, int a, int axis, int d0, int d, int part, int nparts) {
     const int P = c.P;
     const T* src = axis == 0 ? img : imgT;
-    const T base = fma((T)d, A.k1, A.k0);
+    const NCS_G double* g = c.ang64 + 6 * a;
+    const double k2d = g[1], based = fma((double)d, g[0], g[2]);
     int s_begin, s_end;
     block_step_range(A, c.N, d0, part, nparts, s_begin, s_end);
     const T k2 = A.k2;
@@ -841,17 +873,18 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
     const char* row = reinterpret_cast<const char*>(src + (size_t)max(s_begin, 0) * P);
     const size_t pitch = (size_t)P * sizeof(T);
     constexpr unsigned pad_bytes = kPadL * sizeof(T);
-    constexpr int B = 8;   // steps per unrolled group (loads in flight per lane)
+    constexpr int B = 8;   // steps per anchor and unrolled group (loads in flight per lane)
     int s = s_begin;
     for (; s + B <= s_end; s += B) {
-        const T xa = fma((T)s, k2, base);
+        const Anchor an = make_anchor(fma((double)s, k2d, based));
+        const T t0 = (T)an.t;
         Pair<T> v[B];
         T f[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-            const T xi = j == 0 ? xa : fma((T)j, k2, xa);
-            f[j] = frac_part(xi);
-            const unsigned boff = (unsigned)floor_int(xi) * (unsigned)sizeof(T) + pad_bytes;
+            const T t = j == 0 ? t0 : fma((T)j, k2, t0);
+            f[j] = frac_part(t);
+            const unsigned boff = (unsigned)(an.i + floor_int(t)) * (unsigned)sizeof(T) + pad_bytes;
             v[j] = *reinterpret_cast<const Pair<T>*>(row + (size_t)j * pitch + boff);
         }
 #pragma unroll
@@ -859,10 +892,11 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
         row += B * pitch;
     }
     for (; s < s_end; ++s) {
-        const T xi = fma((T)s, k2, base);
-        const unsigned boff = (unsigned)floor_int(xi) * (unsigned)sizeof(T) + pad_bytes;
+        const Anchor an = make_anchor(fma((double)s, k2d, based));
+        const T t = (T)an.t;
+        const unsigned boff = (unsigned)an.i * (unsigned)sizeof(T) + pad_bytes;
         const Pair<T> v = *reinterpret_cast<const Pair<T>*>(row + boff);
-        acc += fma(frac_part(xi), v.b - v.a, v.a);
+        acc += fma(t, v.b - v.a, v.a);
         row += pitch;
     }
     return acc;
@@ -876,13 +910,13 @@ __device__ inline T ray_sum_direct(const DevCtx<T>& c, const T* __restrict__ img
 // step ranges go to red[range * 64 + ray].
 template <class T>
 __device__ inline void ray_sum_pair(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
-                                    const AngleT<T>& A, int axis, int d0, int lane, int wave, T* red) {
+                                    const AngleT<T>& A, int a, int axis, int d0, int lane, int wave, T* red) {
     const int N = c.N, P = c.P;
     const T* src = axis == 0 ? img : imgT;
     const int h = lane >> 5, pr = lane & 31;
     const int da = d0 + 2 * pr;
-    const T base0 = fma((T)da, A.k1, A.k0);
-    const T base1 = fma((T)(da + 1), A.k1, A.k0);
+    const NCS_G double* g = c.ang64 + 6 * a;
+    const double k2d = g[1], b0d = fma((double)da, g[0], g[2]), b1d = fma((double)(da + 1), g[0], g[2]);
     const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
     const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
     const T lo_x = T(-2), hi_x = T(N + 1);
@@ -898,22 +932,28 @@ __device__ inline void ray_sum_pair(const DevCtx<T>& c, const T* __restrict__ im
     } else if (bhi < lo_x || blo > hi_x) {
         s_end = s_begin;
     }
-    const T cmax = (T)N;
+    const T k2 = A.k2;
     T acc0 = T(0), acc1 = T(0);
-#pragma unroll NCS_UNROLL_PAIR
-    for (int s = s_begin; s < s_end; ++s) {
-        const T x0 = fma((T)s, A.k2, base0), x1 = fma((T)s, A.k2, base1);
-        const T l0 = med3(floor(x0), T(-2), cmax), l1 = med3(floor(x1), T(-2), cmax);   // zero columns off the image
-        // the 4 elements from the smaller tap, kept inside the padded row
-        const int base = min((int)fmin(l0, l1), N - 2);
-        const Four<T> v = *reinterpret_cast<const Four<T>*>(src + (size_t)s * P + base + kPadL);
-        const T fb = (T)base;
-        const int j0 = min(max((int)(l0 - fb), 0), 2), j1 = min(max((int)(l1 - fb), 0), 2);
-        const T f0 = x0 - l0, f1 = x1 - l1;
-        const T u0 = pick(j0, v.a, v.b, v.c), w0 = pick(j0, v.b, v.c, v.d);
-        const T u1 = pick(j1, v.a, v.b, v.c), w1 = pick(j1, v.b, v.c, v.d);
-        acc0 += fma(f0, w0 - u0, u0);
-        acc1 += fma(f1, w1 - u1, u1);
+    for (int s0 = s_begin; s0 < s_end; s0 += NCS_UNROLL_PAIR) {
+        // anchors of both rays every NCS_UNROLL_PAIR steps (coordinates as integer + offset)
+        const Anchor a0 = make_anchor(fma((double)s0, k2d, b0d)), a1 = make_anchor(fma((double)s0, k2d, b1d));
+        const T t00 = (T)a0.t, t10 = (T)a1.t;
+#pragma unroll
+        for (int j = 0; j < NCS_UNROLL_PAIR; ++j) {
+            if (s0 + j >= s_end) break;
+            const T t0 = j == 0 ? t00 : fma((T)j, k2, t00), t1 = j == 0 ? t10 : fma((T)j, k2, t10);
+            // taps off the image read the zero columns
+            const int l0 = min(max(a0.i + floor_int(t0), -2), N), l1 = min(max(a1.i + floor_int(t1), -2), N);
+            // the 4 elements from the smaller tap, kept inside the padded row
+            const int base = min(min(l0, l1), N - 2);
+            const Four<T> v = *reinterpret_cast<const Four<T>*>(src + (size_t)(s0 + j) * P + base + kPadL);
+            const int j0 = min(max(l0 - base, 0), 2), j1 = min(max(l1 - base, 0), 2);
+            const T f0 = frac_part(t0), f1 = frac_part(t1);
+            const T u0 = pick(j0, v.a, v.b, v.c), w0 = pick(j0, v.b, v.c, v.d);
+            const T u1 = pick(j1, v.a, v.b, v.c), w1 = pick(j1, v.b, v.c, v.d);
+            acc0 += fma(f0, w0 - u0, u0);
+            acc1 += fma(f1, w1 - u1, u1);
+        }
     }
     red[range * kRays + 2 * pr] = acc0;
     red[range * kRays + 2 * pr + 1] = acc1;
@@ -946,11 +986,12 @@ __device__ inline int row_window_base(const AngleT<T>& A, int s, T blo, T cmax) 
 
 template <class T>
 __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
-                                const AngleT<T>& A, int axis, int d0, int d, int lane, int wave, T* stage,
+                                const AngleT<T>& A, int a, int axis, int d0, int d, int lane, int wave, T* stage,
                                 int* rbase) {
     const int N = c.N, P = c.P;
     const T* src = axis == 0 ? img : imgT;
-    const T base = fma((T)d, A.k1, A.k0);
+    const NCS_G double* g = c.ang64 + 6 * a;
+    const double k2d = g[1], based = fma((double)d, g[0], g[2]);
     const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
     const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
     const T lo_x = T(-2), hi_x = T(N + 1);
@@ -996,11 +1037,14 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
             }
         }
         wave_lds_sync();
+        // one anchor per staged group (offsets of at most 15 columns)
+        const Anchor an = make_anchor(fma((double)s0, k2d, based));
+        const T t0 = (T)an.t;
         for (int i = 0; i < ns; ++i) {
-            const T xi = fma((T)(s0 + i), A.k2, base);
-            const T fl = med3(floor(xi), T(-2), cmax);   // taps off the image read the zero columns
-            const T f = xi - fl;
-            int j = (int)fl + kPadL - rbase[i];
+            const T t = fma((T)i, A.k2, t0);
+            const int fl = min(max(an.i + floor_int(t), -2), N);   // taps off the image read the zero columns
+            const T f = frac_part(t);
+            int j = fl + kPadL - rbase[i];
             j = min(max(j, 0), kRowWin - 2);
             const T* tp = stage + i * kRowWin + j;
             const T v0 = tp[0], v1 = tp[1];
@@ -1146,7 +1190,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
         return;
     }
     if (VARIANT == 3) {
-        ray_sum_pair(c, img, imgT, A, axis, d0, lane, wave, red);
+        ray_sum_pair(c, img, imgT, A, a, axis, d0, lane, wave, red);
         __syncthreads();
         if (wave != 0 || stop) return;   // a stopped slice writes nothing
         T sum = red[lane];
@@ -1161,10 +1205,10 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     if (VARIANT == 1) {
         __shared__ __attribute__((aligned(16))) T stage[kWaves * kStageRows * kRowWin];
         __shared__ int rbase[kWaves * kStageRows];
-        acc = ray_sum_lds(c, img, imgT, A, axis, d0, d, lane, wave, stage + wave * kStageRows * kRowWin,
+        acc = ray_sum_lds(c, img, imgT, A, a, axis, d0, d, lane, wave, stage + wave * kStageRows * kRowWin,
                           rbase + wave * kStageRows);
     } else {
-        acc = ray_sum_direct(c, img, imgT, A, axis, d0, d, wave, kWaves);
+        acc = ray_sum_direct(c, img, imgT, A, a, axis, d0, d, wave, kWaves);
     }
     red[wave * kRays + lane] = acc;
     __syncthreads();

@@ -1,0 +1,94 @@
+"""GPU parity over the lengths the time-to-gap measurements run, against stored
+FP64 oracle trajectories (tests/golden/make_long.py writes them, calling only
+the oracle).
+
+* 256^2 CT (360 x 367, lambda 0.005; Section 4.1), seeds 0 and 1: the FP32
+  library from x = 0 for as many iterations as its run of that slice takes to
+  the 1e-4 relative objective gap (3107 and 3251), every objective f(x^k)
+  within 1e-5 relative and x^K within rel-L2 1e-4; and the FP64 library over
+  all 12000 stored iterations, every objective within 1e-10.  The smallest of
+  those objectives is the f* of the relative gap, so the FP64 run that the
+  benchmark takes f* from is checked against the oracle over that length.
+* 128^2 PET (180 x 185, isotropic TV lambda 0.02; Section 4.2), seed 0: the
+  FP32 library for 19496 iterations (the length of its run to the gap) at the
+  same gates.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import ct_problem, log, pet_problem, rel_l2
+from paper_1810_13100_amd import ncs
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _fixture(case):
+    d = np.load(os.path.join(GOLDEN, case + ".npz"))
+    return {k: d[k] for k in d.files}
+
+
+def _solver(prob, fx, dtype):
+    pet = prob.kind == "pet"
+    p = ncs.Params(float(fx["alpha"]), float(fx["beta"]), float(fx["gamma"]), float(fx["lam"]),
+                   data_term=ncs.DATA_POISSON if pet else ncs.DATA_QUADRATIC,
+                   tv_term=ncs.TV_ISO if pet else ncs.TV_ANISO)
+    b = torch.tensor(prob.b, dtype=dtype, device=DEV)
+    bg = torch.tensor(prob.bg, dtype=dtype, device=DEV) if pet else None
+    return ncs.Solver(ncs.Geometry(prob.n_side, prob.n_angles, prob.n_bins), p, b=b, bg=bg, dtype=dtype)
+
+
+def _run(prob, fx, dtype, iters):
+    s = _solver(prob, fx, dtype)
+    s.set_init()
+    obj = s.iterate(iters, record=True)
+    x = s.x().double().cpu().numpy()
+    s.close()
+    return x, obj
+
+
+@pytest.mark.parametrize("case", ["ct256_s0", "ct256_s1"])
+def test_ct256_fp32_to_the_gap_iteration(case):
+    fx = _fixture(case)
+    K = int(fx["k_state"])
+    prob = ct_problem("c2", seed=int(fx["seed"]))
+    log(f"long parity {case}: FP32, {K} iterations")
+    x, obj = _run(prob, fx, torch.float32, K)
+    ex = rel_l2(x, fx["x"])
+    ef = float(np.max(np.abs(obj - fx["obj"][:K]) / np.abs(fx["obj"][:K])))
+    gap = (fx["obj"][K - 1] - fx["obj"].min()) / abs(fx["obj"].min())
+    log(f"  rel-L2 x {ex:.2e}, max rel f {ef:.2e} (oracle gap at K: {gap:.2e})")
+    assert ex <= 1e-4 and ef <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["ct256_s0", "ct256_s1"])
+def test_ct256_fp64_f_star_run(case):
+    fx = _fixture(case)
+    K = int(fx["k_total"])
+    prob = ct_problem("c2", seed=int(fx["seed"]))
+    log(f"long parity {case}: FP64, {K} iterations")
+    x, obj = _run(prob, fx, torch.float64, K)
+    ef = float(np.max(np.abs(obj - fx["obj"]) / np.abs(fx["obj"])))
+    fs_gpu, fs_ref = float(obj.min()), float(fx["obj"].min())
+    log(f"  max rel f {ef:.2e}; f* {fs_gpu:.10g} vs oracle {fs_ref:.10g}")
+    assert ef <= 1e-10
+    assert abs(fs_gpu - fs_ref) <= 1e-10 * abs(fs_ref)
+
+
+def test_pet128_fp32_to_the_gap_iteration():
+    fx = _fixture("pet128_s0")
+    K = int(fx["k_state"])
+    prob = pet_problem("c3", seed=int(fx["seed"]))
+    log(f"long parity pet128_s0: FP32, {K} iterations")
+    x, obj = _run(prob, fx, torch.float32, K)
+    ref = fx["obj"][:K]
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(obj), fin)
+    ex = rel_l2(x, fx["x"])
+    ef = float(np.max(np.abs(obj[fin] - ref[fin]) / np.abs(ref[fin])))
+    log(f"  rel-L2 x {ex:.2e}, max rel f {ef:.2e}")
+    assert ex <= 1e-4 and ef <= 1e-5

@@ -4,11 +4,11 @@ The direct kernel (projector 2) reads image rows without clamping the tap
 column: it relies on the kPadL = 96 zero columns on each side of a padded row
 (csrc/ncs_internal.h) to hold every tap of a 64-ray block at every step of the
 block's step range.  This test replays the
-kernels' single-precision address arithmetic (per-angle coefficients from
-double on the host rounded to float, the block step range with its float
-divisions, the anchored fused multiply-adds of the unrolled loops and the
-remainder loop) for the workload geometries and asserts that every read stays
-inside the padded row: columns -96 .. N+95.  Fused multiply-adds are replayed
+kernel's address arithmetic (the block step range with its single-precision
+divisions on coefficients rounded to float; each tap column as the floor of a
+double-precision anchor plus the floor of a single-precision offset) for the
+workload geometries and asserts that every read stays inside the padded row:
+columns -96 .. N+95.  Fused multiply-adds are replayed
 exactly: the product of a small integer and a float is exact in double, so
 one rounding of the double sum is the fused result.
 """
@@ -28,6 +28,20 @@ def _r32(x):
 def _fma32(a, b, c):
     """fma(a, b, c) in single precision for integer-valued a (exact product in double)."""
     return _r32(np.asarray(a, np.float64) * np.asarray(b, np.float64) + np.asarray(c, np.float64))
+
+
+def _angles64(n, na, ns):
+    """k1, k2, k0 per angle in double, as the host computes them."""
+    hn, hs = 0.5 * (n - 1), 0.5 * (ns - 1)
+    out = []
+    for a in range(na):
+        th = math.pi * a / na
+        ct, st = math.cos(th), math.sin(th)
+        if 4 * a <= na or 4 * a >= 3 * na:
+            out.append((1.0 / ct, -st / ct, -hs / ct + hn * st / ct + hn))
+        else:
+            out.append((1.0 / st, -ct / st, -hs / st + hn * ct / st + hn))
+    return out
 
 
 def _angles(n, na, ns):
@@ -65,20 +79,21 @@ def _block_range(k1, k2, k0, n, d0, part, nparts):
     return sb, se
 
 
-def _coords(base, k2, sb, se, unroll):
-    """Coordinates of each step of [sb, se) as the unrolled loop forms them
-    (rows: lanes, columns: steps)."""
+def _tap_columns(base64, k2d, k2, sb, se, unroll):
+    """Floor of each step's coordinate as the unrolled loop forms it (rows:
+    lanes, columns: steps): an anchor fma(s, k2, base) in double split into
+    an integer and a fraction t0, then fma(j, k2, t0) in single precision."""
     cols = []
     s = sb
-    while s + unroll <= se:
-        xa = _fma32(s, k2, base)
-        cols.append(xa)
-        for j in range(1, unroll):
-            cols.append(_fma32(j, k2, xa))
-        s += unroll
-    for s in range(s, se):
-        cols.append(_fma32(s, k2, base))
-    return np.stack(cols, axis=1) if cols else np.zeros((base.size, 0), F32)
+    while s < se:
+        xa = s * k2d + base64
+        ia = np.floor(xa)
+        t0 = _r32(xa - ia)
+        for j in range(unroll if s + unroll <= se else 1):
+            t = t0 if j == 0 else _fma32(j, k2, t0)
+            cols.append(ia + np.floor(t.astype(np.float64)))
+        s += unroll if s + unroll <= se else 1
+    return np.stack(cols, axis=1) if cols else np.zeros((base64.size, 0))
 
 
 GEOMS = [(16, 7, 23), (64, 90, 92), (128, 179, 130), (128, 180, 185), (256, 358, 260), (256, 360, 367),
@@ -91,19 +106,21 @@ def test_direct_projector_reads_stay_in_the_padded_rows(geom):
     nb = (ns + 63) // 64
     angles = range(na) if n <= 256 else sorted(set(range(0, na, 5)) | {179, 180, 537, 538, na - 1})
     tab = _angles(n, na, ns)
+    tab64 = _angles64(n, na, ns)
     lo, hi = 0, 0
     for a in angles:
         k1, k2, k0 = tab[a]
+        k1d, k2d, k0d = tab64[a]
         for rb in range(nb):
             d0 = rb * 64
             lanes = np.arange(d0, d0 + 64)
             # projector 2: one ray per lane, 4 waves split the steps, anchors every 8 steps
-            base = _fma32(lanes, k1, k0)
+            base64 = lanes * k1d + k0d
             for part in range(4):
                 sb, se = _block_range(k1, k2, k0, n, d0, part, 4)
                 if se <= sb:
                     continue
-                c = np.floor(_coords(base, k2, sb, se, 8).astype(np.float64))
+                c = _tap_columns(base64, k2d, k2, sb, se, 8)
                 lo, hi = min(lo, c.min()), max(hi, c.max() + 1)
                 assert c.min() >= -PAD and c.max() + 1 <= n + PAD - 1, (a, rb, part, c.min(), c.max())
     # the margins are used, but with room to spare
