@@ -235,6 +235,20 @@ ncs_status ncs_adjoint(ncs_handle* h, const void* y_dev, void* x_dev);
 ncs_status ncs_apply_minv(ncs_handle* h, const void* w_dev, void* out_dev);
 ncs_status ncs_objective(ncs_handle* h, const void* x_dev, double* f);
 
+/* y = E x like ncs_forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no handle, no allocation of any kind.  Parallel beam
+ * (geom->beam = 0), single precision; x_dev: N*N floats, row-major; y_dev:
+ * N_theta*N_s floats (a*N_s + d); both caller-owned device memory.  The
+ * projector is the direct kernel (projector 2).  Its workspace (descriptor,
+ * angle tables, the padded image and its transpose) lives in one fixed
+ * 6 MiB device array per GPU, held until the process ends; geometries whose
+ * workspace exceeds it (about 2 N (N + 192) * 4 bytes plus 100 bytes per
+ * angle) return NCS_ERR_INVALID_ARG.  Asynchronous on `stream`.  Calls that
+ * overlap on one GPU share that array and race: serialise them (one stream,
+ * or an event between them). */
+ncs_status ncs_forward_noalloc(const ncs_geometry* geom, const float* x_dev, float* y_dev, void* stream);
+
 /* Filtered backprojection with the method's own circulant inverse:
  * x = alpha M^+ E^T y (N*N values from N_theta*N_s).  Since E^T E is close to
  * the circulant of eq. (circ_R), this approximates the least-squares image

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -698,6 +699,42 @@ ncs_status validate(const ncs_geometry& g, const ncs_params& p, int32_t dtype) {
 
 // One slice: tables, workspace, multiplier.  ext_ctl (nullable) is a control
 // block owned by a batch; autotune = time the projector variants.
+// Per-angle geometry of a parallel beam in double (the AngleT fields in
+// order: k1, k2, k0, q1, q2, q0, kappa, kappa^2, kappa - kappa^2, 1 - kappa)
+// and each angle's stepping axis (0: rows).  Section 4.1.1 leaves the
+// discretisation open; this is the Joseph reading with the integer 45-degree
+// test.
+void angle_table(const ncs_geometry& g, std::vector<double>& tab, std::vector<int>& axis) {
+    const int N = g.n_side, NA = g.n_angles, NS = g.n_bins;
+    tab.assign(10 * (size_t)NA, 0.0);
+    axis.assign(NA, 0);
+    const double hn = 0.5 * (N - 1), hs = 0.5 * (NS - 1);
+    for (int a = 0; a < NA; ++a) {
+        const double th = kPi * a / NA;
+        const double ct = std::cos(th), st = std::sin(th);
+        const bool rows = (4 * (long long)a <= NA) || (4 * (long long)a >= 3 * (long long)NA);
+        axis[a] = rows ? 0 : 1;
+        double* t = &tab[10 * (size_t)a];
+        if (rows) {   // xi = column of ray d on row r
+            t[0] = 1.0 / ct;
+            t[1] = -st / ct;
+            t[2] = -hs / ct + hn * st / ct + hn;
+            t[6] = 1.0 / std::fabs(ct);
+        } else {      // eta = row of ray d on column c
+            t[0] = 1.0 / st;
+            t[1] = -ct / st;
+            t[2] = -hs / st + hn * ct / st + hn;
+            t[6] = 1.0 / std::fabs(st);
+        }
+        t[3] = ct;
+        t[4] = st;
+        t[5] = hs - hn * (ct + st);
+        t[7] = t[6] * t[6];
+        t[8] = t[6] - t[7];
+        t[9] = 1.0 - t[6];
+    }
+}
+
 ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype, const void* b_dev,
                        const void* bg_dev, hipStream_t stream, Control* ext_ctl, bool autotune,
                        ncs_handle** out, bool operators_only = false);
@@ -753,34 +790,8 @@ ncs_status setup_slice(const ncs_geometry& g, const ncs_params& p, int32_t dtype
 
     // ---- per-angle table (double) --------------------------------------
     const int NA = g.n_angles, NS = g.n_bins;
-    h->tab.assign(10 * (size_t)NA, 0.0);
-    std::vector<int> axis(NA);
-    const double hn = 0.5 * (N - 1), hs = 0.5 * (NS - 1);
-    for (int a = 0; a < NA; ++a) {
-        const double th = kPi * a / NA;
-        const double ct = std::cos(th), st = std::sin(th);
-        const bool rows = (4 * (long long)a <= NA) || (4 * (long long)a >= 3 * (long long)NA);
-        axis[a] = rows ? 0 : 1;
-        double* t = &h->tab[10 * (size_t)a];
-        if (rows) {   // xi = column of ray d on row r
-            t[0] = 1.0 / ct;
-            t[1] = -st / ct;
-            t[2] = -hs / ct + hn * st / ct + hn;
-            t[6] = 1.0 / std::fabs(ct);
-        } else {      // eta = row of ray d on column c
-            t[0] = 1.0 / st;
-            t[1] = -ct / st;
-            t[2] = -hs / st + hn * ct / st + hn;
-            t[6] = 1.0 / std::fabs(st);
-        }
-        t[3] = ct;
-        t[4] = st;
-        t[5] = hs - hn * (ct + st);
-        t[7] = t[6] * t[6];
-        t[8] = t[6] - t[7];
-        t[9] = 1.0 - t[6];
-    }
-
+    std::vector<int> axis;
+    angle_table(g, h->tab, axis);
     // ---- workspace ---------------------------------------------------------
     const size_t e = h->esz;
     const int NH = N / 2 + 1;
@@ -1292,6 +1303,110 @@ ncs_status ncs_forward(ncs_handle* h, const void* x_dev, void* y_dev) {
         NCS_HIP(launch_pad_image<float>(c, dctx<float>(h), (const float*)x_dev, h->stream));
         NCS_HIP(launch_project_plain<float>(c, dctx<float>(h), h->projector, (float*)y_dev, h->stream));
     }
+    return NCS_OK;
+}
+
+}  // extern "C"
+
+// ---- E x without allocating: workspace in a fixed device array -----------
+namespace {
+
+// Descriptor, angle tables and the padded image pair of ncs_forward_noalloc.
+// Every call on a device uses that device's copy, which keeps the last call's
+// contents (each call rewrites all it reads before reading it).
+constexpr size_t kNoAllocScratch = (size_t)6 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// The device address of this device's scratch array (the host-side symbol is
+// only a stand-in): looked up once per device, with that device current.
+ncs_status scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_err("ncs_forward_noalloc: device %d outside [0, %d)", dev, kMaxDevices);
+        return NCS_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_err("ncs_forward_noalloc: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+            return NCS_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return NCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ncs_status ncs_forward_noalloc(const ncs_geometry* geom, const float* x_dev, float* y_dev, void* stream) {
+    if (!geom || !x_dev || !y_dev) {
+        set_err("ncs_forward_noalloc: null geometry, input or output pointer");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const ncs_geometry& g = *geom;
+    if (g.beam != NCS_BEAM_PARALLEL) {
+        set_err("ncs_forward_noalloc: parallel beams only (beam 0)");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (!is_pow2(g.n_side) || g.n_side < 16 || g.n_side > 1024 || g.n_angles < 1 || g.n_angles > (1 << 20) ||
+        g.n_bins < 2 || g.n_bins > (1 << 20)) {
+        set_err("ncs_forward_noalloc: need n_side a power of two in [16, 1024], n_angles >= 1, n_bins >= 2");
+        return NCS_ERR_INVALID_ARG;
+    }
+    const int N = g.n_side, NA = g.n_angles, NS = g.n_bins;
+    const size_t P = (size_t)N + 2 * kPadL;
+    // layout: descriptor | AngleT table | double coefficients | axes | padded image | padded transpose
+    const size_t o_ang = align256(sizeof(DevCtx<float>));
+    const size_t o_ang64 = o_ang + align256((size_t)NA * sizeof(AngleT<float>));
+    const size_t o_axis = o_ang64 + align256((size_t)NA * 6 * sizeof(double));
+    const size_t o_img = o_axis + align256((size_t)NA * sizeof(int32_t));
+    const size_t o_imgT = o_img + align256((size_t)N * P * sizeof(float));
+    const size_t need = o_imgT + (size_t)N * P * sizeof(float);
+    if (need > kNoAllocScratch) {
+        set_err("ncs_forward_noalloc: geometry %d^2, %d x %d needs %zu bytes of workspace, more than the %zu "
+                "the fixed array holds", N, NA, NS, need, kNoAllocScratch);
+        return NCS_ERR_INVALID_ARG;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_err("ncs_forward_noalloc: hipGetDevice failed");
+        return NCS_ERR_HIP;
+    }
+    unsigned char* base = nullptr;
+    ncs_status s = scratch_address(dev, &base);
+    if (s) return s;
+    DevCtx<float> c{};
+    c.N = N;
+    while ((1 << c.log2N) < N) ++c.log2N;
+    c.NA = NA;
+    c.NS = NS;
+    c.PU = NS + 3;
+    c.P = (int)P;
+    c.nb_proj = project_blocks(NA, NS);
+    c.nwg_proj = c.nb_proj;
+    c.nb_tv = tv_blocks(N);
+    c.ang = reinterpret_cast<const AngleT<float>*>(base + o_ang);
+    c.ang64 = reinterpret_cast<const double*>(base + o_ang64);
+    c.axis = reinterpret_cast<const int32_t*>(base + o_axis);
+    c.xsc = reinterpret_cast<float*>(base + o_img);
+    c.xscT = reinterpret_cast<float*>(base + o_imgT);
+    DevCtx<float>* dc = reinterpret_cast<DevCtx<float>*>(base);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    NCS_HIP(launch_parallel_tables(c, dc, reinterpret_cast<AngleT<float>*>(base + o_ang),
+                                   reinterpret_cast<double*>(base + o_ang64), reinterpret_cast<int32_t*>(base + o_axis),
+                                   st));
+    NCS_HIP(launch_pad_image_full<float>(c, dc, x_dev, st));
+    NCS_HIP(launch_project_plain<float>(c, dc, 2, y_dev, st));
     return NCS_OK;
 }
 

@@ -190,6 +190,11 @@ template <class T> hipError_t launch_backproject_plain(const DevCtx<T>& hc, cons
 template <class T> hipError_t launch_fbp(const DevCtx<T>& hc, const DevCtx<T>* dc, int backprojector, const T* y, T* out, hipStream_t st);
 template <class T> hipError_t launch_apply_minv(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* w, T* out, T scale, hipStream_t st);
 template <class T> hipError_t launch_pad_image(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st);
+// a parallel beam's descriptor (by value) and tables written on the device
+hipError_t launch_parallel_tables(const DevCtx<float>& hc, DevCtx<float>* dst, AngleT<float>* ang, double* ang64,
+                                  int32_t* axis, hipStream_t st);
+// the padded scratch pair including its zero margins
+template <class T> hipError_t launch_pad_image_full(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st);
 // Plain projections read the padded scratch pair (xsc, xscT): pad first.
 template <class T> hipError_t launch_project_plain(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, T* out, hipStream_t st);
 template <class T> hipError_t launch_project_setp(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, hipStream_t st);

@@ -1511,6 +1511,72 @@ __global__ __launch_bounds__(256) void k_pad_image(const DevCtx<T>* __restrict__
     c.xscT[(size_t)col * c.P + r + kPadL] = v;
 }
 
+// Descriptor and per-angle tables of a parallel beam written on the device
+// (the descriptor arrives by value as a kernel argument): angle a's AngleT
+// fields and its double-precision coefficients, as the host computes them for
+// a handle (Joseph reading of Section 4.1.1; integer 45-degree test).
+__global__ __launch_bounds__(256) void k_parallel_tables(DevCtx<float> c, DevCtx<float>* __restrict__ dst,
+                                                         AngleT<float>* __restrict__ ang, double* __restrict__ ang64,
+                                                         int32_t* __restrict__ axis) {
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a == 0) *dst = c;
+    if (a >= c.NA) return;
+    const int N = c.N, NA = c.NA, NS = c.NS;
+    const double hn = 0.5 * (N - 1), hs = 0.5 * (NS - 1);
+    const double th = 3.14159265358979323846 * a / NA;
+    const double ct = cos(th), st = sin(th);
+    const bool rows = (4 * (long long)a <= NA) || (4 * (long long)a >= 3 * (long long)NA);
+    double t[10];
+    if (rows) {
+        t[0] = 1.0 / ct;
+        t[1] = -st / ct;
+        t[2] = -hs / ct + hn * st / ct + hn;
+        t[6] = 1.0 / fabs(ct);
+    } else {
+        t[0] = 1.0 / st;
+        t[1] = -ct / st;
+        t[2] = -hs / st + hn * ct / st + hn;
+        t[6] = 1.0 / fabs(st);
+    }
+    t[3] = ct;
+    t[4] = st;
+    t[5] = hs - hn * (ct + st);
+    t[7] = t[6] * t[6];
+    t[8] = t[6] - t[7];
+    t[9] = 1.0 - t[6];
+    AngleT<float> A;
+    A.k1 = (float)t[0];
+    A.k2 = (float)t[1];
+    A.k0 = (float)t[2];
+    A.q1 = (float)t[3];
+    A.q2 = (float)t[4];
+    A.q0 = (float)t[5];
+    A.kappa = (float)t[6];
+    A.kappa2 = (float)t[7];
+    A.kd = (float)t[8];
+    A.omk = (float)t[9];
+    ang[a] = A;
+    for (int k = 0; k < 6; ++k) ang64[6 * a + k] = t[k];
+    axis[a] = rows ? 0 : 1;
+}
+
+// The whole padded scratch pair, margins included: row-major and transposed
+// copies of img with kPadL zero columns on each side (for scratch memory whose
+// margins hold another call's values).
+template <class T>
+__global__ __launch_bounds__(256) void k_pad_image_full(const DevCtx<T>* __restrict__ ctxs,
+                                                        const T* __restrict__ img) {
+    const DevCtx<T>& c = ctxs[0];
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t tot = (size_t)c.N * c.P;
+    if (e >= tot) return;
+    const int r = (int)(e / (size_t)c.P);
+    const int col = (int)(e - (size_t)r * c.P) - kPadL;
+    const bool in = col >= 0 && col < c.N;
+    c.xsc[e] = in ? img[(size_t)r * c.N + col] : T(0);
+    c.xscT[e] = in ? img[(size_t)col * c.N + r] : T(0);
+}
+
 // Dual initialisation from x0 (fixed-point relations of the optimality
 // conditions): u = grad g_data(E x0) from p = E x0; v from D x0.
 template <class T>
@@ -1919,6 +1985,18 @@ hipError_t launch_apply_minv(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* 
     return hipGetLastError();
 }
 
+hipError_t launch_parallel_tables(const DevCtx<float>& hc, DevCtx<float>* dst, AngleT<float>* ang, double* ang64,
+                                  int32_t* axis, hipStream_t st) {
+    hipLaunchKernelGGL(k_parallel_tables, dim3(blocks_for((size_t)hc.NA)), dim3(256), 0, st, hc, dst, ang, ang64, axis);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_pad_image_full(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st) {
+    hipLaunchKernelGGL((k_pad_image_full<T>), dim3(blocks_for((size_t)hc.N * hc.P)), dim3(256), 0, st, dc, img);
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_pad_image(const DevCtx<T>& hc, const DevCtx<T>* dc, const T* img, hipStream_t st) {
     hipLaunchKernelGGL((k_pad_image<T>), dim3(tv_blocks(hc.N)), dim3(256), 0, st, dc, img);
@@ -1999,6 +2077,7 @@ hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projecto
     template hipError_t launch_apply_minv<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, T, hipStream_t);  \
     template hipError_t launch_fbp<T>(const DevCtx<T>&, const DevCtx<T>*, int, const T*, T*, hipStream_t);       \
     template hipError_t launch_pad_image<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, hipStream_t);          \
+    template hipError_t launch_pad_image_full<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, hipStream_t);     \
     template hipError_t launch_project_plain<T>(const DevCtx<T>&, const DevCtx<T>*, int, T*, hipStream_t);       \
     template hipError_t launch_project_setp<T>(const DevCtx<T>&, const DevCtx<T>*, int, hipStream_t);            \
     template hipError_t launch_eval_objective<T>(const DevCtx<T>&, const DevCtx<T>*, int, const T*, hipStream_t); \

@@ -48,7 +48,7 @@ _STATUS_NAMES = {
 EXPORTED = [
     "ncs_setup", "ncs_set_init", "ncs_set_x", "ncs_iterate", "ncs_solve", "ncs_get_objectives",
     "ncs_get_iteration", "ncs_get_x", "ncs_get_u", "ncs_get_v", "ncs_get_t", "ncs_get_state", "ncs_set_state",
-    "ncs_forward", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_prefilter", "ncs_fbp", "ncs_get_eigenvalues",
+    "ncs_forward", "ncs_forward_noalloc", "ncs_adjoint", "ncs_apply_minv", "ncs_objective", "ncs_prefilter", "ncs_fbp", "ncs_get_eigenvalues",
     "ncs_time_phases", "ncs_get_info", "ncs_destroy", "ncs_last_error",
     "ncs_batch_setup", "ncs_batch_set_init", "ncs_batch_solve", "ncs_batch_slice", "ncs_batch_destroy",
 ]
@@ -115,6 +115,7 @@ def load_library() -> ctypes.CDLL:
         "ncs_get_state": ([vp, vp, psz], i32),
         "ncs_set_state": ([vp, vp, ctypes.c_size_t], i32),
         "ncs_forward": ([vp, vp, vp], i32),
+        "ncs_forward_noalloc": ([ctypes.POINTER(_Geometry), vp, vp, vp], i32),
         "ncs_adjoint": ([vp, vp, vp], i32),
         "ncs_apply_minv": ([vp, vp, vp], i32),
         "ncs_prefilter": ([vp, vp, vp], i32),
@@ -145,6 +146,24 @@ def _check(status: int, allow=(NCS_OK,)) -> int:
         return status
     msg = load_library().ncs_last_error().decode(errors="replace")
     raise NcsError(status, msg)
+
+
+def forward_noalloc(geom: "Geometry", x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """y = E x through ncs_forward_noalloc: no handle, and the library allocates
+    nothing (its workspace is a fixed device array).  x: N*N float32, y:
+    N_theta*N_s float32, both on the current device; runs on torch's current
+    stream."""
+    lib = load_library()
+    if x.dtype != torch.float32 or y.dtype != torch.float32 or not x.is_cuda or not y.is_cuda:
+        raise ValueError("forward_noalloc takes float32 device tensors")
+    if x.numel() != geom.n_side * geom.n_side or y.numel() != geom.n_angles * geom.n_bins:
+        raise ValueError("forward_noalloc: x must hold N*N values and y N_theta*N_s")
+    if not (x.is_contiguous() and y.is_contiguous()):
+        raise ValueError("forward_noalloc: x and y must be contiguous")
+    g = geom._c()
+    stream = torch.cuda.current_stream(x.device).cuda_stream
+    _check(lib.ncs_forward_noalloc(ctypes.byref(g), x.data_ptr(), y.data_ptr(), stream))
+    return y
 
 
 @dataclass
