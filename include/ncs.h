@@ -191,11 +191,17 @@ ncs_status ncs_iterate(ncs_handle* h, int32_t k, double* obj_host);
 
 /* Iterate until f(x^k) <= f_target (NaN: no target), at most max_iters
  * iterations.  The objective is tested on the device after every iteration;
- * the host checks every params.check_every iterations.  iters_done and
- * f_final (either may be NULL) receive the iterations run in this call and
- * the last objective.  Returns NCS_OK when the target was reached,
+ * the host checks every params.check_every iterations.  fp_residual_tol > 0
+ * adds a second stop, tested at those checks only: the fixed-point residual
+ * of the primal iterate |x^k - x^{k-1}|_2 <= fp_residual_tol |x^k|_2 (the
+ * iterates converge to a fixed point of the NCS map, Theorem 1, so the step
+ * vanishes; it is formed in double from x^k and xbar = 2 x^k - x^{k-1}, so
+ * with NCS_F32 its floor is about 1e-7).  fp_residual_tol <= 0 disables it;
+ * NaN is NCS_ERR_INVALID_ARG.  iters_done and f_final (either may be NULL)
+ * receive the iterations run in this call and the last objective.  Returns
+ * NCS_OK when the target or the residual tolerance was reached,
  * NCS_NOT_CONVERGED when the budget ran out, or an error. */
-ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target,
+ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target, double fp_residual_tol,
                      int32_t* iters_done, double* f_final);
 
 /* Objective history: obj_host[i] = f after iteration first + i (iterations

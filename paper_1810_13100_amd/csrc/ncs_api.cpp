@@ -1079,11 +1079,16 @@ ncs_status ncs_iterate(ncs_handle* h, int32_t k, double* obj_host) {
     return NCS_OK;
 }
 
-ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target, int32_t* iters_done, double* f_final) {
+ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target, double fp_residual_tol, int32_t* iters_done,
+                     double* f_final) {
     ncs_status s = check_handle(h);
     if (s) return s;
     if (max_iters < 0) {
         set_err("ncs_solve: max_iters must be >= 0");
+        return NCS_ERR_INVALID_ARG;
+    }
+    if (fp_residual_tol != fp_residual_tol) {
+        set_err("ncs_solve: fp_residual_tol is NaN");
         return NCS_ERR_INVALID_ARG;
     }
     if (!h->b) {
@@ -1102,6 +1107,13 @@ ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target, int32_t*
         const int chunk = std::min(remaining, (int)h->p.check_every);
         NCS_HIP(launch_iters(h, chunk));
         remaining -= chunk;
+        if (fp_residual_tol > 0.0) {
+            if (h->dtype == NCS_F64) {
+                NCS_HIP(launch_step_residual<double>(dctx<double>(h), h->stream));
+            } else {
+                NCS_HIP(launch_step_residual<float>(dctx<float>(h), h->stream));
+            }
+        }
         if ((s = read_control(h, &c))) return s;
         if (c.status == -4) {
             set_err("ncs_solve: objective became NaN at iteration %d", c.iter);
@@ -1109,6 +1121,10 @@ ncs_status ncs_solve(ncs_handle* h, int32_t max_iters, double f_target, int32_t*
             break;
         }
         if (c.status == 1) {
+            result = NCS_OK;
+            break;
+        }
+        if (fp_residual_tol > 0.0 && c.iter > 0 && std::sqrt(c.step_sq) <= fp_residual_tol * std::sqrt(c.x_sq)) {
             result = NCS_OK;
             break;
         }

@@ -67,6 +67,8 @@ struct Control {
     double f_last;       // objective after the last iteration
     double data_const;   // constant added to the data term (PET: sum log Gamma(b+1))
     double eval_out;     // result slot of a one-off objective evaluation
+    double step_sq;      // |x^k - x^{k-1}|^2 at the last residual evaluation
+    double x_sq;         // |x^k|^2 at the same evaluation
 };
 
 constexpr int kHistCap = 65536;   // objective history ring (doubles)
@@ -205,6 +207,8 @@ template <class T> hipError_t launch_data_const(const DevCtx<T>& hc, const DevCt
 template <class T> hipError_t launch_dual_init(const DevCtx<T>& hc, const DevCtx<T>* dc, hipStream_t st);
 // |E 1|^2 into ctl->eval_out (projection of the ones image, double sum)
 template <class T> hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projector, hipStream_t st);
+// |x^k - x^{k-1}|^2 and |x^k|^2 of one slice into its control block
+template <class T> hipError_t launch_step_residual(const DevCtx<T>* dc, hipStream_t st);
 
 // Control block updates queued on the stream (no memset nodes, capturable):
 //   op 0: reset  (iter = 0, stop = 0, status = 0, f_target)

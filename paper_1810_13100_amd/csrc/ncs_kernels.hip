@@ -1447,6 +1447,32 @@ __global__ __launch_bounds__(256) void k_ones_image(const DevCtx<T>* __restrict_
     c.xscT[(size_t)col * c.P + r + kPadL] = T(1);
 }
 
+// Fixed-point residual of the primal iterate: |x^k - x^{k-1}|^2, formed as
+// |xbar - x^k|^2 since xbar = 2 x^k - x^{k-1}, and |x^k|^2, both in double,
+// into the control block.  One workgroup strides over the image (evaluated at
+// host checks only).
+template <class T>
+__global__ __launch_bounds__(256) void k_step_residual(const DevCtx<T>* __restrict__ ctxs) {
+    const DevCtx<T>& c = ctxs[0];
+    __shared__ double sh_d[kWaves], sh_x[kWaves];
+    const size_t nn = (size_t)c.N * c.N;
+    double ds = 0.0, xs = 0.0;
+    for (size_t pix = threadIdx.x; pix < nn; pix += 256) {
+        const int r = (int)(pix >> c.log2N);
+        const int col = (int)(pix & (size_t)(c.N - 1));
+        const double xp = (double)c.x[pix];
+        const double d = (double)c.xbar[(size_t)r * c.P + col + kPadL] - xp;
+        ds = fma(d, d, ds);
+        xs = fma(xp, xp, xs);
+    }
+    const double td = block_sum256(ds, sh_d);
+    const double tx = block_sum256(xs, sh_x);
+    if (threadIdx.x == 0) {
+        c.ctl->step_sq = td;
+        c.ctl->x_sq = tx;
+    }
+}
+
 // which: 1 = evaluation (eval_out = data + constant + lambda TV),
 //        2 = data constant (data_const = sum of data partials),
 //        3 = plain sum (eval_out = sum of data partials).
@@ -2068,6 +2094,12 @@ hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projecto
     return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_step_residual(const DevCtx<T>* dc, hipStream_t st) {
+    hipLaunchKernelGGL((k_step_residual<T>), dim3(1), dim3(256), 0, st, dc);
+    return hipGetLastError();
+}
+
 #define NCS_INSTANTIATE(T)                                                                                        \
     template hipError_t launch_iterations<T>(const IterLaunch<T>&, int, hipStream_t);                            \
     template hipError_t launch_bp_iter<T>(const IterLaunch<T>&, int, hipStream_t);                                \
@@ -2085,7 +2117,8 @@ hipError_t launch_e1_norm(const DevCtx<T>& hc, const DevCtx<T>* dc, int projecto
     template hipError_t launch_unpad_sinogram<T>(const DevCtx<T>&, const DevCtx<T>*, const T*, T*, hipStream_t); \
     template hipError_t launch_data_const<T>(const DevCtx<T>&, const DevCtx<T>*, hipStream_t);                   \
     template hipError_t launch_dual_init<T>(const DevCtx<T>&, const DevCtx<T>*, hipStream_t);                   \
-    template hipError_t launch_e1_norm<T>(const DevCtx<T>&, const DevCtx<T>*, int, hipStream_t);
+    template hipError_t launch_e1_norm<T>(const DevCtx<T>&, const DevCtx<T>*, int, hipStream_t);                 \
+    template hipError_t launch_step_residual<T>(const DevCtx<T>*, hipStream_t);
 
 NCS_INSTANTIATE(float)
 NCS_INSTANTIATE(double)

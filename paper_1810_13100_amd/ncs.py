@@ -105,7 +105,7 @@ def load_library() -> ctypes.CDLL:
         "ncs_set_init": ([vp, vp, i32], i32),
         "ncs_set_x": ([vp, vp], i32),
         "ncs_iterate": ([vp, i32, pdbl], i32),
-        "ncs_solve": ([vp, i32, dbl, pi32, pdbl], i32),
+        "ncs_solve": ([vp, i32, dbl, dbl, pi32, pdbl], i32),
         "ncs_get_objectives": ([vp, i32, i32, pdbl], i32),
         "ncs_get_iteration": ([vp, pi32], i32),
         "ncs_get_x": ([vp, vp], i32),
@@ -280,11 +280,14 @@ class Solver:
         _check(self.lib.ncs_iterate(self.h, k, None))
         return None
 
-    def solve(self, max_iters: int, f_target: float = math.nan) -> tuple[int, int, float]:
-        """Returns (status, iterations run, last objective); status is NCS_OK or NCS_NOT_CONVERGED."""
+    def solve(self, max_iters: int, f_target: float = math.nan,
+              fp_residual_tol: float = 0.0) -> tuple[int, int, float]:
+        """Returns (status, iterations run, last objective); status is NCS_OK or NCS_NOT_CONVERGED.
+        fp_residual_tol > 0 also stops at a host check once |x^k - x^{k-1}| <= tol |x^k|."""
         it = ctypes.c_int32()
         f = ctypes.c_double()
-        st = _check(self.lib.ncs_solve(self.h, max_iters, f_target, ctypes.byref(it), ctypes.byref(f)),
+        st = _check(self.lib.ncs_solve(self.h, max_iters, f_target, fp_residual_tol, ctypes.byref(it),
+                                       ctypes.byref(f)),
                     allow=(NCS_OK, NCS_NOT_CONVERGED))
         return st, it.value, f.value
 

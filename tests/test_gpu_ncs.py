@@ -179,6 +179,39 @@ def test_solve_stops_at_first_target_crossing():
     s.close()
 
 
+def test_solve_stops_on_the_fixed_point_residual():
+    """fp_residual_tol: the host checks |x^k - x^{k-1}| <= tol |x^k| every
+    check_every iterations; the oracle's iterates, continued chunk by chunk,
+    fix the first check that passes."""
+    prob = ct_problem("c1")
+    par = ct_params(64, 90)
+    every, checks = 10, 30
+    res, x, u, v = [], None, None, None
+    for _ in range(checks):
+        t = solvers.ncs(prob, par, every, x0=x, u0=u, v0=v, record=False)
+        x, u, v = t.x, t.u, t.v
+        res.append(float(np.linalg.norm(t.x - t.x_prev) / np.linalg.norm(t.x)))
+    res = np.array(res)
+    tol = float(res[14]) * (1 + 1e-7)
+    first = int(np.nonzero(res <= tol)[0][0])
+    assert np.all(np.abs(res[:first] - tol) > 1e-6 * tol)   # no check decided by rounding
+    s = make_solver(prob, par, torch.float64, check_every=every)
+    s.set_init()
+    st, iters, f = s.solve(every * checks, math.nan, tol)
+    log(f"residual stop: status {st}, {iters} iterations (oracle {every * (first + 1)}), "
+        f"residuals at the checks {res[:first + 1]}")
+    assert st == ncs.NCS_OK and iters == every * (first + 1)
+    xg = s.x().cpu().numpy()
+    np.testing.assert_allclose(xg, oracle_ncs(prob, par, iters).x, rtol=0, atol=1e-9 * np.abs(xg).max())
+    # a tolerance no check reaches runs the whole budget; NaN is rejected
+    s.set_init()
+    st, iters, _ = s.solve(50, math.nan, 1e-300)
+    assert st == ncs.NCS_NOT_CONVERGED and iters == 50
+    with pytest.raises(ncs.NcsError):
+        s.solve(10, math.nan, math.nan)
+    s.close()
+
+
 def test_objective_history_matches_iterate():
     prob = ct_problem("c1")
     par = ct_params(64, 90)
