@@ -489,11 +489,16 @@ def cone_legs(ncs, torch, dev, steps: int, fstar_iters: int) -> dict:
     return out
 
 
-def batch_throughput(ncs, torch, dev, iters: int) -> dict:
+# alpha per image side of the uneven batch: the fastest of a scan over
+# alpha in {1/4, ..., 8} x 3e-4 (256/N)^2 and beta/alpha in {1, 3, 10}
+# (iterations of one slice to the 1e-4 gap); beta = 3 alpha, gamma = 0.3 alpha C_R
+BATCH_ALPHA = {128: 2.4e-3, 256: 6e-4, 512: 3e-4}
+
+
+def batch_slices(ncs, torch, dev):
     """The uneven batch: 205 slices of 128^2, 205 of 256^2 and 102 of 512^2
     (angles round(1.4 side), bins side + side/64), shuffled; every slice has its
-    own seeded phantom and noise.  Timed: `iters` batch iterations of all 512
-    slices in shared launches (replayed graphs, objective every iteration)."""
+    own seeded phantom and 1% Gaussian noise."""
     import ncs_inputs
     sides = ncs_inputs.batch_sides()
     ops, geoms, pars, bs = {}, [], [], []
@@ -501,9 +506,8 @@ def batch_throughput(ncs, torch, dev, iters: int) -> dict:
     for i, side in enumerate(sides):
         n, na, nb = ncs_inputs.batch_geometry(int(side))
         g = ncs.Geometry(n, na, nb)
-        c_r = na * n / math.pi
-        alpha = 0.01 * (64.0 / n) ** 2      # the 64^2 and 256^2 tunings, alpha ~ 1/n
-        p = ncs.Params(alpha, BETA_RATIO * alpha, GAMMA_FRAC * alpha * c_r, LAMBDA)
+        alpha = BATCH_ALPHA[n]
+        p = ncs.Params(alpha, BETA_RATIO * alpha, GAMMA_FRAC * alpha * na * n / math.pi, LAMBDA)
         if n not in ops:
             ops[n] = ncs.Solver(g, p)
         seed = 10_000 + i
@@ -516,24 +520,88 @@ def batch_throughput(ncs, torch, dev, iters: int) -> dict:
     for o in ops.values():
         o.close()
     torch.cuda.synchronize()
+    return sides, geoms, pars, bs
+
+
+def batch_legs(ncs, torch, dev, iters: int, gap_ref_iters: int) -> dict:
+    """Timed: `iters` batch iterations of all 512 slices in shared launches
+    (replayed graphs, objective every iteration).  With gap_ref_iters > 0 also
+    the wall time until every slice has stopped at its own target
+    f* (1 + 1e-4), f* the smallest objective of the slice over gap_ref_iters
+    FP32 iterations of the same batch (each slice stops on the device; stopped
+    slices leave the shared launches)."""
+    sides, geoms, pars, bs = batch_slices(ncs, torch, dev)
     t0 = time.perf_counter()
     bat = ncs.Batch(geoms, pars, bs)
     setup_s = time.perf_counter() - t0
     bat.set_init()
-    bat.solve(5)
+    bat.solve(50)   # graphs captured, every kernel run once
     torch.cuda.synchronize()
     progress(f"batch: timing {iters} iterations of {len(sides)} slices")
     t0 = time.perf_counter()
     _, it, _ = bat.solve(iters)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    bat.close()
     taps = sum(1.8 * g.n_side * (g.n_side + 1) * g.n_angles for g in geoms)   # nnz(E) estimate per slice
-    return {"slices": len(sides), "mix": {"128": int((sides == 128).sum()), "256": int((sides == 256).sum()),
-                                           "512": int((sides == 512).sum())},
-            "iterations": iters, "seconds": dt, "slice_iterations_per_s": len(sides) * iters / dt,
-            "ms_per_batch_iteration": dt / iters * 1e3, "est_taps_per_s": 2 * taps * iters / dt,
-            "setup_s": setup_s, "alpha": "0.01 (64/N)^2, beta = 3 alpha, gamma = 0.3 alpha C_R"}
+    out = {"slices": len(sides), "mix": {"128": int((sides == 128).sum()), "256": int((sides == 256).sum()),
+                                         "512": int((sides == 512).sum())},
+           "iterations": iters, "seconds": dt, "slice_iterations_per_s": len(sides) * iters / dt,
+           "ms_per_batch_iteration": dt / iters * 1e3, "est_taps_per_s": 2 * taps * iters / dt,
+           "setup_s": setup_s,
+           "alpha": {str(k): v for k, v in BATCH_ALPHA.items()}, "beta": "3 alpha", "gamma": "0.3 alpha C_R",
+           "time_to_all_stop": None}
+    if gap_ref_iters > 0:
+        n = len(sides)
+        fstar = np.full(n, np.inf)
+        bat.set_init()
+        done, t0 = 0, time.perf_counter()
+        last = np.zeros(n)
+        while done < gap_ref_iters:
+            k = min(4000, gap_ref_iters - done)
+            bat.solve(k)
+            for i in range(n):
+                h = bat.slice(i).objectives(done, k)
+                fstar[i] = min(fstar[i], float(h.min()))
+                if done + k == gap_ref_iters:
+                    last[i] = abs(h[-1] - h[-1001]) / abs(fstar[i]) if k > 1000 else np.nan
+            done += k
+            progress(f"batch f*: {done}/{gap_ref_iters} iterations ({time.perf_counter() - t0:.0f} s)")
+        ref_s = time.perf_counter() - t0
+        bat.set_init()
+        torch.cuda.synchronize()
+        progress("batch: timing the per-slice stop at the 1e-4 gap")
+        # calls of at most 2000 iterations; a slice that has stopped sits out
+        # the later calls (target -inf)
+        target = fstar * (1.0 + GAP)
+        its, f = np.zeros(n, dtype=np.int64), np.full(n, np.inf)
+        done_mask = np.zeros(n, dtype=bool)
+        t0 = time.perf_counter()
+        run = 0
+        while run < gap_ref_iters and not done_mask.all():
+            k = min(2000, gap_ref_iters - run)
+            _, it_c, f_c = bat.solve(k, np.where(done_mask, -np.inf, target))
+            its += np.asarray(it_c)
+            f = np.where(done_mask, f, f_c)
+            done_mask |= f_c <= target
+            run += k
+            progress(f"batch: {int(done_mask.sum())}/{n} slices stopped after {run} iterations "
+                     f"({time.perf_counter() - t0:.0f} s)")
+        torch.cuda.synchronize()
+        m4 = time.perf_counter() - t0
+        per = {}
+        for side in (128, 256, 512):
+            sel = its[sides == side]
+            per[str(side)] = {"median": float(np.median(sel)), "min": int(sel.min()), "max": int(sel.max())}
+        out["time_to_all_stop"] = {
+            "seconds": m4, "reached": int(np.sum(f <= fstar * (1.0 + GAP))), "slices": n,
+            "iterations_by_side": per, "slice_iterations": int(its.sum()),
+            "f_star_source": f"min f of each slice over {gap_ref_iters} FP32 iterations of the same batch "
+                             f"({ref_s:.0f} s)",
+            "f_star_rel_change_last_1000_max": float(np.nanmax(last)),
+            "check_every": 50, "rel_gap": GAP}
+        progress(f"batch: all {n} slices stopped after {m4:.1f} s (max {int(its.max())} iterations)")
+    bat.close()
+    return out
 
 
 class _BlockRows:
@@ -622,6 +690,9 @@ def main() -> int:
     ap.add_argument("--pdhg-iters", type=int, default=100000, help="iteration budget of the PDHG comparison")
     ap.add_argument("--admm-iters", type=int, default=5000, help="iteration budget of the ADMM-CG comparison")
     ap.add_argument("--batch-iters", type=int, default=40, help="iterations of the uneven 512-slice batch (0: skip)")
+    ap.add_argument("--batch-gap-iters", type=int, default=0,
+                    help="FP32 iterations of the batch's f* run before timing the per-slice stop at the 1e-4 gap "
+                         "(0: skip; the 512^2 slices need about 16000 iterations, the leg takes about 15 minutes)")
     ap.add_argument("--projector", type=int, default=0,
                     help="forward-projector kernel of the headline solver (0: the setup timing picks it)")
     ap.add_argument("--backprojector", type=int, default=0,
@@ -685,7 +756,7 @@ def main() -> int:
 
     pet = None if args.no_gap else pet_time_to_gap(ncs, torch, dev, 20000)
     fan = None if args.no_gap else fan_time_to_gap(ncs, torch, dev, 30000)
-    batch = batch_throughput(ncs, torch, dev, args.batch_iters) if args.batch_iters > 0 else None
+    batch = batch_legs(ncs, torch, dev, args.batch_iters, args.batch_gap_iters) if args.batch_iters > 0 else None
     cone_out = None
     if args.cone_steps > 0:
         cone_out = cone_legs(ncs, torch, dev, args.cone_steps, 0 if args.no_gap else args.cone_fstar_iters)

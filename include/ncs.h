@@ -306,9 +306,13 @@ void ncs_destroy(ncs_handle* h);
  * Every phase of an iteration is one launch over the workgroups of all active
  * slices (a workgroup -> slice map; slices are pinned to XCDs so that a
  * slice's workgroups share one L2).  Each slice keeps its own geometry,
- * parameters, data, state, objective history and device stop flag; the host
- * checks every params[0].check_every iterations and drops stopped slices
- * from the maps.  Not captured in HIP graphs (the launches are large). */
+ * parameters, data, state, objective history and device stop flag (the
+ * workgroups of a stopped slice exit at once).  The iterations between two
+ * host checks (params[0].check_every) are one replayed HIP graph, captured on
+ * a private stream at first use; params[0].graph_chunk < 0 gives direct
+ * launches instead.  At a check the maps are rebuilt without the stopped
+ * slices (and the graph re-captured) once a quarter of the projection
+ * workgroups in them belong to stopped slices. */
 typedef struct ncs_batch ncs_batch;
 
 /* geoms, params, b_dev: arrays of n_slices (b_dev entries non-NULL); bg_dev:
@@ -326,10 +330,12 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
 ncs_status ncs_batch_set_init(ncs_batch* b, const void* const* x0_dev, int32_t dual_from_x0);
 
 /* Iterate every slice until its objective reaches f_target[i] (NULL or NaN:
- * none), at most max_iters iterations.  iters_done and f_final (NULL or
- * arrays of n_slices) receive per-slice results.  Returns NCS_OK when every
- * slice reached its target, NCS_NOT_CONVERGED otherwise, NCS_ERR_NONFINITE
- * if a slice produced a NaN objective. */
+ * none), at most max_iters iterations.  f_target[i] = -infinity makes slice i
+ * sit out this call (no iterations, its state untouched), so a long solve can
+ * be split into calls that leave finished slices alone.  iters_done and
+ * f_final (NULL or arrays of n_slices) receive per-slice results.  Returns
+ * NCS_OK when every slice taking part reached its target, NCS_NOT_CONVERGED
+ * otherwise, NCS_ERR_NONFINITE if a slice produced a NaN objective. */
 ncs_status ncs_batch_solve(ncs_batch* b, int32_t max_iters, const double* f_target,
                            int32_t* iters_done, double* f_final);
 

@@ -15,6 +15,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <limits>
 #include <vector>
 
 using namespace ncs;
@@ -137,10 +138,17 @@ struct ncs_batch {
     int blocks[5] = {0, 0, 0, 0, 0};
     std::vector<int> xcd_of;      // slice -> XCD it is pinned to
     std::vector<char> active;
+    std::vector<char> mapped;     // the active flags the maps were built from
     int max_N = 0;
     int projector = 2;
     int backprojector = 2;
     int check_every = 50;
+    // the iterations between two host checks replayed as one captured graph,
+    // one per chunk length (two kept); dropped whenever the maps are rebuilt
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    int graph_k[2] = {0, 0};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -1609,7 +1617,23 @@ namespace {
 // (longest-processing-time assignment by projector workgroups); workgroup b
 // of a launch is dispatched to XCD b mod 8, so the map interleaves the eight
 // per-XCD lists and each slice's workgroups share one XCD's L2.
+void drop_batch_graphs(ncs_batch* B) {
+    for (int j = 0; j < 2; ++j) {
+        if (B->graph[j]) (void)hipGraphExecDestroy(B->graph[j]);
+        B->graph[j] = nullptr;
+        B->graph_k[j] = 0;
+    }
+}
+
+// Projector workgroups of slice i (with its TV tiles): the unit of the map's
+// size and of the work that stopped slices leave idle in it.
+int proj_work(const ncs_batch* B, int i) {
+    const ncs_handle* h = B->slices[i];
+    return project_blocks(h->g.n_angles, h->g.n_bins) + tv_blocks(h->g.n_side);
+}
+
 ncs_status build_maps(ncs_batch* B) {
+    drop_batch_graphs(B);
     const int nphase = 5;
     std::vector<std::vector<Slot>> lists[5];
     for (int ph = 0; ph < nphase; ++ph) lists[ph].assign(kXcds, {});
@@ -1617,8 +1641,7 @@ ncs_status build_maps(ncs_batch* B) {
         if (!B->active[i]) continue;
         const ncs_handle* h = B->slices[i];
         const int N = h->g.n_side;
-        const int cnt[5] = {bp_blocks(N, B->backprojector), N / 2, N / 2 + 1,
-                            project_blocks(h->g.n_angles, h->g.n_bins) + tv_blocks(N), 1};
+        const int cnt[5] = {bp_blocks(N, B->backprojector), N / 2, N / 2 + 1, proj_work(B, i), 1};
         const int x = B->xcd_of[i];
         for (int ph = 0; ph < nphase; ++ph)
             for (int l = 0; l < cnt[ph]; ++l) lists[ph][x].push_back(Slot{i, l});
@@ -1641,6 +1664,7 @@ ncs_status build_maps(ncs_batch* B) {
         }
         NCS_HIP(hipMemcpy(B->maps[ph], flat.data(), flat.size() * sizeof(Slot), hipMemcpyHostToDevice));
     }
+    B->mapped = B->active;
     return NCS_OK;
 }
 
@@ -1658,6 +1682,50 @@ hipError_t batch_iterate(ncs_batch* B, int k) {
     L.projector = B->projector;
     L.backprojector = B->backprojector;
     return launch_iterations<T>(L, k, B->stream);
+}
+
+hipError_t batch_iterate_any(ncs_batch* B, int k, hipStream_t st) {
+    hipStream_t keep = B->stream;
+    B->stream = st;
+    const hipError_t e = B->dtype == NCS_F64 ? batch_iterate<double>(B, k) : batch_iterate<float>(B, k);
+    B->stream = keep;
+    return e;
+}
+
+// k batch iterations as a replayed graph: captured on a private stream at the
+// first request for this k after the maps were (re)built.  A capture failure
+// switches the batch to direct launches.
+hipError_t batch_launch(ncs_batch* B, int k) {
+    if (k <= 0 || B->blocks[3] == 0) return hipSuccess;
+    if (B->use_graphs) {
+        int j = B->graph_k[0] == k ? 0 : B->graph_k[1] == k ? 1 : -1;
+        if (j < 0) {
+            j = B->graph[0] ? 1 : 0;
+            if (B->graph[j]) (void)hipGraphExecDestroy(B->graph[j]);
+            B->graph[j] = nullptr;
+            B->graph_k[j] = 0;
+            bool ok = B->cap_stream || hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking) == hipSuccess;
+            if (ok) ok = hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                const hipError_t le = batch_iterate_any(B, k, B->cap_stream);
+                hipGraph_t graph = nullptr;
+                const hipError_t ee = hipStreamEndCapture(B->cap_stream, &graph);
+                ok = le == hipSuccess && ee == hipSuccess && graph &&
+                     hipGraphInstantiate(&B->graph[j], graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
+            }
+            if (!ok) {
+                (void)hipGetLastError();
+                B->graph[j] = nullptr;
+                drop_batch_graphs(B);
+                B->use_graphs = false;
+                return batch_iterate_any(B, k, B->stream);
+            }
+            B->graph_k[j] = k;
+        }
+        return hipGraphLaunch(B->graph[j], B->stream);
+    }
+    return batch_iterate_any(B, k, B->stream);
 }
 
 
@@ -1765,6 +1833,7 @@ ncs_status ncs_batch_setup(int32_t n_slices, const ncs_geometry* geoms, const nc
     B->dtype = dtype;
     B->stream = static_cast<hipStream_t>(stream);
     B->check_every = params[0].check_every > 0 ? params[0].check_every : 50;
+    B->use_graphs = params[0].graph_chunk >= 0;
     auto fail = [&](ncs_status s) {
         ncs_batch_destroy(B);
         return s;
@@ -1847,6 +1916,8 @@ void ncs_batch_destroy(ncs_batch* B) {
     (void)hipSetDevice(B->device);
     (void)hipStreamSynchronize(B->stream);
     for (ncs_handle* h : B->slices) ncs_destroy(h);
+    drop_batch_graphs(B);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
     for (Slot* m : B->maps)
         if (m) (void)hipFree(m);
     if (B->dctxs) (void)hipFree(B->dctxs);
@@ -1861,7 +1932,7 @@ ncs_status ncs_batch_set_init(ncs_batch* B, const void* const* x0_dev, int32_t d
         if ((s = ncs_set_init(B->slices[i], x0_dev ? x0_dev[i] : nullptr, dual_from_x0))) return s;
         B->active[i] = 1;
     }
-    return build_maps(B);
+    return B->mapped != B->active ? build_maps(B) : NCS_OK;
 }
 
 ncs_status ncs_batch_solve(ncs_batch* B, int32_t max_iters, const double* f_target, int32_t* iters_done,
@@ -1873,41 +1944,46 @@ ncs_status ncs_batch_solve(ncs_batch* B, int32_t max_iters, const double* f_targ
         return NCS_ERR_INVALID_ARG;
     }
     std::vector<int> start(B->n);
+    std::vector<char> skip(B->n, 0);
     for (int i = 0; i < B->n; ++i) {
-        NCS_HIP(launch_control(B->ctls + i, 1, 0, f_target ? f_target[i] : std::nan(""), B->stream));
-        B->active[i] = 1;
+        const double t = f_target ? f_target[i] : std::nan("");
+        skip[i] = t == -std::numeric_limits<double>::infinity();
+        if (!skip[i]) NCS_HIP(launch_control(B->ctls + i, 1, 0, t, B->stream));
+        B->active[i] = !skip[i];
     }
     std::vector<Control> c(B->n);
     NCS_HIP(hipMemcpyAsync(c.data(), B->ctls, B->n * sizeof(Control), hipMemcpyDeviceToHost, B->stream));
     NCS_HIP(hipStreamSynchronize(B->stream));
     for (int i = 0; i < B->n; ++i) start[i] = c[i].iter;
-    if ((s = build_maps(B))) return s;
+    if (B->mapped != B->active && (s = build_maps(B))) return s;
     int remaining = max_iters;
     bool any_nan = false;
     while (remaining > 0) {
         const int chunk = std::min(remaining, B->check_every);
-        NCS_HIP(B->dtype == NCS_F64 ? batch_iterate<double>(B, chunk) : batch_iterate<float>(B, chunk));
+        NCS_HIP(batch_launch(B, chunk));
         remaining -= chunk;
         NCS_HIP(hipMemcpyAsync(c.data(), B->ctls, B->n * sizeof(Control), hipMemcpyDeviceToHost, B->stream));
         NCS_HIP(hipStreamSynchronize(B->stream));
-        bool changed = false;
-        int left = 0;
+        int left = 0, work = 0;
         for (int i = 0; i < B->n; ++i) {
             if (B->active[i] && c[i].stop) {
                 B->active[i] = 0;
-                changed = true;
                 any_nan |= c[i].status == -4;
             }
             left += B->active[i];
+            if (B->active[i]) work += proj_work(B, i);
         }
         if (left == 0) break;
-        if (changed && (s = build_maps(B))) return s;
+        // stopped slices' workgroups exit at once; the maps (and the graphs
+        // replaying them) are rebuilt only when a quarter of the projection
+        // workgroups in them belong to stopped slices
+        if (4 * (B->blocks[3] - work) >= B->blocks[3] && (s = build_maps(B))) return s;
     }
     bool all_reached = true;
     for (int i = 0; i < B->n; ++i) {
         if (iters_done) iters_done[i] = c[i].iter - start[i];
         if (f_final) f_final[i] = c[i].f_last;
-        all_reached &= c[i].status == 1;
+        all_reached &= skip[i] || c[i].status == 1;
         B->slices[i]->iter_host = c[i].iter;
     }
     if (any_nan) {

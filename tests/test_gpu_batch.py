@@ -3,7 +3,8 @@
 Each slice of a batch runs the same kernels as a single-slice solve, reading
 its own descriptor, so its trajectory must equal the single-slice run bit for
 bit (same projector kernel) and match the FP64 oracle to the usual gates;
-every slice stops on its own target.
+every slice stops on its own target.  The iterations between host checks are
+replayed HIP graphs; direct launches (graph_chunk < 0) give the same bits.
 """
 import numpy as np
 import pytest
@@ -27,21 +28,22 @@ def _problem(n, na, ns, seed, kind):
     return problems.ct_problem(n, na, ns, seed, 0.01, E=joseph(n, na, ns))
 
 
-def _params(prob, projector=2):
+def _params(prob, projector=2, graph_chunk=0):
     if prob.kind == "pet":
         par = ct_params(prob.n_side, prob.n_angles, alpha=1.0, ratio=3.0, g=1.0)
         return par, ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, data_term=ncs.DATA_POISSON,
-                               tv_term=ncs.TV_ISO, projector=projector, backprojector=projector, check_every=10)
+                               tv_term=ncs.TV_ISO, projector=projector, backprojector=projector, check_every=10,
+                               graph_chunk=graph_chunk)
     par = ct_params(prob.n_side, prob.n_angles)
     return par, ncs.Params(par.alpha, par.beta, par.gamma, prob.lam, projector=projector, backprojector=projector,
-                           check_every=10)
+                           check_every=10, graph_chunk=graph_chunk)
 
 
-def _batch(probs, dtype, projector=2):
+def _batch(probs, dtype, projector=2, graph_chunk=0):
     geoms, params, bs, bgs = [], [], [], []
     for prob in probs:
         geoms.append(ncs.Geometry(prob.n_side, prob.n_angles, prob.n_bins))
-        params.append(_params(prob, projector)[1])
+        params.append(_params(prob, projector, graph_chunk)[1])
         bs.append(torch.tensor(prob.b, dtype=dtype, device=DEV))
         bgs.append(torch.tensor(prob.bg, dtype=dtype, device=DEV) if prob.kind == "pet" else None)
     return ncs.Batch(geoms, params, bs, bgs, dtype=dtype), bs, bgs
@@ -123,4 +125,75 @@ def test_batch_autotuned_kernels():
         ref = oracle_ncs(prob, _params(prob)[0], K)
         ex = rel_l2(bt.slice(i).x().double().cpu().numpy(), ref.x)
         assert ex <= 1e-4, ex
+    bt.close()
+
+
+def test_batch_graph_replay_equals_direct_launches():
+    # per-slice stops inside replayed chunks, maps rebuilt (and graphs
+    # re-captured) as slices stop: the same iterates and counts as direct launches
+    probs = [_problem(*s) for s in SLICES if s[4] == "ct"]
+    refs = [oracle_ncs(p, _params(p)[0], 80) for p in probs]
+    targets = np.array([r.obj[k] * (1 + 1e-12) for r, k in zip(refs, [20, 45, 70, 33, 57])])
+    out = []
+    for gc in (-1, 0):
+        bt, _, _ = _batch(probs, torch.float32, graph_chunk=gc)
+        bt.set_init()
+        st, iters, f = bt.solve(200, targets)
+        xs = [bt.slice(i).x().cpu() for i in range(len(probs))]
+        st2, iters2, _ = bt.solve(37)   # no targets: every slice runs the whole budget, 3 chunks + 7
+        xs2 = [bt.slice(i).x().cpu() for i in range(len(probs))]
+        out.append((list(iters), xs, list(iters2), xs2))
+        bt.close()
+    log(f"graph vs direct: stops {out[1][0]} / {out[0][0]}")
+    assert out[0][0] == out[1][0] and out[0][2] == out[1][2] == [37] * len(probs)
+    for a, b in zip(out[0][1] + out[0][3], out[1][1] + out[1][3]):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.timeout(900)
+def test_batch_with_a_512_slice():
+    """A 512^2 slice of the uneven batch's geometry (717 angles x 520 bins) with
+    a 128^2 and a 256^2 one: 20 FP32 iterations against the FP64 oracle, and
+    the 512^2 slice equal bit for bit to its single-slice run."""
+    geo = [(512, 717, 520, 7), (128, 179, 130, 8), (256, 358, 260, 9)]
+    log("assembling the oracle's 512^2 projector (about a minute)")
+    probs = [problems.ct_problem(n, na, ns, seed, 0.005, E=joseph(n, na, ns)) for n, na, ns, seed in geo]
+    K = 20
+    bt, bs, _ = _batch(probs, torch.float32)
+    bt.set_init()
+    st, iters, _ = bt.solve(K)
+    assert list(iters) == [K] * len(probs)
+    for i, prob in enumerate(probs):
+        ref = oracle_ncs(prob, _params(prob)[0], K)
+        sl = bt.slice(i)
+        ex = rel_l2(sl.x().double().cpu().numpy(), ref.x)
+        ef = float(np.max(np.abs(sl.objectives(0, K) - ref.obj) / np.abs(ref.obj)))
+        log(f"  slice {geo[i]}: rel-L2 x {ex:.2e}, max rel f {ef:.2e}")
+        assert ex <= 1e-4 and ef <= 1e-5
+    p = _params(probs[0])[1]
+    solo = ncs.Solver(ncs.Geometry(512, 717, 520), p, b=bs[0])
+    solo.set_init()
+    solo.iterate(K)
+    assert torch.equal(solo.x().cpu(), bt.slice(0).x().cpu())
+    solo.close()
+    bt.close()
+
+
+def test_batch_slice_sits_out_with_minus_infinity_target():
+    probs = [_problem(*s) for s in SLICES if s[4] == "ct"]
+    bt, _, _ = _batch(probs, torch.float64)
+    bt.set_init()
+    bt.solve(15)
+    before = [bt.slice(i).x().cpu() for i in range(len(probs))]
+    t = np.array([-np.inf, np.nan, -np.inf, np.nan, np.nan])
+    st, iters, _ = bt.solve(23, t)
+    assert list(iters) == [0, 23, 0, 23, 23]
+    for i in range(len(probs)):
+        after = bt.slice(i).x().cpu()
+        assert torch.equal(after, before[i]) == (i in (0, 2))
+        assert bt.slice(i).iteration() == (15 if i in (0, 2) else 38)
+    # the slices that sat out continue exactly as if never paused
+    ref = oracle_ncs(probs[0], _params(probs[0])[0], 30)
+    bt.solve(15, np.array([np.nan, -np.inf, -np.inf, -np.inf, -np.inf]))
+    assert rel_l2(bt.slice(0).x().cpu().numpy(), ref.x) <= 1e-10
     bt.close()
