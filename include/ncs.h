@@ -111,8 +111,10 @@ typedef struct {
     int32_t diverge_checks; /* ncs_solve: stop with NCS_ERR_DIVERGED after this many
                                consecutive checks with a growing objective; <= 0 disables */
     int32_t projector; /* forward-projector kernel: 0 = time all at setup and keep the
-                          fastest, 1 = LDS-staged row windows, 2 = direct coalesced loads,
-                          3 = two adjacent rays per lane, one 16-byte load per step */
+                          fastest, 1 = each step's 96-element row window copied through LDS
+                          (two steps' windows per 16-byte load), 2 = direct loads, one
+                          8-byte gather per ray and step, 3 = two adjacent rays per lane,
+                          one 16-byte load per step */
     int32_t graph_chunk; /* largest number of iterations per replayed HIP graph; 0 selects 32,
                             < 0 disables graphs (every kernel launched directly).  One graph
                             per power of two up to it is captured at the first iteration

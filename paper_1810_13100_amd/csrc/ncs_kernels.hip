@@ -46,8 +46,11 @@ namespace {
 
 constexpr int kRays = 64;      // rays per projector workgroup (one per lane)
 constexpr int kWaves = 4;      // waves per projector / TV workgroup
-constexpr int kRowWin = 100;   // LDS-staged projector: padded-row elements staged per step
-constexpr int kStageRows = 16; // LDS-staged projector: steps staged at a time by one wave
+constexpr int kRowWin = 96;    // LDS-window projector: padded-row elements staged per step (16-byte multiple)
+#ifndef NCS_STAGE_ROWS
+#define NCS_STAGE_ROWS 8
+#endif
+constexpr int kStageRows = NCS_STAGE_ROWS;   // LDS-window projector: steps (windows) in flight per wave
 constexpr int kBpWaves = 8;    // direct backprojector: waves per 8 x 8 pixel tile
 constexpr int kFftThreads = 256;
 constexpr int kFinGroup = 8;  // objective partials loaded per thread before they are added
@@ -959,17 +962,21 @@ __device__ inline void ray_sum_pair(const DevCtx<T>& c, const T* __restrict__ im
     red[range * kRays + 2 * pr + 1] = acc1;
 }
 
-// Ray sum with LDS-staged row windows.  For each step s the 64 rays of the
-// block read padded-row elements in [lo, lo + 95] (the block spans
-// 63 |k1| <= 89.1 columns), lo from the clamped smallest coordinate of the
-// block; each wave stages those 100-element windows (16-byte aligned) for
-// kStageRows of its steps at a time with 16-byte loads into a region of LDS
-// only it uses, then marches the steps reading both taps from LDS.  The
-// arithmetic of every tap is that of the direct method.
-template <class T>
-struct alignas(16) Quad {
-    T v[4];
-};
+// Ray sum through LDS row windows.  At step s the 64 rays of a block read
+// padded-row elements within 93 of the block's smallest tap (the block spans
+// 63 |k1| <= 89.1 columns, plus the second tap), so the wave copies the
+// kRowWin-element window that starts at the smallest tap, rounded down to 16
+// bytes, into LDS with coalesced 16-byte loads, and each lane reads its two
+// taps there.  The texture-address unit spends about 16 cycles on any vector
+// load instruction, whatever its lanes and width, so what counts is loads per
+// step: in FP32 a window is 24 lanes' worth, and one instruction loads two
+// steps' windows (lanes 0-23 and 32-55), half a load per step against one
+// gather per step in the direct method.  The smallest tap is the first
+// lane's for k1 > 0 and the last lane's otherwise (the coordinate is monotone
+// in the ray index).  Steps, anchors and the arithmetic of every tap are those
+// of the direct method; each wave holds kStageRows windows (its steps in
+// flight).
+typedef unsigned int Bytes16 __attribute__((ext_vector_type(4)));
 
 __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -978,78 +985,86 @@ __device__ inline void wave_lds_sync() {
 }
 
 template <class T>
-__device__ inline int row_window_base(const AngleT<T>& A, int s, T blo, T cmax) {
-    // element index (column + kPadL) of the column left of the clamped smallest coordinate
-    const int lo = (int)med3(floor(fma((T)s, A.k2, blo)), T(-2), cmax) + kPadL - 1;
-    return lo & ~3;
-}
-
-template <class T>
 __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
-                                const AngleT<T>& A, int a, int axis, int d0, int d, int lane, int wave, T* stage,
-                                int* rbase) {
-    const int N = c.N, P = c.P;
+                                const AngleT<T>& A, int a, int axis, int d0, int d, int lane, int part, int nparts,
+                                T* slots) {
+    const int P = c.P;
     const T* src = axis == 0 ? img : imgT;
     const NCS_G double* g = c.ang64 + 6 * a;
     const double k2d = g[1], based = fma((double)d, g[0], g[2]);
-    const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
-    const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
-    const T lo_x = T(-2), hi_x = T(N + 1);
-    const int SW = N / kWaves;
-    int s_begin = wave * SW, s_end = s_begin + SW;
-    if (A.k2 > T(0)) {
-        s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
-        s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
-    } else if (A.k2 < T(0)) {
-        s_begin = max(s_begin, sat_int(floor((hi_x - blo) / A.k2)) - 1);
-        s_end = min(s_end, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
-    } else if (bhi < lo_x || blo > hi_x) {
-        s_end = s_begin;
-    }
-    const T cmax = (T)N;
-    constexpr int NQ = kRowWin / 4;
+    int s_begin, s_end;
+    block_step_range(A, c.N, d0, part, nparts, s_begin, s_end);
+    const T k2 = A.k2;
+    const int lmin = __builtin_amdgcn_readfirstlane(A.k1 > T(0) ? 0 : kRays - 1);
+    constexpr int EQ = 16 / (int)sizeof(T);   // elements per 16-byte load
+    constexpr int NQ = kRowWin / EQ;          // lanes per window (24 in FP32, 48 in FP64)
+    constexpr int WPI = NQ <= 32 ? 2 : 1;     // windows per load instruction
+    constexpr int B = kStageRows;
+    static_assert(B % WPI == 0, "steps per group must be a multiple of the windows per load");
+    const int half = WPI == 2 ? lane >> 5 : 0;
+    const int hmask = -half;                  // all ones in the upper half of the wave
+    const int ql = WPI == 2 ? lane & 31 : lane;
+    const bool loader = ql < NQ;
+    const int wmax = P - kRowWin;             // last window start inside the row
+    const int pitch32 = P * (int)sizeof(T);
+    const unsigned lane_off = (unsigned)(half * pitch32 + ql * 16);
+    T* const st = slots + half * kRowWin + ql * EQ;
+    const char* row = reinterpret_cast<const char*>(src + (size_t)max(s_begin, 0) * P);
     T acc = T(0);
-    for (int s0 = s_begin; s0 < s_end; s0 += kStageRows) {
-        const int ns = min(kStageRows, s_end - s0);
-        wave_lds_sync();   // the previous rows have been read
-        if (lane < ns) rbase[lane] = row_window_base(A, s0 + lane, blo, cmax);
-        {
-            // all loads of the lane in flight before the stores
-            constexpr int R = (kStageRows * NQ + 63) / 64;
-            Quad<T> v[R];
+    int s = s_begin;
+    for (; s + B <= s_end; s += B) {
+        const Anchor an = make_anchor(fma((double)s, k2d, based));
+        const T t0 = (T)an.t;
+        const int ei = an.i + kPadL;
+        const int eimin = __builtin_amdgcn_readlane(ei, lmin);
+        int e[B], w[B];
+        T f[B];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int qi = lane + 64 * r;
-                const int i = qi / NQ, q = qi - i * NQ;
-                const int e = qi < ns * NQ ? row_window_base(A, s0 + i, blo, cmax) + 4 * q : -4;
+        for (int j = 0; j < B; ++j) {
+            const T t = j == 0 ? t0 : fma((T)j, k2, t0);
+            const int fl = floor_int(t);
+            f[j] = frac_part(t);
+            e[j] = ei + fl;
+            w[j] = min((eimin + __builtin_amdgcn_readlane(fl, lmin)) & ~(EQ - 1), wmax);
+        }
+        Bytes16 v[B / WPI];
+        if (loader) {   // all loads of the group in flight together (scalar base, 32-bit lane offset)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) v[r].v[k] = T(0);
-                // P and e are multiples of 4: a quad is wholly inside the padded row or wholly outside
-                if (e >= 0 && e < P) v[r] = *reinterpret_cast<const Quad<T>*>(src + (size_t)(s0 + i) * P + e);
+            for (int p = 0; p < B / WPI; ++p) {
+                // the lane's window start, w[2p] or w[2p + 1] (bytes), without an indexed access
+                const int wb0 = w[WPI * p] * (int)sizeof(T);
+                const int dwb = WPI == 2 ? (w[2 * p + 1] - w[2 * p]) * (int)sizeof(T) : 0;
+                const unsigned off = lane_off + (unsigned)wb0 + (unsigned)(dwb & hmask);
+                v[p] = *reinterpret_cast<const Bytes16*>(row + (unsigned)(WPI * p * pitch32) + off);
             }
+        }
+        wave_lds_sync();   // the previous group's taps have been read
+        if (loader) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int qi = lane + 64 * r;
-                if (qi < ns * NQ) {
-                    const int i = qi / NQ, q = qi - i * NQ;
-                    *reinterpret_cast<Quad<T>*>(stage + i * kRowWin + 4 * q) = v[r];
-                }
-            }
+            for (int p = 0; p < B / WPI; ++p) *reinterpret_cast<Bytes16*>(st + WPI * p * kRowWin) = v[p];
         }
         wave_lds_sync();
-        // one anchor per staged group (offsets of at most 15 columns)
-        const Anchor an = make_anchor(fma((double)s0, k2d, based));
-        const T t0 = (T)an.t;
-        for (int i = 0; i < ns; ++i) {
-            const T t = fma((T)i, A.k2, t0);
-            const int fl = min(max(an.i + floor_int(t), -2), N);   // taps off the image read the zero columns
-            const T f = frac_part(t);
-            int j = fl + kPadL - rbase[i];
-            j = min(max(j, 0), kRowWin - 2);
-            const T* tp = stage + i * kRowWin + j;
-            const T v0 = tp[0], v1 = tp[1];
-            acc += fma(f, v1 - v0, v0);
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const T* tp = (slots + (j * kRowWin - w[j])) + e[j];
+            acc += fma(f[j], tp[1] - tp[0], tp[0]);
         }
+        row += (size_t)B * pitch32;
+    }
+    for (; s < s_end; ++s) {   // remaining steps one at a time (window slot 0, loaded by the lower half)
+        const Anchor an = make_anchor(fma((double)s, k2d, based));
+        const T t = (T)an.t;
+        const int e = an.i + kPadL;
+        const int w = min(__builtin_amdgcn_readlane(e, lmin) & ~(EQ - 1), wmax);
+        Bytes16 v;
+        const bool ld = loader && half == 0;
+        if (ld) v = *reinterpret_cast<const Bytes16*>(row + ((unsigned)(w * (int)sizeof(T)) + lane_off));
+        wave_lds_sync();
+        if (ld) *reinterpret_cast<Bytes16*>(st) = v;
+        wave_lds_sync();
+        const T* tp = (slots - w) + e;
+        acc += fma(t, tp[1] - tp[0], tp[0]);
+        row += pitch32;
     }
     return acc;
 }
@@ -1204,9 +1219,7 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     T acc;
     if (VARIANT == 1) {
         __shared__ __attribute__((aligned(16))) T stage[kWaves * kStageRows * kRowWin];
-        __shared__ int rbase[kWaves * kStageRows];
-        acc = ray_sum_lds(c, img, imgT, A, a, axis, d0, d, lane, wave, stage + wave * kStageRows * kRowWin,
-                          rbase + wave * kStageRows);
+        acc = ray_sum_lds(c, img, imgT, A, a, axis, d0, d, lane, wave, kWaves, stage + wave * kStageRows * kRowWin);
     } else {
         acc = ray_sum_direct(c, img, imgT, A, a, axis, d0, d, wave, kWaves);
     }

@@ -1,4 +1,5 @@
-"""Address bounds and grid decode of the direct projector, checked on the CPU.
+"""Address bounds and grid decode of the direct and LDS-window projectors,
+checked on the CPU.
 
 The direct kernel (projector 2) reads image rows without clamping the tap
 column: it relies on the kPadL = 96 zero columns on each side of a padded row
@@ -8,7 +9,11 @@ kernel's address arithmetic (the block step range with its single-precision
 divisions on coefficients rounded to float; each tap column as the floor of a
 double-precision anchor plus the floor of a single-precision offset) for the
 workload geometries and asserts that every read stays inside the padded row:
-columns -96 .. N+95.  Fused multiply-adds are replayed
+columns -96 .. N+95.  The LDS-window kernel (projector 1) walks the same steps
+with the same taps and copies, per step, the 96-element window that starts at
+the block's smallest tap rounded down to 16 bytes: its first or last lane's
+tap must be the smallest, the window must lie inside the padded row and hold
+both taps of every lane.  Fused multiply-adds are replayed
 exactly: the product of a small integer and a float is exact in double, so
 one rounding of the double sum is the fused result.
 """
@@ -18,6 +23,7 @@ import numpy as np
 import pytest
 
 PAD = 96
+WIN = 96            # elements of the LDS window of projector 1
 F32 = np.float32
 
 
@@ -101,7 +107,7 @@ GEOMS = [(16, 7, 23), (64, 90, 92), (128, 179, 130), (128, 180, 185), (256, 358,
 
 
 @pytest.mark.parametrize("geom", GEOMS, ids=[f"{g[0]}x{g[1]}x{g[2]}" for g in GEOMS])
-def test_direct_projector_reads_stay_in_the_padded_rows(geom):
+def test_projector_reads_stay_in_the_padded_rows_and_windows(geom):
     n, na, ns = geom
     nb = (ns + 63) // 64
     angles = range(na) if n <= 256 else sorted(set(range(0, na, 5)) | {179, 180, 537, 538, na - 1})
@@ -123,6 +129,16 @@ def test_direct_projector_reads_stay_in_the_padded_rows(geom):
                 c = _tap_columns(base64, k2d, k2, sb, se, 8)
                 lo, hi = min(lo, c.min()), max(hi, c.max() + 1)
                 assert c.min() >= -PAD and c.max() + 1 <= n + PAD - 1, (a, rb, part, c.min(), c.max())
+                # projector 1: the window of each step (FP32: 4 elements per 16 bytes, FP64: 2)
+                e = (c + PAD).astype(np.int64)
+                lmin = 0 if k1 > 0 else 63
+                assert np.array_equal(e[lmin], e.min(axis=0)), (a, rb, part)
+                P = n + 2 * PAD
+                for eq in (4, 2):
+                    w = np.minimum(e[lmin] & ~(eq - 1), P - WIN)
+                    assert w.min() >= 0 and w.max() + WIN <= P
+                    off = e - w
+                    assert off.min() >= 0 and off.max() + 1 <= WIN - 1, (a, rb, part, off.min(), off.max())
     # the margins are used, but with room to spare
     assert lo >= -PAD and hi <= n + PAD - 1
 
