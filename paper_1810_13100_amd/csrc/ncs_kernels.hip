@@ -829,27 +829,30 @@ __device__ inline double project_epilogue(const DevCtx<T>& c, int a, int d, T q,
 }
 
 // Steps [s_begin, s_end) of part `part` of `nparts` of the steps where some ray
-// of the 64-ray block starting at d0 has its coordinate in [-2, N + 1].  All
-// rays of an angle share the slope k2 in s, so the block's coordinates at step
-// s span [blo, bhi] + s k2; one step of margin on each side keeps the range
-// conservative under rounding.
+// of the 64-ray block starting at d0 has its coordinate in [-2, N + 1]: that
+// range, split evenly, so the waves of a workgroup (one per SIMD) get equal
+// shares whatever the angle and block.  All rays of an angle share the slope
+// k2 in s, so the block's coordinates at step s span [blo, bhi] + s k2; one
+// step of margin on each side keeps the range conservative under rounding.
 template <class T>
 __device__ inline void block_step_range(const AngleT<T>& A, int N, int d0, int part, int nparts, int& s_begin,
                                         int& s_end) {
     const T bA = fma((T)d0, A.k1, A.k0), bB = fma((T)(d0 + kRays - 1), A.k1, A.k0);
     const T blo = fmin(bA, bB), bhi = fmax(bA, bB);
     const T lo_x = T(-2), hi_x = T(N + 1);
-    s_begin = (part * N) / nparts;
-    s_end = ((part + 1) * N) / nparts;
+    int sb = 0, se = N;
     if (A.k2 > T(0)) {
-        s_begin = max(s_begin, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
-        s_end = min(s_end, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
+        sb = max(sb, sat_int(floor((lo_x - bhi) / A.k2)) - 1);
+        se = min(se, sat_int(ceil((hi_x - blo) / A.k2)) + 2);
     } else if (A.k2 < T(0)) {
-        s_begin = max(s_begin, sat_int(floor((hi_x - blo) / A.k2)) - 1);
-        s_end = min(s_end, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
+        sb = max(sb, sat_int(floor((hi_x - blo) / A.k2)) - 1);
+        se = min(se, sat_int(ceil((lo_x - bhi) / A.k2)) + 2);
     } else if (bhi < lo_x || blo > hi_x) {
-        s_end = s_begin;
+        se = sb;
     }
+    const int len = max(se - sb, 0);
+    s_begin = sb + (part * len) / nparts;
+    s_end = sb + ((part + 1) * len) / nparts;
 }
 
 // Ray sum of the lane's ray by the direct method: one lane per ray, the waves

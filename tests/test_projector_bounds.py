@@ -70,10 +70,11 @@ def _sat(v):
 
 
 def _block_range(k1, k2, k0, n, d0, part, nparts):
+    """The block's culled step range, split evenly into nparts."""
     bA, bB = _fma32(d0, k1, k0), _fma32(d0 + 63, k1, k0)
     blo, bhi = min(bA, bB), max(bA, bB)
     lo_x, hi_x = F32(-2), F32(n + 1)
-    sb, se = (part * n) // nparts, ((part + 1) * n) // nparts
+    sb, se = 0, n
     if k2 > 0:
         sb = max(sb, _sat(np.floor(F32(lo_x - bhi) / k2)) - 1)
         se = min(se, _sat(np.ceil(F32(hi_x - blo) / k2)) + 2)
@@ -82,7 +83,8 @@ def _block_range(k1, k2, k0, n, d0, part, nparts):
         se = min(se, _sat(np.ceil(F32(lo_x - bhi) / k2)) + 2)
     elif bhi < lo_x or blo > hi_x:
         se = sb
-    return sb, se
+    ln = max(se - sb, 0)
+    return sb + (part * ln) // nparts, sb + ((part + 1) * ln) // nparts
 
 
 def _tap_columns(base64, k2d, k2, sb, se, unroll):
