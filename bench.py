@@ -69,9 +69,11 @@ def make_data(ncs, torch, dev):
     return geom, b
 
 
-def measured_traffic(kernel: str, traffic_file: str = TRAFFIC_FILE, source: str = KERNEL_SOURCE):
+def measured_traffic(kernel: str, traffic_file: str = TRAFFIC_FILE, source: str = KERNEL_SOURCE,
+                     variants: dict | None = None):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the kernel source changed since the counters were taken."""
+    None when the kernel source changed since the counters were taken or the
+    counters were taken with other kernel variants than `variants`."""
     import hashlib
     try:
         with open(traffic_file) as f:
@@ -81,6 +83,8 @@ def measured_traffic(kernel: str, traffic_file: str = TRAFFIC_FILE, source: str 
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != digest:
+        return None
+    if variants and any(rec.get(k) != v for k, v in variants.items()):
         return None
     entry = rec.get("kernels", {}).get(kernel)
     return None if entry is None else entry.get("bytes_per_launch")
@@ -744,7 +748,8 @@ def main() -> int:
         achieved = flops / (dom_ms * 1e-3) / 1e12
         roof = {"kernel": dominant, "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                "traffic": measured_traffic(dominant),
+                "traffic": measured_traffic(dominant, variants={"projector": info["projector"],
+                                                                "backprojector": info["backprojector"]}),
                 "work_per_launch": f"2 x nnz(E) = {flops:.4g} flop", "ms_per_launch": dom_ms}
     else:
         roof = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
