@@ -511,6 +511,8 @@ void ensure_graphs(ncs_handle* h) {
             ok = le == hipSuccess && ee == hipSuccess && graph &&
                  hipGraphInstantiate(&h->graphs[l], graph, nullptr, nullptr, 0) == hipSuccess;
             if (graph) (void)hipGraphDestroy(graph);
+            // move the executable graph to the device now rather than at its first launch
+            if (ok) ok = hipGraphUpload(h->graphs[l], h->stream) == hipSuccess;
         }
         if (!ok) {
             (void)hipGetLastError();
@@ -1713,6 +1715,7 @@ hipError_t batch_launch(ncs_batch* B, int k) {
                 ok = le == hipSuccess && ee == hipSuccess && graph &&
                      hipGraphInstantiate(&B->graph[j], graph, nullptr, nullptr, 0) == hipSuccess;
                 if (graph) (void)hipGraphDestroy(graph);
+                if (ok) ok = hipGraphUpload(B->graph[j], B->stream) == hipSuccess;
             }
             if (!ok) {
                 (void)hipGetLastError();
