@@ -1834,6 +1834,10 @@ __global__ __launch_bounds__(256) void k_admm_update(const DevCtx<T>* __restrict
 
 __global__ void k_control(Control* ctl, int op, int iter_value, double f_target) {
     if (threadIdx.x != 0) return;
+    if (op == 3 || op == 4) {   // raise / clear the stop flag alone (dry replays of captured graphs)
+        ctl->stop = op == 3 ? 1 : 0;
+        return;
+    }
     if (op == 0) ctl->iter = 0;
     if (op == 2) ctl->iter = iter_value;
     ctl->stop = 0;
