@@ -1015,13 +1015,12 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
     const char* row = reinterpret_cast<const char*>(src + (size_t)max(s_begin, 0) * P);
     T acc = T(0);
     int s = s_begin;
-    for (; s + B <= s_end; s += B) {
-        const Anchor an = make_anchor(fma((double)s, k2d, based));
+    // coordinates of the B steps from sg: fractions, tap element indices, window starts
+    auto coords = [&](int sg, T(&f)[B], int(&e)[B], int(&w)[B]) {
+        const Anchor an = make_anchor(fma((double)sg, k2d, based));
         const T t0 = (T)an.t;
         const int ei = an.i + kPadL;
         const int eimin = __builtin_amdgcn_readlane(ei, lmin);
-        int e[B], w[B];
-        T f[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             const T t = j == 0 ? t0 : fma((T)j, k2, t0);
@@ -1030,17 +1029,22 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
             e[j] = ei + fl;
             w[j] = min((eimin + __builtin_amdgcn_readlane(fl, lmin)) & ~(EQ - 1), wmax);
         }
-        Bytes16 v[B / WPI];
-        if (loader) {   // all loads of the group in flight together (scalar base, 32-bit lane offset)
+    };
+    // the group's window loads, all in flight together (scalar base, 32-bit lane offset)
+    auto issue = [&](const char* rg, const int(&w)[B], Bytes16(&v)[B / WPI]) {
+        if (loader) {
 #pragma unroll
             for (int p = 0; p < B / WPI; ++p) {
                 // the lane's window start, w[2p] or w[2p + 1] (bytes), without an indexed access
                 const int wb0 = w[WPI * p] * (int)sizeof(T);
                 const int dwb = WPI == 2 ? (w[2 * p + 1] - w[2 * p]) * (int)sizeof(T) : 0;
                 const unsigned off = lane_off + (unsigned)wb0 + (unsigned)(dwb & hmask);
-                v[p] = *reinterpret_cast<const Bytes16*>(row + (unsigned)(WPI * p * pitch32) + off);
+                v[p] = *reinterpret_cast<const Bytes16*>(rg + (unsigned)(WPI * p * pitch32) + off);
             }
         }
+    };
+    // windows into LDS, then each lane's two taps per step
+    auto consume = [&](const T(&f)[B], const int(&e)[B], const int(&w)[B], const Bytes16(&v)[B / WPI]) {
         wave_lds_sync();   // the previous group's taps have been read
         if (loader) {
 #pragma unroll
@@ -1052,7 +1056,18 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
             const T* tp = (slots + (j * kRowWin - w[j])) + e[j];
             acc += fma(f[j], tp[1] - tp[0], tp[0]);
         }
-        row += (size_t)B * pitch32;
+    };
+    const size_t gstep = (size_t)B * pitch32;
+    const int ng = (s_end - s) / B;   // whole groups (s_end >= s)
+    for (int gi = 0; gi < ng; ++gi) {
+        T f[B];
+        int e[B], w[B];
+        Bytes16 v[B / WPI];
+        coords(s, f, e, w);
+        issue(row, w, v);
+        consume(f, e, w, v);
+        s += B;
+        row += gstep;
     }
     for (; s < s_end; ++s) {   // remaining steps one at a time (window slot 0, loaded by the lower half)
         const Anchor an = make_anchor(fma((double)s, k2d, based));
