@@ -649,16 +649,19 @@ constexpr int kBpWin = 26;
 template <class T>
 constexpr int bp_chunk() { return sizeof(T) == 4 ? 384 : 192; }
 
-// woffb: LDS byte offset, relative to win, of detector bin 0 in this angle's window
+// woffb: LDS byte offset, relative to win, of detector bin 0 in this angle's
+// window; the window holds kappa u (the angle's weight scale folded in at
+// staging), so each tap is the floor as an integer, the fraction, the two
+// clamped weights and two multiply-adds.
 template <class T>
 __device__ inline void bp_window_tap(T& acc, T tc, const T* __restrict__ win, int woffb, const AngleT<T>& A) {
-    const T fl = floor(tc);
-    const T f = tc - fl;
-    const T* wp = reinterpret_cast<const T*>(reinterpret_cast<const char*>(win) + (int)fl * (int)sizeof(T) + woffb);
+    const int fl = floor_int(tc);
+    const T f = frac_part(tc);
+    const T* wp = reinterpret_cast<const T*>(reinterpret_cast<const char*>(win) + fl * (int)sizeof(T) + woffb);
     const T y0 = wp[0], y1 = wp[1];
     const T w0 = clamp01(fma(-A.kappa, f, T(1)));
     const T w1 = clamp01(fma(A.kappa, f, A.omk));
-    acc = fma(A.kappa, fma(w1, y1, w0 * y0), acc);
+    acc = fma(w1, y1, fma(w0, y0, acc));
 }
 
 template <class T, bool ITER>
@@ -681,6 +684,7 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
     __shared__ T win[CH * kBpWin];
     __shared__ int wbase[CH];
     __shared__ T tref[CH];
+    __shared__ T kap[CH];
     __shared__ T red[kBpQuadWaves * kBpTile * kBpTile];
     const T* ysrc = ITER ? c.u : ysrc_plain;
     const int N = c.N;
@@ -722,6 +726,7 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
             const int wb = (int)floor(torg + span * (fmin(q1, 0.0) + fmin(q2, 0.0))) - 1;
             wbase[k] = wb;
             tref[k] = (T)(torg - (double)wb);
+            kap[k] = ang[a0 + k].kappa;
         }
         __syncthreads();
         {
@@ -739,7 +744,7 @@ __global__ __launch_bounds__(kBpQuadWaves * 64) void k_backproject_lds(const Dev
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int e = threadIdx.x + r * NT;
-                if (e < nch * kBpWin) win[e] = vals[r];
+                if (e < nch * kBpWin) win[e] = kap[e / kBpWin] * vals[r];
             }
         }
         __syncthreads();
