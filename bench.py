@@ -757,6 +757,18 @@ def main() -> int:
     ms_per_step = ms_total / args.steps
     its = 1000.0 / ms_per_step
 
+    # steady state as a distribution: 5 more runs of 2,000 replayed iterations
+    # (HIP events on the solver's stream), reported beside the timed steps
+    m1 = []
+    for _ in range(5):
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        s.iterate(2000)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        m1.append(2000 * 1000.0 / f0.elapsed_time(f1))
+    m1_out = {"iterations": 2000, "it_per_s": m1, "median": float(np.median(m1))}
+
     calibration_copy(torch, dev)
     dominant = max(phases, key=phases.get)
     flops = 2.0 * info["nnz"]          # one multiply-add per nonzero of E
@@ -785,7 +797,7 @@ def main() -> int:
                    "nnz_E": info["nnz"]},
         "kernels": {"projector": info["projector"], "backprojector": info["backprojector"],
                     "chosen_by": "setup timing" if args.projector == 0 and args.backprojector == 0 else "flags"},
-        "wall_s_timed": wall, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "pet_time_to_gap": pet, "fan_time_to_gap": fan,
+        "wall_s_timed": wall, "steady_state_5x2000": m1_out, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "pet_time_to_gap": pet, "fan_time_to_gap": fan,
         "batch": batch, "cone": cone_out,
         "cpu_baseline": cpu, "host": platform.node(),
     }
