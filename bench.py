@@ -440,7 +440,7 @@ def cone_legs(ncs, torch, dev, steps: int, fstar_iters: int) -> dict:
         "workload": "256^2 x 64 cone beam, 72 views x 64 rows x 368 columns, source radius 512, "
                     "anisotropic 3D TV lambda 0.005, random-ellipsoid volume seed 0, 1% Gaussian noise",
         "dtype": "f32", "iterations": steps, "seconds": dt, "it_per_s": steps / dt, "ms_per_iteration": 1e3 * dt / steps,
-        "setup_s": setup_s, "nnz_E": info["nnz"], "phases_ms": phases, "roofline": roof,
+        "setup_s": setup_s, "nnz_E": info["nnz"], "phases_ms": phases, "roofline": roof, "roofline_per_kernel": per_kernel,
         "bin_window": info["bin_window"]}
     progress(f"cone beam: {steps / dt:.1f} it/s, phases {phases}")
     if fstar_iters <= 0:
@@ -784,6 +784,24 @@ def main() -> int:
         roof = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
                 "frac": None, "traffic": None, "ms_per_launch": dom_ms}
 
+    # every kernel of the iteration against its own bound: the projector pair
+    # against the FP32 vector peak (2 flops per nonzero of E), the DFT passes
+    # against HBM with their algorithmic bytes (the arrays they must read and
+    # write once; FP32 values, complex half spectrum of (N/2 + 1) N entries)
+    n2 = N_SIDE * N_SIDE
+    half = (N_SIDE // 2 + 1) * N_SIDE
+    fft_bytes = {"fft_rows": 4 * n2 + 8 * half, "fft_cols_multiplier": 16 * half + 4 * half,
+                 "fft_rows_inv_update": 8 * half + 4 * n2 + 3 * 4 * n2}
+    per_kernel = {}
+    for k, ms in phases.items():
+        if k in ("project_dataprox_tv", "backproject"):
+            a = flops / (ms * 1e-3) / 1e12
+            per_kernel[k] = {"bound": "alu", "achieved": a, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": a / FP32_VECTOR_PEAK_TFLOPS, "ms_per_launch": ms}
+        elif k in fft_bytes:
+            a = fft_bytes[k] / (ms * 1e-3) / 1e9
+            per_kernel[k] = {"bound": "hbm", "achieved": a, "peak": 8000.0, "unit": "GB/s", "frac": a / 8000.0,
+                             "algorithmic_bytes": fft_bytes[k], "ms_per_launch": ms}
     cpu = cpu_baseline(args.cpu_iters) if args.cpu_iters > 0 else None
     s.close()
     out = {
@@ -797,7 +815,7 @@ def main() -> int:
                    "nnz_E": info["nnz"]},
         "kernels": {"projector": info["projector"], "backprojector": info["backprojector"],
                     "chosen_by": "setup timing" if args.projector == 0 and args.backprojector == 0 else "flags"},
-        "wall_s_timed": wall, "steady_state_5x2000": m1_out, "phases_ms": phases, "roofline": roof, "time_to_gap": gap, "pet_time_to_gap": pet, "fan_time_to_gap": fan,
+        "wall_s_timed": wall, "steady_state_5x2000": m1_out, "phases_ms": phases, "roofline": roof, "roofline_per_kernel": per_kernel, "time_to_gap": gap, "pet_time_to_gap": pet, "fan_time_to_gap": fan,
         "batch": batch, "cone": cone_out,
         "cpu_baseline": cpu, "host": platform.node(),
     }
