@@ -440,7 +440,7 @@ def cone_legs(ncs, torch, dev, steps: int, fstar_iters: int) -> dict:
         "workload": "256^2 x 64 cone beam, 72 views x 64 rows x 368 columns, source radius 512, "
                     "anisotropic 3D TV lambda 0.005, random-ellipsoid volume seed 0, 1% Gaussian noise",
         "dtype": "f32", "iterations": steps, "seconds": dt, "it_per_s": steps / dt, "ms_per_iteration": 1e3 * dt / steps,
-        "setup_s": setup_s, "nnz_E": info["nnz"], "phases_ms": phases, "roofline": roof, "roofline_per_kernel": per_kernel,
+        "setup_s": setup_s, "nnz_E": info["nnz"], "phases_ms": phases, "roofline": roof,
         "bin_window": info["bin_window"]}
     progress(f"cone beam: {steps / dt:.1f} it/s, phases {phases}")
     if fstar_iters <= 0:
@@ -608,6 +608,43 @@ def batch_legs(ncs, torch, dev, iters: int, gap_ref_iters: int) -> dict:
     return out
 
 
+def paper_context(ncs, torch, dev, iters: int = 500) -> dict:
+    """The paper's parallel-beam experiment shape, 512^2 with 60 angles x 729
+    bins and lambda = 1 (its data are not available: a seeded random-ellipse
+    phantom with 1% noise stands in), timed like the headline: iterations/s of
+    replayed graphs with the objective every iteration.  Context beside the
+    paper's Table 1 (1000 iterations at 512^2 in 5.32 s on its GPU, angles not
+    stated there)."""
+    import ncs_inputs
+    n, na, nb = 512, 60, 729
+    g = ncs.Geometry(n, na, nb)
+    alpha = 1e-4
+    p = ncs.Params(alpha, BETA_RATIO * alpha, GAMMA_FRAC * alpha * na * n / math.pi, 1.0)
+    op = ncs.Solver(g, p)
+    x = torch.tensor(ncs_inputs.phantom(n, 0).ravel(), dtype=torch.float32, device=dev)
+    clean = op.forward(x)
+    eps = torch.tensor(ncs_inputs.gaussian_noise(0, g.m), dtype=torch.float32, device=dev)
+    b = (clean + 0.01 * float(clean.max()) * eps).contiguous()
+    op.close()
+    s = ncs.Solver(g, p, b=b)
+    s.set_init()
+    s.iterate(100)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.iterate(iters)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    info = s.info()
+    s.close()
+    return {"workload": "512^2 parallel-beam CT, 60 angles x 729 bins, lambda 1, random-ellipse phantom seed 0, "
+                        "1% Gaussian noise", "iterations": iters, "it_per_s": 1000.0 / ms, "ms_per_iteration": ms,
+            "kernels": {"projector": info["projector"], "backprojector": info["backprojector"]},
+            "paper_table1_512": {"it_per_s": 1000 / 5.32, "hardware": "NVIDIA TITAN Xp, MATLAB; angles not stated"}}
+
+
 class _BlockRows:
     """y = A @ x for a CSR matrix split into row blocks, one block per pool
     thread (SciPy's CSR product releases the GIL, so the blocks run in parallel)."""
@@ -732,6 +769,7 @@ def main() -> int:
     cone_out = None
     if args.cone_steps > 0:
         cone_out = cone_legs(ncs, torch, dev, args.cone_steps, 0 if args.no_gap else args.cone_fstar_iters)
+    context = None if args.no_gap else paper_context(ncs, torch, dev)
 
     # per-kernel timing: HIP events around 50 back-to-back launches of each
     # phase on the solver's stream; it moves the state, so the timed run
@@ -816,7 +854,7 @@ def main() -> int:
         "kernels": {"projector": info["projector"], "backprojector": info["backprojector"],
                     "chosen_by": "setup timing" if args.projector == 0 and args.backprojector == 0 else "flags"},
         "wall_s_timed": wall, "steady_state_5x2000": m1_out, "phases_ms": phases, "roofline": roof, "roofline_per_kernel": per_kernel, "time_to_gap": gap, "pet_time_to_gap": pet, "fan_time_to_gap": fan,
-        "batch": batch, "cone": cone_out,
+        "batch": batch, "cone": cone_out, "paper_context_512": context,
         "cpu_baseline": cpu, "host": platform.node(),
     }
     print(json.dumps(out), flush=True)
