@@ -95,7 +95,7 @@ struct DevCtx {
     const NCS_G double* ang64;       // per angle k1, k2, k0, q1, q2, q0 in double (both precisions)
     const NCS_G int32_t* axis;
     NCS_G T* x;        // N*N current image
-    NCS_G T* xbar;     // N*P padded extrapolated image 2x+ - x (two zero columns each side)
+    NCS_G T* xbar;     // N*P padded extrapolated image 2x+ - x (kPadL zero columns each side)
     NCS_G T* xbarT;    // N*P padded transpose of xbar (row c holds column c)
     NCS_G T* xsc;      // N*P padded scratch image (plain projections)
     NCS_G T* xscT;     // N*P padded scratch transpose

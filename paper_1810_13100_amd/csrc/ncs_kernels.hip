@@ -1095,7 +1095,7 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
 // Fan beam: the lane's ray summed over this wave's quarter of the steps.  Each
 // ray steps along its own axis (from the table), so lanes of one wave may read
 // the row-major or the transposed copy; each lane keeps to the steps where its
-// coordinate lies in [-2, N+1] (two zero columns each side absorb the taps of
+// coordinate lies in [-2, N+1] (the zero columns each side absorb the taps of
 // the steps next to those).  The arithmetic of a tap is the direct method's.
 template <class T>
 __device__ inline T ray_sum_fan(const DevCtx<T>& c, const T* __restrict__ img, const T* __restrict__ imgT,
