@@ -38,7 +38,7 @@ def main(argv=None) -> int:
     ap.add_argument("--angles", type=int, default=360)
     ap.add_argument("--bins", type=int, default=367)
     ap.add_argument("--lam", type=float, default=0.005)
-    ap.add_argument("--alpha", type=float, default=3e-4)
+    ap.add_argument("--alpha", type=float, default=2.4e-3)
     ap.add_argument("--pairs", type=int, default=2048)
     ap.add_argument("--val", type=int, default=64)
     ap.add_argument("--k0", type=int, default=300)
