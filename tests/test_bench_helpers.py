@@ -1,0 +1,49 @@
+"""Host-side helpers of bench.py, on the CPU: the counted-traffic lookup is
+reported only for the kernel source and variants it was taken with, and the
+threaded row-block product of the CPU baseline equals the plain CSR product."""
+import hashlib
+import json
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import scipy.sparse as sp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _record(tmp_path, source_text, variants):
+    src = tmp_path / "kernels.hip"
+    src.write_text(source_text)
+    rec = {"kernel_source_sha256": hashlib.sha256(source_text.encode()).hexdigest(),
+           "kernels": {"project_dataprox_tv": {"bytes_per_launch": 123.0}}, **variants}
+    tf = tmp_path / "traffic.json"
+    tf.write_text(json.dumps(rec))
+    return str(tf), str(src)
+
+
+def test_traffic_needs_the_same_source_and_variants(tmp_path):
+    tf, src = _record(tmp_path, "kernel text", {"projector": 1, "backprojector": 1})
+    v = {"projector": 1, "backprojector": 1}
+    assert bench.measured_traffic("project_dataprox_tv", tf, src, v) == 123.0
+    assert bench.measured_traffic("backproject", tf, src, v) is None               # kernel not counted
+    assert bench.measured_traffic("project_dataprox_tv", tf, src, {"projector": 2, "backprojector": 1}) is None
+    with open(src, "w") as f:
+        f.write("kernel text changed")
+    assert bench.measured_traffic("project_dataprox_tv", tf, src, v) is None      # source changed
+    assert bench.measured_traffic("project_dataprox_tv", str(tmp_path / "missing.json"), src, v) is None
+
+
+def test_threaded_row_blocks_equal_the_csr_product():
+    rng = np.random.default_rng(0)
+    a = sp.random(1000, 700, density=0.02, random_state=1, format="csr")
+    x = rng.standard_normal(700)
+    with ThreadPoolExecutor(4) as pool:
+        for parts in (1, 3, 4, 7):
+            b = bench._BlockRows(a, pool, parts)
+            np.testing.assert_array_equal(b @ x, a @ x)

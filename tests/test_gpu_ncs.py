@@ -99,7 +99,7 @@ def test_pet_128(prec):
 def test_ct_256_full_size(prec):
     prob = ct_problem("c2")
     log(f"NCS parity 256^2 CT (360 x 367), 100 iterations, {prec}")
-    check_trajectory(prob, ct_params(256, 360, alpha=3e-4), 100, prec)
+    check_trajectory(prob, ct_params(256, 360, alpha=2.4e-3), 100, prec)
 
 
 def test_checkpoint_resume_is_bitwise():
