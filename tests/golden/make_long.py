@@ -6,7 +6,7 @@ problem run by the oracle's NCS (the CT form of Section 4.1 or the PET form of
 Section 4.2) from x = u = v = 0:
 
 * ``ct256_s<seed>``: 256 x 256 parallel-beam CT, 360 angles x 367 bins,
-  anisotropic TV lambda = 0.005, alpha = 3e-4, beta = 3 alpha,
+  anisotropic TV lambda = 0.005, alpha = 2.4e-3, beta = 3 alpha,
   gamma = 0.3 alpha C_R.  The image and duals are stored after ``k_state``
   iterations (the iteration at which the single-precision run of that slice
   first reaches the 1e-4 relative objective gap) and the objective f(x^k) for
@@ -40,15 +40,15 @@ from oracle import operators, problems, projector, solvers  # noqa: E402
 
 # case -> (kind, seed, k_state, k_total)
 CASES = {
-    "ct256_s0": ("ct", 0, 3107, 12000),
-    "ct256_s1": ("ct", 1, 3251, 12000),
+    "ct256_s0": ("ct", 0, 2258, 12000),
+    "ct256_s1": ("ct", 1, 2492, 12000),
     "pet128_s0": ("pet", 0, 19496, 19496),
 }
 
 
 def case_problem(kind: str, seed: int):
     if kind == "ct":
-        n, na, ns, lam, alpha = 256, 360, 367, 0.005, 3e-4
+        n, na, ns, lam, alpha = 256, 360, 367, 0.005, 2.4e-3
         gamma = 0.3 * alpha * operators.default_c_r(n, na)
         prob = problems.ct_problem(n, na, ns, seed, lam, E=projector.joseph_matrix(n, na, ns))
     else:

@@ -2,13 +2,13 @@
 FP64 oracle trajectories (tests/golden/make_long.py writes them, calling only
 the oracle).
 
-* 256^2 CT (360 x 367, lambda 0.005; Section 4.1), seeds 0 and 1: the FP32
-  library from x = 0 for as many iterations as its run of that slice takes to
-  the 1e-4 relative objective gap (3107 and 3251), every objective f(x^k)
-  within 1e-5 relative and x^K within rel-L2 1e-4; and the FP64 library over
-  all 12000 stored iterations, every objective within 1e-10.  The smallest of
-  those objectives is the f* of the relative gap, so the FP64 run that the
-  benchmark takes f* from is checked against the oracle over that length.
+* 256^2 CT (360 x 367, lambda 0.005, alpha 2.4e-3; Section 4.1), seeds 0 and
+  1: the FP32 library from x = 0 for as many iterations as its run of that
+  slice takes to the 1e-4 relative objective gap (2258 and 2492), every
+  objective f(x^k) within 1e-5 relative and x^K within rel-L2 1e-4; and the
+  FP64 library over all 12000 stored iterations, every objective within
+  1e-10, and its smallest objective within 1e-10 of the oracle's: the FP64
+  library is what the benchmark's f* runs use.
 * 128^2 PET (180 x 185, isotropic TV lambda 0.02; Section 4.2), seed 0: the
   FP32 library for 19496 iterations (the length of its run to the gap) at the
   same gates.
