@@ -13,8 +13,8 @@ Section 4.2) from x = u = v = 0:
   every k up to ``k_total``, whose minimum is the reference value f* of the
   relative gap.
 * ``pet128_s<seed>``: 128 x 128 PET, 180 x 185, 1e6 expected counts with a 5%
-  uniform background, isotropic TV lambda = 0.02, alpha = 1, beta = 3,
-  gamma = C_R, to the same kind of ``k_state``.
+  uniform background, isotropic TV lambda = 0.02, alpha = 0.05, beta = 3 alpha,
+  gamma = 0.3 alpha C_R, to the same kind of ``k_state``.
 
 Output: ``<case>.npz`` next to this script with arrays ``x``, ``u``, ``v`` (at
 ``k_state``), ``obj`` (f(x^1) ... f(x^k_total)) and scalars ``k_state``,
@@ -42,7 +42,7 @@ from oracle import operators, problems, projector, solvers  # noqa: E402
 CASES = {
     "ct256_s0": ("ct", 0, 2258, 12000),
     "ct256_s1": ("ct", 1, 2492, 12000),
-    "pet128_s0": ("pet", 0, 19496, 19496),
+    "pet128_s0": ("pet", 0, 3957, 3957),
 }
 
 
@@ -52,8 +52,8 @@ def case_problem(kind: str, seed: int):
         gamma = 0.3 * alpha * operators.default_c_r(n, na)
         prob = problems.ct_problem(n, na, ns, seed, lam, E=projector.joseph_matrix(n, na, ns))
     else:
-        n, na, ns, lam, alpha = 128, 180, 185, 0.02, 1.0
-        gamma = 1.0 * alpha * operators.default_c_r(n, na)
+        n, na, ns, lam, alpha = 128, 180, 185, 0.02, 0.05
+        gamma = 0.3 * alpha * operators.default_c_r(n, na)
         prob = problems.pet_problem(n, na, ns, seed, lam, tv="iso", E=projector.joseph_matrix(n, na, ns))
     return prob, problems.Params(alpha, 3.0 * alpha, gamma)
 

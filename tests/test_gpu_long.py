@@ -9,9 +9,9 @@ the oracle).
   FP64 library over all 12000 stored iterations, every objective within
   1e-10, and its smallest objective within 1e-10 of the oracle's: the FP64
   library is what the benchmark's f* runs use.
-* 128^2 PET (180 x 185, isotropic TV lambda 0.02; Section 4.2), seed 0: the
-  FP32 library for 19496 iterations (the length of its run to the gap) at the
-  same gates.
+* 128^2 PET (180 x 185, isotropic TV lambda 0.02, alpha 0.05; Section 4.2),
+  seed 0: the FP32 library for 3957 iterations (the length of its run to the
+  gap, against f* from a converged double-precision run) at the same gates.
 """
 import os
 
