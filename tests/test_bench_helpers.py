@@ -1,6 +1,7 @@
 """Host-side helpers of bench.py, on the CPU: the counted-traffic lookup is
 reported only for the kernel source and variants it was taken with, and the
-threaded row-block product of the CPU baseline equals the plain CSR product."""
+threaded row-block product of the CPU baseline equals the plain CSR product,
+and the constrained time-to-gap stops on the objective of the projected iterate."""
 import hashlib
 import json
 import os
@@ -47,3 +48,38 @@ def test_threaded_row_blocks_equal_the_csr_product():
         for parts in (1, 3, 4, 7):
             b = bench._BlockRows(a, pool, parts)
             np.testing.assert_array_equal(b @ x, a @ x)
+
+
+class _FakeSolver:
+    """A stand-in for a constrained solve: x^k approaches the constrained
+    minimiser (1, 0) from the infeasible side, x^k = (1, -0.5^k), and the
+    objective is f(x) = (x0 - 1)^2 + x1 (without the indicator of x >= 0), so
+    f(x^k) lies below the constrained minimum f* = 0 at every k."""
+    def __init__(self):
+        self.k = 0
+
+    def iterate(self, k, record=False):
+        self.k += k
+
+    def x(self):
+        import torch
+        return torch.tensor([1.0, -0.5 ** self.k], dtype=torch.float64)
+
+    def objective(self, x):
+        return float((x[0] - 1.0) ** 2 + x[1])
+
+
+def test_projected_stop_ignores_infeasible_iterates_below_f_star():
+    s = _FakeSolver()
+    assert s.objective(s.x()) < 0.0          # the raw objective is below f* already
+    it, f = bench.solve_projected(s, 0.0, 1000, chunk=4)
+    assert it == 4 and f == 0.0              # the projection (1, 0) attains f* = 0
+
+    class _Shifted(_FakeSolver):             # x^k = (1 + 2^-k, -0.5^k): projected f = 4^-k
+        def x(self):
+            import torch
+            return torch.tensor([1.0 + 0.5 ** self.k, -0.5 ** self.k], dtype=torch.float64)
+    s = _Shifted()
+    it, f = bench.solve_projected(s, 1e-4, 1000, chunk=2)
+    assert it == 8 and abs(f - 0.5 ** 16) < 1e-18    # first chunk end with 4^-k <= 1e-4
+    assert bench.solve_projected(_Shifted(), 1e-4, 6, chunk=2) == (None, None)
