@@ -1203,9 +1203,14 @@ __global__ __launch_bounds__(256) void k_project(const DevCtx<T>* __restrict__ c
     if (c.aorder) {   // XCDs 0-3: row-stepping blocks, XCDs 4-7: column-stepping blocks
         const int xcd = local & 7, k = (local >> 3) * 4 + (xcd & 3);
         const bool colsax = xcd >= 4;
-        if (k >= (colsax ? c.NA - c.nar : c.nar) * nb) return;   // an idle slot of the split grid
-        const int j = k / nb;
-        rb = k - j * nb;
+        const int nang = colsax ? c.NA - c.nar : c.nar;
+        if (k >= nang * nb) return;   // an idle slot of the split grid
+        // longest first: the central ray blocks of every angle are dispatched
+        // before the outer ones, whose rays cross less of the image (many
+        // none), so the workgroups left after the first resident round are
+        // the short ones.  Order of rb: c0, c0 + 1, c0 - 1, c0 + 2, ...
+        const int rbi = k / nang, j = k - rbi * nang;
+        rb = (nb - 1) / 2 + ((rbi & 1) ? (rbi + 1) >> 1 : -(rbi >> 1));
         a = c.aorder[(colsax ? c.nar : 0) + j];
     } else {
         a = local / nb;

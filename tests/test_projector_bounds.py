@@ -150,7 +150,8 @@ def test_axis_split_grid_covers_every_block_once(geom):
     """The single-slice projection grid sends row-stepping blocks to XCDs 0-3
     and column-stepping ones to XCDs 4-7 (workgroup b on XCD b mod 8): replay
     the kernel's decode of every workgroup of the grid the host launches and
-    check that each (angle, 64-ray block) pair is taken exactly once."""
+    check that each (angle, 64-ray block) pair is taken exactly once, and that
+    the ray blocks go out central ones first (longest first)."""
     n, na, ns = geom
     nb = (ns + 63) // 64
     rows = [a for a in range(na) if 4 * a <= na or 4 * a >= 3 * na]
@@ -158,13 +159,19 @@ def test_axis_split_grid_covers_every_block_once(geom):
     nar = len(rows)
     wgs = 8 * ((max(nar, na - nar) * nb + 3) // 4)   # project_wgs_split
     seen = np.zeros((na, nb), dtype=int)
+    last_dist = [0.0, 0.0]
     for local in range(wgs):
         xcd, k = local & 7, (local >> 3) * 4 + (local & 3)
         colsax = xcd >= 4
-        if k >= (na - nar if colsax else nar) * nb:
+        nang = na - nar if colsax else nar
+        if k >= nang * nb:
             continue
-        j, rb = divmod(k, nb)
+        rbi, j = divmod(k, nang)
+        rb = (nb - 1) // 2 + ((rbi + 1) // 2 if rbi % 2 else -(rbi // 2))
         a = order[(nar if colsax else 0) + j]
         assert (xcd >= 4) == (a not in set(rows))
         seen[a, rb] += 1
+        dist = abs(rb + 0.5 - nb / 2)    # the block's distance from the detector's centre
+        assert dist >= last_dist[colsax]
+        last_dist[colsax] = dist
     assert np.all(seen == 1)
