@@ -804,6 +804,7 @@ def main() -> int:
     ap.add_argument("--backprojector", type=int, default=0,
                     help="backprojector kernel of the headline solver (0: the setup timing picks it)")
     ap.add_argument("--cone-steps", type=int, default=50, help="timed cone-beam iterations (0: skip the cone legs)")
+    ap.add_argument("--steady-runs", type=int, default=5, help="more runs of 2,000 iterations after the timed steps")
     ap.add_argument("--cone-fstar-iters", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -863,14 +864,14 @@ def main() -> int:
     # steady state as a distribution: 5 more runs of 2,000 replayed iterations
     # (HIP events on the solver's stream), reported beside the timed steps
     m1 = []
-    for _ in range(5):
+    for _ in range(args.steady_runs):
         f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         f0.record(stream)
         s.iterate(2000)
         f1.record(stream)
         torch.cuda.synchronize()
         m1.append(2000 * 1000.0 / f0.elapsed_time(f1))
-    m1_out = {"iterations": 2000, "it_per_s": m1, "median": float(np.median(m1))}
+    m1_out = {"iterations": 2000, "it_per_s": m1, "median": float(np.median(m1))} if m1 else None
 
     calibration_copy(torch, dev)
     dominant = max(phases, key=phases.get)
