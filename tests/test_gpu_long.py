@@ -11,7 +11,10 @@ the oracle).
   library is what the benchmark's f* runs use.
 * 128^2 PET (180 x 185, isotropic TV lambda 0.02, alpha 0.05; Section 4.2),
   seed 0: the FP32 library for 3957 iterations (the length of its run to the
-  gap, against f* from a converged double-precision run) at the same gates.
+  gap, against f* from a converged double-precision run) at the same gates;
+  and the FP64 library over the 100,000 iterations at alpha 0.2 (without and
+  with x >= 0) that give the benchmark's PET f*, every stored objective within
+  1e-10.
 """
 import os
 
@@ -92,3 +95,38 @@ def test_pet128_fp32_to_the_gap_iteration():
     ef = float(np.max(np.abs(obj[fin] - ref[fin]) / np.abs(ref[fin])))
     log(f"  rel-L2 x {ex:.2e}, max rel f {ef:.2e}")
     assert ex <= 1e-4 and ef <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["pet128_s0_fstar", "pet128_s0_pos_fstar"])
+def test_pet128_fp64_f_star_run(case):
+    """The double-precision runs behind the PET time-to-gap's f*: 100,000
+    iterations at alpha 0.2 (without and with x >= 0) against the oracle's
+    (tests/golden/make_pet_fstar.py).  Every 1,000th objective and the last
+    1,000 within 1e-10 relative; the reference value the benchmark takes (the
+    smallest finite objective without constraints, the last one with x >= 0)
+    within 1e-10 of the oracle's; x^100000 within rel-L2 1e-8."""
+    fx = _fixture(case)
+    K, pos = int(fx["iters"]), int(fx["positivity"])
+    prob = pet_problem("c3", seed=0)
+    log(f"long parity {case}: FP64, {K} iterations, positivity {pos}")
+    p = ncs.Params(float(fx["alpha"]), float(fx["beta"]), float(fx["gamma"]), float(fx["lam"]),
+                   data_term=ncs.DATA_POISSON, tv_term=ncs.TV_ISO, positivity=pos)
+    s = ncs.Solver(ncs.Geometry(prob.n_side, prob.n_angles, prob.n_bins), p,
+                   b=torch.tensor(prob.b, dtype=torch.float64, device=DEV),
+                   bg=torch.tensor(prob.bg, dtype=torch.float64, device=DEV), dtype=torch.float64)
+    s.set_init()
+    obj = np.concatenate([s.iterate(20000, record=True) for _ in range(K // 20000)])   # history: 65,536 per call
+    x = s.x().cpu().numpy()
+    s.close()
+    e1000 = float(np.max(np.abs(obj[999::1000] - fx["obj_every_1000"]) / np.abs(fx["obj_every_1000"])))
+    elast = float(np.max(np.abs(obj[-1000:] - fx["obj_last_1000"]) / np.abs(fx["obj_last_1000"])))
+    ex = rel_l2(x, fx["x"])
+    if pos:
+        ref, got = float(fx["obj_last_1000"][-1]), float(obj[-1])
+    else:
+        ref, got = float(fx["f_min"]), float(obj[np.isfinite(obj)].min())
+    log(f"  max rel f (every 1000th) {e1000:.2e}, last 1000 {elast:.2e}, rel-L2 x {ex:.2e}; "
+        f"f* {got:.12g} vs oracle {ref:.12g}")
+    assert e1000 <= 1e-10 and elast <= 1e-10
+    assert abs(got - ref) <= 1e-10 * abs(ref)
+    assert ex <= 1e-8
