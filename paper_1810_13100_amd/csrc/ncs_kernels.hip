@@ -1013,14 +1013,15 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
     const int hmask = -half;                  // all ones in the upper half of the wave
     const int ql = WPI == 2 ? lane & 31 : lane;
     const bool loader = ql < NQ;
-    const int wmax = P - kRowWin;             // last window start inside the row
+    const int wmaxb = (P - kRowWin) * (int)sizeof(T);   // last window start inside the row (bytes)
     const int pitch32 = P * (int)sizeof(T);
     const unsigned lane_off = (unsigned)(half * pitch32 + ql * 16);
     T* const st = slots + half * kRowWin + ql * EQ;
     const char* row = reinterpret_cast<const char*>(src + (size_t)max(s_begin, 0) * P);
     T acc = T(0);
     int s = s_begin;
-    // coordinates of the B steps from sg: fractions, tap element indices, window starts
+    // coordinates of the B steps from sg: fractions, tap element indices, window
+    // starts (in bytes, so that neither the loads nor the LDS reads rescale them)
     auto coords = [&](int sg, T(&f)[B], int(&e)[B], int(&w)[B]) {
         const Anchor an = make_anchor(fma((double)sg, k2d, based));
         const T t0 = (T)an.t;
@@ -1032,7 +1033,7 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
             const int fl = floor_int(t);
             f[j] = frac_part(t);
             e[j] = ei + fl;
-            w[j] = min((eimin + __builtin_amdgcn_readlane(fl, lmin)) & ~(EQ - 1), wmax);
+            w[j] = min(((eimin + __builtin_amdgcn_readlane(fl, lmin)) * (int)sizeof(T)) & ~15, wmaxb);
         }
     };
     // the group's window loads, all in flight together (scalar base, 32-bit lane offset)
@@ -1041,8 +1042,8 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
 #pragma unroll
             for (int p = 0; p < B / WPI; ++p) {
                 // the lane's window start, w[2p] or w[2p + 1] (bytes), without an indexed access
-                const int wb0 = w[WPI * p] * (int)sizeof(T);
-                const int dwb = WPI == 2 ? (w[2 * p + 1] - w[2 * p]) * (int)sizeof(T) : 0;
+                const int wb0 = w[WPI * p];
+                const int dwb = WPI == 2 ? w[2 * p + 1] - w[2 * p] : 0;
                 const unsigned off = lane_off + (unsigned)wb0 + (unsigned)(dwb & hmask);
                 v[p] = *reinterpret_cast<const Bytes16*>(rg + (unsigned)(WPI * p * pitch32) + off);
             }
@@ -1058,7 +1059,7 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
         wave_lds_sync();
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-            const T* tp = (slots + (j * kRowWin - w[j])) + e[j];
+            const T* tp = reinterpret_cast<const T*>(reinterpret_cast<const char*>(slots + j * kRowWin) - w[j]) + e[j];
             acc += fma(f[j], tp[1] - tp[0], tp[0]);
         }
     };
@@ -1078,14 +1079,14 @@ __device__ inline T ray_sum_lds(const DevCtx<T>& c, const T* __restrict__ img, c
         const Anchor an = make_anchor(fma((double)s, k2d, based));
         const T t = (T)an.t;
         const int e = an.i + kPadL;
-        const int w = min(__builtin_amdgcn_readlane(e, lmin) & ~(EQ - 1), wmax);
+        const int w = min((__builtin_amdgcn_readlane(e, lmin) * (int)sizeof(T)) & ~15, wmaxb);
         Bytes16 v;
         const bool ld = loader && half == 0;
-        if (ld) v = *reinterpret_cast<const Bytes16*>(row + ((unsigned)(w * (int)sizeof(T)) + lane_off));
+        if (ld) v = *reinterpret_cast<const Bytes16*>(row + ((unsigned)w + lane_off));
         wave_lds_sync();
         if (ld) *reinterpret_cast<Bytes16*>(st) = v;
         wave_lds_sync();
-        const T* tp = (slots - w) + e;
+        const T* tp = reinterpret_cast<const T*>(reinterpret_cast<const char*>(slots) - w) + e;
         acc += fma(t, tp[1] - tp[0], tp[0]);
         row += pitch32;
     }
