@@ -305,14 +305,15 @@ def pet_params(ncs, c_r: float, alpha: float, gamma_frac: float, positivity: int
 
 def solve_projected(s, f_target: float, max_iters: int, chunk: int = 64):
     """Iterations until the projection max(x^k, 0) has f <= f_target, tested
-    every `chunk` iterations.  With x >= 0 the objective the library reports
+    every `chunk` iterations (and after the last of max_iters).  With x >= 0 the objective the library reports
     for x^k leaves out the indicator, so an infeasible iterate can lie below
     the constrained minimum; the projection is feasible, and its objective is
     the constrained one."""
     done = 0
     while done < max_iters:
-        s.iterate(chunk)
-        done += chunk
+        k = min(chunk, max_iters - done)
+        s.iterate(k)
+        done += k
         f = s.objective(s.x().clamp_(min=0))
         if f <= f_target:
             return done, f

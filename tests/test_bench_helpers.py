@@ -83,3 +83,7 @@ def test_projected_stop_ignores_infeasible_iterates_below_f_star():
     it, f = bench.solve_projected(s, 1e-4, 1000, chunk=2)
     assert it == 8 and abs(f - 0.5 ** 16) < 1e-18    # first chunk end with 4^-k <= 1e-4
     assert bench.solve_projected(_Shifted(), 1e-4, 6, chunk=2) == (None, None)
+    s = _Shifted()
+    assert bench.solve_projected(s, 1e-4, 6, chunk=4) == (None, None) and s.k == 6   # no overshoot
+    it, f = bench.solve_projected(_Shifted(), 1e-4, 7, chunk=4)
+    assert it == 7 and f == 0.25 ** 7                  # tested after the last iteration (4^-7 <= 1e-4)

@@ -115,6 +115,7 @@ def test_pet128_fp64_f_star_run(case):
                    b=torch.tensor(prob.b, dtype=torch.float64, device=DEV),
                    bg=torch.tensor(prob.bg, dtype=torch.float64, device=DEV), dtype=torch.float64)
     s.set_init()
+    assert K % 20000 == 0
     obj = np.concatenate([s.iterate(20000, record=True) for _ in range(K // 20000)])   # history: 65,536 per call
     x = s.x().cpu().numpy()
     s.close()
