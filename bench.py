@@ -414,7 +414,8 @@ def fan_time_to_gap(ncs, torch, dev, fstar_iters: int) -> dict:
     s64.close()
     out = {"workload": "256^2 fan beam, 90 views x 368 bins, source radius 512, anisotropic TV lambda 0.005, seed 0",
            "params": f"alpha {alpha}, beta 3 alpha, gamma = alpha N_v N / (2 pi) = {gamma:.4g}, 16 probes (eq. H-fan)",
-           "f_star": fstar, "f_star_source": f"min f over {fstar_iters} FP64 NCS iterations"}
+           "f_star": fstar, "f_star_source": f"min f over {fstar_iters} FP64 NCS iterations",
+           "f_star_rel_change_last_1000": float(abs(obj[-1] - obj[-1001]) / abs(obj[-1]))}
     gamma_p = 1.05 * alpha * (lam_e + (BETA_RATIO ** 2) * 8.0)
     for name, pp, budget in (("ncs", p, 60000),
                              ("pdhg", ncs.Params(alpha, BETA_RATIO * alpha, gamma_p, lam, method=ncs.METHOD_PDHG),
@@ -520,20 +521,24 @@ def cone_legs(ncs, torch, dev, steps: int, fstar_iters: int) -> dict:
     p_pdhg = cone.ConeParams(alpha, 3 * alpha, gamma_p, lam, method=ncs.METHOD_PDHG)
     progress(f"cone beam f*: {fstar_iters} FP64 NCS and PDHG iterations at 128^2 x 32")
     fstar = np.inf
+    tails = []
     for pp in (p_ncs, p_pdhg):
         s64 = cone.ConeSolver(geom, pp, b=b.double(), dtype=torch.float64)
         s64.set_init()
         done = 0
         while done < fstar_iters:
             k = min(2000, fstar_iters - done)
-            fstar = min(fstar, float(np.nanmin(s64.iterate(k, record=True))))
+            obj = s64.iterate(k, record=True)
+            fstar = min(fstar, float(np.nanmin(obj)))
             done += k
+        tails.append(float(abs(obj[-1] - obj[-1001]) / abs(obj[-1])))
         s64.close()
     gap = {"workload": "128^2 x 32 cone beam, 48 views x 32 rows x 184 columns, source radius 256, "
                        "anisotropic 3D TV lambda 0.005, seed 0, 1% noise",
            "params": f"alpha {alpha}, beta 3 alpha, NCS gamma 3.2 alpha N_v N / (2 pi) = {gamma:.4g}, "
                      f"PDHG gamma_P = {gamma_p:.4g}, 16 probes (eq. H-fan, 3D DFT)",
-           "f_star": fstar, "f_star_source": f"min f over {fstar_iters} FP64 NCS and {fstar_iters} FP64 PDHG iterations"}
+           "f_star": fstar, "f_star_source": f"min f over {fstar_iters} FP64 NCS and {fstar_iters} FP64 PDHG iterations",
+           "f_star_rel_change_last_1000": {"ncs": tails[0], "pdhg": tails[1]}}
     target = fstar * (1.0 + GAP)
     for name, pp, budget in (("ncs", p_ncs, 40000), ("pdhg", p_pdhg, 80000)):
         s = cone.ConeSolver(geom, pp, b=b)
@@ -806,7 +811,7 @@ def main() -> int:
                     help="backprojector kernel of the headline solver (0: the setup timing picks it)")
     ap.add_argument("--cone-steps", type=int, default=50, help="timed cone-beam iterations (0: skip the cone legs)")
     ap.add_argument("--steady-runs", type=int, default=5, help="more runs of 2,000 iterations after the timed steps")
-    ap.add_argument("--cone-fstar-iters", type=int, default=10000)
+    ap.add_argument("--cone-fstar-iters", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -831,7 +836,7 @@ def main() -> int:
         gap = time_to_gap(ncs, torch, dev, geom, args)
 
     pet = None if args.no_gap else pet_time_to_gap(ncs, torch, dev, 100000)
-    fan = None if args.no_gap else fan_time_to_gap(ncs, torch, dev, 30000)
+    fan = None if args.no_gap else fan_time_to_gap(ncs, torch, dev, 60000)
     batch = batch_legs(ncs, torch, dev, args.batch_iters, args.batch_gap_iters) if args.batch_iters > 0 else None
     cone_out = None
     if args.cone_steps > 0:
